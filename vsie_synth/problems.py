@@ -1,0 +1,62 @@
+"""Named problem instances: voxel grid + conductor meshes + frequency.
+
+  * ``tiny_case``  : 16^3 voxels at 5 mm, homogeneous sphere r = 35 mm (eps_r 52, sigma 0.55),
+                     one 60 mm square strip loop about 10 mm from the sphere (near, one port),
+                     closed cylindrical shield r = 150 mm, L = 300 mm, 2000 triangles (far).
+  * ``small_case`` : a scaled-down variant of the same layout for quick tests.
+  * ``two_mm_case``: 96x112x128 voxels at 2 mm, head-like phantom (seed 0), eight conformal
+                     loops on a 120 mm cylinder (near, eight ports), open tube shield
+                     r = 340 mm, L = 1.2 m, about 20k triangles (far).
+  * ``mie_case``   : the sphere alone (plane-wave excitation is built by the consumer).
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .meshes import FAR, NEAR, cylinder_shield, loop_array, strip_loop_flat
+from .phantoms import Grid, head_phantom, sphere_phantom
+
+LARMOR_7T_HZ = 297.2e6
+
+
+@dataclass
+class Problem:
+    grid: Grid
+    meshes: list = field(default_factory=list)
+    freq_hz: float = LARMOR_7T_HZ
+    name: str = ""
+
+    def n_ports(self):
+        return sum(m.n_ports for m in self.meshes)
+
+
+def tiny_case():
+    g = sphere_phantom((16, 16, 16), 5e-3, 35e-3, 52.0, 0.55)
+    # small offsets keep RWG edge midpoints off voxel faces (stencil base selection is a floor)
+    loop = strip_loop_flat((45.5e-3, 0.37e-3, -0.41e-3), side=60e-3, width=5e-3, step=5e-3)
+    shield = cylinder_shield(0.150, 0.300, 40, 20, closed=True, cap_rings=3)
+    return Problem(g, [shield, loop], LARMOR_7T_HZ, "tiny")
+
+
+def small_case(n=8, shield_around=12, shield_along=6):
+    """8^3 voxels at 5 mm, sphere r = 17 mm, 30 mm loop, coarse closed shield (fast tests)."""
+    g = sphere_phantom((n, n, n), 5e-3, 17e-3, 52.0, 0.55)
+    loop = strip_loop_flat((25.5e-3, 0.37e-3, -0.41e-3), side=30e-3, width=5e-3, step=5e-3)
+    shield = cylinder_shield(0.080, 0.160, shield_around, shield_along, closed=True, cap_rings=2)
+    return Problem(g, [shield, loop], LARMOR_7T_HZ, "small")
+
+
+def two_mm_case(seed=0, n=(96, 112, 128), h=2e-3, n_loops=8, shield_around=128, shield_along=78):
+    g = head_phantom(seed, n, h)
+    coil = loop_array(n_loops, radius=0.12, length=0.1, gap=10e-3, width=5e-3, step=2e-3,
+                      z_centre=0.37e-3, phi_offset=0.0013)
+    shield = cylinder_shield(0.340, 1.2, shield_around, shield_along, closed=False)
+    return Problem(g, [shield, coil], LARMOR_7T_HZ, "2mm")
+
+
+def mie_case(n=16, h=5e-3, radius=35e-3):
+    return Problem(sphere_phantom((n, n, n), h, radius, 52.0, 0.55), [], LARMOR_7T_HZ, "mie")
+
+
+__all__ = ["Problem", "tiny_case", "small_case", "two_mm_case", "mie_case", "NEAR", "FAR",
+           "LARMOR_7T_HZ"]
