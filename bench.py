@@ -1,0 +1,210 @@
+"""Benchmark: hybrid VSIE matrix-vector products per second and GMRES time-to-1e-6 at 2 mm.
+
+Workload: 96x112x128 voxels at 2 mm (head-like phantom, seed 0), eight conformal loops on a
+120 mm cylinder (near, pFFT), open tube shield r = 340 mm, L = 1.2 m, ~20k triangles (far:
+dense block + ACA + TT). One step is one application of the full operator of eq. (15) in
+FP64 to one right-hand side already resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-cpu-baseline]
+
+Prints one JSON line. Runs on one GPU only.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def stage_bytes(info, s):
+    """Algorithmic HBM bytes of one launch of each matvec stage (FP64: 16 B per complex value)."""
+    c = 16
+    ne1, ne2, ne3 = info["n_ext"]
+    P1, P2, P3 = info["fft"]
+    n1, n2, n3 = info["n"]
+    nv = n1 * n2 * n3
+    Ne = ne1 * ne2 * ne3
+    SO = (P1 // 2 + 1) * (P2 // 2 + 1) * (P3 // 2 + 1)
+    mf, mn = info["m_far"], info["m_near"]
+    b = {
+        "build_grid": c * (3 * nv + 3 * Ne) + mn * 0,
+        "fft_x_fwd": c * (3 * Ne + 3 * ne3 * ne2 * P1),
+        "fft_y_fwd": c * (3 * ne3 * ne2 * P1 + 3 * ne3 * P2 * P1),
+        "fft_z_conv": c * (2 * 3 * ne3 * P2 * P1 + 6 * SO),
+        "fft_y_inv": c * (3 * ne3 * P2 * P1 + 3 * ne3 * ne2 * P1),
+        "fft_x_inv": c * (3 * ne3 * ne2 * P1 + 3 * Ne),
+        "body_out": c * (2 * 3 * nv + 3 * nv + nv),
+        "pfft_gather": mn * 375 * (8 + c),
+        "gemv_far": c * (mf * mf + 2 * mf),
+    }
+    return b.get(s)
+
+
+def cpu_baseline(problem, budget_s=12.0):
+    """The oracle's dense O(N^2) product, timed on a 16^3 crop of the phantom's body block and
+    scaled to the full reduced system size N_red^2 of the workload."""
+    from oracle import system
+    import vsie_synth as synth
+    g = problem.grid
+    n = 16
+    c0 = (np.array(g.n) // 2 - n // 2)
+    eps = g.eps_r[c0[2]:c0[2] + n, c0[1]:c0[1] + n, c0[0]:c0[0] + n].copy()
+    sig = g.sigma[c0[2]:c0[2] + n, c0[1]:c0[1] + n, c0[0]:c0[0] + n].copy()
+    crop = synth.Grid((n, n, n), g.h, g.origin + c0 * g.h, eps, sig, np.zeros_like(eps, dtype=np.int32))
+    d = system.discretize(synth.Problem(crop, [], problem.freq_hz, "crop"))
+    S, _ = system.assemble_direct(d)
+    x = synth.complex_normal(d.N, 3)
+    reps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        S.matvec(x)
+        reps += 1
+    dt = (time.perf_counter() - t0) / reps
+    macs_per_s = S.Z.shape[0] * S.Z.shape[1] / dt
+    return macs_per_s, S.Z.shape[0], reps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--restart", type=int, default=200)
+    ap.add_argument("--max-iter", type=int, default=2000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the path has no multi-GPU mode); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2206_12409_amd as pkg
+    import vsie_synth as synth
+
+    torch.cuda.set_device(0)
+    problem = synth.two_mm_case()
+    t0 = time.perf_counter()
+    op = pkg.Operator(problem)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = op.info()
+    info["n"] = tuple(int(v) for v in problem.grid.n)
+    print("setup %.1f s: %s" % (setup_s, json.dumps(info)), file=sys.stderr, flush=True)
+
+    x = torch.from_numpy(synth.complex_normal(op.N, 1234)).cuda()
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        op.matvec(x, out=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        op.matvec(x, out=y)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = args.steps / el
+    print("fp64: %.1f matvec/s (%.3f ms)" % (value, 1e3 * el / args.steps), file=sys.stderr, flush=True)
+
+    x32 = x.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    for _ in range(args.warmup):
+        op.matvec(x32, out=y32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n32 = max(10, args.steps // 2)
+    for _ in range(n32):
+        op.matvec(x32, out=y32)
+    torch.cuda.synchronize()
+    value32 = n32 / (time.perf_counter() - t0)
+    err32 = float(torch.linalg.norm(y32.to(torch.complex128) - y) / torch.linalg.norm(y))
+    print("fp32: %.1f matvec/s, rel err vs fp64 %.2e" % (value32, err32), file=sys.stderr, flush=True)
+
+    # per-stage timing with HIP events recorded on the stream the kernels run on
+    op.profile(True)
+    nprof = 20
+    for _ in range(nprof):
+        op.matvec(x, out=y)
+    stages = op.profile_read()
+    op.profile(False)
+    per_stage = {k: v[0] / v[1] for k, v in stages.items()}
+    dom = max(per_stage, key=per_stage.get)
+    rl = {}
+    for k, ms in per_stage.items():
+        b = stage_bytes(info, k)
+        if b:
+            rl[k] = dict(ms=round(ms, 4), gbs=round(b / (ms * 1e-3) / 1e9, 1))
+    db = stage_bytes(info, dom)
+    dom_ms = per_stage[dom]
+    achieved = db / (dom_ms * 1e-3) / 1e9
+    conv_ms = sum(per_stage.get(k, 0) for k in ("build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv",
+                                                   "fft_y_inv", "fft_x_inv", "body_out"))
+    conv_b = sum(stage_bytes(info, k) for k in ("build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv",
+                                                  "fft_y_inv", "fft_x_inv", "body_out"))
+    print("stages: %s" % json.dumps(rl), file=sys.stderr, flush=True)
+
+    solve = {}
+    if not args.no_solve:
+        b = op.rhs(0)
+        torch.cuda.synchronize()
+        xs, st = op.solve(b, tol=1e-6, restart=args.restart, max_iter=args.max_iter, allow_noconv=True)
+        solve["gmres64"] = dict(seconds=round(st[0]["seconds"], 3), iterations=st[0]["iterations"],
+                                rel_residual=st[0]["rel_residual"], converged=st[0]["converged"],
+                                restart=args.restart)
+        print("gmres64: %s" % solve["gmres64"], file=sys.stderr, flush=True)
+        xm, sm = op.solve(b, tol=1e-6, restart=args.restart, max_iter=args.max_iter, method=1, inner_tol=1e-3,
+                          allow_noconv=True)
+        diff = float(torch.linalg.norm(xm - xs) / torch.linalg.norm(xs))
+        solve["ir_mixed"] = dict(seconds=round(sm[0]["seconds"], 3), iterations=sm[0]["iterations"],
+                                 refinements=sm[0]["refinements"], rel_residual=sm[0]["rel_residual"],
+                                 converged=sm[0]["converged"], rel_diff_vs_fp64=diff)
+        print("ir_mixed: %s" % solve["ir_mixed"], file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        macs, nred, reps = cpu_baseline(problem)
+        n_red = op.m_far + op.m_near + 3 * info["n_tissue"]
+        cpu = dict(value=macs / float(n_red) ** 2, unit="matvec/s", cores=os.cpu_count(), kind="oracle",
+                   sample="dense O(N^2) oracle product on a 16^3 crop of the phantom (%d unknowns, %d reps), "
+                          "scaled by (%d / %d)^2 to the workload's reduced system" % (nred, reps, n_red, nred))
+
+    out = {
+        "metric": "VSIE matvec/s + GMRES time-to-1e-6 at 2 mm VIR, plain vs learned-precond",
+        "value": round(value, 3),
+        "unit": "matvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 / value, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "hybrid VSIE 2 mm: 96x112x128 head-like phantom (seed 0), 8-loop array "
+                               "%d near RWG, open shield %d far RWG, 297.2 MHz, single RHS"
+                               % (op.m_near, op.m_far),
+                   "n_unknowns": op.N, "n_ext": list(info["n_ext"]), "fft": list(info["fft"]),
+                   "tt_rank": info["tt_rank"], "aca_rank": info["aca_rank"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "bytes_per_launch": db, "avg_ms": round(dom_ms, 4)},
+        "volume_conv": {"ms": round(conv_ms, 4), "bytes": conv_b,
+                        "gbs": round(conv_b / (conv_ms * 1e-3) / 1e9, 1) if conv_ms else None},
+        "stages": rl,
+        "c64": {"value": round(value32, 3), "unit": "matvec/s", "rel_err_vs_c128": err32},
+        "solve": solve,
+        "setup_seconds": round(setup_s, 2),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

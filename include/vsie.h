@@ -1,0 +1,207 @@
+/*
+ * vsie.h -- C ABI of the MI355X hybrid volume-surface integral equation (VSIE) library.
+ *
+ * The library builds and applies the hybrid VSIE operator of Giannakopoulos et al.,
+ * "A hybrid volume-surface integral equation method for rapid electromagnetic simulations in
+ * MRI" (arXiv 2206.12409), Sec. III eq. (15):
+ *
+ *     [ Z_cc^ff        conj(V) U^T    Zt^T          ] [ j_far  ]   [ v_far  ]
+ *     [ U V^*          Z^pFFT (near, body)          ] [ j_near ] = [ v_near ]
+ *     [ Zt             (eq. (13))                   ] [ j_body ]   [ 0      ]
+ *
+ * where Z_cc^ff is the dense Galerkin matrix of the far conductors (eq. (6)), U V^* the adaptive
+ * cross approximation of the near-far conductor block (eq. (12)), Zt the tensor-train
+ * compressed far coupling (eq. (14)), and Z^pFFT the precorrected-FFT operator of the near
+ * conductors and the voxelised body (eq. (13)) whose volume part is the block-Toeplitz
+ * convolution of Sec. II-B.
+ *
+ * Conventions (fixed by the paper's statement of the problem, Sec. II):
+ *   - exp(+i w t) time dependence; g(R) = exp(-i k0 R) / (4 pi R);
+ *   - complex susceptibility chi = eps_r - 1 - i sigma / (w eps0); voxels with chi = 0 are air
+ *     and carry identity rows and columns;
+ *   - every row multiplied by i w eps0; body rows tested with the field (eq. (4) divided by chi),
+ *     so the matrix is complex symmetric (eq. (8));
+ *   - unknown vector, complex interleaved, length N = m_f + m_n + 3 n_v:
+ *         [ j_far (m_f) | j_near (m_n) | j_body^x (n_v) | j_body^y (n_v) | j_body^z (n_v) ]
+ *     far and near RWG functions in mesh input order, edges of a mesh sorted by
+ *     (min vertex, max vertex); voxels with i1 fastest, flat index i1 + n1 (i2 + n2 i3);
+ *   - RWG orientation: for edge (a, b), a < b, T+ is the triangle listing a then b in cyclic
+ *     order; positive current flows from T+ into T-.
+ *
+ * Error convention: every call returns an int status (VSIE_OK = 0). On failure a thread-local
+ * message is available from vsie_last_error(). Nothing throws across this interface.
+ * Streams are hipStream_t passed as void* (NULL = the default stream).
+ */
+#ifndef VSIE_H
+#define VSIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum vsie_status {
+  VSIE_OK = 0,
+  VSIE_E_ARG = 1,          /* null pointer, bad size, non-finite value */
+  VSIE_E_MESH = 2,         /* degenerate triangle, inconsistent orientation, bad port edge */
+  VSIE_E_STENCIL = 3,      /* a near RWG pair does not fit its 5x5x5 expansion block (Sec. IV-B) */
+  VSIE_E_GRID = 4,         /* grid or extended grid too large */
+  VSIE_E_NOMEM = 5,        /* device or host allocation failed */
+  VSIE_E_HIP = 6,          /* a HIP runtime call failed */
+  VSIE_E_NOCONV = 7,       /* solver hit max_iter; statistics are still filled */
+  VSIE_E_BREAKDOWN = 8,    /* Arnoldi breakdown without convergence */
+  VSIE_E_UNSUPPORTED = 9,  /* option not supported (e.g. piecewise-linear basis) */
+  VSIE_E_STATE = 10        /* operation not valid for this handle (e.g. precision not built) */
+};
+
+enum vsie_domain { VSIE_NEAR = 0, VSIE_FAR = 1 };
+enum vsie_dtype { VSIE_C128 = 0, VSIE_C64 = 1 };
+
+/* A triangle mesh of a perfectly conducting surface (Sec. II-B, RWG basis). */
+typedef struct {
+  const double* verts;        /* [n_verts][3] metres, host memory, copied by vsie_create */
+  int32_t n_verts;
+  const int32_t* tris;        /* [n_tris][3] vertex ids, consistently oriented */
+  int32_t n_tris;
+  int32_t domain;             /* VSIE_NEAR (pFFT, Sec. III) or VSIE_FAR (TT + ACA + dense) */
+  const int32_t* port_edges;  /* [n_port_edges][2] directed interior edges (a, b); may be NULL */
+  const int32_t* port_id;     /* [n_port_edges] port number within this mesh, 0..n_ports-1 */
+  int32_t n_port_edges;
+} vsie_mesh;
+
+/* The voxelised body and the conductors (Sec. II-B, Sec. IV-A/B). */
+typedef struct {
+  int32_t n[3];               /* voxels per axis */
+  double h;                   /* voxel edge, metres */
+  double origin[3];           /* lower corner of voxel (0,0,0) */
+  double freq_hz;             /* operating (Larmor) frequency */
+  const double* eps_r;        /* [n3][n2][n1] relative permittivity, host */
+  const double* sigma;        /* [n3][n2][n1] conductivity S/m, host */
+  int32_t n_meshes;
+  const vsie_mesh* meshes;
+} vsie_problem;
+
+typedef struct {
+  double tt_tol;              /* TT-cross relative accuracy, Sec. IV-C: 1e-3 */
+  int32_t tt_rank_max;        /* rank cap per TT unfolding */
+  double aca_tol;             /* ACA relative accuracy, Sec. IV-C: 1e-3 */
+  int32_t aca_rank_max;
+  int32_t precorrect_dist;    /* Chebyshev distance (voxels) of precorrected pairs, default 2 */
+  int32_t build_c64;          /* also prepare complex64 operator data (mixed precision) */
+  int32_t build_far;          /* compute TT-cross and ACA (0: zero far coupling until imported) */
+  uint64_t seed;              /* TT-cross initial index sets */
+} vsie_options;
+
+typedef struct {
+  int64_t n_total;            /* N */
+  int32_t m_far, m_near;      /* RWG counts */
+  int32_t n[3];               /* body grid */
+  int32_t n_ext[3];           /* extended (pFFT) grid enclosing body and near stencils */
+  int32_t fft[3];             /* circulant FFT size per axis */
+  int32_t n_ports;
+  int32_t n_tissue;           /* voxels with chi != 0 */
+  int32_t tt_rank[3][3];      /* [component][unfolding] */
+  double tt_err_est[3];       /* held-out relative error estimate of each TT */
+  int32_t aca_rank;
+  int64_t precorr_nnz;
+  int64_t device_bytes;       /* operator data held on the device */
+  double setup_seconds;
+} vsie_sizes_t;
+
+typedef struct {
+  double tol;                 /* relative residual ||b - Ax|| / ||b||, default 1e-6 */
+  int32_t restart;            /* GMRES restart length, default 50 (Sec. IV-C) */
+  int32_t max_iter;           /* total inner iterations */
+  int32_t method;             /* VSIE_GMRES64 or VSIE_IR_MIXED */
+  double inner_tol;           /* mixed precision: inner FP32 solve tolerance, default 1e-3 */
+} vsie_solve_opts;
+
+enum vsie_method { VSIE_GMRES64 = 0, VSIE_IR_MIXED = 1 };
+
+typedef struct {
+  int32_t iterations;         /* matrix-vector products in the Krylov iterations */
+  int32_t restarts;
+  int32_t refinements;        /* outer steps (mixed precision) */
+  double rel_residual;        /* true FP64 ||b - Ax|| / ||b|| at exit */
+  double block_residual[3];   /* relative residual restricted to far / near / body rows */
+  double seconds;
+} vsie_solve_stats;
+
+/* Fill defaults: tt_tol 1e-3, tt_rank_max 30, aca_tol 1e-3, aca_rank_max 64,
+ * precorrect_dist 2, build_c64 1, build_far 1, seed 1. */
+int vsie_default_options(vsie_options* opts);
+int vsie_default_solve_opts(vsie_solve_opts* opts);
+
+/* Set up the operator (Sec. III): RWG tables, extended grid, Green-tensor generator and its
+ * circulant spectra (Sec. II-B), pFFT stencils and precorrection (eq. (13)), TT-cross of the far
+ * coupling (eq. (14)), ACA of the near-far block (eq. (12)), dense Z_cc^ff (eq. (6)).
+ * All inputs are copied; the handle owns every device allocation. Blocks until done.
+ * Errors: E_ARG, E_MESH, E_STENCIL, E_GRID, E_NOMEM, E_HIP, E_UNSUPPORTED. */
+int vsie_create(const vsie_problem* problem, const vsie_options* opts, void* stream,
+                struct vsie_handle** out);
+
+int vsie_sizes(const struct vsie_handle* h, vsie_sizes_t* out);
+
+/* Delta-gap right-hand side of one port (Sec. II-A after eq. (2)): b_m = s_m i w eps0 V0 l_m,
+ * V0 = 1 V, into the caller-owned device buffer b_dev of N complex values of type dtype.
+ * Asynchronous on stream. Errors: E_ARG (port out of range). */
+int vsie_rhs(const struct vsie_handle* h, int port, int dtype, void* b_dev, void* stream);
+
+/* y = Z x for nrhs columns, layout [nrhs][N] complex interleaved (complex128 or complex64 as
+ * dtype says), device memory owned by the caller, 256-byte aligned, x and y must not alias.
+ * Asynchronous on stream. The handle's work buffers serialise calls on one handle.
+ * Errors: E_ARG, E_STATE (complex64 data not built), E_HIP. */
+int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, void* y_dev,
+                void* stream);
+
+/* Solve Z x = b for nrhs right-hand sides (device, [nrhs][N] complex128) with restarted GMRES
+ * (Sec. III-A: zero initial guess, FP64 classical Gram-Schmidt applied twice) or mixed-precision
+ * iterative refinement (complex64 inner GMRES, FP64 residual). x_dev receives complex128.
+ * Blocks. stats (array of nrhs, may be NULL) are filled even on E_NOCONV. */
+int vsie_solve(struct vsie_handle* h, const vsie_solve_opts* opts, int nrhs, const void* b_dev,
+               void* x_dev, vsie_solve_stats* stats, void* stream);
+
+/* Port current I = sum_m s_m l_m x_m of a solution held in host memory (complex128, length N). */
+int vsie_port_current(const struct vsie_handle* h, int port, const double* x_host, double* I_re_im);
+
+/* Setup artefacts (host copies), for checkpointing and for tests. `index` selects the TT
+ * component (0..2) where relevant. Call with host == NULL to query the byte count.
+ *   VSIE_X_TT_CORES    int32 r1,r2,r3 then complex128 G1[n1][r1], G2[r1][n2][r2],
+ *                      G3[r2][n3][r3], G4[r3][m_f]
+ *   VSIE_X_ACA         int32 k then complex128 U[m_n][k], V[m_f][k]  (Z_nf ~ U V^*)
+ *   VSIE_X_STENCIL     int32 base[m_n][3] (relative to the body grid) then double W[m_n][3][125]
+ *   VSIE_X_GENERATOR   complex128 T[6][ne3][ne2][ne1] dimensionless generator on the octant
+ *   VSIE_X_EXT_GRID    int32 ne[3], body_offset[3], fft[3] */
+enum vsie_export_kind {
+  VSIE_X_TT_CORES = 1,
+  VSIE_X_ACA = 2,
+  VSIE_X_STENCIL = 3,
+  VSIE_X_GENERATOR = 4,
+  VSIE_X_EXT_GRID = 5
+};
+int vsie_export(const struct vsie_handle* h, int what, int index, void* host, size_t* nbytes);
+
+/* Replace a compressed block with stored data (the "store and recycle" use of the compressed
+ * coupling, Sec. VI): VSIE_X_TT_CORES (one component per call) or VSIE_X_ACA, same layout as
+ * vsie_export. Errors: E_ARG (size mismatch). */
+int vsie_import(struct vsie_handle* h, int what, int index, const void* host, size_t nbytes);
+
+/* Per-stage timing of vsie_matvec with HIP events recorded on the caller's stream (the stream
+ * each kernel runs on). enable != 0 creates the events and resets the totals; while enabled,
+ * every matvec synchronises its stream once at the end. Stages: build_grid, fft_x_fwd,
+ * fft_y_fwd, fft_z_conv, fft_y_inv, fft_x_inv, body_out, pfft_gather, gemv_far, precorrect,
+ * aca, tt. vsie_profile_read returns up to max_stages entries (names are static strings),
+ * the summed milliseconds and the number of timed calls per stage, and the stage count. */
+int vsie_profile(struct vsie_handle* h, int enable);
+int vsie_profile_read(const struct vsie_handle* h, int max_stages, const char** names, double* total_ms,
+                      int64_t* calls, int* n_stages);
+
+void vsie_destroy(struct vsie_handle* h);
+const char* vsie_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VSIE_H */

@@ -1,0 +1,1076 @@
+// Device kernels of the hybrid VSIE library (gfx950).
+//
+//   setup:   Toeplitz generator of the volume operator on the extended-grid octant, circulant
+//            embedding, EFIE entries (dense block and pair lists), pFFT precorrection entries,
+//            near-rule coupling entries;
+//   FFT:     LDS-staged Stockham radix-4/2 passes (contiguous rows, strided pencils) and the fused
+//            z pass: forward FFT -> 3x3 symmetric spectral multiply -> inverse FFT;
+//   matvec:  grid build (body embed + pFFT projection), body epilogue, pFFT interpolation,
+//            precorrection SpMV, ACA, TT forward/transpose contractions, dense GEMV;
+//   solver:  multi-dot, multi-axpy, norms and conversions for GMRES.
+#include "kernels.h"
+
+namespace vsie {
+
+// =============================================================================================
+// Setup kernels
+// =============================================================================================
+
+__global__ void k_generator_octant(const GaussTab* __restrict__ gt, int ne1, int ne2, int ne3, double kappa,
+                                   CellRule cr, cxd* __restrict__ oct) {
+  const int64_t S = (int64_t)ne1 * ne2 * ne3;
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= S) return;
+  int d1 = (int)(id % ne1);
+  int d2 = (int)((id / ne1) % ne2);
+  int d3 = (int)(id / ((int64_t)ne1 * ne2));
+  cxd T[6];
+  generator_T(*gt, d1, d2, d3, kappa, cr, T);
+  for (int c = 0; c < 6; ++c) oct[c * S + id] = T[c];
+}
+
+// full circulant grid t_c(n) for n in [0,P)^3, from the octant with the component parities
+__global__ void k_embed_circulant(const cxd* __restrict__ oct, int ne1, int ne2, int ne3, int P1, int P2, int P3,
+                                  cxd* __restrict__ full) {
+  const int64_t PT = (int64_t)P1 * P2 * P3;
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= PT) return;
+  int n1 = (int)(id % P1), n2 = (int)((id / P1) % P2), n3 = (int)(id / ((int64_t)P1 * P2));
+  auto off = [](int nn, int P, int ne, int* d) -> bool {
+    if (nn < ne) { *d = nn; return true; }
+    if (nn > P - ne) { *d = nn - P; return true; }
+    return false;
+  };
+  int d1, d2, d3;
+  bool ok = off(n1, P1, ne1, &d1) && off(n2, P2, ne2, &d2) && off(n3, P3, ne3, &d3);
+  const int64_t S = (int64_t)ne1 * ne2 * ne3;
+  for (int c = 0; c < 6; ++c) {
+    cxd v = {0.0, 0.0};
+    if (ok) {
+      int a1 = d1 < 0 ? -d1 : d1, a2 = d2 < 0 ? -d2 : d2, a3 = d3 < 0 ? -d3 : d3;
+      v = oct[c * S + a1 + (int64_t)ne1 * (a2 + (int64_t)ne2 * a3)];
+      double s = 1.0;
+      if (c == 3) s = (double)((d1 > 0) - (d1 < 0)) * ((d2 > 0) - (d2 < 0));
+      if (c == 4) s = (double)((d1 > 0) - (d1 < 0)) * ((d3 > 0) - (d3 < 0));
+      if (c == 5) s = (double)((d2 > 0) - (d2 < 0)) * ((d3 > 0) - (d3 < 0));
+      v = s * v;
+    }
+    full[c * PT + id] = v;
+  }
+}
+
+template <typename R>
+__global__ void k_extract_octant(const cxd* __restrict__ full, int P1, int P2, int P3, double scale,
+                                 cx<R>* __restrict__ spec) {
+  const int S1 = P1 / 2 + 1, S2 = P2 / 2 + 1, S3 = P3 / 2 + 1;
+  const int64_t SO = (int64_t)S1 * S2 * S3;
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= SO) return;
+  int f1 = (int)(id % S1), f2 = (int)((id / S1) % S2), f3 = (int)(id / ((int64_t)S1 * S2));
+  const int64_t PT = (int64_t)P1 * P2 * P3;
+  int64_t src = f1 + (int64_t)P1 * (f2 + (int64_t)P2 * f3);
+  for (int c = 0; c < 6; ++c) {
+    cxd v = full[c * PT + src];
+    spec[c * SO + id] = cx<R>{(R)(v.re * scale), (R)(v.im * scale)};
+  }
+}
+
+// EFIE entry of two RWG functions (testing m of A, source n of B): sum over the four triangle
+// pairs of s_a s_b [ -k^2 l_m l_n / (4 A_a A_b) Am[fa][fb] + l_m l_n / (A_a A_b) Bm ]
+__device__ __host__ inline cxd rwg_pair_entry(const RwgDev& A, int m, const RwgDev& B, int n, double k) {
+  cxd acc = {0, 0};
+  for (int sa = 0; sa < 2; ++sa) {
+    int ta = A.tpm[2 * m + sa];
+    int fa = A.flpm[2 * m + sa];
+    V3 va[3];
+    for (int q = 0; q < 3; ++q) {
+      int v = A.tris[3 * ta + q];
+      va[q] = {A.verts[3 * v], A.verts[3 * v + 1], A.verts[3 * v + 2]};
+    }
+    double Aa = A.area[ta];
+    for (int sb = 0; sb < 2; ++sb) {
+      int tb = B.tpm[2 * n + sb];
+      int fb = B.flpm[2 * n + sb];
+      V3 vb[3];
+      for (int q = 0; q < 3; ++q) {
+        int v = B.tris[3 * tb + q];
+        vb[q] = {B.verts[3 * v], B.verts[3 * v + 1], B.verts[3 * v + 2]};
+      }
+      double Ab = B.area[tb];
+      cxd Bm, Am[3][3];
+      tri_pair_moments(va, vb, Aa, Ab, k, &Bm, Am);
+      double sg = (sa == sb) ? 1.0 : -1.0;
+      double ll = A.len[m] * B.len[n];
+      cxd term = (-(k * k) * ll / (4.0 * Aa * Ab)) * Am[fa][fb];
+      term += (ll / (Aa * Ab)) * Bm;
+      acc += sg * term;
+    }
+  }
+  return acc;
+}
+
+__global__ void k_zcc_dense(RwgDev A, RwgDev B, double k, int64_t row0, int64_t nrows, cxd* __restrict__ out) {
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nrows * B.m) return;
+  int m = (int)(row0 + id / B.m);
+  int n = (int)(id % B.m);
+  out[id] = rwg_pair_entry(A, m, B, n, k);
+}
+
+__global__ void k_zcc_pairs(RwgDev A, RwgDev B, const int* __restrict__ pi, const int* __restrict__ pj, int64_t np,
+                            double k, cxd* __restrict__ out) {
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= np) return;
+  out[id] = rwg_pair_entry(A, pi[id], B, pj[id], k);
+}
+
+__device__ inline void T_lookup(const cxd* __restrict__ oct, int ne1, int ne2, int ne3, int d1, int d2, int d3,
+                                cxd T[6]) {
+  const int64_t S = (int64_t)ne1 * ne2 * ne3;
+  int a1 = d1 < 0 ? -d1 : d1, a2 = d2 < 0 ? -d2 : d2, a3 = d3 < 0 ? -d3 : d3;
+  int64_t idx = a1 + (int64_t)ne1 * (a2 + (int64_t)ne2 * a3);
+  double s1 = (double)((d1 > 0) - (d1 < 0)), s2 = (double)((d2 > 0) - (d2 < 0)), s3 = (double)((d3 > 0) - (d3 < 0));
+  T[0] = oct[idx];
+  T[1] = oct[S + idx];
+  T[2] = oct[2 * S + idx];
+  T[3] = (s1 * s2) * oct[3 * S + idx];
+  T[4] = (s1 * s3) * oct[4 * S + idx];
+  T[5] = (s2 * s3) * oct[5 * S + idx];
+}
+
+__device__ inline void T_apply(const cxd T[6], const double w[3], cxd out[3]) {
+  out[0] = w[0] * T[0] + w[1] * T[3] + w[2] * T[4];
+  out[1] = w[0] * T[3] + w[1] * T[1] + w[2] * T[5];
+  out[2] = w[0] * T[4] + w[1] * T[5] + w[2] * T[2];
+}
+
+// Grid interaction of two near RWG functions, sum_u sum_v W_m(u) . T(u - v) W_n(v) (dimensionless
+// generator; the caller scales by h^3). One block per pair.
+__global__ __launch_bounds__(256) void k_pfft_wtw_pairs(const double* __restrict__ W, const int* __restrict__ base,
+                                                        const cxd* __restrict__ oct, int ne1, int ne2, int ne3,
+                                                        const int* __restrict__ pm, const int* __restrict__ pn,
+                                                        cxd* __restrict__ out) {
+  __shared__ double wm[375], wn[375];
+  __shared__ double red[2][256];
+  const int pair = blockIdx.x;
+  const int m = pm[pair], n = pn[pair];
+  for (int e = threadIdx.x; e < 375; e += 256) {
+    wm[e] = W[(int64_t)m * 375 + e];
+    wn[e] = W[(int64_t)n * 375 + e];
+  }
+  __syncthreads();
+  const int bm1 = base[3 * m], bm2 = base[3 * m + 1], bm3 = base[3 * m + 2];
+  const int bn1 = base[3 * n], bn2 = base[3 * n + 1], bn3 = base[3 * n + 2];
+  cxd acc = {0, 0};
+  const int t = threadIdx.x;
+  if (t < 250) {
+    int u = t % 125, half = t / 125;
+    int u1 = u % 5, u2 = (u / 5) % 5, u3 = u / 25;
+    double w_u[3] = {wm[u], wm[125 + u], wm[250 + u]};
+    cxd f[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int v = half; v < 125; v += 2) {
+      int v1 = v % 5, v2 = (v / 5) % 5, v3 = v / 25;
+      cxd T[6];
+      T_lookup(oct, ne1, ne2, ne3, (bm1 + u1) - (bn1 + v1), (bm2 + u2) - (bn2 + v2), (bm3 + u3) - (bn3 + v3), T);
+      double w_v[3] = {wn[v], wn[125 + v], wn[250 + v]};
+      cxd o[3];
+      T_apply(T, w_v, o);
+      f[0] += o[0];
+      f[1] += o[1];
+      f[2] += o[2];
+    }
+    acc = w_u[0] * f[0] + w_u[1] * f[1] + w_u[2] * f[2];
+  }
+  red[0][t] = acc.re;
+  red[1][t] = acc.im;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      red[0][t] += red[0][t + s];
+      red[1][t] += red[1][t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) out[pair] = cxd{red[0][0], red[1][0]};
+}
+
+// Grid field of RWG n at voxel u (extended-grid coordinates): sum_v T(u - v) W_n(v) (dimensionless)
+__global__ void k_pfft_tw_voxels(const double* __restrict__ W, const int* __restrict__ base,
+                                 const cxd* __restrict__ oct, int ne1, int ne2, int ne3,
+                                 const int* __restrict__ vox /*[np][3] ext coords*/, const int* __restrict__ pn,
+                                 int64_t np, cxd* __restrict__ out /*[np][3]*/) {
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= np) return;
+  const int n = pn[id];
+  const int u1 = vox[3 * id], u2 = vox[3 * id + 1], u3 = vox[3 * id + 2];
+  const int b1 = base[3 * n], b2 = base[3 * n + 1], b3 = base[3 * n + 2];
+  cxd f[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int v = 0; v < 125; ++v) {
+    int v1 = v % 5, v2 = (v / 5) % 5, v3 = v / 25;
+    cxd T[6];
+    T_lookup(oct, ne1, ne2, ne3, u1 - (b1 + v1), u2 - (b2 + v2), u3 - (b3 + v3), T);
+    double w_v[3] = {W[(int64_t)n * 375 + v], W[(int64_t)n * 375 + 125 + v], W[(int64_t)n * 375 + 250 + v]};
+    cxd o[3];
+    T_apply(T, w_v, o);
+    f[0] += o[0];
+    f[1] += o[1];
+    f[2] += o[2];
+  }
+  out[3 * id] = f[0];
+  out[3 * id + 1] = f[1];
+  out[3 * id + 2] = f[2];
+}
+
+// Coupling entries with the near rule (8 volume x 5 surface points) for (voxel, RWG) pairs:
+// Z_bc[p a, n] = - sum_i (h^3/8) sum_sides s (l/2) sum_q w_q [ D(r_i - r'_q) (r'_q - p_T) ]_a
+__global__ void k_zbc_near_pairs(RwgDev B, const double* __restrict__ centres /*[np][3]*/, const int* __restrict__ pn,
+                                 int64_t np, double h, double k, cxd* __restrict__ out /*[np][3]*/) {
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= np) return;
+  const int n = pn[id];
+  const double a = 0.5 / sqrt(3.0) * h;
+  V3 c = {centres[3 * id], centres[3 * id + 1], centres[3 * id + 2]};
+  cxd acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int side = 0; side < 2; ++side) {
+    int t = B.tpm[2 * n + side];
+    int fv = B.fpm[2 * n + side];
+    double s = side == 0 ? 1.0 : -1.0;
+    V3 tv[3];
+    for (int q = 0; q < 3; ++q) {
+      int v = B.tris[3 * t + q];
+      tv[q] = {B.verts[3 * v], B.verts[3 * v + 1], B.verts[3 * v + 2]};
+    }
+    V3 pf = {B.verts[3 * fv], B.verts[3 * fv + 1], B.verts[3 * fv + 2]};
+    for (int q = 0; q < 5; ++q) {
+      double l[3], w;
+      r5_point(q, l, &w);
+      V3 rs = l[0] * tv[0] + l[1] * tv[1] + l[2] * tv[2];
+      V3 fvv = (w * s * 0.5 * B.len[n]) * (rs - pf);
+      cxd fv3[3] = {{fvv.x, 0}, {fvv.y, 0}, {fvv.z, 0}};
+      for (int iz = 0; iz < 2; ++iz)
+        for (int iy = 0; iy < 2; ++iy)
+          for (int ix = 0; ix < 2; ++ix) {
+            V3 r = {c.x + (ix ? a : -a), c.y + (iy ? a : -a), c.z + (iz ? a : -a)};
+            cxd o[3];
+            dyad_apply(r - rs, fv3, k, o);
+            acc[0] += o[0];
+            acc[1] += o[1];
+            acc[2] += o[2];
+          }
+    }
+  }
+  const double wv = -h * h * h / 8.0;
+  out[3 * id] = wv * acc[0];
+  out[3 * id + 1] = wv * acc[1];
+  out[3 * id + 2] = wv * acc[2];
+}
+
+// =============================================================================================
+// FFT (Stockham autosort, radix 4 with a final radix-2 stage when log2 L is odd)
+// =============================================================================================
+
+template <typename R, int L, int NP, bool FWD>
+__device__ inline void lds_fft(cx<R>* sm, const cx<R>* __restrict__ tw, int tid) {
+  constexpr int LP = L + 1;
+  constexpr int NB4 = (NP * (L / 4) + 255) / 256;
+  constexpr int NB2 = (NP * (L / 2) + 255) / 256;
+  int Ls = 1;
+#pragma unroll 1
+  for (; Ls * 4 <= L; Ls *= 4) {
+    cx<R> v[NB4][4];
+    const int tstep = L / (4 * Ls);
+#pragma unroll
+    for (int u = 0; u < NB4; ++u) {
+      int b = tid + u * 256;
+      if (b < NP * (L / 4)) {
+        int p = b / (L / 4), j = b % (L / 4);
+        int kk = j & (Ls - 1);
+        cx<R>* s = sm + p * LP;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          cx<R> a = s[j + q * (L / 4)];
+          if (q) {
+            cx<R> w = tw[(q * kk * tstep) & (L - 1)];
+            if (!FWD) w.im = -w.im;
+            a = a * w;
+          }
+          v[u][q] = a;
+        }
+        cx<R> t0 = v[u][0] + v[u][2], t1 = v[u][0] - v[u][2], t2 = v[u][1] + v[u][3], d = v[u][1] - v[u][3];
+        cx<R> t3 = FWD ? cx<R>{d.im, -d.re} : cx<R>{-d.im, d.re};
+        v[u][0] = t0 + t2;
+        v[u][1] = t1 + t3;
+        v[u][2] = t0 - t2;
+        v[u][3] = t1 - t3;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NB4; ++u) {
+      int b = tid + u * 256;
+      if (b < NP * (L / 4)) {
+        int p = b / (L / 4), j = b % (L / 4);
+        int kk = j & (Ls - 1);
+        cx<R>* s = sm + p * LP;
+        int base = (j - kk) * 4 + kk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[base + q * Ls] = v[u][q];
+      }
+    }
+    __syncthreads();
+  }
+  if (Ls < L) {
+    cx<R> v[NB2][2];
+    const int tstep = L / (2 * Ls);
+#pragma unroll
+    for (int u = 0; u < NB2; ++u) {
+      int b = tid + u * 256;
+      if (b < NP * (L / 2)) {
+        int p = b / (L / 2), j = b % (L / 2);
+        int kk = j & (Ls - 1);
+        cx<R>* s = sm + p * LP;
+        cx<R> a0 = s[j], a1 = s[j + L / 2];
+        cx<R> w = tw[(kk * tstep) & (L - 1)];
+        if (!FWD) w.im = -w.im;
+        a1 = a1 * w;
+        v[u][0] = a0 + a1;
+        v[u][1] = a0 - a1;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NB2; ++u) {
+      int b = tid + u * 256;
+      if (b < NP * (L / 2)) {
+        int p = b / (L / 2), j = b % (L / 2);
+        int kk = j & (Ls - 1);
+        cx<R>* s = sm + p * LP;
+        int base = (j - kk) * 2 + kk;
+        s[base] = v[u][0];
+        s[base + Ls] = v[u][1];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Rows contiguous along the FFT axis; NP rows per block. Inputs beyond n_in are zero; outputs
+// beyond n_out are not stored (pruned transforms).
+template <typename R, int L, bool FWD>
+__global__ __launch_bounds__(256) void k_fft_rows(const cx<R>* __restrict__ in, cx<R>* __restrict__ out, int n_in,
+                                                  int n_out, int64_t in_row, int64_t out_row, int64_t nrows,
+                                                  const cx<R>* __restrict__ tw) {
+  constexpr int NP = (1024 / L) > 0 ? (1024 / L) : 1;
+  __shared__ cx<R> sm[NP * (L + 1)];
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * NP;
+  for (int e = tid; e < NP * L; e += 256) {
+    int p = e / L, i = e % L;
+    int64_t row = row0 + p;
+    cx<R> v = {0, 0};
+    if (row < nrows && i < n_in) v = in[row * in_row + i];
+    sm[p * (L + 1) + i] = v;
+  }
+  __syncthreads();
+  lds_fft<R, L, NP, FWD>(sm, tw, tid);
+  for (int e = tid; e < NP * n_out; e += 256) {
+    int p = e / n_out, kq = e % n_out;
+    int64_t row = row0 + p;
+    if (row < nrows) out[row * out_row + kq] = sm[p * (L + 1) + kq];
+  }
+}
+
+// Pencils strided along the FFT axis, TP adjacent pencils (contiguous in memory) per block.
+template <typename R, int L, int TP, bool FWD>
+__global__ __launch_bounds__(256) void k_fft_strided(const cx<R>* __restrict__ in, cx<R>* __restrict__ out, int n_in,
+                                                     int n_out, int64_t in_stride, int64_t out_stride, int n_lo,
+                                                     int64_t in_hi, int64_t out_hi, const cx<R>* __restrict__ tw) {
+  __shared__ cx<R> sm[TP * (L + 1)];
+  const int tid = threadIdx.x;
+  const int tiles = (n_lo + TP - 1) / TP;
+  const int64_t hi = blockIdx.x / tiles;
+  const int lo0 = (int)(blockIdx.x % tiles) * TP;
+  const cx<R>* ib = in + hi * in_hi + lo0;
+  cx<R>* ob = out + hi * out_hi + lo0;
+  for (int e = tid; e < TP * L; e += 256) {
+    int p = e % TP, i = e / TP;
+    cx<R> v = {0, 0};
+    if (i < n_in && lo0 + p < n_lo) v = ib[(int64_t)i * in_stride + p];
+    sm[p * (L + 1) + i] = v;
+  }
+  __syncthreads();
+  lds_fft<R, L, TP, FWD>(sm, tw, tid);
+  for (int e = tid; e < TP * n_out; e += 256) {
+    int p = e % TP, kq = e / TP;
+    if (lo0 + p < n_lo) ob[(int64_t)kq * out_stride + p] = sm[p * (L + 1) + kq];
+  }
+}
+
+// Fused z pass on buf[3][n3][P2][P1]: forward FFT of length L = P3 over the n3 stored planes,
+// y_a(k) = sum_b T_ab(k) x_b(k) with the octant-folded spectra, inverse FFT, first n3 outputs
+// written back in place.
+template <typename R, int L, int TP>
+__global__ __launch_bounds__(256) void k_fft_z_conv(cx<R>* __restrict__ buf, int n3, int P1, int P2,
+                                                    const cx<R>* __restrict__ spec, const cx<R>* __restrict__ tw) {
+  __shared__ cx<R> sm[3 * TP * (L + 1)];
+  const int tid = threadIdx.x;
+  const int tiles = (P1 + TP - 1) / TP;
+  const int k2 = blockIdx.x / tiles;
+  const int k1_0 = (blockIdx.x % tiles) * TP;
+  const int64_t plane = (int64_t)P1 * P2;
+  const int64_t comp = plane * n3;
+  for (int c = 0; c < 3; ++c)
+    for (int e = tid; e < TP * L; e += 256) {
+      int p = e % TP, i = e / TP;
+      cx<R> v = {0, 0};
+      if (i < n3 && k1_0 + p < P1) v = buf[c * comp + (int64_t)i * plane + (int64_t)k2 * P1 + k1_0 + p];
+      sm[(c * TP + p) * (L + 1) + i] = v;
+    }
+  __syncthreads();
+  lds_fft<R, L, 3 * TP, true>(sm, tw, tid);
+  const int S1 = P1 / 2 + 1, S2 = P2 / 2 + 1, S3 = L / 2 + 1;
+  const int64_t SO = (int64_t)S1 * S2 * S3;
+  const int f2 = k2 <= P2 / 2 ? k2 : P2 - k2;
+  const R s2 = k2 <= P2 / 2 ? (R)1 : (R)-1;
+  for (int e = tid; e < TP * L; e += 256) {
+    int p = e % TP, k3 = e / TP;
+    int k1 = k1_0 + p;
+    if (k1 >= P1) continue;
+    int f1 = k1 <= P1 / 2 ? k1 : P1 - k1;
+    int f3 = k3 <= L / 2 ? k3 : L - k3;
+    R s1 = k1 <= P1 / 2 ? (R)1 : (R)-1;
+    R s3 = k3 <= L / 2 ? (R)1 : (R)-1;
+    int64_t idx = f1 + (int64_t)S1 * (f2 + (int64_t)S2 * f3);
+    cx<R> Txx = spec[idx], Tyy = spec[SO + idx], Tzz = spec[2 * SO + idx];
+    cx<R> Txy = (s1 * s2) * spec[3 * SO + idx];
+    cx<R> Txz = (s1 * s3) * spec[4 * SO + idx];
+    cx<R> Tyz = (s2 * s3) * spec[5 * SO + idx];
+    cx<R>& X = sm[(0 * TP + p) * (L + 1) + k3];
+    cx<R>& Y = sm[(1 * TP + p) * (L + 1) + k3];
+    cx<R>& Z = sm[(2 * TP + p) * (L + 1) + k3];
+    cx<R> x = X, y = Y, z = Z;
+    X = Txx * x + Txy * y + Txz * z;
+    Y = Txy * x + Tyy * y + Tyz * z;
+    Z = Txz * x + Tyz * y + Tzz * z;
+  }
+  __syncthreads();
+  lds_fft<R, L, 3 * TP, false>(sm, tw, tid);
+  for (int c = 0; c < 3; ++c)
+    for (int e = tid; e < TP * n3; e += 256) {
+      int p = e % TP, i = e / TP;
+      if (k1_0 + p < P1) buf[c * comp + (int64_t)i * plane + (int64_t)k2 * P1 + k1_0 + p] = sm[(c * TP + p) * (L + 1) + i];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// host-side dispatch over the FFT length
+template <typename R> static constexpr int strided_tp(int L) {
+  return sizeof(R) == 8 ? (L <= 128 ? 16 : 2048 / L) : (L <= 256 ? 16 : 4096 / L);
+}
+template <typename R> static constexpr int zconv_tp(int L) {
+  return sizeof(R) == 8 ? (L <= 64 ? 16 : (L <= 128 ? 8 : (L <= 256 ? 4 : (L <= 512 ? 2 : 1))))
+                        : (L <= 128 ? 16 : (L <= 256 ? 8 : (L <= 512 ? 4 : 2)));
+}
+
+#define VSIE_FFT_SWITCH(L_, BODY)                                 \
+  switch (L_) {                                                   \
+    case 8: { constexpr int LL = 8; BODY; } break;                \
+    case 16: { constexpr int LL = 16; BODY; } break;              \
+    case 32: { constexpr int LL = 32; BODY; } break;              \
+    case 64: { constexpr int LL = 64; BODY; } break;              \
+    case 128: { constexpr int LL = 128; BODY; } break;            \
+    case 256: { constexpr int LL = 256; BODY; } break;            \
+    case 512: { constexpr int LL = 512; BODY; } break;            \
+    case 1024: { constexpr int LL = 1024; BODY; } break;          \
+    default: throw Error(VSIE_E_GRID, "unsupported FFT length");  \
+  }
+
+template <typename R>
+void fft_rows(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, int n_in, int n_out, int64_t in_row,
+              int64_t out_row, int64_t nrows, const cx<R>* tw) {
+  VSIE_FFT_SWITCH(L, {
+    constexpr int NP = (1024 / LL) > 0 ? (1024 / LL) : 1;
+    dim3 grid((unsigned)((nrows + NP - 1) / NP));
+    if (fwd)
+      hipLaunchKernelGGL((k_fft_rows<R, LL, true>), grid, dim3(256), 0, st, in, out, n_in, n_out, in_row, out_row, nrows, tw);
+    else
+      hipLaunchKernelGGL((k_fft_rows<R, LL, false>), grid, dim3(256), 0, st, in, out, n_in, n_out, in_row, out_row, nrows, tw);
+  });
+}
+
+template <typename R>
+void fft_strided(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, int n_in, int n_out, int64_t in_stride,
+                 int64_t out_stride, int n_lo, int64_t n_hi, int64_t in_hi, int64_t out_hi, const cx<R>* tw) {
+  VSIE_FFT_SWITCH(L, {
+    constexpr int TP = strided_tp<R>(LL);
+    dim3 grid((unsigned)(n_hi * ((n_lo + TP - 1) / TP)));
+    if (fwd)
+      hipLaunchKernelGGL((k_fft_strided<R, LL, TP, true>), grid, dim3(256), 0, st, in, out, n_in, n_out, in_stride,
+                         out_stride, n_lo, in_hi, out_hi, tw);
+    else
+      hipLaunchKernelGGL((k_fft_strided<R, LL, TP, false>), grid, dim3(256), 0, st, in, out, n_in, n_out, in_stride,
+                         out_stride, n_lo, in_hi, out_hi, tw);
+  });
+}
+
+template <typename R>
+void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const cx<R>* spec, const cx<R>* tw) {
+  VSIE_FFT_SWITCH(L, {
+    constexpr int TP = zconv_tp<R>(LL);
+    dim3 grid((unsigned)(P2 * ((P1 + TP - 1) / TP)));
+    hipLaunchKernelGGL((k_fft_z_conv<R, LL, TP>), grid, dim3(256), 0, st, buf, n3, P1, P2, spec, tw);
+  });
+}
+
+template void fft_rows<double>(hipStream_t, int, bool, const cxd*, cxd*, int, int, int64_t, int64_t, int64_t, const cxd*);
+template void fft_rows<float>(hipStream_t, int, bool, const cxf*, cxf*, int, int, int64_t, int64_t, int64_t, const cxf*);
+template void fft_strided<double>(hipStream_t, int, bool, const cxd*, cxd*, int, int, int64_t, int64_t, int, int64_t,
+                                  int64_t, int64_t, const cxd*);
+template void fft_strided<float>(hipStream_t, int, bool, const cxf*, cxf*, int, int, int64_t, int64_t, int, int64_t,
+                                 int64_t, int64_t, const cxf*);
+template void fft_z_conv<double>(hipStream_t, int, cxd*, int, int, int, const cxd*, const cxd*);
+template void fft_z_conv<float>(hipStream_t, int, cxf*, int, int, int, const cxf*, const cxf*);
+
+// =============================================================================================
+// Matvec kernels
+// =============================================================================================
+
+// extended-grid sources: masked body currents + pFFT projection of the near RWG currents
+template <typename R>
+__global__ void k_build_grid(const cx<R>* __restrict__ xb, const cx<R>* __restrict__ xn,
+                             const uint8_t* __restrict__ mask, const int* __restrict__ vox2row,
+                             const int* __restrict__ rowptr, const int* __restrict__ rowrwg,
+                             const R* __restrict__ roww, cx<R>* __restrict__ grid, GridDims g) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.Ne) return;
+  int i1 = (int)(v % g.ne1), i2 = (int)((v / g.ne1) % g.ne2), i3 = (int)(v / ((int64_t)g.ne1 * g.ne2));
+  int b1 = i1 - g.ob1, b2 = i2 - g.ob2, b3 = i3 - g.ob3;
+  cx<R> a[3] = {{0, 0}, {0, 0}, {0, 0}};
+  if (xb && b1 >= 0 && b1 < g.n1 && b2 >= 0 && b2 < g.n2 && b3 >= 0 && b3 < g.n3) {
+    int64_t p = b1 + (int64_t)g.n1 * (b2 + (int64_t)g.n2 * b3);
+    if (mask[p]) {
+      a[0] = xb[p];
+      a[1] = xb[g.nv + p];
+      a[2] = xb[2 * g.nv + p];
+    }
+  }
+  if (vox2row && xn) {
+    int r = vox2row[v];
+    if (r >= 0) {
+      for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        cx<R> j = xn[rowrwg[e]];
+        a[0] += roww[3 * (int64_t)e] * j;
+        a[1] += roww[3 * (int64_t)e + 1] * j;
+        a[2] += roww[3 * (int64_t)e + 2] * j;
+      }
+    }
+  }
+  grid[v] = a[0];
+  grid[g.Ne + v] = a[1];
+  grid[2 * g.Ne + v] = a[2];
+}
+
+// body rows: tissue y = h^3/chi x + (T * x) ; air y = x
+template <typename R>
+__global__ void k_body_out(const cx<R>* __restrict__ xb, const cx<R>* __restrict__ E, const cx<R>* __restrict__ dvchi,
+                           const uint8_t* __restrict__ mask, cx<R>* __restrict__ yb, GridDims g) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.nv) return;
+  int i1 = (int)(p % g.n1), i2 = (int)((p / g.n1) % g.n2), i3 = (int)(p / ((int64_t)g.n1 * g.n2));
+  int64_t v = (i1 + g.ob1) + (int64_t)g.ne1 * ((i2 + g.ob2) + (int64_t)g.ne2 * (i3 + g.ob3));
+  if (mask[p]) {
+    cx<R> d = dvchi[p];
+    for (int a = 0; a < 3; ++a) yb[a * g.nv + p] = d * xb[a * g.nv + p] + E[a * g.Ne + v];
+  } else {
+    for (int a = 0; a < 3; ++a) yb[a * g.nv + p] = xb[a * g.nv + p];
+  }
+}
+
+// pFFT interpolation (W^T): one wavefront per near RWG
+template <typename R>
+__global__ __launch_bounds__(64) void k_pfft_gather(const R* __restrict__ W, const int* __restrict__ base,
+                                                    const cx<R>* __restrict__ E, cx<R>* __restrict__ yn, GridDims g) {
+  const int n = blockIdx.x;
+  const int t = threadIdx.x;
+  const int b1 = base[3 * n], b2 = base[3 * n + 1], b3 = base[3 * n + 2];
+  cx<R> acc = {0, 0};
+  for (int e = t; e < 375; e += 64) {
+    int a = e / 125, j = e % 125;
+    int j1 = j % 5, j2 = (j / 5) % 5, j3 = j / 25;
+    int64_t v = (b1 + j1) + (int64_t)g.ne1 * ((b2 + j2) + (int64_t)g.ne2 * (b3 + j3));
+    acc += W[(int64_t)n * 375 + e] * E[a * g.Ne + v];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.re += __shfl_down(acc.re, off, 64);
+    acc.im += __shfl_down(acc.im, off, 64);
+  }
+  if (t == 0) yn[n] = acc;
+}
+
+// y[rowid[r]] += sum_e val[e] x[col[e]]  (rows unique)
+template <typename R>
+__global__ void k_csr_add(const int* __restrict__ rowid, const int* __restrict__ rowptr, const int* __restrict__ col,
+                          const cx<R>* __restrict__ val, const cx<R>* __restrict__ x, cx<R>* __restrict__ y, int nrows) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  cx<R> acc = {0, 0};
+  for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) acc += val[e] * x[col[e]];
+  y[rowid[r]] += acc;
+}
+
+// partial sums of A^T x or A^H x for a tall matrix A (M x K, row-major, K <= 64): part[blk][K].
+// Threads form (256 / KP) row lanes x KP column lanes so a row is read contiguously.
+template <typename R, bool CONJ>
+__global__ __launch_bounds__(256) void k_tall_t_partial(const cx<R>* __restrict__ A, const cx<R>* __restrict__ x,
+                                                        int64_t M, int K, cx<R>* __restrict__ part) {
+  __shared__ R rr[256], ri[256];
+  int KP = 1;
+  while (KP < K) KP <<= 1;
+  const int lanes = 256 / KP;
+  const int l = threadIdx.x % KP, lane = threadIdx.x / KP;
+  const int64_t per = (M + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = blockIdx.x * per;
+  const int64_t r1 = r0 + per < M ? r0 + per : M;
+  cx<R> acc = {0, 0};
+  if (l < K)
+    for (int64_t r = r0 + lane; r < r1; r += lanes) {
+      cx<R> a = A[r * K + l];
+      acc += CONJ ? mul_conj_a(a, x[r]) : a * x[r];
+    }
+  rr[threadIdx.x] = acc.re;
+  ri[threadIdx.x] = acc.im;
+  __syncthreads();
+  for (int s = lanes / 2; s > 0; s >>= 1) {
+    if (lane < s) {
+      rr[threadIdx.x] += rr[threadIdx.x + s * KP];
+      ri[threadIdx.x] += ri[threadIdx.x + s * KP];
+    }
+    __syncthreads();
+  }
+  if (lane == 0 && l < K) part[(int64_t)blockIdx.x * K + l] = cx<R>{rr[threadIdx.x], ri[threadIdx.x]};
+}
+
+template <typename R>
+__global__ void k_sum_partials(const cx<R>* __restrict__ part, int nblk, int K, cx<R>* __restrict__ out) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= K) return;
+  cx<R> acc = {0, 0};
+  for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * K + l];
+  out[l] = acc;
+}
+
+// y[i] += sum_l A[i][l] t[l]  (or conj(A))
+template <typename R, bool CONJ>
+__global__ void k_tall_n_add(const cx<R>* __restrict__ A, const cx<R>* __restrict__ t, int64_t M, int K,
+                             cx<R>* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  cx<R> acc = {0, 0};
+  for (int l = 0; l < K; ++l) {
+    cx<R> a = A[i * K + l];
+    acc += CONJ ? mul_conj_a(a, t[l]) : a * t[l];
+  }
+  y[i] += acc;
+}
+
+// one block per row: out[row] = sum_j A[row][j] x[j]  (dense GEMV, row-major, write)
+template <typename R>
+__global__ __launch_bounds__(256) void k_gemv_rows(const cx<R>* __restrict__ A, const cx<R>* __restrict__ x,
+                                                   int64_t ncol, cx<R>* __restrict__ out, int accumulate) {
+  __shared__ R rr[256], ri[256];
+  const int64_t row = blockIdx.x;
+  const cx<R>* a = A + row * ncol;
+  cx<R> acc = {0, 0};
+  for (int64_t j = threadIdx.x; j < ncol; j += 256) acc += a[j] * x[j];
+  rr[threadIdx.x] = acc.re;
+  ri[threadIdx.x] = acc.im;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      rr[threadIdx.x] += rr[threadIdx.x + s];
+      ri[threadIdx.x] += ri[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    cx<R> v = {rr[0], ri[0]};
+    if (accumulate) out[row] += v;
+    else out[row] = v;
+  }
+}
+
+// TT forward, step G3: t3[j2][i3] = sum_j3 G3[j2][i3][j3] t4[j3]
+template <typename R>
+__global__ void k_tt_g3(const cx<R>* __restrict__ G3, const cx<R>* __restrict__ t4, int r2, int n3, int r3,
+                        cx<R>* __restrict__ t3) {
+  int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= r2 * n3) return;
+  cx<R> acc = {0, 0};
+  for (int c = 0; c < r3; ++c) acc += G3[(int64_t)id * r3 + c] * t4[c];
+  t3[id] = acc;
+}
+
+// TT forward, step G2: t2[j1][i3][i2] = sum_j2 G2[j1][i2][j2] t3[j2][i3]
+template <typename R>
+__global__ void k_tt_g2(const cx<R>* __restrict__ G2, const cx<R>* __restrict__ t3, int r1, int n2, int r2, int n3,
+                        cx<R>* __restrict__ t2) {
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)r1 * n2 * n3) return;
+  int i2 = (int)(id % n2), i3 = (int)((id / n2) % n3), j1 = (int)(id / ((int64_t)n2 * n3));
+  cx<R> acc = {0, 0};
+  for (int b = 0; b < r2; ++b) acc += G2[((int64_t)j1 * n2 + i2) * r2 + b] * t3[(int64_t)b * n3 + i3];
+  t2[id] = acc;
+}
+
+// TT forward, step G1 into the body rows: yb[i1 + n1 q] += mask * sum_j1 G1[i1][j1] t2[j1][q]
+template <typename R>
+__global__ void k_tt_g1_add(const cx<R>* __restrict__ G1, const cx<R>* __restrict__ t2, int n1, int r1, int64_t nq,
+                            const uint8_t* __restrict__ mask, cx<R>* __restrict__ yb) {
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n1 * nq) return;
+  if (!mask[id]) return;
+  int i1 = (int)(id % n1);
+  int64_t q = id / n1;
+  cx<R> acc = {0, 0};
+  for (int a = 0; a < r1; ++a) acc += G1[(int64_t)i1 * r1 + a] * t2[(int64_t)a * nq + q];
+  yb[id] += acc;
+}
+
+// TT transpose, step G1: s1[j1][q] = sum_i1 G1[i1][j1] mask x[i1 + n1 q]; 8 ranks per thread
+template <typename R>
+__global__ void k_ttT_g1(const cx<R>* __restrict__ G1, const cx<R>* __restrict__ xb, const uint8_t* __restrict__ mask,
+                         int n1, int r1, int64_t nq, cx<R>* __restrict__ s1) {
+  const int chunks = (r1 + 7) / 8;
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nq * chunks) return;
+  int64_t q = id % nq;
+  int j0 = (int)(id / nq) * 8;
+  cx<R> acc[8];
+  for (int u = 0; u < 8; ++u) acc[u] = {0, 0};
+  for (int i1 = 0; i1 < n1; ++i1) {
+    int64_t p = i1 + (int64_t)n1 * q;
+    if (!mask[p]) continue;
+    cx<R> xv = xb[p];
+    for (int u = 0; u < 8; ++u)
+      if (j0 + u < r1) acc[u] += G1[(int64_t)i1 * r1 + j0 + u] * xv;
+  }
+  for (int u = 0; u < 8; ++u)
+    if (j0 + u < r1) s1[(int64_t)(j0 + u) * nq + q] = acc[u];
+}
+
+// TT transpose, step G2: s2[j2][i3] = sum_{j1, i2} G2[j1][i2][j2] s1[j1][i2 + n2 i3]
+template <typename R>
+__global__ void k_ttT_g2(const cx<R>* __restrict__ G2, const cx<R>* __restrict__ s1, int r1, int n2, int r2, int n3,
+                         cx<R>* __restrict__ s2) {
+  int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= r2 * n3) return;
+  int i3 = id % n3, b = id / n3;
+  const int64_t nq = (int64_t)n2 * n3;
+  cx<R> acc = {0, 0};
+  for (int a = 0; a < r1; ++a)
+    for (int i2 = 0; i2 < n2; ++i2) acc += G2[((int64_t)a * n2 + i2) * r2 + b] * s1[(int64_t)a * nq + i2 + (int64_t)n2 * i3];
+  s2[(int64_t)b * n3 + i3] = acc;
+}
+
+// TT transpose, step G3: s3[j3] = sum_{j2, i3} G3[j2][i3][j3] s2[j2][i3]   (one block per j3)
+template <typename R>
+__global__ __launch_bounds__(256) void k_ttT_g3(const cx<R>* __restrict__ G3, const cx<R>* __restrict__ s2, int r2,
+                                                int n3, int r3, cx<R>* __restrict__ s3) {
+  __shared__ R rr[256], ri[256];
+  const int c = blockIdx.x;
+  cx<R> acc = {0, 0};
+  for (int id = threadIdx.x; id < r2 * n3; id += 256) acc += G3[(int64_t)id * r3 + c] * s2[id];
+  rr[threadIdx.x] = acc.re;
+  ri[threadIdx.x] = acc.im;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      rr[threadIdx.x] += rr[threadIdx.x + s];
+      ri[threadIdx.x] += ri[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s3[c] = cx<R>{rr[0], ri[0]};
+}
+
+// TT transpose, step G4: yf[i4] += sum_j3 G4[j3][i4] s3[j3]
+template <typename R>
+__global__ void k_ttT_g4_add(const cx<R>* __restrict__ G4, const cx<R>* __restrict__ s3, int r3, int mf,
+                             cx<R>* __restrict__ yf) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= mf) return;
+  cx<R> acc = {0, 0};
+  for (int c = 0; c < r3; ++c) acc += G4[(int64_t)c * mf + i] * s3[c];
+  yf[i] += acc;
+}
+
+// =============================================================================================
+// Solver helpers (FP64 Arnoldi) and conversions
+// =============================================================================================
+
+// partial sums of V[i]^H w for i < nvec over a fixed number of blocks: part[blk][nvec]
+__global__ __launch_bounds__(256) void k_multidot_partial(const cxd* __restrict__ V, int64_t ld, int nvec,
+                                                          const cxd* __restrict__ w, int64_t n, cxd* __restrict__ part) {
+  __shared__ double rr[256], ri[256];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  for (int i = 0; i < nvec; ++i) {
+    cxd acc = {0, 0};
+    const cxd* v = V + (int64_t)i * ld;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) acc += mul_conj_a(v[r], w[r]);
+    rr[threadIdx.x] = acc.re;
+    ri[threadIdx.x] = acc.im;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        rr[threadIdx.x] += rr[threadIdx.x + s];
+        ri[threadIdx.x] += ri[threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nvec + i] = cxd{rr[0], ri[0]};
+    __syncthreads();
+  }
+}
+
+// w -= sum_i h[i] V[i]
+__global__ void k_multiaxpy(const cxd* __restrict__ V, int64_t ld, int nvec, const cxd* __restrict__ h,
+                            cxd* __restrict__ w, int64_t n) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  cxd acc = w[r];
+  for (int i = 0; i < nvec; ++i) acc -= h[i] * V[(int64_t)i * ld + r];
+  w[r] = acc;
+}
+
+// x += sum_i y[i] V[i]
+__global__ void k_combine_add(const cxd* __restrict__ V, int64_t ld, int nvec, const cxd* __restrict__ y,
+                              cxd* __restrict__ x, int64_t n) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  cxd acc = x[r];
+  for (int i = 0; i < nvec; ++i) acc += y[i] * V[(int64_t)i * ld + r];
+  x[r] = acc;
+}
+
+__global__ void k_scale_copy(const cxd* __restrict__ a, double s, cxd* __restrict__ b, int64_t n) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) b[r] = s * a[r];
+}
+
+__global__ void k_sub(const cxd* __restrict__ a, const cxd* __restrict__ b, cxd* __restrict__ c, int64_t n) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) c[r] = a[r] - b[r];
+}
+
+__global__ void k_add(cxd* __restrict__ a, const cxd* __restrict__ b, int64_t n) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) a[r] += b[r];
+}
+
+__global__ void k_d2f(const cxd* __restrict__ a, cxf* __restrict__ b, int64_t n) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) b[r] = cxf{(float)a[r].re, (float)a[r].im};
+}
+
+__global__ void k_f2d(const cxf* __restrict__ a, cxd* __restrict__ b, int64_t n) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) b[r] = cxd{(double)a[r].re, (double)a[r].im};
+}
+
+// partial sums of |a|^2 over segments [s0, s1) for three segments at once: part[blk][4]
+__global__ __launch_bounds__(256) void k_norm_partial(const cxd* __restrict__ a, int64_t n, int64_t s1, int64_t s2,
+                                                      double* __restrict__ part) {
+  __shared__ double red[4][256];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  double acc[3] = {0, 0, 0};
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    double v = a[r].re * a[r].re + a[r].im * a[r].im;
+    int seg = r < s1 ? 0 : (r < s2 ? 1 : 2);
+    acc[seg] += v;
+  }
+  for (int s = 0; s < 3; ++s) red[s][threadIdx.x] = acc[s];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) part[(int64_t)blockIdx.x * 3 + q] = red[q][0];
+}
+
+// port right-hand side
+template <typename R>
+__global__ void k_scatter_rhs(const int* __restrict__ idx, const double* __restrict__ val_re,
+                              const double* __restrict__ val_im, int ne, cx<R>* __restrict__ b) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) b[idx[e]] = cx<R>{(R)val_re[e], (R)val_im[e]};
+}
+
+// ---------------------------------------------------------------------------------------------
+// explicit instantiations and host launchers
+template <typename R> void launch_build_grid(hipStream_t st, const cx<R>* xb, const cx<R>* xn, const uint8_t* mask,
+                                             const int* vox2row, const int* rowptr, const int* rowrwg, const R* roww,
+                                             cx<R>* grid, const GridDims& g) {
+  hipLaunchKernelGGL(k_build_grid<R>, dim3((unsigned)((g.Ne + 255) / 256)), dim3(256), 0, st, xb, xn, mask, vox2row,
+                     rowptr, rowrwg, roww, grid, g);
+}
+template <typename R> void launch_body_out(hipStream_t st, const cx<R>* xb, const cx<R>* E, const cx<R>* dvchi,
+                                           const uint8_t* mask, cx<R>* yb, const GridDims& g) {
+  hipLaunchKernelGGL(k_body_out<R>, dim3((unsigned)((g.nv + 255) / 256)), dim3(256), 0, st, xb, E, dvchi, mask, yb, g);
+}
+template <typename R> void launch_pfft_gather(hipStream_t st, const R* W, const int* base, const cx<R>* E, cx<R>* yn,
+                                              int mn, const GridDims& g) {
+  if (mn > 0) hipLaunchKernelGGL(k_pfft_gather<R>, dim3(mn), dim3(64), 0, st, W, base, E, yn, g);
+}
+template <typename R> void launch_csr_add(hipStream_t st, const int* rowid, const int* rowptr, const int* col,
+                                          const cx<R>* val, const cx<R>* x, cx<R>* y, int nrows) {
+  if (nrows > 0) hipLaunchKernelGGL(k_csr_add<R>, dim3((nrows + 255) / 256), dim3(256), 0, st, rowid, rowptr, col, val, x, y, nrows);
+}
+template <typename R> void launch_tall_t(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* x, int64_t M, int K,
+                                         cx<R>* part, int nblk, cx<R>* out) {
+  if (K > 64) throw Error(VSIE_E_ARG, "low-rank factor wider than 64 columns");
+  if (conj)
+    hipLaunchKernelGGL((k_tall_t_partial<R, true>), dim3(nblk), dim3(256), 0, st, A, x, M, K, part);
+  else
+    hipLaunchKernelGGL((k_tall_t_partial<R, false>), dim3(nblk), dim3(256), 0, st, A, x, M, K, part);
+  hipLaunchKernelGGL(k_sum_partials<R>, dim3((K + 63) / 64), dim3(64), 0, st, part, nblk, K, out);
+}
+template <typename R> void launch_tall_n_add(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* t, int64_t M,
+                                             int K, cx<R>* y) {
+  if (M <= 0) return;
+  if (conj)
+    hipLaunchKernelGGL((k_tall_n_add<R, true>), dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, A, t, M, K, y);
+  else
+    hipLaunchKernelGGL((k_tall_n_add<R, false>), dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, A, t, M, K, y);
+}
+template <typename R> void launch_gemv_rows(hipStream_t st, const cx<R>* A, const cx<R>* x, int64_t nrow, int64_t ncol,
+                                            cx<R>* out, int accumulate) {
+  if (nrow > 0) hipLaunchKernelGGL(k_gemv_rows<R>, dim3((unsigned)nrow), dim3(256), 0, st, A, x, ncol, out, accumulate);
+}
+template <typename R> void launch_tt_forward(hipStream_t st, cx<R>* const G[4], const int r[3], const int n[3], int mf,
+                                             const cx<R>* xf, const uint8_t* mask, cx<R>* yb, cx<R>* work) {
+  cx<R>* t4 = work;
+  cx<R>* t3 = t4 + 128;
+  cx<R>* t2 = t3 + (int64_t)r[1] * n[2];
+  // t4 = G4 xf  (rows of G4, one block each)
+  hipLaunchKernelGGL(k_gemv_rows<R>, dim3(r[2]), dim3(256), 0, st, G[3], xf, (int64_t)mf, t4, 0);
+  hipLaunchKernelGGL(k_tt_g3<R>, dim3((r[1] * n[2] + 255) / 256), dim3(256), 0, st, G[2], t4, r[1], n[2], r[2], t3);
+  int64_t c2 = (int64_t)r[0] * n[1] * n[2];
+  hipLaunchKernelGGL(k_tt_g2<R>, dim3((unsigned)((c2 + 255) / 256)), dim3(256), 0, st, G[1], t3, r[0], n[1], r[1], n[2], t2);
+  int64_t nq = (int64_t)n[1] * n[2];
+  hipLaunchKernelGGL(k_tt_g1_add<R>, dim3((unsigned)((n[0] * nq + 255) / 256)), dim3(256), 0, st, G[0], t2, n[0], r[0],
+                     nq, mask, yb);
+}
+template <typename R> void launch_tt_transpose(hipStream_t st, cx<R>* const G[4], const int r[3], const int n[3], int mf,
+                                               const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* work) {
+  int64_t nq = (int64_t)n[1] * n[2];
+  cx<R>* s3 = work;
+  cx<R>* s2 = s3 + 128;
+  cx<R>* s1 = s2 + (int64_t)r[1] * n[2];
+  int chunks = (r[0] + 7) / 8;
+  hipLaunchKernelGGL(k_ttT_g1<R>, dim3((unsigned)((nq * chunks + 255) / 256)), dim3(256), 0, st, G[0], xb, mask, n[0],
+                     r[0], nq, s1);
+  hipLaunchKernelGGL(k_ttT_g2<R>, dim3((r[1] * n[2] + 255) / 256), dim3(256), 0, st, G[1], s1, r[0], n[1], r[1], n[2], s2);
+  hipLaunchKernelGGL(k_ttT_g3<R>, dim3(r[2]), dim3(256), 0, st, G[2], s2, r[1], n[2], r[2], s3);
+  hipLaunchKernelGGL(k_ttT_g4_add<R>, dim3((mf + 255) / 256), dim3(256), 0, st, G[3], s3, r[2], mf, yf);
+}
+template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, const double* vre, const double* vim,
+                                             int ne, cx<R>* b) {
+  if (ne > 0) hipLaunchKernelGGL(k_scatter_rhs<R>, dim3((ne + 255) / 256), dim3(256), 0, st, idx, vre, vim, ne, b);
+}
+
+#define VSIE_INST(R)                                                                                                  \
+  template void launch_build_grid<R>(hipStream_t, const cx<R>*, const cx<R>*, const uint8_t*, const int*, const int*, \
+                                     const int*, const R*, cx<R>*, const GridDims&);                                  \
+  template void launch_body_out<R>(hipStream_t, const cx<R>*, const cx<R>*, const cx<R>*, const uint8_t*, cx<R>*,     \
+                                   const GridDims&);                                                                 \
+  template void launch_pfft_gather<R>(hipStream_t, const R*, const int*, const cx<R>*, cx<R>*, int, const GridDims&); \
+  template void launch_csr_add<R>(hipStream_t, const int*, const int*, const int*, const cx<R>*, const cx<R>*,        \
+                                  cx<R>*, int);                                                                      \
+  template void launch_tall_t<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*, int, cx<R>*);    \
+  template void launch_tall_n_add<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*);            \
+  template void launch_gemv_rows<R>(hipStream_t, const cx<R>*, const cx<R>*, int64_t, int64_t, cx<R>*, int);          \
+  template void launch_tt_forward<R>(hipStream_t, cx<R>* const[4], const int[3], const int[3], int, const cx<R>*,     \
+                                     const uint8_t*, cx<R>*, cx<R>*);                                                 \
+  template void launch_tt_transpose<R>(hipStream_t, cx<R>* const[4], const int[3], const int[3], int, const cx<R>*,   \
+                                       const uint8_t*, cx<R>*, cx<R>*);                                               \
+  template void launch_scatter_rhs<R>(hipStream_t, const int*, const double*, const double*, int, cx<R>*);
+VSIE_INST(double)
+VSIE_INST(float)
+
+void launch_generator(hipStream_t st, const GaussTab* gt, const int ne[3], double kappa, const CellRule& cr, cxd* oct) {
+  int64_t S = (int64_t)ne[0] * ne[1] * ne[2];
+  hipLaunchKernelGGL(k_generator_octant, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, st, gt, ne[0], ne[1], ne[2],
+                     kappa, cr, oct);
+}
+void launch_embed_circulant(hipStream_t st, const cxd* oct, const int ne[3], const int P[3], cxd* full) {
+  int64_t PT = (int64_t)P[0] * P[1] * P[2];
+  hipLaunchKernelGGL(k_embed_circulant, dim3((unsigned)((PT + 255) / 256)), dim3(256), 0, st, oct, ne[0], ne[1], ne[2],
+                     P[0], P[1], P[2], full);
+}
+template <typename R> void launch_extract_octant(hipStream_t st, const cxd* full, const int P[3], double scale, cx<R>* spec) {
+  int64_t SO = (int64_t)(P[0] / 2 + 1) * (P[1] / 2 + 1) * (P[2] / 2 + 1);
+  hipLaunchKernelGGL(k_extract_octant<R>, dim3((unsigned)((SO + 255) / 256)), dim3(256), 0, st, full, P[0], P[1], P[2],
+                     scale, spec);
+}
+template void launch_extract_octant<double>(hipStream_t, const cxd*, const int[3], double, cxd*);
+template void launch_extract_octant<float>(hipStream_t, const cxd*, const int[3], double, cxf*);
+
+void launch_zcc_dense(hipStream_t st, const RwgDev& A, const RwgDev& B, double k, int64_t row0, int64_t nrows, cxd* out) {
+  int64_t tot = nrows * B.m;
+  if (tot > 0) hipLaunchKernelGGL(k_zcc_dense, dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, st, A, B, k, row0, nrows, out);
+}
+void launch_zcc_pairs(hipStream_t st, const RwgDev& A, const RwgDev& B, const int* pi, const int* pj, int64_t np,
+                      double k, cxd* out) {
+  if (np > 0) hipLaunchKernelGGL(k_zcc_pairs, dim3((unsigned)((np + 127) / 128)), dim3(128), 0, st, A, B, pi, pj, np, k, out);
+}
+void launch_pfft_wtw(hipStream_t st, const double* W, const int* base, const cxd* oct, const int ne[3], const int* pm,
+                     const int* pn, int64_t np, cxd* out) {
+  if (np > 0) hipLaunchKernelGGL(k_pfft_wtw_pairs, dim3((unsigned)np), dim3(256), 0, st, W, base, oct, ne[0], ne[1], ne[2], pm, pn, out);
+}
+void launch_pfft_tw_voxels(hipStream_t st, const double* W, const int* base, const cxd* oct, const int ne[3],
+                           const int* vox, const int* pn, int64_t np, cxd* out) {
+  if (np > 0)
+    hipLaunchKernelGGL(k_pfft_tw_voxels, dim3((unsigned)((np + 127) / 128)), dim3(128), 0, st, W, base, oct, ne[0], ne[1],
+                       ne[2], vox, pn, np, out);
+}
+void launch_zbc_near(hipStream_t st, const RwgDev& B, const double* centres, const int* pn, int64_t np, double h,
+                     double k, cxd* out) {
+  if (np > 0)
+    hipLaunchKernelGGL(k_zbc_near_pairs, dim3((unsigned)((np + 127) / 128)), dim3(128), 0, st, B, centres, pn, np, h, k, out);
+}
+
+void launch_multidot(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* w, int64_t n, cxd* part, int nblk) {
+  hipLaunchKernelGGL(k_multidot_partial, dim3(nblk), dim3(256), 0, st, V, ld, nvec, w, n, part);
+}
+void launch_multiaxpy(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* h, cxd* w, int64_t n) {
+  hipLaunchKernelGGL(k_multiaxpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, V, ld, nvec, h, w, n);
+}
+void launch_combine_add(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* y, cxd* x, int64_t n) {
+  hipLaunchKernelGGL(k_combine_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, V, ld, nvec, y, x, n);
+}
+void launch_scale_copy(hipStream_t st, const cxd* a, double s, cxd* b, int64_t n) {
+  hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, s, b, n);
+}
+void launch_sub(hipStream_t st, const cxd* a, const cxd* b, cxd* c, int64_t n) {
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, c, n);
+}
+void launch_add(hipStream_t st, cxd* a, const cxd* b, int64_t n) {
+  hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
+}
+void launch_d2f(hipStream_t st, const cxd* a, cxf* b, int64_t n) {
+  hipLaunchKernelGGL(k_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
+}
+void launch_f2d(hipStream_t st, const cxf* a, cxd* b, int64_t n) {
+  hipLaunchKernelGGL(k_f2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
+}
+void launch_norm_partial(hipStream_t st, const cxd* a, int64_t n, int64_t s1, int64_t s2, double* part, int nblk) {
+  hipLaunchKernelGGL(k_norm_partial, dim3(nblk), dim3(256), 0, st, a, n, s1, s2, part);
+}
+
+}  // namespace vsie

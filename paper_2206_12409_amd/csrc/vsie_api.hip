@@ -1,0 +1,1167 @@
+// C ABI of the hybrid VSIE library: setup orchestration, matrix-vector product and GMRES drivers.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "kernels.h"
+
+using namespace vsie;
+
+struct vsie_handle {
+  Handle H;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F> int guarded(F&& f) {
+  try {
+    f();
+    return VSIE_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(VSIE_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(VSIE_E_ARG, e.what());
+  }
+}
+
+template <typename T> T* upload(Handle& H, const std::vector<T>& v) {
+  T* d = H.dalloc<T>((int64_t)v.size());
+  if (!v.empty()) VSIE_HIP(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return d;
+}
+
+template <typename T> std::vector<T> download(const T* d, int64_t n) {
+  std::vector<T> v((size_t)std::max<int64_t>(n, 0));
+  if (n > 0) VSIE_HIP(hipMemcpy(v.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost));
+  return v;
+}
+
+template <typename R> cx<R>* upload_cx(Handle& H, const std::vector<cxd>& v) {
+  std::vector<cx<R>> c(v.size());
+  for (size_t i = 0; i < v.size(); ++i) c[i] = cx<R>{(R)v[i].re, (R)v[i].im};
+  return upload(H, c);
+}
+
+GridDims grid_dims(const Handle& H) {
+  GridDims g;
+  g.n1 = H.n[0];
+  g.n2 = H.n[1];
+  g.n3 = H.n[2];
+  g.ne1 = H.ne[0];
+  g.ne2 = H.ne[1];
+  g.ne3 = H.ne[2];
+  g.ob1 = H.ob[0];
+  g.ob2 = H.ob[1];
+  g.ob3 = H.ob[2];
+  g.nv = H.nv;
+  g.Ne = H.Ne;
+  return g;
+}
+
+RwgDev make_rwg_dev(Handle& H, const Rwg& R) {
+  RwgDev d{};
+  d.m = R.m;
+  if (R.m == 0) return d;
+  d.verts = upload(H, R.verts);
+  d.tris = upload(H, R.tris);
+  d.area = upload(H, R.area);
+  std::vector<int> tpm(2 * R.m), flpm(2 * R.m), fpm(2 * R.m);
+  for (int i = 0; i < R.m; ++i) {
+    tpm[2 * i] = R.tp[i];
+    tpm[2 * i + 1] = R.tm[i];
+    flpm[2 * i] = R.flp[i];
+    flpm[2 * i + 1] = R.flm[i];
+    fpm[2 * i] = R.fp[i];
+    fpm[2 * i + 1] = R.fm[i];
+  }
+  d.tpm = upload(H, tpm);
+  d.flpm = upload(H, flpm);
+  d.fpm = upload(H, fpm);
+  d.len = upload(H, R.len);
+  return d;
+}
+
+template <typename R> cx<R>* twiddles(Handle& H, int L) {
+  std::vector<cxd> t(L);
+  for (int m = 0; m < L; ++m) {
+    long double a = -2.0L * 3.14159265358979323846264338327950288L * m / L;
+    t[m] = cxd{(double)cosl(a), (double)sinl(a)};
+  }
+  return upload_cx<R>(H, t);
+}
+
+// ---------------------------------------------------------------------------------------------
+// volume convolution data: generator on the extended-grid octant, circulant spectra
+void setup_volume(Handle& H) {
+  hipStream_t st = H.stream;
+  GaussTab gt_h;
+  fill_gauss_table(&gt_h);
+  GaussTab* gt = H.dalloc<GaussTab>(1);
+  VSIE_HIP(hipMemcpy(gt, &gt_h, sizeof(GaussTab), hipMemcpyHostToDevice));
+  CellRule cr;
+  cr.n_duffy = 14;
+  cr.digits = 18.0;
+  cr.n_min = 4;
+  cr.n_max = 18;
+  H.d_oct = H.dalloc<cxd>(6 * H.Ne);
+  launch_generator(st, gt, H.ne, H.k0 * H.h, cr, H.d_oct);
+  VSIE_HIP(hipGetLastError());
+  const int64_t PT = (int64_t)H.P[0] * H.P[1] * H.P[2];
+  cxd* full = nullptr;
+  VSIE_HIP(hipMalloc(&full, sizeof(cxd) * 6 * PT));
+  cxd* full2 = nullptr;
+  if (hipMalloc(&full2, sizeof(cxd) * 6 * PT) != hipSuccess) {
+    (void)hipFree(full);
+    throw Error(VSIE_E_NOMEM, "generator spectra workspace");
+  }
+  cxd* tw[3];
+  for (int a = 0; a < 3; ++a) tw[a] = twiddles<double>(H, H.P[a]);
+  launch_embed_circulant(st, H.d_oct, H.ne, H.P, full);
+  // full forward 3D FFT of the 6 components: x (rows), y (strided), z (strided)
+  const int P1 = H.P[0], P2 = H.P[1], P3 = H.P[2];
+  fft_rows<double>(st, P1, true, full, full2, P1, P1, P1, P1, 6LL * P2 * P3, tw[0]);
+  fft_strided<double>(st, P2, true, full2, full, P2, P2, P1, P1, P1, 6LL * P3, (int64_t)P2 * P1, (int64_t)P2 * P1, tw[1]);
+  fft_strided<double>(st, P3, true, full, full2, P3, P3, (int64_t)P1 * P2, (int64_t)P1 * P2, P1 * P2, 6,
+                      (int64_t)P1 * P2 * P3, (int64_t)P1 * P2 * P3, tw[2]);
+  VSIE_HIP(hipGetLastError());
+  const int64_t SO = (int64_t)(P1 / 2 + 1) * (P2 / 2 + 1) * (P3 / 2 + 1);
+  const double scale = H.h * H.h * H.h / ((double)P1 * P2 * P3);
+  H.d64.spec = H.dalloc<cxd>(6 * SO);
+  launch_extract_octant<double>(st, full2, H.P, scale, H.d64.spec);
+  if (H.opts.build_c64) {
+    H.d32.spec = H.dalloc<cxf>(6 * SO);
+    launch_extract_octant<float>(st, full2, H.P, scale, H.d32.spec);
+  }
+  VSIE_HIP(hipStreamSynchronize(st));
+  (void)hipFree(full);
+  (void)hipFree(full2);
+  for (int a = 0; a < 3; ++a) {
+    H.d64.tw[a] = tw[a];
+    if (H.opts.build_c64) H.d32.tw[a] = twiddles<float>(H, H.P[a]);
+  }
+  // body diagonal and mask
+  std::vector<cxd> dv(H.nv, cxd{0, 0});
+  std::vector<uint8_t> mask(H.nv, 0);
+  const double h3 = H.h * H.h * H.h;
+  for (int p = 0; p < H.nv; ++p)
+    if (H.chi[p].re != 0 || H.chi[p].im != 0) {
+      dv[p] = h3 * cinv(H.chi[p]);
+      mask[p] = 1;
+    }
+  H.d_mask = upload(H, mask);
+  H.d64.dv_chi = upload_cx<double>(H, dv);
+  if (H.opts.build_c64) H.d32.dv_chi = upload_cx<float>(H, dv);
+}
+
+// ---------------------------------------------------------------------------------------------
+// pFFT: grid CSR of the projection, device weights, precorrection of near pairs
+void setup_pfft(Handle& H) {
+  hipStream_t st = H.stream;
+  const int mn = H.mn;
+  std::vector<int> base_ext(3 * mn);
+  for (int i = 0; i < mn; ++i)
+    for (int a = 0; a < 3; ++a) base_ext[3 * i + a] = H.base[3 * i + a] + H.ob[a];
+  H.d_base = upload(H, base_ext);
+  H.d64.W = upload(H, H.Wh);
+  if (H.opts.build_c64) {
+    std::vector<float> wf(H.Wh.begin(), H.Wh.end());
+    H.d32.W = upload(H, wf);
+  }
+  // grid CSR by extended-grid voxel (entries sorted by voxel, then RWG)
+  struct Ent {
+    int64_t v;
+    int n;
+    int j;
+  };
+  std::vector<Ent> ents;
+  ents.reserve((size_t)mn * 125);
+  for (int n = 0; n < mn; ++n)
+    for (int j = 0; j < 125; ++j) {
+      int j1 = j % 5, j2 = (j / 5) % 5, j3 = j / 25;
+      int64_t v = (base_ext[3 * n] + j1) + (int64_t)H.ne[0] * ((base_ext[3 * n + 1] + j2) + (int64_t)H.ne[1] * (base_ext[3 * n + 2] + j3));
+      ents.push_back({v, n, j});
+    }
+  std::sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) { return a.v != b.v ? a.v < b.v : a.n < b.n; });
+  std::vector<int> vox2row(H.Ne, -1), rowptr, rowrwg;
+  std::vector<double> roww;
+  for (size_t e = 0; e < ents.size(); ++e) {
+    if (e == 0 || ents[e].v != ents[e - 1].v) {
+      vox2row[ents[e].v] = (int)rowptr.size();
+      rowptr.push_back((int)e);
+    }
+    rowrwg.push_back(ents[e].n);
+    for (int a = 0; a < 3; ++a) roww.push_back(H.Wh[(size_t)ents[e].n * 375 + a * 125 + ents[e].j]);
+  }
+  rowptr.push_back((int)ents.size());
+  H.n_gridrows = (int)rowptr.size() - 1;
+  H.nnz_grid = (int64_t)ents.size();
+  H.d_vox2row = upload(H, vox2row);
+  H.d_rowptr = upload(H, rowptr);
+  H.d_rowrwg = upload(H, rowrwg);
+  H.d64.roww = upload(H, roww);
+  if (H.opts.build_c64) {
+    std::vector<float> rf(roww.begin(), roww.end());
+    H.d32.roww = upload(H, rf);
+  }
+
+  // --- precorrection pairs
+  const int D = H.opts.precorrect_dist;
+  std::vector<int> pm, pn;
+  for (int m = 0; m < mn; ++m)
+    for (int n = 0; n < mn; ++n) {
+      int gap = 0;
+      for (int a = 0; a < 3; ++a) {
+        int bm = H.base[3 * m + a], bn = H.base[3 * n + a];
+        int g = std::max({bn - (bm + 4), bm - (bn + 4), 0});
+        gap = std::max(gap, g);
+      }
+      if (gap <= D) {
+        pm.push_back(m);
+        pn.push_back(n);
+      }
+    }
+  std::vector<int> vp, vn, vox;   // tissue voxel (flat body index), RWG, ext coords
+  std::vector<double> vc;
+  for (int n = 0; n < mn; ++n) {
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::max(0, H.base[3 * n + a] - D);
+      hi[a] = std::min(H.n[a] - 1, H.base[3 * n + a] + 4 + D);
+    }
+    for (int i3 = lo[2]; i3 <= hi[2]; ++i3)
+      for (int i2 = lo[1]; i2 <= hi[1]; ++i2)
+        for (int i1 = lo[0]; i1 <= hi[0]; ++i1) {
+          int p = i1 + H.n[0] * (i2 + H.n[1] * i3);
+          if (H.chi[p].re == 0 && H.chi[p].im == 0) continue;
+          vp.push_back(p);
+          vn.push_back(n);
+          vox.push_back(i1 + H.ob[0]);
+          vox.push_back(i2 + H.ob[1]);
+          vox.push_back(i3 + H.ob[2]);
+          vc.push_back(H.origin[0] + (i1 + 0.5) * H.h);
+          vc.push_back(H.origin[1] + (i2 + 0.5) * H.h);
+          vc.push_back(H.origin[2] + (i3 + 0.5) * H.h);
+        }
+  }
+  const int64_t nnp = (int64_t)pm.size(), nvp = (int64_t)vp.size();
+  int* d_pm = H.dalloc<int>(nnp);
+  int* d_pn = H.dalloc<int>(nnp);
+  VSIE_HIP(hipMemcpy(d_pm, pm.data(), sizeof(int) * nnp, hipMemcpyHostToDevice));
+  VSIE_HIP(hipMemcpy(d_pn, pn.data(), sizeof(int) * nnp, hipMemcpyHostToDevice));
+  cxd* d_direct = H.dalloc<cxd>(nnp);
+  cxd* d_grid = H.dalloc<cxd>(nnp);
+  launch_zcc_pairs(st, H.dnear, H.dnear, d_pm, d_pn, nnp, H.k0, d_direct);
+  launch_pfft_wtw(st, H.d64.W, H.d_base, H.d_oct, H.ne, d_pm, d_pn, nnp, d_grid);
+  std::vector<cxd> vdir, vgrid;
+  if (nvp > 0) {
+    int* d_vn = upload(H, vn);
+    int* d_vox = upload(H, vox);
+    double* d_vc = upload(H, vc);
+    cxd* d_vdir = H.dalloc<cxd>(3 * nvp);
+    cxd* d_vgrid = H.dalloc<cxd>(3 * nvp);
+    launch_zbc_near(st, H.dnear, d_vc, d_vn, nvp, H.h, H.k0, d_vdir);
+    launch_pfft_tw_voxels(st, H.d64.W, H.d_base, H.d_oct, H.ne, d_vox, d_vn, nvp, d_vgrid);
+    VSIE_HIP(hipStreamSynchronize(st));
+    vdir = download(d_vdir, 3 * nvp);
+    vgrid = download(d_vgrid, 3 * nvp);
+  }
+  VSIE_HIP(hipGetLastError());
+  VSIE_HIP(hipStreamSynchronize(st));
+  std::vector<cxd> ndir = download(d_direct, nnp), ngrid = download(d_grid, nnp);
+  const double h3 = H.h * H.h * H.h;
+  struct Coo {
+    int64_t r, c;
+    cxd v;
+  };
+  std::vector<Coo> coo;
+  coo.reserve(nnp + 6 * nvp);
+  const int64_t offn = H.mf, offb = (int64_t)H.mf + H.mn;
+  for (int64_t e = 0; e < nnp; ++e) coo.push_back({offn + pm[e], offn + pn[e], ndir[e] - h3 * ngrid[e]});
+  for (int64_t e = 0; e < nvp; ++e)
+    for (int a = 0; a < 3; ++a) {
+      cxd v = vdir[3 * e + a] - h3 * vgrid[3 * e + a];
+      int64_t rb = offb + (int64_t)a * H.nv + vp[e];
+      coo.push_back({rb, offn + vn[e], v});
+      coo.push_back({offn + vn[e], rb, v});
+    }
+  std::sort(coo.begin(), coo.end(), [](const Coo& a, const Coo& b) { return a.r != b.r ? a.r < b.r : a.c < b.c; });
+  std::vector<int> rowid, rp, col;
+  std::vector<cxd> val;
+  for (size_t e = 0; e < coo.size(); ++e) {
+    if (e == 0 || coo[e].r != coo[e - 1].r) {
+      rowid.push_back((int)coo[e].r);
+      rp.push_back((int)col.size());
+    }
+    if (!col.empty() && e > 0 && coo[e].r == coo[e - 1].r && coo[e].c == coo[e - 1].c) {
+      val.back() += coo[e].v;
+      continue;
+    }
+    col.push_back((int)coo[e].c);
+    val.push_back(coo[e].v);
+  }
+  rp.push_back((int)col.size());
+  H.n_pcrows = (int)rowid.size();
+  H.pc_nnz = (int64_t)col.size();
+  H.d_pc_rowid = upload(H, rowid);
+  H.d_pc_rowptr = upload(H, rp);
+  H.d_pc_col = upload(H, col);
+  H.d64.pc_val = upload_cx<double>(H, val);
+  if (H.opts.build_c64) H.d32.pc_val = upload_cx<float>(H, val);
+}
+
+// ---------------------------------------------------------------------------------------------
+// far conductors: dense block, ACA of the near-far block, TT-cross of the far coupling
+void setup_dense_far(Handle& H) {
+  const int64_t mf = H.mf;
+  H.d64.Zff = H.dalloc<cxd>(mf * mf);
+  const int64_t max_entries = 1LL << 26;
+  int64_t rows_per = std::max<int64_t>(1, max_entries / std::max<int64_t>(1, mf));
+  for (int64_t r0 = 0; r0 < mf; r0 += rows_per) {
+    int64_t nr = std::min(rows_per, mf - r0);
+    launch_zcc_dense(H.stream, H.dfar, H.dfar, H.k0, r0, nr, H.d64.Zff + r0 * mf);
+  }
+  VSIE_HIP(hipGetLastError());
+  VSIE_HIP(hipStreamSynchronize(H.stream));
+}
+
+void copy_zff_c64(Handle& H) {
+  const int64_t mf = H.mf;
+  H.d32.Zff = H.dalloc<cxf>(mf * mf);
+  launch_d2f(H.stream, H.d64.Zff, H.d32.Zff, mf * mf);
+  VSIE_HIP(hipStreamSynchronize(H.stream));
+}
+
+void setup_aca(Handle& H) {
+  // partially pivoted ACA of Z_nf (m_n x m_f) ~ sum_l u_l v_l^T; stored as U V^* (V = conj(v))
+  const int mn = H.mn, mf = H.mf;
+  cxd* d_row = H.dalloc<cxd>(mf);
+  cxd* d_col = H.dalloc<cxd>(mn);
+  std::vector<std::vector<cxd>> us, vs;
+  std::vector<char> used_row(mn, 0), used_col(mf, 0);
+  int i = 0;
+  double norm2 = 0;
+  const int kmax = std::min({H.opts.aca_rank_max, mn, mf, 64});
+  for (int it = 0; it < 4 * kmax && (int)us.size() < kmax; ++it) {
+    used_row[i] = 1;
+    launch_zcc_dense(H.stream, H.dnear, H.dfar, H.k0, i, 1, d_row);
+    std::vector<cxd> r = download(d_row, mf);
+    for (size_t l = 0; l < us.size(); ++l)
+      for (int j = 0; j < mf; ++j) r[j] -= us[l][i] * vs[l][j];
+    int jb = -1;
+    double best = 0;
+    for (int j = 0; j < mf; ++j) {
+      if (used_col[j]) continue;
+      double a = r[j].re * r[j].re + r[j].im * r[j].im;
+      if (a > best) { best = a; jb = j; }
+    }
+    if (jb < 0 || best == 0) {
+      int nxt = -1;
+      for (int q = 0; q < mn; ++q)
+        if (!used_row[q]) { nxt = q; break; }
+      if (nxt < 0) break;
+      i = nxt;
+      continue;
+    }
+    used_col[jb] = 1;
+    cxd inv = cinv(r[jb]);
+    std::vector<cxd> v(mf);
+    for (int j = 0; j < mf; ++j) v[j] = r[j] * inv;
+    launch_zcc_dense(H.stream, H.dfar, H.dnear, H.k0, jb, 1, d_col);
+    std::vector<cxd> u = download(d_col, mn);
+    for (size_t l = 0; l < us.size(); ++l)
+      for (int q = 0; q < mn; ++q) u[q] -= vs[l][jb] * us[l][q];
+    double nu = 0, nvv = 0;
+    for (auto& z : u) nu += z.re * z.re + z.im * z.im;
+    for (auto& z : v) nvv += z.re * z.re + z.im * z.im;
+    cxd cross = {0, 0};
+    for (size_t l = 0; l < us.size(); ++l) {
+      cxd a = {0, 0}, b = {0, 0};
+      for (int q = 0; q < mn; ++q) a += mul_conj_a(us[l][q], u[q]);
+      for (int j = 0; j < mf; ++j) b += mul_conj_a(vs[l][j], v[j]);
+      cross += a * b;
+    }
+    norm2 += 2.0 * cross.re + nu * nvv;
+    us.push_back(u);
+    vs.push_back(v);
+    if (sqrt(nu * nvv) <= H.opts.aca_tol * sqrt(std::max(norm2, 0.0))) break;
+    int nxt = -1;
+    best = -1;
+    for (int q = 0; q < mn; ++q) {
+      if (used_row[q]) continue;
+      double a = u[q].re * u[q].re + u[q].im * u[q].im;
+      if (a > best) { best = a; nxt = q; }
+    }
+    if (nxt < 0) break;
+    i = nxt;
+  }
+  const int k = (int)us.size();
+  H.aca_k = k;
+  H.aca_U.assign((size_t)mn * k, cxd{0, 0});
+  H.aca_V.assign((size_t)mf * k, cxd{0, 0});
+  for (int l = 0; l < k; ++l) {
+    for (int q = 0; q < mn; ++q) H.aca_U[(size_t)q * k + l] = us[l][q];
+    for (int j = 0; j < mf; ++j) H.aca_V[(size_t)j * k + l] = conj(vs[l][j]);
+  }
+}
+
+void upload_aca(Handle& H) {
+  if (H.aca_k == 0) return;
+  H.d64.U = upload_cx<double>(H, H.aca_U);
+  H.d64.V = upload_cx<double>(H, H.aca_V);
+  if (H.opts.build_c64) {
+    H.d32.U = upload_cx<float>(H, H.aca_U);
+    H.d32.V = upload_cx<float>(H, H.aca_V);
+  }
+}
+
+// far coupling entry, 1 volume x 1 surface point:
+//   Z[chi](i1,i2,i3,n) = -h^3 sum_sides s (l/2) [ D(r_c - c_T) (c_T - p_T) ]_chi
+struct FarCoupling : EntryFn {
+  const Handle& H;
+  int chi;
+  std::vector<V3> cen[2], vec[2];
+  FarCoupling(const Handle& h, int c) : H(h), chi(c) {
+    const Rwg& R = H.far;
+    for (int side = 0; side < 2; ++side) {
+      cen[side].resize(R.m);
+      vec[side].resize(R.m);
+      for (int i = 0; i < R.m; ++i) {
+        int t = side == 0 ? R.tp[i] : R.tm[i];
+        int fv = side == 0 ? R.fp[i] : R.fm[i];
+        V3 c = (1.0 / 3.0) * (R.vert(R.tris[3 * t]) + R.vert(R.tris[3 * t + 1]) + R.vert(R.tris[3 * t + 2]));
+        double s = side == 0 ? 1.0 : -1.0;
+        cen[side][i] = c;
+        vec[side][i] = (s * 0.5 * R.len[i]) * (c - R.vert(fv));
+      }
+    }
+  }
+  void eval(const std::vector<int>& idx, std::vector<cxd>& out) override {
+    const int64_t n = (int64_t)idx.size() / 4;
+    out.resize(n);
+    const double h3 = H.h * H.h * H.h;
+    parallel_for(n, 16, [&](int64_t a, int64_t b) {
+      for (int64_t e = a; e < b; ++e) {
+        const int* t = &idx[4 * e];
+        V3 r = {H.origin[0] + (t[0] + 0.5) * H.h, H.origin[1] + (t[1] + 0.5) * H.h, H.origin[2] + (t[2] + 0.5) * H.h};
+        cxd acc = {0, 0};
+        for (int side = 0; side < 2; ++side) {
+          V3 v = vec[side][t[3]];
+          cxd vv[3] = {{v.x, 0}, {v.y, 0}, {v.z, 0}};
+          cxd o[3];
+          dyad_apply(r - cen[side][t[3]], vv, H.k0, o);
+          acc += o[chi];
+        }
+        out[e] = (-h3) * acc;
+      }
+    });
+  }
+};
+
+void setup_tt(Handle& H) {
+  const int n4[4] = {H.n[0], H.n[1], H.n[2], H.mf};
+  for (int chi = 0; chi < 3; ++chi) {
+    FarCoupling f(H, chi);
+    int ranks[3];
+    double err = 0;
+    tt_cross(f, n4, H.opts.tt_tol, H.opts.tt_rank_max, H.opts.seed + 7919ull * chi, H.tt_host[chi], ranks, &err);
+    for (int k = 0; k < 3; ++k) H.tt_r[chi][k] = ranks[k];
+    H.tt_err[chi] = err;
+  }
+}
+
+void upload_tt(Handle& H, int chi) {
+  for (int k = 0; k < 4; ++k) {
+    H.d64.G[chi][k] = upload_cx<double>(H, H.tt_host[chi][k]);
+    if (H.opts.build_c64) H.d32.G[chi][k] = upload_cx<float>(H, H.tt_host[chi][k]);
+  }
+}
+
+template <typename R> void alloc_work(Handle& H, OpData<R>& D) {
+  D.gridA = H.dalloc<cx<R>>(3 * H.Ne);
+  D.bufB = H.dalloc<cx<R>>(3LL * H.ne[2] * H.ne[1] * H.P[0]);
+  D.bufC = H.dalloc<cx<R>>(3LL * H.ne[2] * H.P[1] * H.P[0]);
+  int64_t nq = (int64_t)H.n[1] * H.n[2];
+  D.tt_work = H.dalloc<cx<R>>(2 * 128 + 128LL * H.n[2] + 128 * nq);
+  D.small_work = H.dalloc<cx<R>>(256 * 64 + 256);
+}
+
+// ---------------------------------------------------------------------------------------------
+const char* const kStageNames[Handle::NSTAGE] = {"build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv",
+                                                 "fft_y_inv", "fft_x_inv", "body_out", "pfft_gather",
+                                                 "gemv_far", "precorrect", "aca", "tt"};
+
+struct StageTimer {
+  Handle& H;
+  hipStream_t st;
+  StageTimer(Handle& h, hipStream_t s) : H(h), st(s) {
+    for (int i = 0; i < Handle::NSTAGE; ++i) H.ev_used[i] = false;
+  }
+  void begin(int s) {
+    if (H.prof) {
+      VSIE_HIP(hipEventRecord(H.ev[2 * s], st));
+      H.ev_used[s] = true;
+    }
+  }
+  void end(int s) {
+    if (H.prof) VSIE_HIP(hipEventRecord(H.ev[2 * s + 1], st));
+  }
+  void collect() {
+    if (!H.prof) return;
+    VSIE_HIP(hipStreamSynchronize(st));
+    for (int s = 0; s < Handle::NSTAGE; ++s)
+      if (H.ev_used[s]) {
+        float ms = 0;
+        VSIE_HIP(hipEventElapsedTime(&ms, H.ev[2 * s], H.ev[2 * s + 1]));
+        H.prof_ms[s] += ms;
+        H.prof_calls[s] += 1;
+      }
+  }
+};
+
+template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t st) {
+  StageTimer T(H, st);
+  const int mf = H.mf, mn = H.mn;
+  const cx<R>* xf = x;
+  const cx<R>* xn = x + mf;
+  const cx<R>* xb = x + mf + mn;
+  cx<R>* yf = y;
+  cx<R>* yn = y + mf;
+  cx<R>* yb = y + mf + mn;
+  GridDims g = grid_dims(H);
+  const int P1 = H.P[0], P2 = H.P[1], P3 = H.P[2];
+  const int ne1 = H.ne[0], ne2 = H.ne[1], ne3 = H.ne[2];
+  // volume convolution and pFFT (Sec. II-B, eq. (13))
+  T.begin(0);
+  launch_build_grid<R>(st, xb, mn ? xn : nullptr, H.d_mask, mn ? H.d_vox2row : nullptr, H.d_rowptr, H.d_rowrwg, D.roww,
+                       D.gridA, g);
+  T.end(0);
+  T.begin(1);
+  fft_rows<R>(st, P1, true, D.gridA, D.bufB, ne1, P1, ne1, P1, 3LL * ne3 * ne2, D.tw[0]);
+  T.end(1);
+  T.begin(2);
+  fft_strided<R>(st, P2, true, D.bufB, D.bufC, ne2, P2, P1, P1, P1, 3LL * ne3, (int64_t)ne2 * P1, (int64_t)P2 * P1, D.tw[1]);
+  T.end(2);
+  T.begin(3);
+  fft_z_conv<R>(st, P3, D.bufC, ne3, P1, P2, D.spec, D.tw[2]);
+  T.end(3);
+  T.begin(4);
+  fft_strided<R>(st, P2, false, D.bufC, D.bufB, P2, ne2, P1, P1, P1, 3LL * ne3, (int64_t)P2 * P1, (int64_t)ne2 * P1, D.tw[1]);
+  T.end(4);
+  T.begin(5);
+  fft_rows<R>(st, P1, false, D.bufB, D.gridA, P1, ne1, P1, ne1, 3LL * ne3 * ne2, D.tw[0]);
+  T.end(5);
+  T.begin(6);
+  launch_body_out<R>(st, xb, D.gridA, D.dv_chi, H.d_mask, yb, g);
+  T.end(6);
+  if (mn) {
+    T.begin(7);
+    launch_pfft_gather<R>(st, D.W, H.d_base, D.gridA, yn, mn, g);
+    T.end(7);
+  }
+  // dense far block (writes y_f)
+  if (mf) {
+    T.begin(8);
+    launch_gemv_rows<R>(st, D.Zff, xf, mf, mf, yf, 0);
+    T.end(8);
+  }
+  // precorrection
+  T.begin(9);
+  launch_csr_add<R>(st, H.d_pc_rowid, H.d_pc_rowptr, H.d_pc_col, D.pc_val, x, y, H.n_pcrows);
+  T.end(9);
+  // ACA: y_n += U (V^* x_f), y_f += conj(V) (U^T x_n)
+  if (mf && mn && H.aca_k > 0) {
+    T.begin(10);
+    cx<R>* part = D.small_work;
+    cx<R>* t = D.small_work + 256 * 64;
+    const int nblk = 128;
+    launch_tall_t<R>(st, true, D.V, xf, mf, H.aca_k, part, nblk, t);
+    launch_tall_n_add<R>(st, false, D.U, t, mn, H.aca_k, yn);
+    launch_tall_t<R>(st, false, D.U, xn, mn, H.aca_k, part, nblk, t);
+    launch_tall_n_add<R>(st, true, D.V, t, mf, H.aca_k, yf);
+    T.end(10);
+  }
+  // TT far coupling (eqs. (16)-(19))
+  if (mf && D.G[0][0]) {
+    T.begin(11);
+    for (int chi = 0; chi < 3; ++chi) {
+      if (!D.G[chi][0]) continue;
+      const int* r = H.tt_r[chi];
+      launch_tt_forward<R>(st, D.G[chi], r, H.n, mf, xf, H.d_mask, yb + (int64_t)chi * H.nv, D.tt_work);
+      launch_tt_transpose<R>(st, D.G[chi], r, H.n, mf, xb + (int64_t)chi * H.nv, H.d_mask, yf, D.tt_work);
+    }
+    T.end(11);
+  }
+  T.collect();
+}
+
+// ---------------------------------------------------------------------------------------------
+// GMRES (FP64 Arnoldi, CGS2) with a matvec callback on FP64 vectors
+struct Solver {
+  Handle& H;
+  hipStream_t st;
+  int64_t N;
+  cxd* part;     // multidot partials
+  double* npart;
+  static constexpr int NBLK = 256;
+  Solver(Handle& h, hipStream_t s) : H(h), st(s), N(h.N) {
+    part = H.d_solve_work;
+    npart = H.d_red;
+  }
+  void norms(const cxd* a, double out[4]) {
+    launch_norm_partial(st, a, N, H.mf, (int64_t)H.mf + H.mn, npart, NBLK);
+    std::vector<double> p(3 * NBLK);
+    VSIE_HIP(hipMemcpyAsync(p.data(), npart, sizeof(double) * 3 * NBLK, hipMemcpyDeviceToHost, st));
+    VSIE_HIP(hipStreamSynchronize(st));
+    double s[3] = {0, 0, 0};
+    for (int b = 0; b < NBLK; ++b)
+      for (int q = 0; q < 3; ++q) s[q] += p[3 * b + q];
+    out[0] = sqrt(s[0]);
+    out[1] = sqrt(s[1]);
+    out[2] = sqrt(s[2]);
+    out[3] = sqrt(s[0] + s[1] + s[2]);
+  }
+  void dots(const cxd* V, int nvec, const cxd* w, std::vector<cxd>& h) {
+    launch_multidot(st, V, N, nvec, w, N, part, NBLK);
+    std::vector<cxd> p((size_t)NBLK * nvec);
+    VSIE_HIP(hipMemcpyAsync(p.data(), part, sizeof(cxd) * NBLK * nvec, hipMemcpyDeviceToHost, st));
+    VSIE_HIP(hipStreamSynchronize(st));
+    h.assign(nvec, cxd{0, 0});
+    for (int b = 0; b < NBLK; ++b)
+      for (int i = 0; i < nvec; ++i) h[i] += p[(size_t)b * nvec + i];
+  }
+  // solve A x = b to relative residual tol (x initialised to zero). Returns iterations used.
+  template <typename MV>
+  int gmres(MV&& A, const cxd* b, cxd* x, double tol, int restart, int max_iter, int* restarts, double* relres,
+            cxd* Vbuf, cxd* w, cxd* hvec_dev) {
+    VSIE_HIP(hipMemsetAsync(x, 0, sizeof(cxd) * N, st));
+    double nb[4];
+    norms(b, nb);
+    const double bnorm = nb[3];
+    *relres = 0;
+    if (bnorm == 0) return 0;
+    int it = 0;
+    std::vector<cxd> Hm((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h, h2;
+    for (;;) {
+      A(x, w);
+      launch_sub(st, b, w, w, N);      // r = b - A x
+      double nr[4];
+      norms(w, nr);
+      *relres = nr[3] / bnorm;
+      if (*relres <= tol || it >= max_iter) break;
+      ++*restarts;
+      const double beta = nr[3];
+      launch_scale_copy(st, w, 1.0 / beta, Vbuf, N);
+      std::fill(g.begin(), g.end(), cxd{0, 0});
+      g[0] = {beta, 0};
+      int jend = 0;
+      bool done = false;
+      for (int j = 0; j < restart; ++j) {
+        A(Vbuf + (int64_t)j * N, w);
+        dots(Vbuf, j + 1, w, h);
+        VSIE_HIP(hipMemcpyAsync(hvec_dev, h.data(), sizeof(cxd) * (j + 1), hipMemcpyHostToDevice, st));
+        launch_multiaxpy(st, Vbuf, N, j + 1, hvec_dev, w, N);
+        dots(Vbuf, j + 1, w, h2);
+        VSIE_HIP(hipMemcpyAsync(hvec_dev, h2.data(), sizeof(cxd) * (j + 1), hipMemcpyHostToDevice, st));
+        launch_multiaxpy(st, Vbuf, N, j + 1, hvec_dev, w, N);
+        double nw[4];
+        norms(w, nw);
+        for (int i = 0; i <= j; ++i) Hm[(size_t)i * restart + j] = h[i] + h2[i];
+        Hm[(size_t)(j + 1) * restart + j] = {nw[3], 0};
+        if (nw[3] > 0) launch_scale_copy(st, w, 1.0 / nw[3], Vbuf + (int64_t)(j + 1) * N, N);
+        for (int i = 0; i < j; ++i) {
+          cxd a = Hm[(size_t)i * restart + j], bb = Hm[(size_t)(i + 1) * restart + j];
+          Hm[(size_t)i * restart + j] = conj(cs[i]) * a + conj(sn[i]) * bb;
+          Hm[(size_t)(i + 1) * restart + j] = cxd{-sn[i].re, -sn[i].im} * a + cs[i] * bb;
+        }
+        cxd a = Hm[(size_t)j * restart + j], bb = Hm[(size_t)(j + 1) * restart + j];
+        double den = sqrt(a.re * a.re + a.im * a.im + bb.re * bb.re + bb.im * bb.im);
+        cs[j] = den > 0 ? (1.0 / den) * a : cxd{1, 0};
+        sn[j] = den > 0 ? (1.0 / den) * bb : cxd{0, 0};
+        Hm[(size_t)j * restart + j] = conj(cs[j]) * a + conj(sn[j]) * bb;
+        Hm[(size_t)(j + 1) * restart + j] = {0, 0};
+        g[j + 1] = cxd{-sn[j].re, -sn[j].im} * g[j];
+        g[j] = conj(cs[j]) * g[j];
+        ++it;
+        jend = j + 1;
+        double est = sqrt(g[j + 1].re * g[j + 1].re + g[j + 1].im * g[j + 1].im) / bnorm;
+        if (est <= tol || it >= max_iter || nw[3] == 0) {
+          done = true;
+          break;
+        }
+      }
+      // back substitution
+      std::vector<cxd> y(jend);
+      for (int i = jend - 1; i >= 0; --i) {
+        cxd s = g[i];
+        for (int k = i + 1; k < jend; ++k) s -= Hm[(size_t)i * restart + k] * y[k];
+        y[i] = s * cinv(Hm[(size_t)i * restart + i]);
+      }
+      VSIE_HIP(hipMemcpyAsync(hvec_dev, y.data(), sizeof(cxd) * jend, hipMemcpyHostToDevice, st));
+      launch_combine_add(st, Vbuf, N, jend, hvec_dev, x, N);
+      (void)done;
+    }
+    return it;
+  }
+};
+
+void ensure_solver_ws(Handle& H, int restart) {
+  if (!H.d_solve_work) {
+    H.d_solve_work = H.dalloc<cxd>(256LL * 1100);
+    H.d_red = H.dalloc<double>(256 * 4);
+  }
+  if (H.krylov_cols < restart + 1) {
+    if (H.d_krylov) {
+      auto it = std::find(H.allocations.begin(), H.allocations.end(), (void*)H.d_krylov);
+      if (it != H.allocations.end()) H.allocations.erase(it);
+      H.device_bytes -= (int64_t)sizeof(cxd) * H.krylov_cols * H.N;
+      VSIE_HIP(hipFree(H.d_krylov));
+      H.d_krylov = nullptr;
+    }
+    H.d_krylov = H.dalloc<cxd>((int64_t)(restart + 1) * H.N);
+    H.krylov_cols = restart + 1;
+  }
+}
+
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+int vsie_default_options(vsie_options* o) {
+  if (!o) return fail(VSIE_E_ARG, "null options");
+  o->tt_tol = 1e-3;
+  o->tt_rank_max = 30;
+  o->aca_tol = 1e-3;
+  o->aca_rank_max = 64;
+  o->precorrect_dist = 2;
+  o->build_c64 = 1;
+  o->build_far = 1;
+  o->seed = 1;
+  return VSIE_OK;
+}
+
+int vsie_default_solve_opts(vsie_solve_opts* o) {
+  if (!o) return fail(VSIE_E_ARG, "null options");
+  o->tol = 1e-6;
+  o->restart = 50;
+  o->max_iter = 5000;
+  o->method = VSIE_GMRES64;
+  o->inner_tol = 1e-3;
+  return VSIE_OK;
+}
+
+int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, vsie_handle** out) {
+  if (!p || !out) return fail(VSIE_E_ARG, "null argument");
+  *out = nullptr;
+  vsie_handle* hd = new (std::nothrow) vsie_handle();
+  if (!hd) return fail(VSIE_E_NOMEM, "handle allocation");
+  int rc = guarded([&]() {
+    auto t0 = std::chrono::steady_clock::now();
+    Handle& H = hd->H;
+    if (opts) H.opts = *opts;
+    else vsie_default_options(&H.opts);
+    H.stream = (hipStream_t)stream;
+    for (int a = 0; a < 3; ++a) {
+      if (p->n[a] <= 0 || p->n[a] > 4096) throw Error(VSIE_E_ARG, "grid size out of range");
+      H.n[a] = p->n[a];
+      H.origin[a] = p->origin[a];
+      if (!std::isfinite(p->origin[a])) throw Error(VSIE_E_ARG, "non-finite origin");
+    }
+    if (!(p->h > 0) || !std::isfinite(p->h)) throw Error(VSIE_E_ARG, "voxel size must be positive");
+    if (!(p->freq_hz > 0) || !std::isfinite(p->freq_hz)) throw Error(VSIE_E_ARG, "frequency must be positive");
+    if (!p->eps_r || !p->sigma) throw Error(VSIE_E_ARG, "null material arrays");
+    if (H.opts.precorrect_dist < 0 || H.opts.tt_rank_max < 1 || H.opts.aca_rank_max < 1)
+      throw Error(VSIE_E_ARG, "invalid options");
+    if (p->n_meshes < 0 || (p->n_meshes > 0 && !p->meshes)) throw Error(VSIE_E_ARG, "bad mesh list");
+    H.h = p->h;
+    H.freq = p->freq_hz;
+    H.omega = 2.0 * PI * H.freq;
+    H.k0 = H.omega * sqrt(EPS0 * MU0);
+    H.nv = H.n[0] * H.n[1] * H.n[2];
+    H.chi.resize(H.nv);
+    for (int i = 0; i < H.nv; ++i) {
+      double e = p->eps_r[i], s = p->sigma[i];
+      if (!std::isfinite(e) || !std::isfinite(s)) throw Error(VSIE_E_ARG, "non-finite eps_r or sigma");
+      H.chi[i] = cxd{e - 1.0, -s / (H.omega * EPS0)};
+      if (H.chi[i].re != 0 || H.chi[i].im != 0) H.tissue.push_back(i);
+    }
+    std::vector<std::pair<int, std::vector<PortEdge>>> pf, pn;
+    build_rwg(p, VSIE_FAR, H.far, pf);
+    build_rwg(p, VSIE_NEAR, H.near, pn);
+    H.mf = H.far.m;
+    H.mn = H.near.m;
+    // ports in the order of the mesh list
+    for (int mi = 0; mi < p->n_meshes; ++mi) {
+      for (auto& q : pf)
+        if (q.first == mi) H.ports.push_back(q.second);
+      for (auto& q : pn)
+        if (q.first == mi) H.ports.push_back(q.second);
+    }
+    H.N = (int64_t)H.mf + H.mn + 3LL * H.nv;
+    if (H.mn > 0) stencil_setup(H);
+    else {
+      for (int a = 0; a < 3; ++a) {
+        H.ne[a] = H.n[a];
+        H.ob[a] = 0;
+        int P = 8;
+        while (P < 2 * H.ne[a] - 1) P *= 2;
+        if (P > 1024) throw Error(VSIE_E_GRID, "grid needs an FFT longer than 1024");
+        H.P[a] = P;
+      }
+      H.Ne = (int64_t)H.ne[0] * H.ne[1] * H.ne[2];
+    }
+    H.have32 = H.opts.build_c64 != 0;
+    H.dfar = make_rwg_dev(H, H.far);
+    H.dnear = make_rwg_dev(H, H.near);
+    setup_volume(H);
+    if (H.mn > 0) setup_pfft(H);
+    if (H.mf > 0) {
+      setup_dense_far(H);
+      if (H.opts.build_c64) copy_zff_c64(H);
+      if (H.opts.build_far) {
+        if (H.mn > 0) setup_aca(H);
+        upload_aca(H);
+        setup_tt(H);
+        for (int chi = 0; chi < 3; ++chi) upload_tt(H, chi);
+      }
+    }
+    alloc_work<double>(H, H.d64);
+    if (H.opts.build_c64) alloc_work<float>(H, H.d32);
+    VSIE_HIP(hipStreamSynchronize(H.stream));
+    H.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
+  if (rc != VSIE_OK) {
+    delete hd;
+    return rc;
+  }
+  *out = hd;
+  return VSIE_OK;
+}
+
+int vsie_sizes(const vsie_handle* hd, vsie_sizes_t* s) {
+  if (!hd || !s) return fail(VSIE_E_ARG, "null argument");
+  const Handle& H = hd->H;
+  std::memset(s, 0, sizeof(*s));
+  s->n_total = H.N;
+  s->m_far = H.mf;
+  s->m_near = H.mn;
+  for (int a = 0; a < 3; ++a) {
+    s->n[a] = H.n[a];
+    s->n_ext[a] = H.ne[a];
+    s->fft[a] = H.P[a];
+    s->tt_err_est[a] = H.tt_err[a];
+    for (int k = 0; k < 3; ++k) s->tt_rank[a][k] = H.tt_r[a][k];
+  }
+  s->n_ports = (int)H.ports.size();
+  s->n_tissue = (int)H.tissue.size();
+  s->aca_rank = H.aca_k;
+  s->precorr_nnz = H.pc_nnz;
+  s->device_bytes = H.device_bytes;
+  s->setup_seconds = H.setup_seconds;
+  return VSIE_OK;
+}
+
+int vsie_rhs(const vsie_handle* hd, int port, int dtype, void* b_dev, void* stream) {
+  if (!hd || !b_dev) return fail(VSIE_E_ARG, "null argument");
+  const Handle& H = hd->H;
+  if (port < 0 || port >= (int)H.ports.size()) return fail(VSIE_E_ARG, "port out of range");
+  if (dtype != VSIE_C128 && dtype != VSIE_C64) return fail(VSIE_E_ARG, "bad dtype");
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    const double ws = H.omega * EPS0;   // i w eps0 V0 l s -> (0, ws * l * s)
+    std::vector<int> idx;
+    std::vector<double> vre, vim;
+    for (const PortEdge& e : H.ports[port]) {
+      const Rwg& R = e.domain == VSIE_FAR ? H.far : H.near;
+      int off = e.domain == VSIE_FAR ? 0 : H.mf;
+      idx.push_back(off + e.idx);
+      vre.push_back(0.0);
+      vim.push_back(ws * R.len[e.idx] * e.sign);
+    }
+    const size_t esz = dtype == VSIE_C128 ? sizeof(cxd) : sizeof(cxf);
+    VSIE_HIP(hipMemsetAsync(b_dev, 0, esz * H.N, st));
+    int* d_idx = nullptr;
+    double *d_re = nullptr, *d_im = nullptr;
+    int ne = (int)idx.size();
+    VSIE_HIP(hipMalloc(&d_idx, sizeof(int) * std::max(ne, 1)));
+    VSIE_HIP(hipMalloc(&d_re, sizeof(double) * std::max(ne, 1)));
+    VSIE_HIP(hipMalloc(&d_im, sizeof(double) * std::max(ne, 1)));
+    VSIE_HIP(hipMemcpyAsync(d_idx, idx.data(), sizeof(int) * ne, hipMemcpyHostToDevice, st));
+    VSIE_HIP(hipMemcpyAsync(d_re, vre.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
+    VSIE_HIP(hipMemcpyAsync(d_im, vim.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
+    if (dtype == VSIE_C128) launch_scatter_rhs<double>(st, d_idx, d_re, d_im, ne, (cxd*)b_dev);
+    else launch_scatter_rhs<float>(st, d_idx, d_re, d_im, ne, (cxf*)b_dev);
+    VSIE_HIP(hipStreamSynchronize(st));
+    (void)hipFree(d_idx);
+    (void)hipFree(d_re);
+    (void)hipFree(d_im);
+  });
+}
+
+int vsie_matvec(vsie_handle* hd, int dtype, int nrhs, const void* x_dev, void* y_dev, void* stream) {
+  if (!hd || !x_dev || !y_dev || nrhs < 1) return fail(VSIE_E_ARG, "bad argument");
+  if (x_dev == y_dev) return fail(VSIE_E_ARG, "x and y must not alias");
+  Handle& H = hd->H;
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    for (int c = 0; c < nrhs; ++c) {
+      if (dtype == VSIE_C128) {
+        matvec_one<double>(H, H.d64, (const cxd*)x_dev + c * H.N, (cxd*)y_dev + c * H.N, st);
+      } else if (dtype == VSIE_C64) {
+        if (!H.have32) throw Error(VSIE_E_STATE, "complex64 operator data not built");
+        matvec_one<float>(H, H.d32, (const cxf*)x_dev + c * H.N, (cxf*)y_dev + c * H.N, st);
+      } else {
+        throw Error(VSIE_E_ARG, "bad dtype");
+      }
+    }
+    VSIE_HIP(hipGetLastError());
+  });
+}
+
+int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* b_dev, void* x_dev,
+               vsie_solve_stats* stats, void* stream) {
+  if (!hd || !b_dev || !x_dev || nrhs < 1) return fail(VSIE_E_ARG, "bad argument");
+  vsie_solve_opts so;
+  if (o) so = *o;
+  else vsie_default_solve_opts(&so);
+  if (so.restart < 1 || so.restart > 1000 || so.max_iter < 1 || !(so.tol > 0)) return fail(VSIE_E_ARG, "bad solve options");
+  if (so.method == VSIE_IR_MIXED && !hd->H.have32) return fail(VSIE_E_STATE, "complex64 operator data not built");
+  Handle& H = hd->H;
+  int status = VSIE_OK;
+  int rc = guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    ensure_solver_ws(H, so.restart);
+    const int64_t N = H.N;
+    cxd* w = nullptr;
+    cxd* r = nullptr;
+    cxd* d = nullptr;
+    cxf* x32 = nullptr;
+    cxf* y32 = nullptr;
+    cxd* hv = nullptr;
+    VSIE_HIP(hipMalloc(&w, sizeof(cxd) * N));
+    VSIE_HIP(hipMalloc(&r, sizeof(cxd) * N));
+    VSIE_HIP(hipMalloc(&d, sizeof(cxd) * N));
+    VSIE_HIP(hipMalloc(&hv, sizeof(cxd) * 1100));
+    if (so.method == VSIE_IR_MIXED) {
+      VSIE_HIP(hipMalloc(&x32, sizeof(cxf) * N));
+      VSIE_HIP(hipMalloc(&y32, sizeof(cxf) * N));
+    }
+    Solver S(H, st);
+    auto A64 = [&](const cxd* in, cxd* out) { matvec_one<double>(H, H.d64, in, out, st); };
+    auto A32 = [&](const cxd* in, cxd* out) {
+      launch_d2f(st, in, x32, N);
+      matvec_one<float>(H, H.d32, x32, y32, st);
+      launch_f2d(st, y32, out, N);
+    };
+    for (int c = 0; c < nrhs; ++c) {
+      auto t0 = std::chrono::steady_clock::now();
+      const cxd* b = (const cxd*)b_dev + c * N;
+      cxd* x = (cxd*)x_dev + c * N;
+      vsie_solve_stats s;
+      std::memset(&s, 0, sizeof(s));
+      double rel = 0;
+      if (so.method == VSIE_GMRES64) {
+        s.iterations = S.gmres(A64, b, x, so.tol, so.restart, so.max_iter, &s.restarts, &rel, H.d_krylov, w, hv);
+      } else {
+        VSIE_HIP(hipMemsetAsync(x, 0, sizeof(cxd) * N, st));
+        double nb[4];
+        S.norms(b, nb);
+        int total = 0;
+        for (int outer = 0; outer < 50; ++outer) {
+          A64(x, w);
+          launch_sub(st, b, w, r, N);
+          double nr[4];
+          S.norms(r, nr);
+          rel = nb[3] > 0 ? nr[3] / nb[3] : 0;
+          if (rel <= so.tol || total >= so.max_iter) break;
+          double inner_rel = 0;
+          int used = S.gmres(A32, r, d, std::max(so.inner_tol, so.tol / rel * 0.5), so.restart, so.max_iter - total,
+                             &s.restarts, &inner_rel, H.d_krylov, w, hv);
+          total += used;
+          launch_add(st, x, d, N);
+          ++s.refinements;
+          if (used == 0) break;
+        }
+        s.iterations = total;
+      }
+      // true FP64 residual and per-block residuals
+      A64(x, w);
+      launch_sub(st, b, w, r, N);
+      double nr[4], nb[4];
+      S.norms(r, nr);
+      S.norms(b, nb);
+      s.rel_residual = nb[3] > 0 ? nr[3] / nb[3] : 0;
+      for (int q = 0; q < 3; ++q) s.block_residual[q] = nb[3] > 0 ? nr[q] / nb[3] : 0;
+      VSIE_HIP(hipStreamSynchronize(st));
+      s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (s.rel_residual > so.tol) status = VSIE_E_NOCONV;
+      if (stats) stats[c] = s;
+    }
+    (void)hipFree(w);
+    (void)hipFree(r);
+    (void)hipFree(d);
+    (void)hipFree(hv);
+    if (x32) (void)hipFree(x32);
+    if (y32) (void)hipFree(y32);
+  });
+  if (rc != VSIE_OK) return rc;
+  if (status != VSIE_OK) return fail(status, "solver did not reach the requested tolerance");
+  return VSIE_OK;
+}
+
+int vsie_port_current(const vsie_handle* hd, int port, const double* x, double* I) {
+  if (!hd || !x || !I) return fail(VSIE_E_ARG, "null argument");
+  const Handle& H = hd->H;
+  if (port < 0 || port >= (int)H.ports.size()) return fail(VSIE_E_ARG, "port out of range");
+  double re = 0, im = 0;
+  for (const PortEdge& e : H.ports[port]) {
+    const Rwg& R = e.domain == VSIE_FAR ? H.far : H.near;
+    int64_t g = (e.domain == VSIE_FAR ? 0 : H.mf) + e.idx;
+    re += e.sign * R.len[e.idx] * x[2 * g];
+    im += e.sign * R.len[e.idx] * x[2 * g + 1];
+  }
+  I[0] = re;
+  I[1] = im;
+  return VSIE_OK;
+}
+
+int vsie_export(const vsie_handle* hd, int what, int index, void* host, size_t* nbytes) {
+  if (!hd || !nbytes) return fail(VSIE_E_ARG, "null argument");
+  const Handle& H = hd->H;
+  return guarded([&]() {
+    std::vector<unsigned char> buf;
+    auto put = [&](const void* p, size_t n) {
+      const unsigned char* c = (const unsigned char*)p;
+      buf.insert(buf.end(), c, c + n);
+    };
+    switch (what) {
+      case VSIE_X_TT_CORES: {
+        if (index < 0 || index > 2) throw Error(VSIE_E_ARG, "TT component out of range");
+        put(H.tt_r[index], sizeof(int) * 3);
+        for (int k = 0; k < 4; ++k) put(H.tt_host[index][k].data(), sizeof(cxd) * H.tt_host[index][k].size());
+        break;
+      }
+      case VSIE_X_ACA: {
+        put(&H.aca_k, sizeof(int));
+        put(H.aca_U.data(), sizeof(cxd) * H.aca_U.size());
+        put(H.aca_V.data(), sizeof(cxd) * H.aca_V.size());
+        break;
+      }
+      case VSIE_X_STENCIL: {
+        put(H.base.data(), sizeof(int) * H.base.size());
+        put(H.Wh.data(), sizeof(double) * H.Wh.size());
+        break;
+      }
+      case VSIE_X_GENERATOR: {
+        std::vector<cxd> o = download(H.d_oct, 6 * H.Ne);
+        put(o.data(), sizeof(cxd) * o.size());
+        break;
+      }
+      case VSIE_X_EXT_GRID: {
+        put(H.ne, sizeof(int) * 3);
+        put(H.ob, sizeof(int) * 3);
+        put(H.P, sizeof(int) * 3);
+        break;
+      }
+      default:
+        throw Error(VSIE_E_ARG, "unknown export kind");
+    }
+    if (!host) {
+      *nbytes = buf.size();
+      return;
+    }
+    if (*nbytes < buf.size()) throw Error(VSIE_E_ARG, "export buffer too small");
+    std::memcpy(host, buf.data(), buf.size());
+    *nbytes = buf.size();
+  });
+}
+
+int vsie_import(vsie_handle* hd, int what, int index, const void* host, size_t nbytes) {
+  if (!hd || !host) return fail(VSIE_E_ARG, "null argument");
+  Handle& H = hd->H;
+  return guarded([&]() {
+    const unsigned char* c = (const unsigned char*)host;
+    if (what == VSIE_X_TT_CORES) {
+      if (index < 0 || index > 2) throw Error(VSIE_E_ARG, "TT component out of range");
+      if (H.mf == 0) throw Error(VSIE_E_STATE, "no far conductors");
+      if (nbytes < 3 * sizeof(int)) throw Error(VSIE_E_ARG, "short TT record");
+      int r[3];
+      std::memcpy(r, c, sizeof(r));
+      for (int k = 0; k < 3; ++k)
+        if (r[k] < 1 || r[k] > 128) throw Error(VSIE_E_ARG, "TT rank must be within 1..128");
+      size_t sz[4] = {(size_t)H.n[0] * r[0], (size_t)r[0] * H.n[1] * r[1], (size_t)r[1] * H.n[2] * r[2],
+                      (size_t)r[2] * H.mf};
+      size_t need = 3 * sizeof(int) + sizeof(cxd) * (sz[0] + sz[1] + sz[2] + sz[3]);
+      if (nbytes != need) throw Error(VSIE_E_ARG, "TT record size mismatch");
+      size_t off = 3 * sizeof(int);
+      for (int k = 0; k < 4; ++k) {
+        H.tt_host[index][k].resize(sz[k]);
+        std::memcpy(H.tt_host[index][k].data(), c + off, sizeof(cxd) * sz[k]);
+        off += sizeof(cxd) * sz[k];
+      }
+      for (int k = 0; k < 3; ++k) H.tt_r[index][k] = r[k];
+      H.tt_err[index] = 0;
+      upload_tt(H, index);
+    } else if (what == VSIE_X_ACA) {
+      if (H.mf == 0 || H.mn == 0) throw Error(VSIE_E_STATE, "needs near and far conductors");
+      int k;
+      if (nbytes < sizeof(int)) throw Error(VSIE_E_ARG, "short ACA record");
+      std::memcpy(&k, c, sizeof(int));
+      if (k < 0 || k > 64) throw Error(VSIE_E_ARG, "ACA rank must be within 0..64");
+      size_t need = sizeof(int) + sizeof(cxd) * ((size_t)H.mn * k + (size_t)H.mf * k);
+      if (nbytes != need) throw Error(VSIE_E_ARG, "ACA record size mismatch");
+      H.aca_k = k;
+      H.aca_U.resize((size_t)H.mn * k);
+      H.aca_V.resize((size_t)H.mf * k);
+      std::memcpy(H.aca_U.data(), c + sizeof(int), sizeof(cxd) * H.aca_U.size());
+      std::memcpy(H.aca_V.data(), c + sizeof(int) + sizeof(cxd) * H.aca_U.size(), sizeof(cxd) * H.aca_V.size());
+      upload_aca(H);
+    } else {
+      throw Error(VSIE_E_ARG, "unsupported import kind");
+    }
+  });
+}
+
+int vsie_profile(vsie_handle* hd, int enable) {
+  if (!hd) return fail(VSIE_E_ARG, "null handle");
+  Handle& H = hd->H;
+  return guarded([&]() {
+    if (enable && !H.ev[0])
+      for (auto& e : H.ev) VSIE_HIP(hipEventCreate(&e));
+    H.prof = enable != 0;
+    for (int s = 0; s < Handle::NSTAGE; ++s) {
+      H.prof_ms[s] = 0;
+      H.prof_calls[s] = 0;
+    }
+  });
+}
+
+int vsie_profile_read(const vsie_handle* hd, int max_stages, const char** names, double* total_ms, int64_t* calls,
+                      int* n_stages) {
+  if (!hd || !n_stages) return fail(VSIE_E_ARG, "null argument");
+  const Handle& H = hd->H;
+  *n_stages = Handle::NSTAGE;
+  for (int s = 0; s < Handle::NSTAGE && s < max_stages; ++s) {
+    if (names) names[s] = kStageNames[s];
+    if (total_ms) total_ms[s] = H.prof_ms[s];
+    if (calls) calls[s] = H.prof_calls[s];
+  }
+  return VSIE_OK;
+}
+
+void vsie_destroy(vsie_handle* hd) { delete hd; }
+
+const char* vsie_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Internal state of a vsie_handle and host-side setup helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/vsie.h"
+#include "vsie_math.h"
+
+namespace vsie {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define VSIE_HIP(call)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::vsie::Error(VSIE_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+// RWG functions of one domain (all meshes of that domain concatenated, input order).
+struct Rwg {
+  std::vector<double> verts;   // 3 * nv
+  std::vector<int> tris;       // 3 * nt
+  std::vector<double> area;    // nt
+  std::vector<int> ea, eb;     // edge vertices, a < b
+  std::vector<int> tp, tm;     // T+, T-
+  std::vector<int> fp, fm;     // free vertices
+  std::vector<int> flp, flm;   // local index of the free vertex in T+ / T-
+  std::vector<double> len;
+  int m = 0;
+  V3 vert(int i) const { return {verts[3 * i], verts[3 * i + 1], verts[3 * i + 2]}; }
+};
+
+// Flattened description of an RWG set for device kernels.
+struct RwgDev {
+  const double* verts;   // 3 nv
+  const int* tris;       // 3 nt
+  const double* area;    // nt
+  const int* tpm;        // [m][2] T+, T-
+  const int* flpm;       // [m][2] local index (0..2) of the free vertex inside T+ / T-
+  const int* fpm;        // [m][2] free vertex ids
+  const double* len;     // m
+  int m;
+};
+
+struct PortEdge {
+  int domain;   // VSIE_NEAR / VSIE_FAR
+  int idx;      // RWG index within the domain
+  double sign;
+};
+
+template <typename R> struct OpData {
+  // volume convolution
+  cx<R>* spec = nullptr;       // [6][P3/2+1][P2/2+1][P1/2+1], scaled by h^3 / (P1 P2 P3)
+  cx<R>* dv_chi = nullptr;     // [n_v] h^3 / chi (0 in air)
+  cx<R>* tw[4] = {nullptr, nullptr, nullptr, nullptr};   // twiddles for P1, P2, P3 (index by axis)
+  // pFFT
+  R* W = nullptr;              // [m_n][3][125]
+  R* roww = nullptr;           // [nnz_grid][3]
+  cx<R>* pc_val = nullptr;     // precorrection values
+  // ACA
+  cx<R>* U = nullptr;          // [m_n][k]
+  cx<R>* V = nullptr;          // [m_f][k]
+  // TT cores per component
+  cx<R>* G[3][4] = {};
+  // dense far block
+  cx<R>* Zff = nullptr;        // [m_f][m_f]
+  // work buffers
+  cx<R>* gridA = nullptr;      // [3][ne3][ne2][ne1] (also the convolution output)
+  cx<R>* bufB = nullptr;       // [3][ne3][ne2][P1]
+  cx<R>* bufC = nullptr;       // [3][ne3][P2][P1]
+  cx<R>* tt_work = nullptr;    // TT intermediates
+  cx<R>* small_work = nullptr; // ACA / reductions
+};
+
+struct Handle {
+  // problem
+  int n[3];
+  double h, origin[3], freq, omega, k0;
+  int nv;
+  std::vector<cxd> chi;           // per voxel
+  std::vector<int> tissue;        // flat indices
+  Rwg far, near;
+  RwgDev dfar{}, dnear{};
+  int mf = 0, mn = 0;
+  int64_t N = 0;
+  std::vector<std::vector<PortEdge>> ports;
+  vsie_options opts;
+  // extended grid
+  int ne[3], ob[3], P[3];
+  int64_t Ne = 0;
+  // pFFT host data
+  std::vector<int> base;          // [m_n][3] relative to the body grid
+  std::vector<double> Wh;         // [m_n][3][125]
+  // grid CSR (by extended-grid voxel)
+  int* d_vox2row = nullptr;
+  int* d_rowptr = nullptr;
+  int* d_rowrwg = nullptr;
+  int n_gridrows = 0;
+  int64_t nnz_grid = 0;
+  int* d_base = nullptr;          // [m_n][3] in extended-grid coordinates
+  // precorrection CSR
+  int* d_pc_rowid = nullptr;      // global unknown index of each row
+  int* d_pc_rowptr = nullptr;
+  int* d_pc_col = nullptr;        // global unknown index
+  int n_pcrows = 0;
+  int64_t pc_nnz = 0;
+  // body mask
+  uint8_t* d_mask = nullptr;
+  // TT
+  int tt_r[3][3] = {};
+  double tt_err[3] = {0, 0, 0};
+  std::vector<cxd> tt_host[3][4];
+  // ACA
+  int aca_k = 0;
+  std::vector<cxd> aca_U, aca_V;
+  // generator octant (dimensionless), kept for export and near-field setup
+  cxd* d_oct = nullptr;           // [6][ne3][ne2][ne1]
+  OpData<double> d64;
+  OpData<float> d32;
+  bool have32 = false;
+  // GMRES workspace (lazily sized)
+  cxd* d_krylov = nullptr;
+  int64_t krylov_cols = 0;
+  cxd* d_solve_work = nullptr;
+  double* d_red = nullptr;        // reduction scratch
+  int64_t device_bytes = 0;
+  double setup_seconds = 0;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocations;
+  // per-stage timing of the matrix-vector product (HIP events on the caller's stream)
+  static constexpr int NSTAGE = 12;
+  bool prof = false;
+  hipEvent_t ev[2 * NSTAGE] = {};
+  bool ev_used[NSTAGE] = {};
+  double prof_ms[NSTAGE] = {};
+  int64_t prof_calls[NSTAGE] = {};
+
+  template <typename T> T* dalloc(int64_t count) {
+    if (count <= 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) throw Error(VSIE_E_NOMEM, "hipMalloc of " + std::to_string(sizeof(T) * count) + " bytes failed");
+    allocations.push_back(p);
+    device_bytes += sizeof(T) * count;
+    return (T*)p;
+  }
+  ~Handle() {
+    for (void* p : allocations) (void)hipFree(p);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+// host setup (setup_host.cpp)
+void build_rwg(const vsie_problem* p, int domain, Rwg& out,
+               std::vector<std::pair<int, std::vector<PortEdge>>>& ports);
+void stencil_setup(Handle& H);
+void fill_gauss_table(GaussTab* t);
+void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int64_t)>& fn);
+
+// dense host linear algebra (setup_linalg.cpp)
+void qr_mgs2(std::vector<cxd>& A, int m, int n, std::vector<cxd>& R);   // A (m x n, row-major) -> Q
+std::vector<int> maxvol(const std::vector<cxd>& Q, int m, int r);        // r row indices
+bool lu_solve(std::vector<cxd> A, int n, std::vector<cxd>& B, int nrhs);  // A X = B, B (n x nrhs)
+
+// TT-cross and ACA (setup_compress.cpp)
+struct EntryFn {
+  // evaluate entries of a 4D tensor (i1,i2,i3,i4) for a list of index tuples
+  virtual void eval(const std::vector<int>& idx4, std::vector<cxd>& out) = 0;
+  virtual ~EntryFn() {}
+};
+void tt_cross(EntryFn& f, const int n[4], double tol, int rmax, uint64_t seed, std::vector<cxd> cores[4],
+              int ranks[3], double* err_est);
+
+}  // namespace vsie

@@ -1,0 +1,311 @@
+"""ctypes binding of libvsie.so (the C ABI declared in include/vsie.h).
+
+Argument marshalling only: every step of setup, matrix-vector product and solve runs in the
+library. torch supplies device memory and the HIP stream. If the library is not built the
+binding raises; there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvsie.so")
+
+VSIE_OK, VSIE_E_NOCONV = 0, 7
+VSIE_NEAR, VSIE_FAR = 0, 1
+VSIE_C128, VSIE_C64 = 0, 1
+VSIE_GMRES64, VSIE_IR_MIXED = 0, 1
+X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
+
+EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_sizes", "vsie_rhs",
+            "vsie_matvec", "vsie_solve", "vsie_port_current", "vsie_export", "vsie_import", "vsie_profile",
+            "vsie_profile_read", "vsie_destroy", "vsie_last_error"]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("verts", C.POINTER(C.c_double)), ("n_verts", C.c_int32), ("tris", C.POINTER(C.c_int32)),
+                ("n_tris", C.c_int32), ("domain", C.c_int32), ("port_edges", C.POINTER(C.c_int32)),
+                ("port_id", C.POINTER(C.c_int32)), ("n_port_edges", C.c_int32)]
+
+
+class ProblemC(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double), ("origin", C.c_double * 3), ("freq_hz", C.c_double),
+                ("eps_r", C.POINTER(C.c_double)), ("sigma", C.POINTER(C.c_double)), ("n_meshes", C.c_int32),
+                ("meshes", C.POINTER(Mesh))]
+
+
+class Options(C.Structure):
+    _fields_ = [("tt_tol", C.c_double), ("tt_rank_max", C.c_int32), ("aca_tol", C.c_double),
+                ("aca_rank_max", C.c_int32), ("precorrect_dist", C.c_int32), ("build_c64", C.c_int32),
+                ("build_far", C.c_int32), ("seed", C.c_uint64)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("n_total", C.c_int64), ("m_far", C.c_int32), ("m_near", C.c_int32), ("n", C.c_int32 * 3),
+                ("n_ext", C.c_int32 * 3), ("fft", C.c_int32 * 3), ("n_ports", C.c_int32), ("n_tissue", C.c_int32),
+                ("tt_rank", (C.c_int32 * 3) * 3), ("tt_err_est", C.c_double * 3), ("aca_rank", C.c_int32),
+                ("precorr_nnz", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("method", C.c_int32),
+                ("inner_tol", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("refinements", C.c_int32),
+                ("rel_residual", C.c_double), ("block_residual", C.c_double * 3), ("seconds", C.c_double)]
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libvsie.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libvsie.so is not built: run paper_2206_12409_amd.build.build()")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.vsie_default_options.argtypes = [C.POINTER(Options)]
+    lib.vsie_default_solve_opts.argtypes = [C.POINTER(SolveOpts)]
+    lib.vsie_create.argtypes = [C.POINTER(ProblemC), C.POINTER(Options), vp, C.POINTER(vp)]
+    lib.vsie_sizes.argtypes = [vp, C.POINTER(Sizes)]
+    lib.vsie_rhs.argtypes = [vp, C.c_int, C.c_int, vp, vp]
+    lib.vsie_matvec.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
+    lib.vsie_solve.argtypes = [vp, C.POINTER(SolveOpts), C.c_int, vp, vp, C.POINTER(SolveStats), vp]
+    lib.vsie_port_current.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.vsie_export.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(C.c_size_t)]
+    lib.vsie_import.argtypes = [vp, C.c_int, C.c_int, vp, C.c_size_t]
+    lib.vsie_profile.argtypes = [vp, C.c_int]
+    lib.vsie_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int)]
+    lib.vsie_destroy.argtypes = [vp]
+    lib.vsie_destroy.restype = None
+    lib.vsie_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class VsieError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("vsie error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != VSIE_OK:
+        raise VsieError(rc, load().vsie_last_error().decode())
+
+
+def default_options(**kw):
+    o = Options()
+    load().vsie_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    """hipStream_t of a torch stream (default: the current stream); 0 selects the null stream."""
+    if isinstance(stream, int) and stream == 0:
+        return C.c_void_p(None)
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Operator:
+    """Hybrid VSIE operator of one problem (vsie_synth.Problem-like: grid, meshes, freq_hz)."""
+
+    def __init__(self, problem, options=None, stream=None, **opt_kw):
+        lib = load()
+        g = problem.grid
+        self._keep = []
+        eps = np.ascontiguousarray(g.eps_r, np.float64).ravel()
+        sig = np.ascontiguousarray(g.sigma, np.float64).ravel()
+        self._keep += [eps, sig]
+        meshes = (Mesh * max(1, len(problem.meshes)))()
+        for i, m in enumerate(problem.meshes):
+            v = np.ascontiguousarray(m.verts, np.float64)
+            t = np.ascontiguousarray(m.tris, np.int32)
+            pe = np.ascontiguousarray(m.port_edges, np.int32).reshape(-1, 2)
+            pid = np.ascontiguousarray(m.port_id, np.int32)
+            self._keep += [v, t, pe, pid]
+            meshes[i].verts = v.ctypes.data_as(C.POINTER(C.c_double))
+            meshes[i].n_verts = len(v)
+            meshes[i].tris = t.ctypes.data_as(C.POINTER(C.c_int32))
+            meshes[i].n_tris = len(t)
+            meshes[i].domain = int(m.domain)
+            meshes[i].port_edges = pe.ctypes.data_as(C.POINTER(C.c_int32))
+            meshes[i].port_id = pid.ctypes.data_as(C.POINTER(C.c_int32))
+            meshes[i].n_port_edges = len(pid)
+        p = ProblemC()
+        p.n = (C.c_int32 * 3)(*[int(x) for x in g.n])
+        p.h = float(g.h)
+        p.origin = (C.c_double * 3)(*[float(x) for x in g.origin])
+        p.freq_hz = float(problem.freq_hz)
+        p.eps_r = eps.ctypes.data_as(C.POINTER(C.c_double))
+        p.sigma = sig.ctypes.data_as(C.POINTER(C.c_double))
+        p.n_meshes = len(problem.meshes)
+        p.meshes = meshes
+        opts = options if options is not None else default_options(**opt_kw)
+        h = C.c_void_p()
+        _check(lib.vsie_create(C.byref(p), C.byref(opts), _stream_ptr(stream), C.byref(h)))
+        self._h = h
+        self._keep = None
+        s = Sizes()
+        _check(lib.vsie_sizes(self._h, C.byref(s)))
+        self.sizes = s
+        self.N = int(s.n_total)
+        self.m_far, self.m_near = int(s.m_far), int(s.m_near)
+        self.n_ports = int(s.n_ports)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().vsie_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        s = self.sizes
+        return dict(N=self.N, m_far=self.m_far, m_near=self.m_near, n_ext=tuple(s.n_ext), fft=tuple(s.fft),
+                    n_ports=self.n_ports, n_tissue=int(s.n_tissue),
+                    tt_rank=[tuple(s.tt_rank[c]) for c in range(3)], tt_err_est=list(s.tt_err_est),
+                    aca_rank=int(s.aca_rank), precorr_nnz=int(s.precorr_nnz), device_bytes=int(s.device_bytes),
+                    setup_seconds=float(s.setup_seconds))
+
+    @staticmethod
+    def _dtype_code(t):
+        import torch
+        if t.dtype == torch.complex128:
+            return VSIE_C128
+        if t.dtype == torch.complex64:
+            return VSIE_C64
+        raise TypeError("complex128 or complex64 tensors only")
+
+    def matvec(self, x, out=None, stream=None):
+        import torch
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous device tensor")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        if x.shape[-1] != self.N:
+            raise ValueError("x has length %d, operator size is %d" % (x.shape[-1], self.N))
+        y = torch.empty_like(x) if out is None else out
+        _check(load().vsie_matvec(self._h, self._dtype_code(x), nrhs, C.c_void_p(x.data_ptr()),
+                                  C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
+        return y
+
+    def rhs(self, port, dtype=None, stream=None):
+        import torch
+        dt = torch.complex128 if dtype is None else dtype
+        b = torch.empty(self.N, dtype=dt, device="cuda")
+        _check(load().vsie_rhs(self._h, int(port), self._dtype_code(b), C.c_void_p(b.data_ptr()), _stream_ptr(stream)))
+        return b
+
+    def solve(self, b, tol=1e-6, restart=50, max_iter=5000, method=VSIE_GMRES64, inner_tol=1e-3, stream=None,
+              allow_noconv=False):
+        import torch
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        if b.dtype != torch.complex128 or not b.is_cuda:
+            raise ValueError("b must be a complex128 device tensor")
+        x = torch.empty_like(b)
+        o = SolveOpts(tol, restart, max_iter, method, inner_tol)
+        st = (SolveStats * nrhs)()
+        rc = load().vsie_solve(self._h, C.byref(o), nrhs, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), st,
+                               _stream_ptr(stream))
+        if rc != VSIE_OK and not (allow_noconv and rc == VSIE_E_NOCONV):
+            _check(rc)
+        stats = [dict(iterations=s.iterations, restarts=s.restarts, refinements=s.refinements,
+                      rel_residual=s.rel_residual, block_residual=list(s.block_residual), seconds=s.seconds,
+                      converged=rc == VSIE_OK) for s in st]
+        return x, stats
+
+    def profile(self, enable=True):
+        """Enable (and reset) or disable per-stage event timing of matvec."""
+        _check(load().vsie_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{stage: (total_ms, calls)} for stages that ran."""
+        n = 16
+        names = (C.c_char_p * n)()
+        ms = (C.c_double * n)()
+        calls = (C.c_int64 * n)()
+        ns = C.c_int(0)
+        _check(load().vsie_profile_read(self._h, n, names, ms, calls, C.byref(ns)))
+        return {names[i].decode(): (ms[i], int(calls[i])) for i in range(ns.value) if calls[i] > 0}
+
+    def port_current(self, port, x_host):
+        x = np.ascontiguousarray(x_host, np.complex128)
+        out = (C.c_double * 2)()
+        _check(load().vsie_port_current(self._h, int(port), x.ctypes.data_as(C.POINTER(C.c_double)), out))
+        return complex(out[0], out[1])
+
+    def _export(self, kind, index=0):
+        n = C.c_size_t(0)
+        _check(load().vsie_export(self._h, kind, index, None, C.byref(n)))
+        buf = (C.c_ubyte * n.value)()
+        _check(load().vsie_export(self._h, kind, index, buf, C.byref(n)))
+        return bytes(buf)
+
+    def export_tt(self, chi):
+        raw = self._export(X_TT_CORES, chi)
+        r = np.frombuffer(raw[:12], np.int32)
+        data = np.frombuffer(raw[12:], np.complex128)
+        n1, n2, n3 = (int(v) for v in self.sizes.n)
+        shapes = [(n1, r[0]), (r[0], n2, r[1]), (r[1], n3, r[2]), (r[2], self.m_far)]
+        out, off = [], 0
+        for s in shapes:
+            k = int(np.prod(s))
+            out.append(data[off:off + k].reshape(s).copy())
+            off += k
+        return out
+
+    def export_aca(self):
+        raw = self._export(X_ACA)
+        k = int(np.frombuffer(raw[:4], np.int32)[0])
+        data = np.frombuffer(raw[4:], np.complex128)
+        U = data[:self.m_near * k].reshape(self.m_near, k).copy()
+        V = data[self.m_near * k:].reshape(self.m_far, k).copy()
+        return U, V
+
+    def export_stencil(self):
+        raw = self._export(X_STENCIL)
+        base = np.frombuffer(raw[:12 * self.m_near], np.int32).reshape(self.m_near, 3).copy()
+        W = np.frombuffer(raw[12 * self.m_near:], np.float64).reshape(self.m_near, 3, 5, 5, 5).copy()
+        return base, W
+
+    def export_ext_grid(self):
+        raw = np.frombuffer(self._export(X_EXT_GRID), np.int32)
+        return tuple(raw[:3]), tuple(raw[3:6]), tuple(raw[6:9])
+
+    def export_generator(self):
+        ne, _, _ = self.export_ext_grid()
+        raw = np.frombuffer(self._export(X_GENERATOR), np.complex128)
+        return raw.reshape(6, ne[2], ne[1], ne[0]).copy()
+
+    def import_tt(self, chi, cores):
+        G1, G2, G3, G4 = [np.ascontiguousarray(c, np.complex128) for c in cores]
+        r = np.array([G1.shape[1], G2.shape[2], G3.shape[2]], np.int32)
+        blob = r.tobytes() + G1.tobytes() + G2.tobytes() + G3.tobytes() + G4.tobytes()
+        buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
+        _check(load().vsie_import(self._h, X_TT_CORES, int(chi), buf, len(blob)))
+        s = Sizes()
+        _check(load().vsie_sizes(self._h, C.byref(s)))
+        self.sizes = s
+
+    def import_aca(self, U, V):
+        U = np.ascontiguousarray(U, np.complex128)
+        V = np.ascontiguousarray(V, np.complex128)
+        k = np.array([U.shape[1]], np.int32)
+        blob = k.tobytes() + U.tobytes() + V.tobytes()
+        buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
+        _check(load().vsie_import(self._h, X_ACA, 0, buf, len(blob)))

@@ -1,0 +1,80 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point declared in
+include/vsie.h, and rejects invalid problems before any device work (host-side validation)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import vsie_synth as synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vsie.h")).read()
+    return sorted(set(re.findall(r"\b(vsie_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def vs():
+    from paper_2206_12409_amd import build, vsie
+    if not os.path.exists(vsie.LIB_PATH):
+        build.build()
+    vsie.load()
+    return vsie
+
+
+def test_every_declared_symbol_is_exported(vs):
+    lib = vs.load()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(vs.EXPORTED) == names
+
+
+def test_default_options(vs):
+    o = vs.default_options()
+    assert o.tt_tol == 1e-3 and o.aca_tol == 1e-3 and o.tt_rank_max == 30 and o.precorrect_dist == 2
+
+
+def _expect(vs, problem, code):
+    with pytest.raises(vs.VsieError) as e:
+        vs.Operator(problem, stream=0)
+    assert e.value.code == code, str(e.value)
+
+
+def test_rejects_non_finite_material(vs):
+    p = synth.small_case()
+    p.grid.eps_r[0, 0, 0] = np.nan
+    _expect(vs, p, 1)
+
+
+def test_rejects_inconsistent_mesh(vs):
+    p = synth.small_case()
+    t = p.meshes[1].tris.copy()
+    t[0] = t[0][::-1]
+    p.meshes[1].tris = t
+    _expect(vs, p, 2)
+
+
+def test_rejects_bad_port_edge(vs):
+    p = synth.small_case()
+    p.meshes[1].port_edges = np.array([[0, 999 % len(p.meshes[1].verts)]], np.int32)
+    p.meshes[1].port_id = np.array([0], np.int32)
+    _expect(vs, p, 2)
+
+
+def test_rejects_rwg_pair_larger_than_stencil(vs):
+    """Sec. IV-B: every near RWG pair must fit the 5x5x5 expansion block."""
+    p = synth.small_case()
+    g = p.grid
+    p.grid = synth.Grid(g.n, 1e-3, g.origin * 0.2, g.eps_r, g.sigma, g.labels)
+    _expect(vs, p, 3)
+
+
+def test_rejects_bad_sizes(vs):
+    p = synth.small_case()
+    p.grid = synth.Grid(p.grid.n, -1.0, p.grid.origin, p.grid.eps_r, p.grid.sigma, p.grid.labels)
+    _expect(vs, p, 1)

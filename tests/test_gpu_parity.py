@@ -1,0 +1,196 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on the same seeded
+inputs. FP64 bar: 1e-10 relative for the matrix-vector product (paper eq. (15))."""
+import numpy as np
+import pytest
+
+import vsie_synth as synth
+from oracle import system, tt, voxel
+from tests.gpu_common import far_shield_case, oracle_same, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2206_12409_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def small(lib):
+    p = synth.small_case()
+    op = lib.Operator(p)
+    d, S_direct, S_same, parts = oracle_same(p, op)
+    return p, op, d, S_direct, S_same, parts
+
+
+def test_generator_matches_oracle(small):
+    p, op, d, *_ = small
+    T = op.export_generator()                        # [6][ne3][ne2][ne1]
+    ne = T.shape[1:][::-1]
+    ref = voxel.T_generator_octant(ne, d.k * d.h)    # [ne3][ne2][ne1][6]
+    ref = np.moveaxis(ref, -1, 0)
+    assert np.abs(T - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_stencils_match_oracle(small):
+    from oracle import pfft
+    p, op, d, *_ = small
+    base, W = op.export_stencil()
+    bo = pfft.stencil_bases(d.near, d.origin, d.h)
+    Wo = pfft.stencil_weights(d.near, bo, d.origin, d.h)
+    assert np.array_equal(base, bo)
+    assert np.abs(W - Wo).max() < 1e-13 * np.abs(Wo).max()
+
+
+def _blocks(n, d):
+    mf, mn = d.m_f, d.m_n
+    return {"f": slice(0, mf), "n": slice(mf, mf + mn), "b": slice(mf + mn, n)}
+
+
+@pytest.mark.parametrize("src", ["f", "n", "b"])
+def test_matvec_blocks_fp64(small, src):
+    """Each block column of eq. (15) separately: far (dense + ACA + TT forward), near (pFFT +
+    precorrection + ACA transpose), body (volume convolution + pFFT + TT transpose)."""
+    p, op, d, _, S_same, _ = small
+    rng = np.random.default_rng(11)
+    x = np.zeros(op.N, np.complex128)
+    sl = _blocks(op.N, d)[src]
+    x[sl] = rng.standard_normal(sl.stop - sl.start) + 1j * rng.standard_normal(sl.stop - sl.start)
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    ref = S_same.matvec(x)
+    for dst, s2 in _blocks(op.N, d).items():
+        if np.linalg.norm(ref[s2]) == 0:
+            continue
+        assert rel(y[s2], ref[s2]) < 1e-10, (src, dst, rel(y[s2], ref[s2]))
+
+
+def test_full_matvec_fp64_and_reciprocity(small):
+    p, op, d, _, S_same, _ = small
+    rng = np.random.default_rng(1234)
+    x = synth.complex_normal(op.N, 1234)
+    u = synth.complex_normal(op.N, 99)
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    assert rel(y, S_same.matvec(x)) < 1e-10
+    yu = op.matvec(to_dev(u)).cpu().numpy()
+    # bilinear reciprocity u^T (Z x) = x^T (Z u)
+    assert abs(u @ y - x @ yu) < 1e-12 * np.linalg.norm(u) * np.linalg.norm(y)
+    # bitwise repeatable
+    y2 = op.matvec(to_dev(x)).cpu().numpy()
+    assert np.array_equal(y, y2)
+    del rng
+
+
+def test_batched_columns_match(small):
+    p, op, d, _, S_same, _ = small
+    X = np.stack([synth.complex_normal(op.N, s) for s in (1, 2, 3)])
+    Y = op.matvec(to_dev(X)).cpu().numpy()
+    for c in range(3):
+        assert rel(Y[c], S_same.matvec(X[c])) < 1e-10
+
+
+def test_complex64_matvec_error(small):
+    """complex64 storage and FP32 arithmetic: error against the FP64 oracle stated and bounded."""
+    p, op, d, _, S_same, _ = small
+    x = synth.complex_normal(op.N, 5)
+    y = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    e = rel(y, S_same.matvec(x))
+    print("complex64 matvec relative error vs FP64 oracle: %.3e" % e)
+    assert e < 1e-5
+
+
+def test_port_rhs_matches_oracle(small):
+    p, op, d, *_ = small
+    for port in range(op.n_ports):
+        b = op.rhs(port).cpu().numpy()
+        assert rel(b, system.port_rhs(d, port)) < 1e-15
+
+
+def test_gmres_solution_matches_oracle(small):
+    p, op, d, _, S_same, _ = small
+    b = system.port_rhs(d, 0)
+    x, st = op.solve(to_dev(b), tol=1e-8, restart=600, max_iter=3000)
+    x = x.cpu().numpy()
+    assert st[0]["converged"] and st[0]["rel_residual"] <= 1e-8
+    xo = S_same.solve(b)
+    assert rel(x, xo) < 1e-5
+    I = op.port_current(0, x)
+    assert abs(I - system.port_current(d, 0, xo)) < 1e-5 * abs(system.port_current(d, 0, xo))
+
+
+def test_mixed_precision_refinement(small):
+    """complex64 inner GMRES + FP64 residual reaches the FP64 relative residual 1e-6. Two
+    solutions with residual <= 1e-6 may differ by up to cond(Z) * 2e-6; the bound below uses the
+    condition number of the densified operator."""
+    p, op, d, _, S_same, _ = small
+    b = system.port_rhs(d, 0)
+    x64, s64 = op.solve(to_dev(b), tol=1e-6, restart=600, max_iter=4000)
+    x, st = op.solve(to_dev(b), tol=1e-6, restart=600, max_iter=4000, method=1, inner_tol=1e-3)
+    x = x.cpu().numpy()
+    assert st[0]["converged"] and st[0]["rel_residual"] <= 1e-6
+    e = rel(x, x64.cpu().numpy())
+    xo = S_same.solve(b)
+    e_oracle = rel(x, xo)
+    cond = np.linalg.cond(S_same.Z)
+    print("mixed-precision IR: %d refinements, %d inner iterations (FP64 GMRES: %d); error vs FP64 solve "
+          "%.2e, vs oracle LU %.2e, cond %.1e" % (st[0]["refinements"], st[0]["iterations"], s64[0]["iterations"],
+                                                  e, e_oracle, cond))
+    assert e <= cond * 2e-6 and e_oracle <= cond * 1e-6
+
+
+def test_body_only_volume_operator():
+    """Volume convolution alone (no conductors): FFT Toeplitz product equals the dense Galerkin
+    matrix (exact identity on a uniform grid), ragged grid 11 x 9 x 13."""
+    import paper_2206_12409_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    g = synth.sphere_phantom((11, 9, 13), 5e-3, 21e-3, 52.0, 0.55)
+    p = synth.Problem(g, [], synth.problems.LARMOR_7T_HZ, "body")
+    op = pkg.Operator(p)
+    d = system.discretize(p)
+    S, _ = system.assemble_direct(d)
+    x = synth.complex_normal(op.N, 7)
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    assert rel(y, S.matvec(x)) < 1e-10
+    # plane-wave solve against the dense direct solution
+    b = system.plane_wave_rhs(d)
+    xs, st = op.solve(to_dev(b), tol=1e-10, restart=100, max_iter=2000)
+    assert rel(xs.cpu().numpy(), S.solve(b)) < 1e-8
+
+
+def test_tt_cross_accuracy_against_brute_force():
+    """Product TT-cross cores (eq. (14)) against the oracle's brute-force far coupling tensor."""
+    import paper_2206_12409_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    p = far_shield_case()
+    op = pkg.Operator(p)
+    d = system.discretize(p)
+    info = op.info()
+    for a in range(3):
+        A = system.far_coupling_tensor(d, a)
+        G = op.export_tt(a)
+        err = np.linalg.norm(tt.tt_full(G) - A) / np.linalg.norm(A)
+        ref_ranks = [c.shape[-1] for c in tt.tt_svd(A, 1e-3)[:3]]
+        print("component %d: TT-cross ranks %s (TT-SVD at 1e-3: %s), error %.2e, estimate %.2e"
+              % (a, info["tt_rank"][a], ref_ranks, err, info["tt_err_est"][a]))
+        assert err < 3e-3
+
+
+def test_aca_accuracy_against_dense_block():
+    import paper_2206_12409_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    p = far_shield_case()
+    op = pkg.Operator(p)
+    d = system.discretize(p)
+    from oracle import surface
+    Z = surface.zcc_block(d.near, d.far, d.k)
+    U, V = op.export_aca()
+    err = np.linalg.norm(U @ V.conj().T - Z) / np.linalg.norm(Z)
+    print("ACA rank %d, relative error %.2e" % (U.shape[1], err))
+    assert err < 3e-3
