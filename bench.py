@@ -43,7 +43,11 @@ def stage_bytes(info, s):
         "body_out": c * (2 * 3 * nv + 3 * nv + nv),
         "pfft_gather": mn * 375 * (8 + c),
         "gemv_far": c * (mf * mf + 2 * mf),
+        "precorrect": info["precorr_nnz"] * (c + 4 + c),
+        "aca": 2 * c * (mf + mn) * info["aca_rank"],
     }
+    r = info["tt_rank"]
+    b["tt"] = sum(c * (2 * r[a][2] * mf + 4 * nv + 2 * r[a][0] * n2 * n3) for a in range(3))
     return b.get(s)
 
 
@@ -134,6 +138,7 @@ def main():
     stages = op.profile_read()
     op.profile(False)
     per_stage = {k: v[0] / v[1] for k, v in stages.items()}
+    print("stage ms: %s" % json.dumps({k: round(v, 4) for k, v in per_stage.items()}), file=sys.stderr, flush=True)
     dom = max(per_stage, key=per_stage.get)
     rl = {}
     for k, ms in per_stage.items():

@@ -85,9 +85,9 @@ typedef struct {
 
 typedef struct {
   double tt_tol;              /* TT-cross relative accuracy, Sec. IV-C: 1e-3 */
-  int32_t tt_rank_max;        /* rank cap per TT unfolding */
+  int32_t tt_rank_max;        /* rank cap per TT unfolding, 1..128 */
   double aca_tol;             /* ACA relative accuracy, Sec. IV-C: 1e-3 */
-  int32_t aca_rank_max;
+  int32_t aca_rank_max;       /* 1..256 */
   int32_t precorrect_dist;    /* Chebyshev distance (voxels) of precorrected pairs, default 2 */
   int32_t build_c64;          /* also prepare complex64 operator data (mixed precision) */
   int32_t build_far;          /* compute TT-cross and ACA (0: zero far coupling until imported) */
@@ -129,7 +129,7 @@ typedef struct {
   double seconds;
 } vsie_solve_stats;
 
-/* Fill defaults: tt_tol 1e-3, tt_rank_max 30, aca_tol 1e-3, aca_rank_max 64,
+/* Fill defaults: tt_tol 1e-3, tt_rank_max 64, aca_tol 1e-3, aca_rank_max 128,
  * precorrect_dist 2, build_c64 1, build_far 1, seed 1. */
 int vsie_default_options(vsie_options* opts);
 int vsie_default_solve_opts(vsie_solve_opts* opts);
@@ -170,7 +170,8 @@ int vsie_port_current(const struct vsie_handle* h, int port, const double* x_hos
  * component (0..2) where relevant. Call with host == NULL to query the byte count.
  *   VSIE_X_TT_CORES    int32 r1,r2,r3 then complex128 G1[n1][r1], G2[r1][n2][r2],
  *                      G3[r2][n3][r3], G4[r3][m_f]
- *   VSIE_X_ACA         int32 k then complex128 U[m_n][k], V[m_f][k]  (Z_nf ~ U V^*)
+ *   VSIE_X_ACA         int32 k then complex128 U[m_n][k], V[m_f][k]  (Z_nf ~ U V^*), k <= 256
+ *   (TT ranks accepted by vsie_import: 1..128)
  *   VSIE_X_STENCIL     int32 base[m_n][3] (relative to the body grid) then double W[m_n][3][125]
  *   VSIE_X_GENERATOR   complex128 T[6][ne3][ne2][ne1] dimensionless generator on the octant
  *   VSIE_X_EXT_GRID    int32 ne[3], body_offset[3], fft[3] */

@@ -16,6 +16,9 @@ void launch_generator(hipStream_t st, const GaussTab* gt, const int ne[3], doubl
 void launch_embed_circulant(hipStream_t st, const cxd* oct, const int ne[3], const int P[3], cxd* full);
 template <typename R> void launch_extract_octant(hipStream_t st, const cxd* full, const int P[3], double scale, cx<R>* spec);
 void launch_zcc_dense(hipStream_t st, const RwgDev& A, const RwgDev& B, double k, int64_t row0, int64_t nrows, cxd* out);
+constexpr int SYM_TB = 128;
+void launch_zcc_packed(hipStream_t st, const RwgDev& A, double k, const int* tiles, int64_t tile0, int64_t ntiles,
+                       cxd* out);
 void launch_zcc_pairs(hipStream_t st, const RwgDev& A, const RwgDev& B, const int* pi, const int* pj, int64_t np,
                       double k, cxd* out);
 void launch_pfft_wtw(hipStream_t st, const double* W, const int* base, const cxd* oct, const int ne[3], const int* pm,
@@ -45,16 +48,29 @@ template <typename R> void launch_pfft_gather(hipStream_t st, const R* W, const 
                                               int mn, const GridDims& g);
 template <typename R> void launch_csr_add(hipStream_t st, const int* rowid, const int* rowptr, const int* col,
                                           const cx<R>* val, const cx<R>* x, cx<R>* y, int nrows);
-template <typename R> void launch_tall_t(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* x, int64_t M, int K,
-                                         cx<R>* part, int nblk, cx<R>* out);
-template <typename R> void launch_tall_n_add(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* t, int64_t M,
-                                             int K, cx<R>* y);
+// low-rank factors stored rank-major (A[l][i], K <= 256 ranks of length M)
+template <typename R> void launch_lr_t(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* x, int64_t M, int K,
+                                       cx<R>* part, int max_chunks, cx<R>* out);
+template <typename R> void launch_lr_n_add(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* t, int64_t M,
+                                           int K, cx<R>* y);
 template <typename R> void launch_gemv_rows(hipStream_t st, const cx<R>* A, const cx<R>* x, int64_t nrow, int64_t ncol,
                                             cx<R>* out, int accumulate);
-template <typename R> void launch_tt_forward(hipStream_t st, cx<R>* const G[4], const int r[3], const int n[3], int mf,
-                                             const cx<R>* xf, const uint8_t* mask, cx<R>* yb, cx<R>* work);
-template <typename R> void launch_tt_transpose(hipStream_t st, cx<R>* const G[4], const int r[3], const int n[3], int mf,
-                                               const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* work);
+constexpr int TT_RMAX = 128;
+template <typename R> struct TTDesc {
+  const cx<R>* G1[3];
+  const cx<R>* G2[3];
+  const cx<R>* G3[3];
+  const cx<R>* G4[3];
+  int r1[3], r2[3], r3[3];
+};
+// forward and transpose far coupling of all three components: y_b += mask Zt x_f,
+// y_f += sum_c Zt_c^T (mask x_b)
+template <typename R> void launch_tt(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
+                                     const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* yb, cx<R>* work);
+int64_t tt_work_elems(const int n[3], int mf);
+// y = Z x for the symmetric far block stored as upper-triangle tiles (part: 2 SYM_TB per tile)
+template <typename R> void launch_symv(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x, int m,
+                                       cx<R>* part, cx<R>* y);
 template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, const double* vre, const double* vim,
                                              int ne, cx<R>* b);
 

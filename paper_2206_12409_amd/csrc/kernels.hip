@@ -117,6 +117,22 @@ __global__ void k_zcc_dense(RwgDev A, RwgDev B, double k, int64_t row0, int64_t 
   out[id] = rwg_pair_entry(A, m, B, n, k);
 }
 
+// upper-triangle tiles (I <= J) of the symmetric far block, each tile row-major SYM_TB x SYM_TB,
+// zero-padded beyond m; diagonal tiles are stored in full
+__global__ void k_zcc_packed(RwgDev A, double k, const int* __restrict__ tiles, int64_t tile0, int64_t ntiles,
+                             cxd* __restrict__ out) {
+  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)SYM_TB * SYM_TB;
+  if (id >= ntiles * per) return;
+  const int64_t t = tile0 + id / per;
+  const int e = (int)(id % per);
+  const int m = tiles[2 * t] * SYM_TB + e / SYM_TB;
+  const int n = tiles[2 * t + 1] * SYM_TB + e % SYM_TB;
+  cxd v = {0, 0};
+  if (m < A.m && n < A.m) v = rwg_pair_entry(A, m, A, n, k);
+  out[id] = v;
+}
+
 __global__ void k_zcc_pairs(RwgDev A, RwgDev B, const int* __restrict__ pi, const int* __restrict__ pj, int64_t np,
                             double k, cxd* __restrict__ out) {
   int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -354,88 +370,50 @@ __device__ inline void lds_fft(cx<R>* sm, const cx<R>* __restrict__ tw, int tid)
   }
 }
 
-// Rows contiguous along the FFT axis; NP rows per block. Inputs beyond n_in are zero; outputs
-// beyond n_out are not stored (pruned transforms).
-template <typename R, int L, bool FWD>
-__global__ __launch_bounds__(256) void k_fft_rows(const cx<R>* __restrict__ in, cx<R>* __restrict__ out, int n_in,
-                                                  int n_out, int64_t in_row, int64_t out_row, int64_t nrows,
-                                                  const cx<R>* __restrict__ tw) {
-  constexpr int NP = (1024 / L) > 0 ? (1024 / L) : 1;
-  __shared__ cx<R> sm[NP * (L + 1)];
-  const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * NP;
-  for (int e = tid; e < NP * L; e += 256) {
-    int p = e / L, i = e % L;
-    int64_t row = row0 + p;
-    cx<R> v = {0, 0};
-    if (row < nrows && i < n_in) v = in[row * in_row + i];
-    sm[p * (L + 1) + i] = v;
-  }
-  __syncthreads();
-  lds_fft<R, L, NP, FWD>(sm, tw, tid);
-  for (int e = tid; e < NP * n_out; e += 256) {
-    int p = e / n_out, kq = e % n_out;
-    int64_t row = row0 + p;
-    if (row < nrows) out[row * out_row + kq] = sm[p * (L + 1) + kq];
-  }
-}
-
-// Pencils strided along the FFT axis, TP adjacent pencils (contiguous in memory) per block.
-template <typename R, int L, int TP, bool FWD>
-__global__ __launch_bounds__(256) void k_fft_strided(const cx<R>* __restrict__ in, cx<R>* __restrict__ out, int n_in,
-                                                     int n_out, int64_t in_stride, int64_t out_stride, int n_lo,
-                                                     int64_t in_hi, int64_t out_hi, const cx<R>* __restrict__ tw) {
-  __shared__ cx<R> sm[TP * (L + 1)];
-  const int tid = threadIdx.x;
-  const int tiles = (n_lo + TP - 1) / TP;
-  const int64_t hi = blockIdx.x / tiles;
-  const int lo0 = (int)(blockIdx.x % tiles) * TP;
-  const cx<R>* ib = in + hi * in_hi + lo0;
-  cx<R>* ob = out + hi * out_hi + lo0;
-  for (int e = tid; e < TP * L; e += 256) {
-    int p = e % TP, i = e / TP;
-    cx<R> v = {0, 0};
-    if (i < n_in && lo0 + p < n_lo) v = ib[(int64_t)i * in_stride + p];
-    sm[p * (L + 1) + i] = v;
-  }
-  __syncthreads();
-  lds_fft<R, L, TP, FWD>(sm, tw, tid);
-  for (int e = tid; e < TP * n_out; e += 256) {
-    int p = e % TP, kq = e / TP;
-    if (lo0 + p < n_lo) ob[(int64_t)kq * out_stride + p] = sm[p * (L + 1) + kq];
-  }
-}
-
 // Fused z pass on buf[3][n3][P2][P1]: forward FFT of length L = P3 over the n3 stored planes,
 // y_a(k) = sum_b T_ab(k) x_b(k) with the octant-folded spectra, inverse FFT, first n3 outputs
-// written back in place.
+// written back in place. TP adjacent pencils per block; one component at a time occupies LDS
+// while the transformed components wait in registers (each thread owns the same (pencil, k3)
+// slots in every component, so the 3x3 multiply is thread-local).
 template <typename R, int L, int TP>
 __global__ __launch_bounds__(256) void k_fft_z_conv(cx<R>* __restrict__ buf, int n3, int P1, int P2,
                                                     const cx<R>* __restrict__ spec, const cx<R>* __restrict__ tw) {
-  __shared__ cx<R> sm[3 * TP * (L + 1)];
+  constexpr int EPT = (TP * L + 255) / 256;
+  __shared__ cx<R> sm[TP * (L + 1)];
   const int tid = threadIdx.x;
   const int tiles = (P1 + TP - 1) / TP;
   const int k2 = blockIdx.x / tiles;
   const int k1_0 = (blockIdx.x % tiles) * TP;
   const int64_t plane = (int64_t)P1 * P2;
   const int64_t comp = plane * n3;
-  for (int c = 0; c < 3; ++c)
+  cx<R> X[3][EPT];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
     for (int e = tid; e < TP * L; e += 256) {
       int p = e % TP, i = e / TP;
       cx<R> v = {0, 0};
       if (i < n3 && k1_0 + p < P1) v = buf[c * comp + (int64_t)i * plane + (int64_t)k2 * P1 + k1_0 + p];
-      sm[(c * TP + p) * (L + 1) + i] = v;
+      sm[p * (L + 1) + i] = v;
     }
-  __syncthreads();
-  lds_fft<R, L, 3 * TP, true>(sm, tw, tid);
+    __syncthreads();
+    lds_fft<R, L, TP, true>(sm, tw, tid);
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      int e = tid + u * 256;
+      if (e < TP * L) X[c][u] = sm[(e % TP) * (L + 1) + e / TP];
+    }
+    __syncthreads();
+  }
   const int S1 = P1 / 2 + 1, S2 = P2 / 2 + 1, S3 = L / 2 + 1;
   const int64_t SO = (int64_t)S1 * S2 * S3;
   const int f2 = k2 <= P2 / 2 ? k2 : P2 - k2;
   const R s2 = k2 <= P2 / 2 ? (R)1 : (R)-1;
-  for (int e = tid; e < TP * L; e += 256) {
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    int e = tid + u * 256;
     int p = e % TP, k3 = e / TP;
     int k1 = k1_0 + p;
-    if (k1 >= P1) continue;
+    if (e >= TP * L || k1 >= P1) continue;
     int f1 = k1 <= P1 / 2 ? k1 : P1 - k1;
     int f3 = k3 <= L / 2 ? k3 : L - k3;
     R s1 = k1 <= P1 / 2 ? (R)1 : (R)-1;
@@ -445,31 +423,143 @@ __global__ __launch_bounds__(256) void k_fft_z_conv(cx<R>* __restrict__ buf, int
     cx<R> Txy = (s1 * s2) * spec[3 * SO + idx];
     cx<R> Txz = (s1 * s3) * spec[4 * SO + idx];
     cx<R> Tyz = (s2 * s3) * spec[5 * SO + idx];
-    cx<R>& X = sm[(0 * TP + p) * (L + 1) + k3];
-    cx<R>& Y = sm[(1 * TP + p) * (L + 1) + k3];
-    cx<R>& Z = sm[(2 * TP + p) * (L + 1) + k3];
-    cx<R> x = X, y = Y, z = Z;
-    X = Txx * x + Txy * y + Txz * z;
-    Y = Txy * x + Tyy * y + Tyz * z;
-    Z = Txz * x + Tyz * y + Tzz * z;
+    cx<R> x = X[0][u], y = X[1][u], z = X[2][u];
+    X[0][u] = Txx * x + Txy * y + Txz * z;
+    X[1][u] = Txy * x + Tyy * y + Tyz * z;
+    X[2][u] = Txz * x + Tyz * y + Tzz * z;
   }
-  __syncthreads();
-  lds_fft<R, L, 3 * TP, false>(sm, tw, tid);
-  for (int c = 0; c < 3; ++c)
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      int e = tid + u * 256;
+      if (e < TP * L) sm[(e % TP) * (L + 1) + e / TP] = X[c][u];
+    }
+    __syncthreads();
+    lds_fft<R, L, TP, false>(sm, tw, tid);
     for (int e = tid; e < TP * n3; e += 256) {
       int p = e % TP, i = e / TP;
-      if (k1_0 + p < P1) buf[c * comp + (int64_t)i * plane + (int64_t)k2 * P1 + k1_0 + p] = sm[(c * TP + p) * (L + 1) + i];
+      if (k1_0 + p < P1) buf[c * comp + (int64_t)i * plane + (int64_t)k2 * P1 + k1_0 + p] = sm[p * (L + 1) + i];
     }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Two-level register FFT of length L = A * B (A >= B): thread j < B loads x[j + B m], m < A, and
+// transforms over m in registers; after the twiddle w_L^(j k1) one LDS transpose hands thread
+// k1 < A the values over j, which it transforms in registers to X[k1 + A k2]. Global loads and
+// stores go straight from/to registers; the transpose is the only LDS traffic (conflict-free with
+// the A+1 row padding).
+__host__ __device__ constexpr int bitrev_of(int m, int n) {
+  int r = 0;
+  for (int b = 1, hi = n >> 1; b < n; b <<= 1, hi >>= 1)
+    if (m & b) r |= hi;
+  return r;
+}
+
+template <typename R, int N, int L, bool FWD>
+__device__ inline void reg_dft(cx<R>* v, const cx<R>* __restrict__ tw) {
+#pragma unroll
+  for (int ln = 2; ln <= N; ln <<= 1) {
+#pragma unroll
+    for (int i = 0; i < N; i += ln) {
+#pragma unroll
+      for (int j = 0; j < ln / 2; ++j) {
+        cx<R> t = v[i + j + ln / 2];
+        if (j != 0) {
+          cx<R> w = tw[(j * (N / ln)) * (L / N)];
+          if (!FWD) w.im = -w.im;
+          t = w * t;
+        }
+        cx<R> u = v[i + j];
+        v[i + j] = u + t;
+        v[i + j + ln / 2] = u - t;
+      }
+    }
+  }
+}
+
+template <typename R, int A, int B, int NP, bool FWD, bool STRIDED>
+__global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, cx<R>* __restrict__ out, int n_in,
+                                                 int n_out, int64_t in_stride, int64_t out_stride, int n_lo,
+                                                 int64_t in_hi, int64_t out_hi, int64_t nrows,
+                                                 const cx<R>* __restrict__ tw) {
+  constexpr int L = A * B;
+  __shared__ cx<R> S[NP * B * (A + 1)];
+  const int t = threadIdx.x;
+  int p, u;
+  const cx<R>* ib;
+  cx<R>* ob;
+  bool valid;
+  if (STRIDED) {
+    p = t % NP;
+    u = t / NP;
+    const int tiles = (n_lo + NP - 1) / NP;
+    const int64_t hi = blockIdx.x / tiles;
+    const int lo = (int)(blockIdx.x % tiles) * NP + p;
+    valid = lo < n_lo;
+    ib = in + hi * in_hi + lo;
+    ob = out + hi * out_hi + lo;
+  } else {
+    u = t % A;
+    p = t / A;
+    const int64_t row = (int64_t)blockIdx.x * NP + p;
+    valid = row < nrows;
+    ib = in + row * in_hi;
+    ob = out + row * out_hi;
+  }
+  cx<R>* Sp = S + p * B * (A + 1);
+  if (u < B) {
+    const int j = u;
+    cx<R> v[A];
+#pragma unroll
+    for (int m = 0; m < A; ++m) {
+      const int n = j + B * m;
+      v[bitrev_of(m, A)] = (valid && n < n_in) ? ib[(int64_t)n * in_stride] : cx<R>{0, 0};
+    }
+    reg_dft<R, A, L, FWD>(v, tw);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      cx<R> w = tw[(j * k1) & (L - 1)];
+      if (!FWD) w.im = -w.im;
+      Sp[j * (A + 1) + k1] = (k1 == 0) ? v[k1] : v[k1] * w;
+    }
+  }
+  __syncthreads();
+  if (u < A) {
+    const int k1 = u;
+    cx<R> v[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) v[bitrev_of(j, B)] = Sp[j * (A + 1) + k1];
+    reg_dft<R, B, L, FWD>(v, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) {
+      const int k = k1 + A * k2;
+      if (valid && k < n_out) ob[(int64_t)k * out_stride] = v[k2];
+    }
+  }
+}
+
+template <int L> struct Split;
+template <> struct Split<8> { static constexpr int A = 4, B = 2; };
+template <> struct Split<16> { static constexpr int A = 4, B = 4; };
+template <> struct Split<32> { static constexpr int A = 8, B = 4; };
+template <> struct Split<64> { static constexpr int A = 8, B = 8; };
+template <> struct Split<128> { static constexpr int A = 16, B = 8; };
+template <> struct Split<256> { static constexpr int A = 16, B = 16; };
+template <> struct Split<512> { static constexpr int A = 32, B = 16; };
+template <> struct Split<1024> { static constexpr int A = 32, B = 32; };
+template <typename R, int A> static constexpr int fft2_np() {
+  return (sizeof(R) == 8 ? 128 : 256) / A;
 }
 
 // ---------------------------------------------------------------------------------------------
 // host-side dispatch over the FFT length
-template <typename R> static constexpr int strided_tp(int L) {
-  return sizeof(R) == 8 ? (L <= 128 ? 16 : 2048 / L) : (L <= 256 ? 16 : 4096 / L);
-}
 template <typename R> static constexpr int zconv_tp(int L) {
-  return sizeof(R) == 8 ? (L <= 64 ? 16 : (L <= 128 ? 8 : (L <= 256 ? 4 : (L <= 512 ? 2 : 1))))
-                        : (L <= 128 ? 16 : (L <= 256 ? 8 : (L <= 512 ? 4 : 2)));
+  // one component of TP pencils in LDS (<= 33 KB); 3 x TP*L/256 values per thread in registers
+  return sizeof(R) == 8 ? (L <= 128 ? 16 : (L <= 256 ? 8 : (L <= 512 ? 4 : 2)))
+                        : (L <= 256 ? 16 : (L <= 512 ? 8 : 4));
 }
 
 #define VSIE_FFT_SWITCH(L_, BODY)                                 \
@@ -489,12 +579,16 @@ template <typename R>
 void fft_rows(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, int n_in, int n_out, int64_t in_row,
               int64_t out_row, int64_t nrows, const cx<R>* tw) {
   VSIE_FFT_SWITCH(L, {
-    constexpr int NP = (1024 / LL) > 0 ? (1024 / LL) : 1;
+    constexpr int A = Split<LL>::A;
+    constexpr int B = Split<LL>::B;
+    constexpr int NP = (sizeof(R) == 8 ? 128 : 256) / A;
     dim3 grid((unsigned)((nrows + NP - 1) / NP));
     if (fwd)
-      hipLaunchKernelGGL((k_fft_rows<R, LL, true>), grid, dim3(256), 0, st, in, out, n_in, n_out, in_row, out_row, nrows, tw);
+      hipLaunchKernelGGL((k_fft2<R, A, B, NP, true, false>), grid, dim3(NP * A), 0, st, in, out, n_in, n_out, 1, 1, 0,
+                         in_row, out_row, nrows, tw);
     else
-      hipLaunchKernelGGL((k_fft_rows<R, LL, false>), grid, dim3(256), 0, st, in, out, n_in, n_out, in_row, out_row, nrows, tw);
+      hipLaunchKernelGGL((k_fft2<R, A, B, NP, false, false>), grid, dim3(NP * A), 0, st, in, out, n_in, n_out, 1, 1, 0,
+                         in_row, out_row, nrows, tw);
   });
 }
 
@@ -502,14 +596,16 @@ template <typename R>
 void fft_strided(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, int n_in, int n_out, int64_t in_stride,
                  int64_t out_stride, int n_lo, int64_t n_hi, int64_t in_hi, int64_t out_hi, const cx<R>* tw) {
   VSIE_FFT_SWITCH(L, {
-    constexpr int TP = strided_tp<R>(LL);
-    dim3 grid((unsigned)(n_hi * ((n_lo + TP - 1) / TP)));
+    constexpr int A = Split<LL>::A;
+    constexpr int B = Split<LL>::B;
+    constexpr int NP = (sizeof(R) == 8 ? 128 : 256) / A;
+    dim3 grid((unsigned)(n_hi * ((n_lo + NP - 1) / NP)));
     if (fwd)
-      hipLaunchKernelGGL((k_fft_strided<R, LL, TP, true>), grid, dim3(256), 0, st, in, out, n_in, n_out, in_stride,
-                         out_stride, n_lo, in_hi, out_hi, tw);
+      hipLaunchKernelGGL((k_fft2<R, A, B, NP, true, true>), grid, dim3(NP * A), 0, st, in, out, n_in, n_out, in_stride,
+                         out_stride, n_lo, in_hi, out_hi, 0, tw);
     else
-      hipLaunchKernelGGL((k_fft_strided<R, LL, TP, false>), grid, dim3(256), 0, st, in, out, n_in, n_out, in_stride,
-                         out_stride, n_lo, in_hi, out_hi, tw);
+      hipLaunchKernelGGL((k_fft2<R, A, B, NP, false, true>), grid, dim3(NP * A), 0, st, in, out, n_in, n_out, in_stride,
+                         out_stride, n_lo, in_hi, out_hi, 0, tw);
   });
 }
 
@@ -607,70 +703,91 @@ __global__ __launch_bounds__(64) void k_pfft_gather(const R* __restrict__ W, con
   if (t == 0) yn[n] = acc;
 }
 
-// y[rowid[r]] += sum_e val[e] x[col[e]]  (rows unique)
+// y[rowid[r]] += sum_e val[e] x[col[e]]  (rows unique); 16 lanes per row, shuffle reduction
 template <typename R>
-__global__ void k_csr_add(const int* __restrict__ rowid, const int* __restrict__ rowptr, const int* __restrict__ col,
-                          const cx<R>* __restrict__ val, const cx<R>* __restrict__ x, cx<R>* __restrict__ y, int nrows) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
+__global__ __launch_bounds__(256) void k_csr_add(const int* __restrict__ rowid, const int* __restrict__ rowptr,
+                                                 const int* __restrict__ col, const cx<R>* __restrict__ val,
+                                                 const cx<R>* __restrict__ x, cx<R>* __restrict__ y, int nrows) {
+  const int r = blockIdx.x * 16 + threadIdx.x / 16;
+  const int lane = threadIdx.x % 16;
   cx<R> acc = {0, 0};
-  for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) acc += val[e] * x[col[e]];
-  y[rowid[r]] += acc;
+  if (r < nrows)
+    for (int e = rowptr[r] + lane; e < rowptr[r + 1]; e += 16) acc += val[e] * x[col[e]];
+  for (int off = 8; off > 0; off >>= 1) {
+    acc.re += __shfl_down(acc.re, off, 16);
+    acc.im += __shfl_down(acc.im, off, 16);
+  }
+  if (r < nrows && lane == 0) y[rowid[r]] += acc;
 }
 
-// partial sums of A^T x or A^H x for a tall matrix A (M x K, row-major, K <= 64): part[blk][K].
-// Threads form (256 / KP) row lanes x KP column lanes so a row is read contiguously.
+// Low-rank factors are stored rank-major on the device: A[l][i], l < K (<= 256), i < M, so every
+// rank vector is contiguous.
+// part[ch][l] = sum_{i in chunk ch} op(A[l][i]) x[i], op = conj if CONJ
 template <typename R, bool CONJ>
-__global__ __launch_bounds__(256) void k_tall_t_partial(const cx<R>* __restrict__ A, const cx<R>* __restrict__ x,
-                                                        int64_t M, int K, cx<R>* __restrict__ part) {
-  __shared__ R rr[256], ri[256];
-  int KP = 1;
-  while (KP < K) KP <<= 1;
-  const int lanes = 256 / KP;
-  const int l = threadIdx.x % KP, lane = threadIdx.x / KP;
-  const int64_t per = (M + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = blockIdx.x * per;
-  const int64_t r1 = r0 + per < M ? r0 + per : M;
+__global__ __launch_bounds__(256) void k_lr_t_partial(const cx<R>* __restrict__ A, const cx<R>* __restrict__ x,
+                                                      int64_t M, int K, int64_t chunk, cx<R>* __restrict__ part) {
+  __shared__ R rr[4], ri[4];
+  const int l = blockIdx.y, ch = blockIdx.x;
+  const cx<R>* a = A + (int64_t)l * M;
+  const int64_t i0 = ch * chunk, i1 = i0 + chunk < M ? i0 + chunk : M;
   cx<R> acc = {0, 0};
-  if (l < K)
-    for (int64_t r = r0 + lane; r < r1; r += lanes) {
-      cx<R> a = A[r * K + l];
-      acc += CONJ ? mul_conj_a(a, x[r]) : a * x[r];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) acc += CONJ ? mul_conj_a(a[i], x[i]) : a[i] * x[i];
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.re += __shfl_down(acc.re, off, 64);
+    acc.im += __shfl_down(acc.im, off, 64);
+  }
+  if (threadIdx.x % 64 == 0) {
+    rr[threadIdx.x / 64] = acc.re;
+    ri[threadIdx.x / 64] = acc.im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[(int64_t)ch * K + l] = cx<R>{(rr[0] + rr[1]) + (rr[2] + rr[3]), (ri[0] + ri[1]) + (ri[2] + ri[3])};
+}
+
+// y[i] += sum_l op(A[l][i]) t[l]; a block covers 64 rows with four wavefronts splitting the ranks
+template <typename R, bool CONJ>
+__global__ __launch_bounds__(256) void k_lr_n_add(const cx<R>* __restrict__ A, const cx<R>* __restrict__ t,
+                                                  int64_t M, int K, cx<R>* __restrict__ y) {
+  __shared__ cx<R> ts[256];
+  __shared__ R rr[4][64], ri[4][64];
+  for (int l = threadIdx.x; l < K; l += 256) ts[l] = t[l];
+  __syncthreads();
+  const int row = threadIdx.x % 64, sl = threadIdx.x / 64;
+  const int64_t i = (int64_t)blockIdx.x * 64 + row;
+  cx<R> acc = {0, 0};
+  if (i < M)
+    for (int l = sl; l < K; l += 4) {
+      cx<R> a = A[(int64_t)l * M + i];
+      acc += CONJ ? mul_conj_a(a, ts[l]) : a * ts[l];
     }
+  rr[sl][row] = acc.re;
+  ri[sl][row] = acc.im;
+  __syncthreads();
+  if (sl == 0 && i < M)
+    y[i] += cx<R>{(rr[0][row] + rr[1][row]) + (rr[2][row] + rr[3][row]),
+                  (ri[0][row] + ri[1][row]) + (ri[2][row] + ri[3][row])};
+}
+
+// out[l] = sum_b part[b][l]: one block per column, tree reduction
+template <typename R>
+__global__ __launch_bounds__(256) void k_sum_partials(const cx<R>* __restrict__ part, int nblk, int K,
+                                                      cx<R>* __restrict__ out) {
+  __shared__ R rr[256], ri[256];
+  const int l = blockIdx.x;
+  cx<R> acc = {0, 0};
+  for (int b = threadIdx.x; b < nblk; b += 256) acc += part[(int64_t)b * K + l];
   rr[threadIdx.x] = acc.re;
   ri[threadIdx.x] = acc.im;
   __syncthreads();
-  for (int s = lanes / 2; s > 0; s >>= 1) {
-    if (lane < s) {
-      rr[threadIdx.x] += rr[threadIdx.x + s * KP];
-      ri[threadIdx.x] += ri[threadIdx.x + s * KP];
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) {
+      rr[threadIdx.x] += rr[threadIdx.x + s2];
+      ri[threadIdx.x] += ri[threadIdx.x + s2];
     }
     __syncthreads();
   }
-  if (lane == 0 && l < K) part[(int64_t)blockIdx.x * K + l] = cx<R>{rr[threadIdx.x], ri[threadIdx.x]};
-}
-
-template <typename R>
-__global__ void k_sum_partials(const cx<R>* __restrict__ part, int nblk, int K, cx<R>* __restrict__ out) {
-  int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= K) return;
-  cx<R> acc = {0, 0};
-  for (int b = 0; b < nblk; ++b) acc += part[(int64_t)b * K + l];
-  out[l] = acc;
-}
-
-// y[i] += sum_l A[i][l] t[l]  (or conj(A))
-template <typename R, bool CONJ>
-__global__ void k_tall_n_add(const cx<R>* __restrict__ A, const cx<R>* __restrict__ t, int64_t M, int K,
-                             cx<R>* __restrict__ y) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  cx<R> acc = {0, 0};
-  for (int l = 0; l < K; ++l) {
-    cx<R> a = A[i * K + l];
-    acc += CONJ ? mul_conj_a(a, t[l]) : a * t[l];
-  }
-  y[i] += acc;
+  if (threadIdx.x == 0) out[l] = cx<R>{rr[0], ri[0]};
 }
 
 // one block per row: out[row] = sum_j A[row][j] x[j]  (dense GEMV, row-major, write)
@@ -699,87 +816,207 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const cx<R>* __restrict__ A, 
   }
 }
 
-// TT forward, step G3: t3[j2][i3] = sum_j3 G3[j2][i3][j3] t4[j3]
+// Symmetric far block from its upper-triangle tiles: one block per tile (I, J) reads the tile
+// once and produces both the row sums Z_IJ x_J and (for I < J) the column sums Z_IJ^T x_I.
+// Thread (rg, cg): 32 column groups of 4 columns (64-byte FP64 segments, a 2 KB row per 32
+// lanes) x 8 row groups of 16 rows. Row sums reduce across the 32 column lanes by shuffles;
+// column sums across row groups by one shuffle and LDS.
 template <typename R>
-__global__ void k_tt_g3(const cx<R>* __restrict__ G3, const cx<R>* __restrict__ t4, int r2, int n3, int r3,
-                        cx<R>* __restrict__ t3) {
-  int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= r2 * n3) return;
-  cx<R> acc = {0, 0};
-  for (int c = 0; c < r3; ++c) acc += G3[(int64_t)id * r3 + c] * t4[c];
-  t3[id] = acc;
-}
-
-// TT forward, step G2: t2[j1][i3][i2] = sum_j2 G2[j1][i2][j2] t3[j2][i3]
-template <typename R>
-__global__ void k_tt_g2(const cx<R>* __restrict__ G2, const cx<R>* __restrict__ t3, int r1, int n2, int r2, int n3,
-                        cx<R>* __restrict__ t2) {
-  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= (int64_t)r1 * n2 * n3) return;
-  int i2 = (int)(id % n2), i3 = (int)((id / n2) % n3), j1 = (int)(id / ((int64_t)n2 * n3));
-  cx<R> acc = {0, 0};
-  for (int b = 0; b < r2; ++b) acc += G2[((int64_t)j1 * n2 + i2) * r2 + b] * t3[(int64_t)b * n3 + i3];
-  t2[id] = acc;
-}
-
-// TT forward, step G1 into the body rows: yb[i1 + n1 q] += mask * sum_j1 G1[i1][j1] t2[j1][q]
-template <typename R>
-__global__ void k_tt_g1_add(const cx<R>* __restrict__ G1, const cx<R>* __restrict__ t2, int n1, int r1, int64_t nq,
-                            const uint8_t* __restrict__ mask, cx<R>* __restrict__ yb) {
-  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n1 * nq) return;
-  if (!mask[id]) return;
-  int i1 = (int)(id % n1);
-  int64_t q = id / n1;
-  cx<R> acc = {0, 0};
-  for (int a = 0; a < r1; ++a) acc += G1[(int64_t)i1 * r1 + a] * t2[(int64_t)a * nq + q];
-  yb[id] += acc;
-}
-
-// TT transpose, step G1: s1[j1][q] = sum_i1 G1[i1][j1] mask x[i1 + n1 q]; 8 ranks per thread
-template <typename R>
-__global__ void k_ttT_g1(const cx<R>* __restrict__ G1, const cx<R>* __restrict__ xb, const uint8_t* __restrict__ mask,
-                         int n1, int r1, int64_t nq, cx<R>* __restrict__ s1) {
-  const int chunks = (r1 + 7) / 8;
-  int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nq * chunks) return;
-  int64_t q = id % nq;
-  int j0 = (int)(id / nq) * 8;
-  cx<R> acc[8];
-  for (int u = 0; u < 8; ++u) acc[u] = {0, 0};
-  for (int i1 = 0; i1 < n1; ++i1) {
-    int64_t p = i1 + (int64_t)n1 * q;
-    if (!mask[p]) continue;
-    cx<R> xv = xb[p];
-    for (int u = 0; u < 8; ++u)
-      if (j0 + u < r1) acc[u] += G1[(int64_t)i1 * r1 + j0 + u] * xv;
+__global__ __launch_bounds__(256) void k_symv_tiles(const cx<R>* __restrict__ Zp, const int* __restrict__ tiles,
+                                                    const cx<R>* __restrict__ x, int m, cx<R>* __restrict__ part) {
+  __shared__ R cr[4][SYM_TB], ci[4][SYM_TB];
+  __shared__ cx<R> xs[SYM_TB];
+  const int64_t t = blockIdx.x;
+  const int I = tiles[2 * t], J = tiles[2 * t + 1];
+  const int cg = threadIdx.x % 32, rg = threadIdx.x / 32;
+  const cx<R>* Z = Zp + t * (int64_t)SYM_TB * SYM_TB;
+  if (threadIdx.x < SYM_TB) {
+    int mm = I * SYM_TB + threadIdx.x;
+    xs[threadIdx.x] = mm < m ? x[mm] : cx<R>{0, 0};
   }
-  for (int u = 0; u < 8; ++u)
-    if (j0 + u < r1) s1[(int64_t)(j0 + u) * nq + q] = acc[u];
+  cx<R> xJ[4], ca[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    int n = J * SYM_TB + cg * 4 + c;
+    xJ[c] = n < m ? x[n] : cx<R>{0, 0};
+    ca[c] = {0, 0};
+  }
+  __syncthreads();
+  cx<R>* out = part + t * 2 * SYM_TB;
+#pragma unroll 4
+  for (int r = 0; r < 16; ++r) {
+    const int row = rg * 16 + r;
+    const cx<R>* zr = Z + (int64_t)row * SYM_TB + cg * 4;
+    const cx<R> xi = xs[row];
+    cx<R> rd = {0, 0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      cx<R> z = zr[c];
+      rd += z * xJ[c];
+      ca[c] += z * xi;
+    }
+    for (int off = 16; off > 0; off >>= 1) {
+      rd.re += __shfl_xor(rd.re, off, 32);
+      rd.im += __shfl_xor(rd.im, off, 32);
+    }
+    if (cg == 0) out[row] = rd;
+  }
+  if (I == J) return;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    ca[c].re += __shfl_xor(ca[c].re, 32, 64);
+    ca[c].im += __shfl_xor(ca[c].im, 32, 64);
+  }
+  const int wave = threadIdx.x / 64;
+  if ((threadIdx.x % 64) < 32)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      cr[wave][cg * 4 + c] = ca[c].re;
+      ci[wave][cg * 4 + c] = ca[c].im;
+    }
+  __syncthreads();
+  if (threadIdx.x < SYM_TB) {
+    int c = threadIdx.x;
+    out[SYM_TB + c] = cx<R>{cr[0][c] + cr[1][c] + cr[2][c] + cr[3][c], ci[0][c] + ci[1][c] + ci[2][c] + ci[3][c]};
+  }
 }
 
-// TT transpose, step G2: s2[j2][i3] = sum_{j1, i2} G2[j1][i2][j2] s1[j1][i2 + n2 i3]
+// y[i] = sum_{J >= I} rowpart(I, J)[i] + sum_{J < I} colpart(J, I)[i], I = i / SYM_TB (fixed order)
 template <typename R>
-__global__ void k_ttT_g2(const cx<R>* __restrict__ G2, const cx<R>* __restrict__ s1, int r1, int n2, int r2, int n3,
-                         cx<R>* __restrict__ s2) {
-  int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= r2 * n3) return;
-  int i3 = id % n3, b = id / n3;
-  const int64_t nq = (int64_t)n2 * n3;
+__global__ void k_symv_reduce(const cx<R>* __restrict__ part, int T, int m, cx<R>* __restrict__ y, int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int I = i / SYM_TB, li = i % SYM_TB;
   cx<R> acc = {0, 0};
-  for (int a = 0; a < r1; ++a)
-    for (int i2 = 0; i2 < n2; ++i2) acc += G2[((int64_t)a * n2 + i2) * r2 + b] * s1[(int64_t)a * nq + i2 + (int64_t)n2 * i3];
-  s2[(int64_t)b * n3 + i3] = acc;
+  for (int J = 0; J < T; ++J) {
+    if (J < I) {
+      int64_t t = (int64_t)J * T - (int64_t)J * (J - 1) / 2 + (I - J);
+      acc += part[t * 2 * SYM_TB + SYM_TB + li];
+    } else {
+      int64_t t = (int64_t)I * T - (int64_t)I * (I - 1) / 2 + (J - I);
+      acc += part[t * 2 * SYM_TB + li];
+    }
+  }
+  if (accumulate) y[i] += acc;
+  else y[i] = acc;
 }
 
-// TT transpose, step G3: s3[j3] = sum_{j2, i3} G3[j2][i3][j3] s2[j2][i3]   (one block per j3)
+// ---------------------------------------------------------------------------------------------
+// Batched strided complex GEMM, C(i,j) = sum_k A(i,k) B(k,j), with element (i,j) of batch b at
+// X[i sr + j sc + b sb]. Optional mask on B (mask index = B's element index) and masked
+// accumulation into C. 32 x 32 output tile per block of 256 threads, K staged in chunks of 16
+// through LDS; each thread owns a 2 x 2 output patch.
+template <typename R> struct GemmArgs {
+  const cx<R>* A;
+  int64_t sar, sac, sab;
+  const cx<R>* B;
+  int64_t sbr, sbc, sbb;
+  cx<R>* C;
+  int64_t scr, scc, scb;
+  int M, N, K;
+  const uint8_t* maskB;
+  const uint8_t* maskC;   // non-null: C += maskC * AB (mask index = C's element index)
+  int accumulate;
+};
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_ttT_g3(const cx<R>* __restrict__ G3, const cx<R>* __restrict__ s2, int r2,
-                                                int n3, int r3, cx<R>* __restrict__ s3) {
+__global__ __launch_bounds__(256) void k_gemm_strided(GemmArgs<R> g) {
+  __shared__ cx<R> As[32][17];
+  __shared__ cx<R> Bs[16][33];
+  const int b = blockIdx.z;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  // output patches: neighbouring threads step along C's unit-stride dimension
+  const bool c_rowfast = g.scc != 1 && g.scr == 1;
+  const int tx = c_rowfast ? threadIdx.x / 16 : threadIdx.x % 16;
+  const int ty = c_rowfast ? threadIdx.x % 16 : threadIdx.x / 16;
+  const cx<R>* A = g.A + b * g.sab;
+  const cx<R>* B = g.B + b * g.sbb;
+  const uint8_t* mB = g.maskB ? g.maskB + b * g.sbb : nullptr;
+  cx<R> acc[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+  // tile loaders walk the operand's unit-stride dimension fastest so loads coalesce
+  const bool a_rowfast = g.sac != 1 && g.sar == 1;
+  const bool b_rowfast = g.sbc != 1 && g.sbr == 1;
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int e = threadIdx.x; e < 32 * 16; e += 256) {
+      int r = a_rowfast ? e % 32 : e / 16, c = a_rowfast ? e / 32 : e % 16;   // A tile rows i0+r, cols k0+c
+      int i = i0 + r, k = k0 + c;
+      As[r][c] = (i < g.M && k < g.K) ? A[i * g.sar + k * g.sac] : cx<R>{0, 0};
+      int rb = b_rowfast ? e % 16 : e / 32, cb = b_rowfast ? e / 16 : e % 32; // B tile rows k0+rb, cols j0+cb
+      int kk = k0 + rb, j = j0 + cb;
+      cx<R> v = {0, 0};
+      if (kk < g.K && j < g.N) {
+        int64_t idx = kk * g.sbr + j * g.sbc;
+        v = B[idx];
+        if (mB && !mB[idx]) v = cx<R>{0, 0};
+      }
+      Bs[rb][cb] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      cx<R> a0 = As[ty][k], a1 = As[ty + 16][k];
+      cx<R> b0 = Bs[k][tx], b1 = Bs[k][tx + 16];
+      acc[0][0] += a0 * b0;
+      acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0;
+      acc[1][1] += a1 * b1;
+    }
+    __syncthreads();
+  }
+  cx<R>* C = g.C + b * g.scb;
+  const uint8_t* mC = g.maskC ? g.maskC + b * g.scb : nullptr;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      int i = i0 + ty + 16 * u, j = j0 + tx + 16 * v;
+      if (i >= g.M || j >= g.N) continue;
+      int64_t idx = i * g.scr + j * g.scc;
+      if (mC) {
+        if (mC[idx]) C[idx] += acc[u][v];
+      } else if (g.accumulate) {
+        C[idx] += acc[u][v];
+      } else {
+        C[idx] = acc[u][v];
+      }
+    }
+}
+
+// out[j2 * n3 + i3] = sum_b part[b][i3][j2]  (split-K reduction of the transposed G2 step)
+template <typename R>
+__global__ void k_splitk_reduce(const cx<R>* __restrict__ part, int nb, int n3, int r2, cx<R>* __restrict__ out) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n3 * r2) return;
+  const int j2 = id % r2, i3 = id / r2;
+  cx<R> acc = {0, 0};
+  for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * n3 * r2 + id];
+  out[(int64_t)j2 * n3 + i3] = acc;
+}
+
+template <typename R> static void gemm(hipStream_t st, const GemmArgs<R>& g, int batch) {
+  if (g.M <= 0 || g.N <= 0 || batch <= 0) return;
+  dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, batch);
+  hipLaunchKernelGGL(k_gemm_strided<R>, grid, dim3(256), 0, st, g);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Tensor-train far coupling (eqs. (16)-(19)). Cores row-major: G1[i1][j1], G2[j1][i2][j2],
+// G3[j2][i3][j3], G4[j3][i4]. Intermediates per component:
+//   forward   t4[j3] -> t3[j2][i3] -> T2[j1][q] (q = i2 + n2 i3) -> y_b[i1 + n1 q]
+//   transpose S1[i3][j1][i2] -> S2[j2][i3] -> s3[j3] -> y_f[i4]
+
+// forward, G4 first: part[c][j3][chunk] = sum_{i4 in chunk} G4[j3][i4] x_f[i4]
+template <typename R>
+__global__ __launch_bounds__(256) void k_tt_f4(TTDesc<R> T, const cx<R>* __restrict__ xf, int mf, int chunk,
+                                               cx<R>* __restrict__ part, int nchunk) {
   __shared__ R rr[256], ri[256];
-  const int c = blockIdx.x;
+  const int c = blockIdx.z, j3 = blockIdx.y, ch = blockIdx.x;
   cx<R> acc = {0, 0};
-  for (int id = threadIdx.x; id < r2 * n3; id += 256) acc += G3[(int64_t)id * r3 + c] * s2[id];
+  if (j3 < T.r3[c]) {
+    const cx<R>* g = T.G4[c] + (int64_t)j3 * mf;
+    const int i0 = ch * chunk, i1 = min(mf, i0 + chunk);
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) acc += g[i] * xf[i];
+  }
   rr[threadIdx.x] = acc.re;
   ri[threadIdx.x] = acc.im;
   __syncthreads();
@@ -790,17 +1027,60 @@ __global__ __launch_bounds__(256) void k_ttT_g3(const cx<R>* __restrict__ G3, co
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) s3[c] = cx<R>{rr[0], ri[0]};
+  if (threadIdx.x == 0) part[((int64_t)c * TT_RMAX + j3) * nchunk + ch] = cx<R>{rr[0], ri[0]};
 }
 
-// TT transpose, step G4: yf[i4] += sum_j3 G4[j3][i4] s3[j3]
+// t3[c][j2][i3] = sum_j3 G3[j2][i3][j3] t4[j3], t4 summed from the partials
 template <typename R>
-__global__ void k_ttT_g4_add(const cx<R>* __restrict__ G4, const cx<R>* __restrict__ s3, int r3, int mf,
-                             cx<R>* __restrict__ yf) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_tt_f3(TTDesc<R> T, const cx<R>* __restrict__ part, int nchunk, int n3, cx<R>* __restrict__ t3) {
+  const int c = blockIdx.z;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r2 = T.r2[c], r3 = T.r3[c];
+  if (id >= r2 * n3) return;
+  cx<R> acc = {0, 0};
+  for (int j3 = 0; j3 < r3; ++j3) {
+    cx<R> t4 = {0, 0};
+    for (int ch = 0; ch < nchunk; ++ch) t4 += part[((int64_t)c * TT_RMAX + j3) * nchunk + ch];
+    acc += T.G3[c][(int64_t)id * r3 + j3] * t4;
+  }
+  t3[(int64_t)c * TT_RMAX * n3 + id] = acc;
+}
+
+// s3[c][j3] = sum_{j2, i3} G3[j2][i3][j3] S2[c][j2][i3]; one block per component
+template <typename R>
+__global__ __launch_bounds__(256) void k_ttT_3(TTDesc<R> T, const cx<R>* __restrict__ s2, int n3,
+                                               cx<R>* __restrict__ s3) {
+  __shared__ R rr[256], ri[256];
+  const int c = blockIdx.z;
+  const int r2 = T.r2[c], r3 = T.r3[c];
+  const int lane = threadIdx.x % 32, slice = threadIdx.x / 32;
+  const int K = r2 * n3;
+  const cx<R>* sv = s2 + (int64_t)c * TT_RMAX * n3;
+  for (int j0 = 0; j0 < r3; j0 += 32) {
+    const int j3 = j0 + lane;
+    cx<R> acc = {0, 0};
+    if (j3 < r3)
+      for (int k = slice; k < K; k += 8) acc += T.G3[c][(int64_t)k * r3 + j3] * sv[k];
+    rr[threadIdx.x] = acc.re;
+    ri[threadIdx.x] = acc.im;
+    __syncthreads();
+    if (slice == 0 && j3 < r3) {
+      cx<R> s = {0, 0};
+      for (int q = 0; q < 8; ++q) s += cx<R>{rr[q * 32 + lane], ri[q * 32 + lane]};
+      s3[c * TT_RMAX + j3] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// y_f[i4] += sum_c sum_j3 G4[c][j3][i4] s3[c][j3]
+template <typename R>
+__global__ void k_ttT_4(TTDesc<R> T, const cx<R>* __restrict__ s3, int mf, cx<R>* __restrict__ yf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= mf) return;
   cx<R> acc = {0, 0};
-  for (int c = 0; c < r3; ++c) acc += G4[(int64_t)c * mf + i] * s3[c];
+  for (int c = 0; c < 3; ++c)
+    for (int j3 = 0; j3 < T.r3[c]; ++j3) acc += T.G4[c][(int64_t)j3 * mf + i] * s3[c * TT_RMAX + j3];
   yf[i] += acc;
 }
 
@@ -929,55 +1209,106 @@ template <typename R> void launch_pfft_gather(hipStream_t st, const R* W, const 
 }
 template <typename R> void launch_csr_add(hipStream_t st, const int* rowid, const int* rowptr, const int* col,
                                           const cx<R>* val, const cx<R>* x, cx<R>* y, int nrows) {
-  if (nrows > 0) hipLaunchKernelGGL(k_csr_add<R>, dim3((nrows + 255) / 256), dim3(256), 0, st, rowid, rowptr, col, val, x, y, nrows);
+  if (nrows > 0) hipLaunchKernelGGL(k_csr_add<R>, dim3((nrows + 15) / 16), dim3(256), 0, st, rowid, rowptr, col, val, x, y, nrows);
 }
-template <typename R> void launch_tall_t(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* x, int64_t M, int K,
-                                         cx<R>* part, int nblk, cx<R>* out) {
-  if (K > 64) throw Error(VSIE_E_ARG, "low-rank factor wider than 64 columns");
+template <typename R> void launch_lr_t(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* x, int64_t M, int K,
+                                       cx<R>* part, int max_chunks, cx<R>* out) {
+  if (K <= 0) return;
+  if (K > 256) throw Error(VSIE_E_ARG, "low-rank factor wider than 256 columns");
+  int64_t chunk = 2048;
+  while ((M + chunk - 1) / chunk > max_chunks) chunk *= 2;
+  const int nch = (int)((M + chunk - 1) / chunk);
+  if (nch == 0) return;
   if (conj)
-    hipLaunchKernelGGL((k_tall_t_partial<R, true>), dim3(nblk), dim3(256), 0, st, A, x, M, K, part);
+    hipLaunchKernelGGL((k_lr_t_partial<R, true>), dim3(nch, K), dim3(256), 0, st, A, x, M, K, chunk, part);
   else
-    hipLaunchKernelGGL((k_tall_t_partial<R, false>), dim3(nblk), dim3(256), 0, st, A, x, M, K, part);
-  hipLaunchKernelGGL(k_sum_partials<R>, dim3((K + 63) / 64), dim3(64), 0, st, part, nblk, K, out);
+    hipLaunchKernelGGL((k_lr_t_partial<R, false>), dim3(nch, K), dim3(256), 0, st, A, x, M, K, chunk, part);
+  hipLaunchKernelGGL(k_sum_partials<R>, dim3(K), dim3(256), 0, st, part, nch, K, out);
 }
-template <typename R> void launch_tall_n_add(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* t, int64_t M,
-                                             int K, cx<R>* y) {
-  if (M <= 0) return;
+template <typename R> void launch_lr_n_add(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* t, int64_t M,
+                                           int K, cx<R>* y) {
+  if (M <= 0 || K <= 0) return;
+  const unsigned nb = (unsigned)((M + 63) / 64);
   if (conj)
-    hipLaunchKernelGGL((k_tall_n_add<R, true>), dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, A, t, M, K, y);
+    hipLaunchKernelGGL((k_lr_n_add<R, true>), dim3(nb), dim3(256), 0, st, A, t, M, K, y);
   else
-    hipLaunchKernelGGL((k_tall_n_add<R, false>), dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, A, t, M, K, y);
+    hipLaunchKernelGGL((k_lr_n_add<R, false>), dim3(nb), dim3(256), 0, st, A, t, M, K, y);
 }
 template <typename R> void launch_gemv_rows(hipStream_t st, const cx<R>* A, const cx<R>* x, int64_t nrow, int64_t ncol,
                                             cx<R>* out, int accumulate) {
   if (nrow > 0) hipLaunchKernelGGL(k_gemv_rows<R>, dim3((unsigned)nrow), dim3(256), 0, st, A, x, ncol, out, accumulate);
 }
-template <typename R> void launch_tt_forward(hipStream_t st, cx<R>* const G[4], const int r[3], const int n[3], int mf,
-                                             const cx<R>* xf, const uint8_t* mask, cx<R>* yb, cx<R>* work) {
-  cx<R>* t4 = work;
-  cx<R>* t3 = t4 + 128;
-  cx<R>* t2 = t3 + (int64_t)r[1] * n[2];
-  // t4 = G4 xf  (rows of G4, one block each)
-  hipLaunchKernelGGL(k_gemv_rows<R>, dim3(r[2]), dim3(256), 0, st, G[3], xf, (int64_t)mf, t4, 0);
-  hipLaunchKernelGGL(k_tt_g3<R>, dim3((r[1] * n[2] + 255) / 256), dim3(256), 0, st, G[2], t4, r[1], n[2], r[2], t3);
-  int64_t c2 = (int64_t)r[0] * n[1] * n[2];
-  hipLaunchKernelGGL(k_tt_g2<R>, dim3((unsigned)((c2 + 255) / 256)), dim3(256), 0, st, G[1], t3, r[0], n[1], r[1], n[2], t2);
-  int64_t nq = (int64_t)n[1] * n[2];
-  hipLaunchKernelGGL(k_tt_g1_add<R>, dim3((unsigned)((n[0] * nq + 255) / 256)), dim3(256), 0, st, G[0], t2, n[0], r[0],
-                     nq, mask, yb);
+template <typename R> void launch_tt(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
+                                     const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* yb, cx<R>* work) {
+  const int n1 = n[0], n2 = n[1], n3 = n[2];
+  const int64_t nq = (int64_t)n2 * n3, nv = (int64_t)n1 * nq;
+  int rmax2 = 1, rmax3 = 1;
+  for (int c = 0; c < 3; ++c) {
+    rmax2 = std::max(rmax2, T.r2[c]);
+    rmax3 = std::max(rmax3, T.r3[c]);
+  }
+  const int chunk = 4096;
+  const int nchunk = (mf + chunk - 1) / chunk;
+  cx<R>* part = work;                                    // 3 * RMAX * nchunk
+  cx<R>* t3 = part + 3LL * TT_RMAX * nchunk;             // 3 * RMAX * n3
+  cx<R>* big = t3 + 3LL * TT_RMAX * n3;                  // RMAX * nq (one component at a time)
+  // forward (eqs. (16)-(17)): G4 x first, then G3, G2, G1
+  hipLaunchKernelGGL(k_tt_f4<R>, dim3(nchunk, rmax3, 3), dim3(256), 0, st, T, xf, mf, chunk, part, nchunk);
+  hipLaunchKernelGGL(k_tt_f3<R>, dim3((rmax2 * n3 + 255) / 256, 1, 3), dim3(256), 0, st, T, part, nchunk, n3, t3);
+  for (int c = 0; c < 3; ++c) {
+    const int r1 = T.r1[c], r2 = T.r2[c];
+    // T2[j1][i3][i2] (= T2[j1][q], q = i2 + n2 i3) = sum_j2 t3[j2][i3] G2[j1][i2][j2], batched over j1:
+    // C(i3, i2) = A(i3, j2) B(j2, i2), stores along i2
+    GemmArgs<R> g2{t3 + (int64_t)c * TT_RMAX * n3, 1, n3, 0,
+                   T.G2[c], 1, r2, (int64_t)n2 * r2,
+                   big, n2, 1, nq, n3, n2, r2, nullptr, nullptr, 0};
+    gemm<R>(st, g2, r1);
+    // y_b[c][i1 + n1 q] += mask * sum_j1 T2[j1][q] G1[i1][j1]: C(q, i1) = A(q, j1) B(j1, i1)
+    GemmArgs<R> g1{big, 1, nq, 0, T.G1[c], 1, r1, 0, yb + (int64_t)c * nv, n1, 1, 0, (int)nq, n1, r1, nullptr, mask, 1};
+    gemm<R>(st, g1, 1);
+  }
+  // transpose (eqs. (18)-(19)): G1 first, summed over the components into y_f
+  cx<R>* s2 = t3;
+  cx<R>* s3 = part;
+  cx<R>* kpart = big + (int64_t)TT_RMAX * nq;            // split-K partials
+  for (int c = 0; c < 3; ++c) {
+    const int r1 = T.r1[c], r2 = T.r2[c];
+    // S1[i3][j1][i2] = sum_i1 G1[i1][j1] mask x_b[c][i1 + n1 (i2 + n2 i3)]   (batched over i3)
+    GemmArgs<R> h1{T.G1[c], 1, r1, 0, xb + (int64_t)c * nv, 1, n1, (int64_t)n1 * n2,
+                   big, n2, 1, (int64_t)r1 * n2, r1, n2, n1, mask, nullptr, 0};
+    gemm<R>(st, h1, n3);
+    // S2^T(i3, j2) = sum_k S1[i3][k] G2[k][j2], k = j1 n2 + i2, split over K in chunks of 128
+    const int K = r1 * n2;
+    const int kc = 128;
+    const int nb = (K + kc - 1) / kc;
+    GemmArgs<R> h2{big, (int64_t)K, 1, kc, T.G2[c], r2, 1, (int64_t)kc * r2,
+                   kpart, r2, 1, (int64_t)n3 * r2, n3, r2, kc, nullptr, nullptr, 0};
+    // the last chunk may be short: run full chunks, then the tail
+    gemm<R>(st, h2, K / kc);
+    if (K % kc) {
+      GemmArgs<R> tail = h2;
+      tail.A = big + (int64_t)(K / kc) * kc;
+      tail.B = T.G2[c] + (int64_t)(K / kc) * kc * r2;
+      tail.C = kpart + (int64_t)(K / kc) * n3 * r2;
+      tail.K = K % kc;
+      gemm<R>(st, tail, 1);
+    }
+    hipLaunchKernelGGL(k_splitk_reduce<R>, dim3((n3 * r2 + 255) / 256), dim3(256), 0, st, kpart, nb, n3, r2,
+                       s2 + (int64_t)c * TT_RMAX * n3);
+  }
+  hipLaunchKernelGGL(k_ttT_3<R>, dim3(1, 1, 3), dim3(256), 0, st, T, s2, n3, s3);
+  hipLaunchKernelGGL(k_ttT_4<R>, dim3((mf + 255) / 256), dim3(256), 0, st, T, s3, mf, yf);
 }
-template <typename R> void launch_tt_transpose(hipStream_t st, cx<R>* const G[4], const int r[3], const int n[3], int mf,
-                                               const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* work) {
-  int64_t nq = (int64_t)n[1] * n[2];
-  cx<R>* s3 = work;
-  cx<R>* s2 = s3 + 128;
-  cx<R>* s1 = s2 + (int64_t)r[1] * n[2];
-  int chunks = (r[0] + 7) / 8;
-  hipLaunchKernelGGL(k_ttT_g1<R>, dim3((unsigned)((nq * chunks + 255) / 256)), dim3(256), 0, st, G[0], xb, mask, n[0],
-                     r[0], nq, s1);
-  hipLaunchKernelGGL(k_ttT_g2<R>, dim3((r[1] * n[2] + 255) / 256), dim3(256), 0, st, G[1], s1, r[0], n[1], r[1], n[2], s2);
-  hipLaunchKernelGGL(k_ttT_g3<R>, dim3(r[2]), dim3(256), 0, st, G[2], s2, r[1], n[2], r[2], s3);
-  hipLaunchKernelGGL(k_ttT_g4_add<R>, dim3((mf + 255) / 256), dim3(256), 0, st, G[3], s3, r[2], mf, yf);
+int64_t tt_work_elems(const int n[3], int mf) {
+  const int nchunk = (mf + 4095) / 4096;
+  const int64_t kparts = (int64_t)((TT_RMAX * n[1] + 127) / 128) * n[2] * TT_RMAX;
+  return 3LL * TT_RMAX * nchunk + 3LL * TT_RMAX * n[2] + (int64_t)TT_RMAX * n[1] * n[2] + kparts;
+}
+template <typename R> void launch_symv(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x, int m,
+                                       cx<R>* part, cx<R>* y) {
+  const int64_t nt = (int64_t)T * (T + 1) / 2;
+  hipLaunchKernelGGL(k_symv_tiles<R>, dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, m, part);
+  hipLaunchKernelGGL(k_symv_reduce<R>, dim3((m + 255) / 256), dim3(256), 0, st, part, T, m, y, 0);
 }
 template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, const double* vre, const double* vim,
                                              int ne, cx<R>* b) {
@@ -992,14 +1323,13 @@ template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, co
   template void launch_pfft_gather<R>(hipStream_t, const R*, const int*, const cx<R>*, cx<R>*, int, const GridDims&); \
   template void launch_csr_add<R>(hipStream_t, const int*, const int*, const int*, const cx<R>*, const cx<R>*,        \
                                   cx<R>*, int);                                                                      \
-  template void launch_tall_t<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*, int, cx<R>*);    \
-  template void launch_tall_n_add<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*);            \
+  template void launch_lr_t<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*, int, cx<R>*);      \
+  template void launch_lr_n_add<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*);              \
   template void launch_gemv_rows<R>(hipStream_t, const cx<R>*, const cx<R>*, int64_t, int64_t, cx<R>*, int);          \
-  template void launch_tt_forward<R>(hipStream_t, cx<R>* const[4], const int[3], const int[3], int, const cx<R>*,     \
-                                     const uint8_t*, cx<R>*, cx<R>*);                                                 \
-  template void launch_tt_transpose<R>(hipStream_t, cx<R>* const[4], const int[3], const int[3], int, const cx<R>*,   \
-                                       const uint8_t*, cx<R>*, cx<R>*);                                               \
-  template void launch_scatter_rhs<R>(hipStream_t, const int*, const double*, const double*, int, cx<R>*);
+  template void launch_tt<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*, const cx<R>*,           \
+                             const uint8_t*, cx<R>*, cx<R>*, cx<R>*);                                                 \
+  template void launch_scatter_rhs<R>(hipStream_t, const int*, const double*, const double*, int, cx<R>*);         \
+  template void launch_symv<R>(hipStream_t, const cx<R>*, const int*, int, const cx<R>*, int, cx<R>*, cx<R>*);
 VSIE_INST(double)
 VSIE_INST(float)
 
@@ -1024,6 +1354,12 @@ template void launch_extract_octant<float>(hipStream_t, const cxd*, const int[3]
 void launch_zcc_dense(hipStream_t st, const RwgDev& A, const RwgDev& B, double k, int64_t row0, int64_t nrows, cxd* out) {
   int64_t tot = nrows * B.m;
   if (tot > 0) hipLaunchKernelGGL(k_zcc_dense, dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, st, A, B, k, row0, nrows, out);
+}
+void launch_zcc_packed(hipStream_t st, const RwgDev& A, double k, const int* tiles, int64_t tile0, int64_t ntiles,
+                       cxd* out) {
+  int64_t tot = ntiles * SYM_TB * SYM_TB;
+  if (tot > 0)
+    hipLaunchKernelGGL(k_zcc_packed, dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, st, A, k, tiles, tile0, ntiles, out);
 }
 void launch_zcc_pairs(hipStream_t st, const RwgDev& A, const RwgDev& B, const int* pi, const int* pj, int64_t np,
                       double k, cxd* out) {

@@ -322,23 +322,34 @@ void setup_pfft(Handle& H) {
 
 // ---------------------------------------------------------------------------------------------
 // far conductors: dense block, ACA of the near-far block, TT-cross of the far coupling
+// dense far block (eq. (6)), symmetric: only the upper-triangle tiles are assembled and stored
 void setup_dense_far(Handle& H) {
-  const int64_t mf = H.mf;
-  H.d64.Zff = H.dalloc<cxd>(mf * mf);
-  const int64_t max_entries = 1LL << 26;
-  int64_t rows_per = std::max<int64_t>(1, max_entries / std::max<int64_t>(1, mf));
-  for (int64_t r0 = 0; r0 < mf; r0 += rows_per) {
-    int64_t nr = std::min(rows_per, mf - r0);
-    launch_zcc_dense(H.stream, H.dfar, H.dfar, H.k0, r0, nr, H.d64.Zff + r0 * mf);
-  }
+  const int T = (H.mf + SYM_TB - 1) / SYM_TB;
+  H.sym_T = T;
+  std::vector<int> tiles;
+  for (int I = 0; I < T; ++I)
+    for (int J = I; J < T; ++J) {
+      tiles.push_back(I);
+      tiles.push_back(J);
+    }
+  H.d_tiles = upload(H, tiles);
+  const int64_t nt = (int64_t)T * (T + 1) / 2;
+  const int64_t per = (int64_t)SYM_TB * SYM_TB;
+  H.d64.Zff = H.dalloc<cxd>(nt * per);
+  H.d64.sym_part = H.dalloc<cxd>(nt * 2 * SYM_TB);
+  const int64_t chunk = std::max<int64_t>(1, (1LL << 26) / per);
+  for (int64_t t0 = 0; t0 < nt; t0 += chunk)
+    launch_zcc_packed(H.stream, H.dfar, H.k0, H.d_tiles, t0, std::min(chunk, nt - t0), H.d64.Zff + t0 * per);
   VSIE_HIP(hipGetLastError());
   VSIE_HIP(hipStreamSynchronize(H.stream));
 }
 
 void copy_zff_c64(Handle& H) {
-  const int64_t mf = H.mf;
-  H.d32.Zff = H.dalloc<cxf>(mf * mf);
-  launch_d2f(H.stream, H.d64.Zff, H.d32.Zff, mf * mf);
+  const int64_t T = H.sym_T;
+  const int64_t n = T * (T + 1) / 2 * SYM_TB * SYM_TB;
+  H.d32.Zff = H.dalloc<cxf>(n);
+  H.d32.sym_part = H.dalloc<cxf>(T * (T + 1) / 2 * 2 * SYM_TB);
+  launch_d2f(H.stream, H.d64.Zff, H.d32.Zff, n);
   VSIE_HIP(hipStreamSynchronize(H.stream));
 }
 
@@ -351,7 +362,7 @@ void setup_aca(Handle& H) {
   std::vector<char> used_row(mn, 0), used_col(mf, 0);
   int i = 0;
   double norm2 = 0;
-  const int kmax = std::min({H.opts.aca_rank_max, mn, mf, 64});
+  const int kmax = std::min({H.opts.aca_rank_max, mn, mf, 256});
   for (int it = 0; it < 4 * kmax && (int)us.size() < kmax; ++it) {
     used_row[i] = 1;
     launch_zcc_dense(H.stream, H.dnear, H.dfar, H.k0, i, 1, d_row);
@@ -415,13 +426,23 @@ void setup_aca(Handle& H) {
   }
 }
 
+// the host keeps U (m_n x k) and V (m_f x k) row-major; the device holds them rank-major
 void upload_aca(Handle& H) {
   if (H.aca_k == 0) return;
-  H.d64.U = upload_cx<double>(H, H.aca_U);
-  H.d64.V = upload_cx<double>(H, H.aca_V);
+  const int k = H.aca_k;
+  auto rank_major = [k](const std::vector<cxd>& A) {
+    const size_t m = A.size() / k;
+    std::vector<cxd> B(A.size());
+    for (size_t i = 0; i < m; ++i)
+      for (int l = 0; l < k; ++l) B[(size_t)l * m + i] = A[i * k + l];
+    return B;
+  };
+  const std::vector<cxd> Ut = rank_major(H.aca_U), Vt = rank_major(H.aca_V);
+  H.d64.U = upload_cx<double>(H, Ut);
+  H.d64.V = upload_cx<double>(H, Vt);
   if (H.opts.build_c64) {
-    H.d32.U = upload_cx<float>(H, H.aca_U);
-    H.d32.V = upload_cx<float>(H, H.aca_V);
+    H.d32.U = upload_cx<float>(H, Ut);
+    H.d32.V = upload_cx<float>(H, Vt);
   }
 }
 
@@ -491,9 +512,8 @@ template <typename R> void alloc_work(Handle& H, OpData<R>& D) {
   D.gridA = H.dalloc<cx<R>>(3 * H.Ne);
   D.bufB = H.dalloc<cx<R>>(3LL * H.ne[2] * H.ne[1] * H.P[0]);
   D.bufC = H.dalloc<cx<R>>(3LL * H.ne[2] * H.P[1] * H.P[0]);
-  int64_t nq = (int64_t)H.n[1] * H.n[2];
-  D.tt_work = H.dalloc<cx<R>>(2 * 128 + 128LL * H.n[2] + 128 * nq);
-  D.small_work = H.dalloc<cx<R>>(256 * 64 + 256);
+  D.tt_work = H.dalloc<cx<R>>(tt_work_elems(H.n, std::max(H.mf, 1)));
+  D.small_work = H.dalloc<cx<R>>(512 * 256 + 256);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -572,7 +592,7 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
   // dense far block (writes y_f)
   if (mf) {
     T.begin(8);
-    launch_gemv_rows<R>(st, D.Zff, xf, mf, mf, yf, 0);
+    launch_symv<R>(st, D.Zff, H.d_tiles, H.sym_T, xf, mf, D.sym_part, yf);
     T.end(8);
   }
   // precorrection
@@ -583,23 +603,27 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
   if (mf && mn && H.aca_k > 0) {
     T.begin(10);
     cx<R>* part = D.small_work;
-    cx<R>* t = D.small_work + 256 * 64;
-    const int nblk = 128;
-    launch_tall_t<R>(st, true, D.V, xf, mf, H.aca_k, part, nblk, t);
-    launch_tall_n_add<R>(st, false, D.U, t, mn, H.aca_k, yn);
-    launch_tall_t<R>(st, false, D.U, xn, mn, H.aca_k, part, nblk, t);
-    launch_tall_n_add<R>(st, true, D.V, t, mf, H.aca_k, yf);
+    cx<R>* t = D.small_work + 512 * 256;
+    launch_lr_t<R>(st, true, D.V, xf, mf, H.aca_k, part, 512, t);
+    launch_lr_n_add<R>(st, false, D.U, t, mn, H.aca_k, yn);
+    launch_lr_t<R>(st, false, D.U, xn, mn, H.aca_k, part, 512, t);
+    launch_lr_n_add<R>(st, true, D.V, t, mf, H.aca_k, yf);
     T.end(10);
   }
   // TT far coupling (eqs. (16)-(19))
-  if (mf && D.G[0][0]) {
+  if (mf && D.G[0][0] && D.G[1][0] && D.G[2][0]) {
     T.begin(11);
-    for (int chi = 0; chi < 3; ++chi) {
-      if (!D.G[chi][0]) continue;
-      const int* r = H.tt_r[chi];
-      launch_tt_forward<R>(st, D.G[chi], r, H.n, mf, xf, H.d_mask, yb + (int64_t)chi * H.nv, D.tt_work);
-      launch_tt_transpose<R>(st, D.G[chi], r, H.n, mf, xb + (int64_t)chi * H.nv, H.d_mask, yf, D.tt_work);
+    TTDesc<R> td;
+    for (int c = 0; c < 3; ++c) {
+      td.G1[c] = D.G[c][0];
+      td.G2[c] = D.G[c][1];
+      td.G3[c] = D.G[c][2];
+      td.G4[c] = D.G[c][3];
+      td.r1[c] = H.tt_r[c][0];
+      td.r2[c] = H.tt_r[c][1];
+      td.r3[c] = H.tt_r[c][2];
     }
+    launch_tt<R>(st, td, H.n, mf, xf, xb, H.d_mask, yf, yb, D.tt_work);
     T.end(11);
   }
   T.collect();
@@ -741,9 +765,9 @@ extern "C" {
 int vsie_default_options(vsie_options* o) {
   if (!o) return fail(VSIE_E_ARG, "null options");
   o->tt_tol = 1e-3;
-  o->tt_rank_max = 30;
+  o->tt_rank_max = 64;
   o->aca_tol = 1e-3;
-  o->aca_rank_max = 64;
+  o->aca_rank_max = 128;
   o->precorrect_dist = 2;
   o->build_c64 = 1;
   o->build_far = 1;
@@ -759,6 +783,14 @@ int vsie_default_solve_opts(vsie_solve_opts* o) {
   o->method = VSIE_GMRES64;
   o->inner_tol = 1e-3;
   return VSIE_OK;
+}
+
+static void progress(const char* what, std::chrono::steady_clock::time_point t0) {
+  static const bool on = getenv("VSIE_VERBOSE") != nullptr;
+  if (!on) return;
+  double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fprintf(stderr, "[vsie] %7.2f s  %s\n", s, what);
+  fflush(stderr);
 }
 
 int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, vsie_handle** out) {
@@ -781,7 +813,8 @@ int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, v
     if (!(p->h > 0) || !std::isfinite(p->h)) throw Error(VSIE_E_ARG, "voxel size must be positive");
     if (!(p->freq_hz > 0) || !std::isfinite(p->freq_hz)) throw Error(VSIE_E_ARG, "frequency must be positive");
     if (!p->eps_r || !p->sigma) throw Error(VSIE_E_ARG, "null material arrays");
-    if (H.opts.precorrect_dist < 0 || H.opts.tt_rank_max < 1 || H.opts.aca_rank_max < 1)
+    if (H.opts.precorrect_dist < 0 || H.opts.tt_rank_max < 1 || H.opts.tt_rank_max > 128 ||
+        H.opts.aca_rank_max < 1 || H.opts.aca_rank_max > 256)
       throw Error(VSIE_E_ARG, "invalid options");
     if (p->n_meshes < 0 || (p->n_meshes > 0 && !p->meshes)) throw Error(VSIE_E_ARG, "bad mesh list");
     H.h = p->h;
@@ -822,18 +855,24 @@ int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, v
       H.Ne = (int64_t)H.ne[0] * H.ne[1] * H.ne[2];
     }
     H.have32 = H.opts.build_c64 != 0;
+    progress("geometry and stencils", t0);
     H.dfar = make_rwg_dev(H, H.far);
     H.dnear = make_rwg_dev(H, H.near);
     setup_volume(H);
+    progress("generator and circulant spectra", t0);
     if (H.mn > 0) setup_pfft(H);
+    progress("pFFT projection and precorrection", t0);
     if (H.mf > 0) {
       setup_dense_far(H);
       if (H.opts.build_c64) copy_zff_c64(H);
+      progress("dense far block", t0);
       if (H.opts.build_far) {
         if (H.mn > 0) setup_aca(H);
         upload_aca(H);
+        progress("ACA", t0);
         setup_tt(H);
         for (int chi = 0; chi < 3; ++chi) upload_tt(H, chi);
+        progress("TT-cross", t0);
       }
     }
     alloc_work<double>(H, H.d64);
@@ -1118,7 +1157,7 @@ int vsie_import(vsie_handle* hd, int what, int index, const void* host, size_t n
       int k;
       if (nbytes < sizeof(int)) throw Error(VSIE_E_ARG, "short ACA record");
       std::memcpy(&k, c, sizeof(int));
-      if (k < 0 || k > 64) throw Error(VSIE_E_ARG, "ACA rank must be within 0..64");
+      if (k < 0 || k > 256) throw Error(VSIE_E_ARG, "ACA rank must be within 0..256");
       size_t need = sizeof(int) + sizeof(cxd) * ((size_t)H.mn * k + (size_t)H.mf * k);
       if (nbytes != need) throw Error(VSIE_E_ARG, "ACA record size mismatch");
       H.aca_k = k;

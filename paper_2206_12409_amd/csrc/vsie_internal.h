@@ -72,7 +72,8 @@ template <typename R> struct OpData {
   // TT cores per component
   cx<R>* G[3][4] = {};
   // dense far block
-  cx<R>* Zff = nullptr;        // [m_f][m_f]
+  cx<R>* Zff = nullptr;        // upper-triangle tiles of the symmetric far block
+  cx<R>* sym_part = nullptr;   // per-tile partial sums
   // work buffers
   cx<R>* gridA = nullptr;      // [3][ne3][ne2][ne1] (also the convolution output)
   cx<R>* bufB = nullptr;       // [3][ne3][ne2][P1]
@@ -113,6 +114,9 @@ struct Handle {
   int* d_pc_col = nullptr;        // global unknown index
   int n_pcrows = 0;
   int64_t pc_nnz = 0;
+  // far block tiling
+  int sym_T = 0;
+  int* d_tiles = nullptr;         // [ntiles][2] (I, J), I <= J
   // body mask
   uint8_t* d_mask = nullptr;
   // TT

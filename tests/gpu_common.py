@@ -27,7 +27,7 @@ def oracle_same(problem, op, tt_eps=1e-4, pc_dist=2):
             op.import_tt(a, cores[a])
         if d.near is not None:
             U, sv, Vh = np.linalg.svd(blocks["nf"], full_matrices=False)
-            r = int(min(64, np.sum(sv > 1e-9 * sv[0])))
+            r = int(min(256, np.sum(sv > 1e-9 * sv[0])))
             aca = (U[:, :r] * sv[:r], Vh[:r].conj().T)
             op.import_aca(*aca)
     S_same, _, parts = system.assemble_same(d, cores, aca, pc_dist, direct_blocks=blocks)

@@ -1,0 +1,209 @@
+"""Full-size parity on the 2 mm workload (96x112x128 voxels, 8-loop array, 20k-triangle shield):
+k-sparse probes through the C ABI, sampled outputs evaluated one by one by the oracle
+(paper eq. (15); the same operator bench.py times)."""
+import numpy as np
+import pytest
+
+import vsie_synth as synth
+from oracle import coupling, pfft, surface, tt, voxel
+from oracle.constants import chi as chi_of, k0 as k0_of
+from oracle.system import merge
+from oracle.rwg import RWG, build_rwg
+from tests.gpu_common import to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def subset(r, idx):
+    idx = np.asarray(idx)
+    return RWG(r.edge[idx], r.tri[idx], r.free[idx], r.free_local[idx], r.length[idx], r.verts, r.tris, r.area)
+
+
+@pytest.fixture(scope="module")
+def big():
+    import paper_2206_12409_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    p = synth.two_mm_case()
+    op = pkg.Operator(p)
+    g = p.grid
+    far = merge(p.meshes, 1)
+    near = merge(p.meshes, 0)
+    rf = build_rwg(far[0], far[1])
+    rn = build_rwg(near[0], near[1])
+    chi = chi_of(g.eps_r, g.sigma, p.freq_hz).ravel()
+    k = k0_of(p.freq_hz)
+    return p, op, rf, rn, chi, k
+
+
+def _idx3(flat, n):
+    return np.stack([flat % n[0], (flat // n[0]) % n[1], flat // (n[0] * n[1])], axis=1)
+
+
+def test_body_probe_sampled_rows(big):
+    """x nonzero at 6 body unknowns: body rows = Z_bb x (volume convolution, eq. (4)/(5)), near
+    rows = W^T T x (pFFT interpolation, eq. (13)); sampled rows against the oracle."""
+    p, op, rf, rn, chi, k = big
+    g = p.grid
+    n = g.n
+    nv = int(np.prod(n))
+    rng = np.random.default_rng(21)
+    tissue = np.nonzero(chi != 0)[0]
+    q = rng.choice(tissue, 6, replace=False)
+    qa = rng.integers(0, 3, 6)
+    qv = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    x = np.zeros(op.N, np.complex128)
+    off = op.m_far + op.m_near
+    x[off + qa * nv + q] = qv
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    # sampled body rows: near the probes, random tissue, random air
+    near_rows = np.unique(np.concatenate([q + s for s in (0, 1, -1, n[0], -n[0] * n[1])]))
+    near_rows = near_rows[(near_rows >= 0) & (near_rows < nv)]
+    rows = np.unique(np.concatenate([near_rows, rng.choice(tissue, 1500, replace=False), rng.choice(nv, 300)]))
+    kap = k * g.h
+    pi = _idx3(rows, n)
+    qi = _idx3(q, n)
+    d = (qi[None, :, :] - pi[:, None, :]).reshape(-1, 3)
+    T = voxel.T_generator(d.astype(float), kap).reshape(len(rows), len(q), 6)
+    comp = {(a, b): c for c, (a, b) in enumerate(voxel.COMPONENTS)}
+    ref = np.zeros((3, len(rows)), np.complex128)
+    for a in range(3):
+        for j in range(len(q)):
+            b = qa[j]
+            c = comp[(min(a, b), max(a, b))]
+            ref[a] += g.h ** 3 * T[:, j, c] * qv[j]
+    for a in range(3):
+        tis = chi[rows] != 0
+        diag = np.zeros(len(rows), np.complex128)
+        for j in range(len(q)):
+            if qa[j] == a:
+                diag[rows == q[j]] += g.h ** 3 / chi[q[j]] * qv[j]
+        ref[a] = np.where(tis, ref[a] + diag, x[off + a * nv + rows])
+    got = np.stack([y[off + a * nv + rows] for a in range(3)])
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
+    # sampled near rows: y_n[m] = h^3 sum_v W_m(v) . sum_q T(q - v) x_q
+    ms = rng.choice(rn.m, 40, replace=False)
+    sub = subset(rn, ms)
+    base = pfft.stencil_bases(sub, g.origin, g.h)
+    W = pfft.stencil_weights(sub, base, g.origin, g.h)
+    vox = pfft.stencil_voxels(base)                                   # (40, 125, 3)
+    refn = np.zeros(len(ms), np.complex128)
+    for i in range(len(ms)):
+        dd = (qi[None, :, :] - vox[i][:, None, :]).reshape(-1, 3)
+        Tm = voxel.T_generator(dd.astype(float), kap).reshape(125, len(q), 6)
+        Wm = W[i].reshape(3, 125)
+        for a in range(3):
+            for j in range(len(q)):
+                b = qa[j]
+                c = comp[(min(a, b), max(a, b))]
+                refn[i] += g.h ** 3 * np.sum(Wm[a] * Tm[:, j, c]) * qv[j]
+    gotn = y[op.m_far + ms]
+    assert np.linalg.norm(gotn - refn) / np.linalg.norm(refn) < 1e-10
+
+
+def test_near_probe_sampled_rows(big):
+    """x = unit current on one near RWG: near rows are the precorrected pFFT column
+    (direct Z_cc for pairs within 2 voxels, W^T T W otherwise); sampled against the oracle."""
+    p, op, rf, rn, chi, k = big
+    g = p.grid
+    rng = np.random.default_rng(5)
+    n0 = int(rng.integers(0, rn.m))
+    x = np.zeros(op.N, np.complex128)
+    x[op.m_far + n0] = 1.0
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    base_all = pfft.stencil_bases(rn, g.origin, g.h)
+    gap = np.maximum(np.maximum(base_all - (base_all[n0] + 4), base_all[n0] - (base_all + 4)), 0).max(1)
+    near = np.nonzero(gap <= 2)[0]
+    farish = np.nonzero((gap > 2) & (gap < 12))[0]
+    ms = np.unique(np.concatenate([rng.choice(near, min(30, len(near)), replace=False),
+                                   rng.choice(farish, min(30, len(farish)), replace=False)]))
+    sub = subset(rn, np.concatenate([[n0], ms]))
+    base = pfft.stencil_bases(sub, g.origin, g.h)
+    W = pfft.stencil_weights(sub, base, g.origin, g.h)
+    vox = pfft.stencil_voxels(base)
+    kap = k * g.h
+    comp = {(a, b): c for c, (a, b) in enumerate(voxel.COMPONENTS)}
+    Zd = surface.zcc_block(subset(rn, ms), subset(rn, [n0]), k)[:, 0]
+    ref = np.zeros(len(ms), np.complex128)
+    W0 = W[0].reshape(3, 125)
+    for i, m in enumerate(ms):
+        if gap[m] <= 2:
+            ref[i] = Zd[i]
+            continue
+        dd = (vox[i + 1][:, None, :] - vox[0][None, :, :]).reshape(-1, 3)
+        Tm = voxel.T_generator(dd.astype(float), kap).reshape(125, 125, 6)
+        Wm = W[i + 1].reshape(3, 125)
+        s = 0
+        for a in range(3):
+            for b in range(3):
+                c = comp[(min(a, b), max(a, b))]
+                s += Wm[a] @ Tm[:, :, c] @ W0[b]
+        ref[i] = g.h ** 3 * s
+    got = y[op.m_far + ms]
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_far_probe_dense_column(big):
+    """x = unit current on one far RWG: far rows are the dense Z_cc^ff column (eq. (6))."""
+    p, op, rf, rn, chi, k = big
+    rng = np.random.default_rng(9)
+    j0 = int(rng.integers(0, rf.m))
+    x = np.zeros(op.N, np.complex128)
+    x[j0] = 1.0
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    ms = np.unique(np.concatenate([[j0], rng.choice(rf.m, 300, replace=False)]))
+    ref = surface.zcc_block(subset(rf, ms), subset(rf, [j0]), k)[:, 0]
+    assert np.linalg.norm(y[ms] - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_tt_and_aca_bilinear_identity(big):
+    """u^T (Z v) = v^T (Z u) across the far/body (TT forward vs transpose, eqs. (16)-(19)) and
+    far/near (U V^* vs conj(V) U^T, eq. (12)) blocks at full size."""
+    p, op, rf, rn, chi, k = big
+    rng = np.random.default_rng(3)
+    N, mf, mn = op.N, op.m_far, op.m_near
+    u = np.zeros(N, np.complex128)
+    u[:mf] = rng.standard_normal(mf) + 1j * rng.standard_normal(mf)
+    for lo, hi in ((mf + mn, N), (mf, mf + mn)):
+        v = np.zeros(N, np.complex128)
+        v[lo:hi] = rng.standard_normal(hi - lo) + 1j * rng.standard_normal(hi - lo)
+        Zv = op.matvec(to_dev(v)).cpu().numpy()
+        Zu = op.matvec(to_dev(u)).cpu().numpy()
+        lhs = u[:mf] @ Zv[:mf]
+        rhs = v[lo:hi] @ Zu[lo:hi]
+        assert abs(lhs - rhs) <= 1e-11 * np.linalg.norm(u) * np.linalg.norm(Zv[:mf]) + 1e-300
+
+
+def test_tt_cross_sampled_entries(big):
+    """Product TT-cross cores against far-coupling entries evaluated by the oracle (1 x 1 point
+    rule) at random positions of the 96 x 112 x 128 x m_f tensor."""
+    p, op, rf, rn, chi, k = big
+    g = p.grid
+    rng = np.random.default_rng(8)
+    vox = rng.choice(int(np.prod(g.n)), 60, replace=False)
+    cols = rng.choice(rf.m, 400, replace=False)
+    i3 = _idx3(vox, g.n)
+    centres = g.origin + (i3 + 0.5) * g.h
+    exact = coupling.zbc_block(centres, g.h, subset(rf, cols), k, "far")     # (3, 60, 400)
+    info = op.info()
+    for a in range(3):
+        G1, G2, G3, G4 = op.export_tt(a)
+        approx = np.einsum("pa,apb,bpc,cl->pl", G1[i3[:, 0]], G2[:, i3[:, 1], :], G3[:, i3[:, 2], :], G4[:, cols])
+        err = np.linalg.norm(approx - exact[a]) / np.linalg.norm(exact[a])
+        print("TT component %d ranks %s: sampled error %.2e (estimate %.2e)"
+              % (a, info["tt_rank"][a], err, info["tt_err_est"][a]))
+        assert err < max(3e-3, 3 * info["tt_err_est"][a])
+
+
+def test_aca_sampled_rows(big):
+    p, op, rf, rn, chi, k = big
+    rng = np.random.default_rng(4)
+    rows = rng.choice(rn.m, 30, replace=False)
+    cols = rng.choice(rf.m, 2000, replace=False)
+    Z = surface.zcc_block(subset(rn, rows), subset(rf, cols), k)
+    U, V = op.export_aca()
+    approx = U[rows] @ V[cols].conj().T
+    err = np.linalg.norm(approx - Z) / np.linalg.norm(Z)
+    print("ACA rank %d: sampled relative error %.2e" % (U.shape[1], err))
+    assert err < 1e-2

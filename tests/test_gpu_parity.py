@@ -128,8 +128,8 @@ def test_mixed_precision_refinement(small):
     condition number of the densified operator."""
     p, op, d, _, S_same, _ = small
     b = system.port_rhs(d, 0)
-    x64, s64 = op.solve(to_dev(b), tol=1e-6, restart=600, max_iter=4000)
-    x, st = op.solve(to_dev(b), tol=1e-6, restart=600, max_iter=4000, method=1, inner_tol=1e-3)
+    x64, s64 = op.solve(to_dev(b), tol=1e-6, restart=600, max_iter=12000)
+    x, st = op.solve(to_dev(b), tol=1e-6, restart=600, max_iter=12000, method=1, inner_tol=1e-3)
     x = x.cpu().numpy()
     assert st[0]["converged"] and st[0]["rel_residual"] <= 1e-6
     e = rel(x, x64.cpu().numpy())
