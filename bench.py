@@ -42,13 +42,67 @@ def stage_bytes(info, s):
         "fft_x_inv": c * (3 * ne3 * ne2 * P1 + 3 * Ne),
         "body_out": c * (2 * 3 * nv + 3 * nv + nv),
         "pfft_gather": mn * 375 * (8 + c),
-        "gemv_far": c * (mf * mf + 2 * mf),
+        # unique entries of the complex-symmetric far block plus x; the packed-tile partial sums
+        # are charged to the reduction kernel
+        "gemv_far": c * (mf * (mf + 1) // 2 + mf),
+        "gemv_far_reduce": c * (((mf + 127) // 128) * mf + mf),
         "precorrect": info["precorr_nnz"] * (c + 4 + c),
         "aca": 2 * c * (mf + mn) * info["aca_rank"],
     }
     r = info["tt_rank"]
-    b["tt"] = sum(c * (2 * r[a][2] * mf + 4 * nv + 2 * r[a][0] * n2 * n3) for a in range(3))
+    # per component: G4 and the merged first-two-core block read in both directions, y_b read and
+    # written (forward), x_b read (transpose)
+    b["tt"] = sum(c * (2 * r[a][2] * mf + 2 * r[a][1] * n1 * n2 + 3 * nv) for a in range(3))
     return b.get(s)
+
+
+KERNEL_OF_STAGE = {   # stages that are a single kernel launch, and that kernel's name
+    "build_grid": "k_build_grid", "fft_x_fwd": "k_fft2", "fft_y_fwd": "k_fft2", "fft_z_conv": "k_fft_z_conv",
+    "fft_y_inv": "k_fft2", "fft_x_inv": "k_fft2", "body_out": "k_body_out", "pfft_gather": "k_pfft_gather",
+    "gemv_far": "k_symv_tiles", "gemv_far_reduce": "k_symv_reduce", "precorrect": "k_csr_add",
+}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
+    kernel source as it is now (sha256 of the HIP kernel file); else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s_2mm.txt" % kernel)
+    src = os.path.join(ROOT, "paper_2206_12409_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha or "traffic_bytes" not in kv:
+        return None
+    return float(kv["traffic_bytes"])
+
+
+def copy_calibration():
+    """A plain device copy of known size for scaling the FETCH_SIZE and WRITE_SIZE counters to
+    bytes: float32 -> float64 conversion of 2^27 elements (512 MiB read, 1 GiB written), so the
+    read and written byte counts differ and each counter can be matched to its side."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+    dst = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copy calibration: 3 x (%d B read, %d B written)" % (src.numel() * 4, dst.numel() * 8),
+          file=sys.stderr, flush=True)
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [d.get("num_threads", 0) for d in threadpool_info() if d.get("user_api") == "blas"]
+        return max(n) if n else 1
+    except Exception:
+        return os.cpu_count()
 
 
 def cpu_baseline(problem, budget_s=12.0):
@@ -83,6 +137,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--max-iter", type=int, default=2000)
+    ap.add_argument("--calib-copy", action="store_true", help="run the copy used to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the path has no multi-GPU mode); got --gpus %d" % args.gpus,
@@ -103,6 +158,8 @@ def main():
     info["n"] = tuple(int(v) for v in problem.grid.n)
     print("setup %.1f s: %s" % (setup_s, json.dumps(info)), file=sys.stderr, flush=True)
 
+    if args.calib_copy:
+        copy_calibration()
     x = torch.from_numpy(synth.complex_normal(op.N, 1234)).cuda()
     y = torch.empty_like(x)
     for _ in range(args.warmup):
@@ -139,7 +196,7 @@ def main():
     op.profile(False)
     per_stage = {k: v[0] / v[1] for k, v in stages.items()}
     print("stage ms: %s" % json.dumps({k: round(v, 4) for k, v in per_stage.items()}), file=sys.stderr, flush=True)
-    dom = max(per_stage, key=per_stage.get)
+    dom = max((k for k in per_stage if k in KERNEL_OF_STAGE), key=per_stage.get)
     rl = {}
     for k, ms in per_stage.items():
         b = stage_bytes(info, k)
@@ -175,7 +232,7 @@ def main():
     if not args.no_cpu_baseline:
         macs, nred, reps = cpu_baseline(problem)
         n_red = op.m_far + op.m_near + 3 * info["n_tissue"]
-        cpu = dict(value=macs / float(n_red) ** 2, unit="matvec/s", cores=os.cpu_count(), kind="oracle",
+        cpu = dict(value=macs / float(n_red) ** 2, unit="matvec/s", cores=blas_threads(), kind="oracle",
                    sample="dense O(N^2) oracle product on a 16^3 crop of the phantom (%d unknowns, %d reps), "
                           "scaled by (%d / %d)^2 to the workload's reduced system" % (nred, reps, n_red, nred))
 
@@ -197,9 +254,10 @@ def main():
                                % (op.m_near, op.m_far),
                    "n_unknowns": op.N, "n_ext": list(info["n_ext"]), "fft": list(info["fft"]),
                    "tt_rank": info["tt_rank"], "aca_rank": info["aca_rank"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                     "bytes_per_launch": db, "avg_ms": round(dom_ms, 4)},
+        "roofline": {"bound": "hbm", "stage": dom, "kernel": KERNEL_OF_STAGE[dom], "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(KERNEL_OF_STAGE[dom]), "bytes_per_launch": db,
+                     "avg_ms": round(dom_ms, 4)},
         "volume_conv": {"ms": round(conv_ms, 4), "bytes": conv_b,
                         "gbs": round(conv_b / (conv_ms * 1e-3) / 1e9, 1) if conv_ms else None},
         "stages": rl,

@@ -113,23 +113,23 @@ typedef struct {
 typedef struct {
   double tol;                 /* relative residual ||b - Ax|| / ||b||, default 1e-6 */
   int32_t restart;            /* GMRES restart length, default 50 (Sec. IV-C) */
-  int32_t max_iter;           /* total inner iterations */
+  int32_t max_iter;           /* GMRES64: iterations; IR_MIXED: total inner complex64 iterations */
   int32_t method;             /* VSIE_GMRES64 or VSIE_IR_MIXED */
-  double inner_tol;           /* mixed precision: inner FP32 solve tolerance, default 1e-3 */
+  double inner_tol;           /* IR_MIXED: inner complex64 solve tolerance, default 1e-3 */
 } vsie_solve_opts;
 
 enum vsie_method { VSIE_GMRES64 = 0, VSIE_IR_MIXED = 1 };
 
 typedef struct {
-  int32_t iterations;         /* matrix-vector products in the Krylov iterations */
+  int32_t iterations;         /* Krylov iterations (IR_MIXED: inner complex64 iterations) */
   int32_t restarts;
-  int32_t refinements;        /* outer steps (mixed precision) */
+  int32_t refinements;        /* IR_MIXED: FP64 outer steps, one FP64 product and inner solve each */
   double rel_residual;        /* true FP64 ||b - Ax|| / ||b|| at exit */
   double block_residual[3];   /* relative residual restricted to far / near / body rows */
   double seconds;
 } vsie_solve_stats;
 
-/* Fill defaults: tt_tol 1e-3, tt_rank_max 64, aca_tol 1e-3, aca_rank_max 128,
+/* Fill defaults: tt_tol 1e-3, tt_rank_max 96, aca_tol 1e-3, aca_rank_max 128,
  * precorrect_dist 2, build_c64 1, build_far 1, seed 1. */
 int vsie_default_options(vsie_options* opts);
 int vsie_default_solve_opts(vsie_solve_opts* opts);
@@ -157,9 +157,13 @@ int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, v
                 void* stream);
 
 /* Solve Z x = b for nrhs right-hand sides (device, [nrhs][N] complex128) with restarted GMRES
- * (Sec. III-A: zero initial guess, FP64 classical Gram-Schmidt applied twice) or mixed-precision
- * iterative refinement (complex64 inner GMRES, FP64 residual). x_dev receives complex128.
- * Blocks. stats (array of nrhs, may be NULL) are filled even on E_NOCONV. */
+ * (Sec. III-A: zero initial guess, FP64 classical Gram-Schmidt applied twice) or the mixed-
+ * precision solver IR_MIXED: FP64 flexible GMRES (20 steps per cycle) on the FP64 operator whose
+ * preconditioner is one cycle (at most `restart` iterations, stopping early at inner_tol) of
+ * complex64 GMRES on Z z = v; with an exact inner solve each outer step is one refinement
+ * x += Z^{-1}(b - Zx). x_dev receives complex128. Blocks.
+ * Allocates its work vectors (IR_MIXED: 41 FP64 vectors of length N besides the Krylov basis).
+ * stats (array of nrhs, may be NULL) are filled even on E_NOCONV. */
 int vsie_solve(struct vsie_handle* h, const vsie_solve_opts* opts, int nrhs, const void* b_dev,
                void* x_dev, vsie_solve_stats* stats, void* stream);
 

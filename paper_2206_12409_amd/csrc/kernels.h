@@ -1,5 +1,6 @@
 // Host-side launchers of the device kernels (kernels.hip).
 #pragma once
+#include <vector>
 #include "vsie_internal.h"
 
 namespace vsie {
@@ -36,7 +37,10 @@ template <typename R>
 void fft_strided(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, int n_in, int n_out, int64_t in_stride,
                  int64_t out_stride, int n_lo, int64_t n_hi, int64_t in_hi, int64_t out_hi, const cx<R>* tw);
 template <typename R>
-void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const cx<R>* spec, const cx<R>* tw);
+void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const cx<R>* spec, const cx<R>* tw,
+                const int* order);
+// block order of the z pass (pairs k2, k1 tile; empty when the LDS-staged variant is used)
+std::vector<int> zconv_order(int L, int P1, int P2, bool fp64);
 
 // matvec
 template <typename R> void launch_build_grid(hipStream_t st, const cx<R>* xb, const cx<R>* xn, const uint8_t* mask,
@@ -56,12 +60,12 @@ template <typename R> void launch_lr_n_add(hipStream_t st, bool conj, const cx<R
 template <typename R> void launch_gemv_rows(hipStream_t st, const cx<R>* A, const cx<R>* x, int64_t nrow, int64_t ncol,
                                             cx<R>* out, int accumulate);
 constexpr int TT_RMAX = 128;
+constexpr int TT_KCHUNK = 64;   // split-K chunk of the transpose contraction over n1 n2
 template <typename R> struct TTDesc {
-  const cx<R>* G1[3];
-  const cx<R>* G2[3];
-  const cx<R>* G3[3];
-  const cx<R>* G4[3];
-  int r1[3], r2[3], r3[3];
+  const cx<R>* M[3];    // merged first two cores, [r2][n1 n2]
+  const cx<R>* G3[3];   // [r2][n3][r3]
+  const cx<R>* G4[3];   // [r3][m_f]
+  int r2[3], r3[3];
 };
 // forward and transpose far coupling of all three components: y_b += mask Zt x_f,
 // y_f += sum_c Zt_c^T (mask x_b)
@@ -69,8 +73,9 @@ template <typename R> void launch_tt(hipStream_t st, const TTDesc<R>& T, const i
                                      const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* yb, cx<R>* work);
 int64_t tt_work_elems(const int n[3], int mf);
 // y = Z x for the symmetric far block stored as upper-triangle tiles (part: 2 SYM_TB per tile)
-template <typename R> void launch_symv(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x, int m,
-                                       cx<R>* part, cx<R>* y);
+template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
+                                             int m, cx<R>* part);
+template <typename R> void launch_symv_reduce(hipStream_t st, const cx<R>* part, int T, int m, cx<R>* y);
 template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, const double* vre, const double* vim,
                                              int ne, cx<R>* b);
 

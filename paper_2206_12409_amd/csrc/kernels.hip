@@ -66,12 +66,14 @@ __global__ void k_extract_octant(const cxd* __restrict__ full, int P1, int P2, i
   const int64_t SO = (int64_t)S1 * S2 * S3;
   int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= SO) return;
-  int f1 = (int)(id % S1), f2 = (int)((id / S1) % S2), f3 = (int)(id / ((int64_t)S1 * S2));
+  // output layout [f2][f1][f3][6]: the six components of one frequency are one contiguous record
+  // and a z pencil (fixed f1, f2) reads consecutive records
+  const int f3 = (int)(id % S3), f1 = (int)((id / S3) % S1), f2 = (int)(id / ((int64_t)S3 * S1));
   const int64_t PT = (int64_t)P1 * P2 * P3;
   int64_t src = f1 + (int64_t)P1 * (f2 + (int64_t)P2 * f3);
   for (int c = 0; c < 6; ++c) {
     cxd v = full[c * PT + src];
-    spec[c * SO + id] = cx<R>{(R)(v.re * scale), (R)(v.im * scale)};
+    spec[6 * id + c] = cx<R>{(R)(v.re * scale), (R)(v.im * scale)};
   }
 }
 
@@ -404,8 +406,7 @@ __global__ __launch_bounds__(256) void k_fft_z_conv(cx<R>* __restrict__ buf, int
     }
     __syncthreads();
   }
-  const int S1 = P1 / 2 + 1, S2 = P2 / 2 + 1, S3 = L / 2 + 1;
-  const int64_t SO = (int64_t)S1 * S2 * S3;
+  const int S1 = P1 / 2 + 1, S3 = L / 2 + 1;
   const int f2 = k2 <= P2 / 2 ? k2 : P2 - k2;
   const R s2 = k2 <= P2 / 2 ? (R)1 : (R)-1;
 #pragma unroll
@@ -418,11 +419,11 @@ __global__ __launch_bounds__(256) void k_fft_z_conv(cx<R>* __restrict__ buf, int
     int f3 = k3 <= L / 2 ? k3 : L - k3;
     R s1 = k1 <= P1 / 2 ? (R)1 : (R)-1;
     R s3 = k3 <= L / 2 ? (R)1 : (R)-1;
-    int64_t idx = f1 + (int64_t)S1 * (f2 + (int64_t)S2 * f3);
-    cx<R> Txx = spec[idx], Tyy = spec[SO + idx], Tzz = spec[2 * SO + idx];
-    cx<R> Txy = (s1 * s2) * spec[3 * SO + idx];
-    cx<R> Txz = (s1 * s3) * spec[4 * SO + idx];
-    cx<R> Tyz = (s2 * s3) * spec[5 * SO + idx];
+    const cx<R>* rec = spec + 6 * (((int64_t)f2 * S1 + f1) * S3 + f3);
+    cx<R> Txx = rec[0], Tyy = rec[1], Tzz = rec[2];
+    cx<R> Txy = (s1 * s2) * rec[3];
+    cx<R> Txz = (s1 * s3) * rec[4];
+    cx<R> Tyz = (s2 * s3) * rec[5];
     cx<R> x = X[0][u], y = X[1][u], z = X[2][u];
     X[0][u] = Txx * x + Txy * y + Txz * z;
     X[1][u] = Txy * x + Tyy * y + Tyz * z;
@@ -541,6 +542,210 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
   }
 }
 
+// Fused z pass as a mixed-radix Stockham FFT whose first and last stages run in registers:
+// T = L / V threads per pencil, V values per thread, NP pencils per block. Radices V, V, ...,
+// then the remainder; a radix-R stage with sub-length Ls takes butterfly b < L / R from positions
+// b + (L / R) q and writes position (b - b mod Ls) R + b mod Ls + q Ls. The last forward stage
+// leaves thread j holding X[b + (L / R) q] for its butterflies b = j + T i, which are exactly the
+// inputs of the first inverse stage (same radix), so the 3 x 3 spectral multiply sits between
+// them without an exchange. Between stages one LDS exchange per component.
+template <int L, int V> struct ZRad {   // radix of stage s of the forward transform (product = L)
+  static constexpr int lg(int x) { return x <= 1 ? 0 : 1 + lg(x / 2); }
+  static constexpr int nst = (lg(L) + lg(V) - 1) / lg(V);
+  static constexpr int rad(int s) {
+    int r = 1;
+    for (int i = 0; i < nst - 1; ++i) r *= V;
+    return (s + 1 < nst) ? V : L / r;
+  }
+};
+
+template <typename R, int RAD, bool FWD>
+__device__ inline void small_dft(cx<R>* a, const cx<R>* __restrict__ tw, int tw_stride) {
+  // in-place DFT of length RAD on a[0..RAD) (natural order in and out); w_RAD^k = tw[k tw_stride]
+  cx<R> v[RAD];
+#pragma unroll
+  for (int q = 0; q < RAD; ++q) v[bitrev_of(q, RAD)] = a[q];
+#pragma unroll
+  for (int ln = 2; ln <= RAD; ln <<= 1) {
+#pragma unroll
+    for (int i = 0; i < RAD; i += ln) {
+#pragma unroll
+      for (int j = 0; j < ln / 2; ++j) {
+        cx<R> t = v[i + j + ln / 2];
+        if (j != 0) {
+          cx<R> w = tw[(j * (RAD / ln)) * tw_stride];
+          if (!FWD) w.im = -w.im;
+          t = w * t;
+        }
+        const cx<R> u = v[i + j];
+        v[i + j] = u + t;
+        v[i + j + ln / 2] = u - t;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RAD; ++q) a[q] = v[q];
+}
+
+// radix-RAD stage on the thread's V / RAD butterflies b = j + T i held in v[i * RAD + q]
+template <typename R, int L, int V, int RAD, bool FWD>
+__device__ inline void zstage(cx<R>* v, int j, int Ls, const cx<R>* __restrict__ tw) {
+  constexpr int T = L / V;
+  constexpr int NB = V / RAD;
+  const int tstep = L / (RAD * Ls);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = j + T * i;
+    const int kk = b & (Ls - 1);
+    cx<R>* a = v + i * RAD;
+    if (Ls > 1) {
+#pragma unroll
+      for (int q = 1; q < RAD; ++q) {
+        cx<R> w = tw[(q * kk * tstep) & (L - 1)];
+        if (!FWD) w.im = -w.im;
+        a[q] = a[q] * w;
+      }
+    }
+    small_dft<R, RAD, FWD>(a, tw, L / RAD);
+  }
+}
+template <typename R, int L, int V, int RAD>
+__device__ inline void zstore(cx<R>* Sp, const cx<R>* v, int j, int Ls) {
+  constexpr int T = L / V;
+  constexpr int NB = V / RAD;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = j + T * i;
+    const int kk = b & (Ls - 1);
+    const int base = (b - kk) * RAD + kk;
+#pragma unroll
+    for (int q = 0; q < RAD; ++q) Sp[base + q * Ls] = v[i * RAD + q];
+  }
+}
+template <typename R, int L, int V, int RAD>
+__device__ inline void zload(const cx<R>* Sp, cx<R>* v, int j) {
+  constexpr int T = L / V;
+  constexpr int NB = V / RAD;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int q = 0; q < RAD; ++q) v[i * RAD + q] = Sp[j + T * i + (L / RAD) * q];
+}
+
+template <typename R, int L, int V, bool FWD, int RAD>
+__device__ inline void zstep(cx<R>* Sp, cx<R>* v, int j, int Ls, bool load, bool store,
+                             const cx<R>* __restrict__ tw) {
+  if (load) {
+    __syncthreads();
+    zload<R, L, V, RAD>(Sp, v, j);
+  }
+  zstage<R, L, V, RAD, FWD>(v, j, Ls, tw);
+  if (store) {
+    if (load) __syncthreads();
+    zstore<R, L, V, RAD>(Sp, v, j, Ls);
+  }
+}
+template <typename R, int L, int V, bool FWD>
+__device__ inline void zstep_any(int rad, cx<R>* Sp, cx<R>* v, int j, int Ls, bool load, bool store,
+                                 const cx<R>* __restrict__ tw) {
+  if (rad == V) zstep<R, L, V, FWD, V>(Sp, v, j, Ls, load, store, tw);
+  else if (rad == V / 2 && V >= 4) zstep<R, L, V, FWD, (V >= 4 ? V / 2 : 2)>(Sp, v, j, Ls, load, store, tw);
+  else if (rad == V / 4 && V >= 8) zstep<R, L, V, FWD, (V >= 8 ? V / 4 : 2)>(Sp, v, j, Ls, load, store, tw);
+}
+
+// all stages of one transform; the first forward (last inverse) stage works on registers only
+template <typename R, int L, int V, bool FWD>
+__device__ inline void zfft(cx<R>* Sp, cx<R>* v, int j, const cx<R>* __restrict__ tw) {
+  using Z = ZRad<L, V>;
+  int Ls = 1;
+  if (FWD) {
+#pragma unroll
+    for (int s = 0; s < Z::nst; ++s) {
+      zstep_any<R, L, V, true>(Z::rad(s), Sp, v, j, Ls, s > 0, s + 1 < Z::nst, tw);
+      Ls *= Z::rad(s);
+    }
+  } else {
+#pragma unroll
+    for (int s = Z::nst - 1; s >= 0; --s) {
+      zstep_any<R, L, V, false>(Z::rad(s), Sp, v, j, Ls, s < Z::nst - 1, s > 0, tw);
+      Ls *= Z::rad(s);
+    }
+  }
+}
+
+template <typename R, int L, int V, int NP>
+__global__ __launch_bounds__(NP * L / V) void k_zconv3(cx<R>* __restrict__ buf, int n3, int P1, int P2,
+                                                       const cx<R>* __restrict__ spec, const cx<R>* __restrict__ tw,
+                                                       const int* __restrict__ order) {
+  constexpr int T = L / V;
+  constexpr int RAD_LAST = ZRad<L, V>::rad(ZRad<L, V>::nst - 1);
+  constexpr int NB_LAST = V / RAD_LAST;
+  __shared__ cx<R> S[NP * (L + 1)];
+  const int t = threadIdx.x;
+  const int p = t % NP, j = t / NP;
+  // the block order puts the (up to four) blocks that read the same folded spectra next to
+  // each other: k2 with P2 - k2 and each k1 tile with its mirror tile
+  const int k2 = order[2 * blockIdx.x];
+  const int k1 = order[2 * blockIdx.x + 1] * NP + p;
+  const bool valid = k1 < P1;
+  const int64_t plane = (int64_t)P1 * P2, comp = plane * n3;
+  cx<R>* col = buf + (int64_t)k2 * P1 + (valid ? k1 : 0);
+  cx<R>* Sp = S + p * (L + 1);
+  cx<R> H[3][V];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    // first stage input x[j + T q]; planes at or beyond L / 2 >= n3 are zero
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int n = j + T * q;
+      H[c][q] = (2 * q < V && valid && n < n3) ? col[c * comp + (int64_t)n * plane] : cx<R>{0, 0};
+    }
+    if (c > 0) __syncthreads();   // the previous component's last exchange has been read
+    zfft<R, L, V, true>(Sp, H[c], j, tw);
+  }
+  // spectral 3 x 3 multiply: H[c][i RAD_LAST + q] is X[k3], k3 = j + T i + (L / RAD_LAST) q
+  {
+    const int S1 = P1 / 2 + 1, S3 = L / 2 + 1;
+    const int f1 = k1 <= P1 / 2 ? k1 : P1 - k1;
+    const int f2 = k2 <= P2 / 2 ? k2 : P2 - k2;
+    const R s1 = k1 <= P1 / 2 ? (R)1 : (R)-1;
+    const R s2 = k2 <= P2 / 2 ? (R)1 : (R)-1;
+    const cx<R>* sp = spec + (valid ? 6 * ((int64_t)f2 * S1 + f1) * S3 : 0);
+#pragma unroll
+    for (int i = 0; i < NB_LAST; ++i)
+#pragma unroll
+      for (int q = 0; q < RAD_LAST; ++q) {
+        const int k3 = j + T * i + (L / RAD_LAST) * q;
+        const int f3 = k3 <= L / 2 ? k3 : L - k3;
+        const R s3 = k3 <= L / 2 ? (R)1 : (R)-1;
+        const cx<R>* rec = sp + 6 * f3;
+        const cx<R> Txx = rec[0], Tyy = rec[1], Tzz = rec[2];
+        const cx<R> Txy = (s1 * s2) * rec[3];
+        const cx<R> Txz = (s1 * s3) * rec[4];
+        const cx<R> Tyz = (s2 * s3) * rec[5];
+        const int e = i * RAD_LAST + q;
+        const cx<R> x = H[0][e], y = H[1][e], z = H[2][e];
+        H[0][e] = Txx * x + Txy * y + Txz * z;
+        H[1][e] = Txy * x + Tyy * y + Tyz * z;
+        H[2][e] = Txz * x + Tyz * y + Tzz * z;
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    __syncthreads();   // LDS free for this component's exchanges
+    zfft<R, L, V, false>(Sp, H[c], j, tw);
+    // last inverse stage output: thread holds x[j + T q]
+#pragma unroll
+    for (int q = 0; q < V / 2; ++q) {
+      const int n = j + T * q;
+      if (valid && n < n3) col[c * comp + (int64_t)n * plane] = H[c][q];
+    }
+  }
+}
+
+#ifndef ZCONV_V64
+#define ZCONV_V64 4
+#endif
 template <int L> struct Split;
 template <> struct Split<8> { static constexpr int A = 4, B = 2; };
 template <> struct Split<16> { static constexpr int A = 4, B = 4; };
@@ -609,8 +814,78 @@ void fft_strided(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, i
   });
 }
 
+int zconv_pencils(int L, bool fp64) {
+  if (L < 64 || L > 1024) return 0;
+  return 256 * (fp64 ? ZCONV_V64 : 8) / L;
+}
+
+std::vector<int> zconv_order(int L, int P1, int P2, bool fp64) {
+  // Blocks that share spectral records (k2 and P2 - k2; k1 tiles t and TL - 1 - t) and input
+  // cache lines (neighbouring tiles t, t + 1) form groups of up to eight. Workgroups are handed
+  // to the eight XCDs round-robin, so the members of a full group are placed eight positions
+  // apart: they run on one XCD, one after another, and share its L2.
+  const int NP = zconv_pencils(L, fp64);
+  std::vector<int> ord;
+  if (NP == 0) return ord;
+  const int TL = (P1 + NP - 1) / NP;
+  std::vector<std::vector<std::pair<int, int>>> groups;
+  std::vector<char> seen((size_t)TL, 0);
+  for (int f2 = 0; f2 <= P2 / 2; ++f2) {
+    std::vector<int> k2s = {f2};
+    if (f2 != 0 && 2 * f2 != P2) k2s.push_back(P2 - f2);
+    std::fill(seen.begin(), seen.end(), 0);
+    for (int t = 0; t < TL; ++t) {
+      if (seen[t]) continue;
+      std::vector<int> ts;
+      for (int u : {t, t + 1, TL - 1 - t, TL - 2 - t})
+        if (u >= 0 && u < TL && !seen[u]) {
+          seen[u] = 1;
+          ts.push_back(u);
+        }
+      std::vector<std::pair<int, int>> g;
+      for (int k2 : k2s)
+        for (int u : ts) g.push_back({k2, u});
+      groups.push_back(g);
+    }
+  }
+  const size_t full = 8;
+  std::vector<const std::vector<std::pair<int, int>>*> big, rest;
+  for (const auto& g : groups) (g.size() == full ? big : rest).push_back(&g);
+  ord.reserve(2 * (size_t)P2 * TL);
+  const size_t nchunk = big.size() / 8;
+  for (size_t c = 0; c < nchunk; ++c)
+    for (size_t m = 0; m < full; ++m)
+      for (size_t j = 0; j < 8; ++j) {
+        const auto& e = (*big[c * 8 + j])[m];
+        ord.push_back(e.first);
+        ord.push_back(e.second);
+      }
+  for (size_t i = nchunk * 8; i < big.size(); ++i) rest.push_back(big[i]);
+  for (const auto* g : rest)
+    for (const auto& e : *g) {
+      ord.push_back(e.first);
+      ord.push_back(e.second);
+    }
+  return ord;
+}
+
 template <typename R>
-void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const cx<R>* spec, const cx<R>* tw) {
+void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const cx<R>* spec, const cx<R>* tw,
+                const int* order) {
+  // register-staged Stockham variant: V values per thread and component, 256 threads per block
+  if (L >= 64 && L <= 1024) {
+    if (!order) throw Error(VSIE_E_STATE, "z-pass block order missing");
+    VSIE_FFT_SWITCH(L, {
+      if constexpr (LL >= 64) {
+        constexpr int V = sizeof(R) == 8 ? ZCONV_V64 : 8;
+        constexpr int NP = 256 * V / LL;
+        dim3 grid((unsigned)(P2 * ((P1 + NP - 1) / NP)));
+        hipLaunchKernelGGL((k_zconv3<R, LL, V, NP>), grid, dim3(NP * LL / V), 0, st, buf, n3, P1, P2, spec, tw,
+                           order);
+      }
+    });
+    return;
+  }
   VSIE_FFT_SWITCH(L, {
     constexpr int TP = zconv_tp<R>(LL);
     dim3 grid((unsigned)(P2 * ((P1 + TP - 1) / TP)));
@@ -624,8 +899,8 @@ template void fft_strided<double>(hipStream_t, int, bool, const cxd*, cxd*, int,
                                   int64_t, int64_t, const cxd*);
 template void fft_strided<float>(hipStream_t, int, bool, const cxf*, cxf*, int, int, int64_t, int64_t, int, int64_t,
                                  int64_t, int64_t, const cxf*);
-template void fft_z_conv<double>(hipStream_t, int, cxd*, int, int, int, const cxd*, const cxd*);
-template void fft_z_conv<float>(hipStream_t, int, cxf*, int, int, int, const cxf*, const cxf*);
+template void fft_z_conv<double>(hipStream_t, int, cxd*, int, int, int, const cxd*, const cxd*, const int*);
+template void fft_z_conv<float>(hipStream_t, int, cxf*, int, int, int, const cxf*, const cxf*, const int*);
 
 // =============================================================================================
 // Matvec kernels
@@ -881,31 +1156,43 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const cx<R>* __restrict__ Zp
   }
 }
 
-// y[i] = sum_{J >= I} rowpart(I, J)[i] + sum_{J < I} colpart(J, I)[i], I = i / SYM_TB (fixed order)
+// y[i] = sum_{J >= I} rowpart(I, J)[i] + sum_{J < I} colpart(J, I)[i], I = i / SYM_TB; a block
+// covers 64 outputs with four wavefronts taking every fourth J (fixed order)
 template <typename R>
-__global__ void k_symv_reduce(const cx<R>* __restrict__ part, int T, int m, cx<R>* __restrict__ y, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const int I = i / SYM_TB, li = i % SYM_TB;
+__global__ __launch_bounds__(256) void k_symv_reduce(const cx<R>* __restrict__ part, int T, int m,
+                                                     cx<R>* __restrict__ y, int accumulate) {
+  __shared__ R rr[4][64], ri[4][64];
+  const int o = threadIdx.x % 64, sl = threadIdx.x / 64;
+  const int i = blockIdx.x * 64 + o;
   cx<R> acc = {0, 0};
-  for (int J = 0; J < T; ++J) {
-    if (J < I) {
-      int64_t t = (int64_t)J * T - (int64_t)J * (J - 1) / 2 + (I - J);
-      acc += part[t * 2 * SYM_TB + SYM_TB + li];
-    } else {
-      int64_t t = (int64_t)I * T - (int64_t)I * (I - 1) / 2 + (J - I);
-      acc += part[t * 2 * SYM_TB + li];
+  if (i < m) {
+    const int I = i / SYM_TB, li = i % SYM_TB;
+    for (int J = sl; J < T; J += 4) {
+      if (J < I) {
+        const int64_t t = (int64_t)J * T - (int64_t)J * (J - 1) / 2 + (I - J);
+        acc += part[t * 2 * SYM_TB + SYM_TB + li];
+      } else {
+        const int64_t t = (int64_t)I * T - (int64_t)I * (I - 1) / 2 + (J - I);
+        acc += part[t * 2 * SYM_TB + li];
+      }
     }
   }
-  if (accumulate) y[i] += acc;
-  else y[i] = acc;
+  rr[sl][o] = acc.re;
+  ri[sl][o] = acc.im;
+  __syncthreads();
+  if (sl == 0 && i < m) {
+    const cx<R> v = {(rr[0][o] + rr[1][o]) + (rr[2][o] + rr[3][o]), (ri[0][o] + ri[1][o]) + (ri[2][o] + ri[3][o])};
+    if (accumulate) y[i] += v;
+    else y[i] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Batched strided complex GEMM, C(i,j) = sum_k A(i,k) B(k,j), with element (i,j) of batch b at
-// X[i sr + j sc + b sb]. Optional mask on B (mask index = B's element index) and masked
-// accumulation into C. 32 x 32 output tile per block of 256 threads, K staged in chunks of 16
-// through LDS; each thread owns a 2 x 2 output patch.
+// X[i sr + j sc + b sb]. Up to three independent problems share one launch (blockIdx.z runs over
+// their batches in turn). Optional mask on B (mask index = B's element index relative to the
+// batch) and masked accumulation into C. Split-K use: batch b covers K indices [b K, b K + K)
+// of a contraction of length ktot, the last batch taking the remainder.
 template <typename R> struct GemmArgs {
   const cx<R>* A;
   int64_t sar, sac, sab;
@@ -914,64 +1201,88 @@ template <typename R> struct GemmArgs {
   cx<R>* C;
   int64_t scr, scc, scb;
   int M, N, K;
+  int64_t ktot;           // > 0: split-K over batches
   const uint8_t* maskB;
   const uint8_t* maskC;   // non-null: C += maskC * AB (mask index = C's element index)
   int accumulate;
 };
+template <typename R> struct GemmSet {
+  GemmArgs<R> g[3];
+  int nbatch[3];
+  int nprob;
+};
 
+// 64 x 64 output tile per block of 256 threads, 4 x 4 outputs per thread (rows ty + 16u, columns
+// tx + 16v); K staged through LDS in chunks of 16. Tile loaders walk each operand's unit-stride
+// dimension fastest; neighbouring threads store along C's unit-stride dimension.
 template <typename R>
-__global__ __launch_bounds__(256) void k_gemm_strided(GemmArgs<R> g) {
-  __shared__ cx<R> As[32][17];
-  __shared__ cx<R> Bs[16][33];
-  const int b = blockIdx.z;
-  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
-  // output patches: neighbouring threads step along C's unit-stride dimension
+__global__ __launch_bounds__(256) void k_zgemm64(GemmSet<R> S) {
+  __shared__ cx<R> As[64][17];
+  __shared__ cx<R> Bs[16][65];
+  int z = blockIdx.z, pi = 0;
+  while (pi + 1 < S.nprob && z >= S.nbatch[pi]) {
+    z -= S.nbatch[pi];
+    ++pi;
+  }
+  const GemmArgs<R>& g = pi == 0 ? S.g[0] : (pi == 1 ? S.g[1] : S.g[2]);
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  int K = g.K;
+  if (g.ktot > 0) K = (int)(g.ktot - (int64_t)z * g.K < g.K ? g.ktot - (int64_t)z * g.K : g.K);
+  if (i0 >= g.M || j0 >= g.N || K <= 0) return;
   const bool c_rowfast = g.scc != 1 && g.scr == 1;
   const int tx = c_rowfast ? threadIdx.x / 16 : threadIdx.x % 16;
   const int ty = c_rowfast ? threadIdx.x % 16 : threadIdx.x / 16;
-  const cx<R>* A = g.A + b * g.sab;
-  const cx<R>* B = g.B + b * g.sbb;
-  const uint8_t* mB = g.maskB ? g.maskB + b * g.sbb : nullptr;
-  cx<R> acc[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
-  // tile loaders walk the operand's unit-stride dimension fastest so loads coalesce
   const bool a_rowfast = g.sac != 1 && g.sar == 1;
   const bool b_rowfast = g.sbc != 1 && g.sbr == 1;
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
-    for (int e = threadIdx.x; e < 32 * 16; e += 256) {
-      int r = a_rowfast ? e % 32 : e / 16, c = a_rowfast ? e / 32 : e % 16;   // A tile rows i0+r, cols k0+c
-      int i = i0 + r, k = k0 + c;
-      As[r][c] = (i < g.M && k < g.K) ? A[i * g.sar + k * g.sac] : cx<R>{0, 0};
-      int rb = b_rowfast ? e % 16 : e / 32, cb = b_rowfast ? e / 16 : e % 32; // B tile rows k0+rb, cols j0+cb
-      int kk = k0 + rb, j = j0 + cb;
+  const cx<R>* A = g.A + z * g.sab;
+  const cx<R>* B = g.B + z * g.sbb;
+  const uint8_t* mB = g.maskB ? g.maskB + z * g.sbb : nullptr;
+  cx<R> acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = cx<R>{0, 0};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int r = a_rowfast ? e % 64 : e / 16, c = a_rowfast ? e / 64 : e % 16;
+      const int i = i0 + r, k = k0 + c;
+      As[r][c] = (i < g.M && k < K) ? A[i * g.sar + k * g.sac] : cx<R>{0, 0};
+      const int rb = b_rowfast ? e % 16 : e / 64, cb = b_rowfast ? e / 16 : e % 64;
+      const int kk = k0 + rb, j = j0 + cb;
       cx<R> v = {0, 0};
-      if (kk < g.K && j < g.N) {
-        int64_t idx = kk * g.sbr + j * g.sbc;
+      if (kk < K && j < g.N) {
+        const int64_t idx = kk * g.sbr + j * g.sbc;
         v = B[idx];
         if (mB && !mB[idx]) v = cx<R>{0, 0};
       }
       Bs[rb][cb] = v;
     }
     __syncthreads();
-#pragma unroll
+#pragma unroll 4
     for (int k = 0; k < 16; ++k) {
-      cx<R> a0 = As[ty][k], a1 = As[ty + 16][k];
-      cx<R> b0 = Bs[k][tx], b1 = Bs[k][tx + 16];
-      acc[0][0] += a0 * b0;
-      acc[0][1] += a0 * b1;
-      acc[1][0] += a1 * b0;
-      acc[1][1] += a1 * b1;
+      cx<R> a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = As[ty + 16 * u][k];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = Bs[k][tx + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
     }
     __syncthreads();
   }
-  cx<R>* C = g.C + b * g.scb;
-  const uint8_t* mC = g.maskC ? g.maskC + b * g.scb : nullptr;
+  cx<R>* C = g.C + z * g.scb;
+  const uint8_t* mC = g.maskC;
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      int i = i0 + ty + 16 * u, j = j0 + tx + 16 * v;
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ty + 16 * u, j = j0 + tx + 16 * v;
       if (i >= g.M || j >= g.N) continue;
-      int64_t idx = i * g.scr + j * g.scc;
+      const int64_t idx = i * g.scr + j * g.scc;
       if (mC) {
         if (mC[idx]) C[idx] += acc[u][v];
       } else if (g.accumulate) {
@@ -982,28 +1293,49 @@ __global__ __launch_bounds__(256) void k_gemm_strided(GemmArgs<R> g) {
     }
 }
 
-// out[j2 * n3 + i3] = sum_b part[b][i3][j2]  (split-K reduction of the transposed G2 step)
-template <typename R>
-__global__ void k_splitk_reduce(const cx<R>* __restrict__ part, int nb, int n3, int r2, cx<R>* __restrict__ out) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n3 * r2) return;
-  const int j2 = id % r2, i3 = id / r2;
-  cx<R> acc = {0, 0};
-  for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * n3 * r2 + id];
-  out[(int64_t)j2 * n3 + i3] = acc;
+template <typename R> static void zgemm(hipStream_t st, const GemmSet<R>& S) {
+  int mx = 0, nx = 0, nz = 0;
+  for (int p = 0; p < S.nprob; ++p) {
+    mx = std::max(mx, S.g[p].M);
+    nx = std::max(nx, S.g[p].N);
+    nz += S.nbatch[p];
+  }
+  if (mx <= 0 || nx <= 0 || nz <= 0) return;
+  hipLaunchKernelGGL(k_zgemm64<R>, dim3((nx + 63) / 64, (mx + 63) / 64, nz), dim3(256), 0, st, S);
 }
 
-template <typename R> static void gemm(hipStream_t st, const GemmArgs<R>& g, int batch) {
-  if (g.M <= 0 || g.N <= 0 || batch <= 0) return;
-  dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, batch);
-  hipLaunchKernelGGL(k_gemm_strided<R>, grid, dim3(256), 0, st, g);
+// s2[c][j2][i3] = sum_b part[c][b][j2][i3]  (split-K reduction of the transpose contraction);
+// a block covers 32 outputs with 8 slices over b
+template <typename R>
+__global__ __launch_bounds__(256) void k_tt_ksum(TTDesc<R> T, const cx<R>* __restrict__ part, int nkc, int n3,
+                                                 cx<R>* __restrict__ s2) {
+  __shared__ R rr[8][32], ri[8][32];
+  const int c = blockIdx.y;
+  const int o = threadIdx.x % 32, sl = threadIdx.x / 32;
+  const int id = blockIdx.x * 32 + o;
+  const bool live = id < T.r2[c] * n3;
+  cx<R> acc = {0, 0};
+  if (live) {
+    const cx<R>* p = part + (int64_t)c * nkc * TT_RMAX * n3 + id;
+    for (int b = sl; b < nkc; b += 8) acc += p[(int64_t)b * TT_RMAX * n3];
+  }
+  rr[sl][o] = acc.re;
+  ri[sl][o] = acc.im;
+  __syncthreads();
+  if (sl == 0 && live) {
+    cx<R> s = {0, 0};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += cx<R>{rr[q][o], ri[q][o]};
+    s2[(int64_t)c * TT_RMAX * n3 + id] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Tensor-train far coupling (eqs. (16)-(19)). Cores row-major: G1[i1][j1], G2[j1][i2][j2],
-// G3[j2][i3][j3], G4[j3][i4]. Intermediates per component:
-//   forward   t4[j3] -> t3[j2][i3] -> T2[j1][q] (q = i2 + n2 i3) -> y_b[i1 + n1 q]
-//   transpose S1[i3][j1][i2] -> S2[j2][i3] -> s3[j3] -> y_f[i4]
+// Tensor-train far coupling (eqs. (16)-(19)). Cores row-major: G3[j2][i3][j3], G4[j3][i4]; the
+// first two cores are held contracted, M[j2][p] = sum_j1 G1[i1][j1] G2[j1][i2][j2] with
+// p = i1 + n1 i2 (n1 n2 r2 entries, a few MB). Intermediates per component:
+//   forward   t4[j3] -> t3[j2][i3] -> y_b[p + n1 n2 i3] += mask * sum_j2 M[j2][p] t3[j2][i3]
+//   transpose S2[j2][i3] = sum_p M[j2][p] mask x_b[p + n1 n2 i3] -> s3[j3] -> y_f[i4]
 
 // forward, G4 first: part[c][j3][chunk] = sum_{i4 in chunk} G4[j3][i4] x_f[i4]
 template <typename R>
@@ -1030,58 +1362,80 @@ __global__ __launch_bounds__(256) void k_tt_f4(TTDesc<R> T, const cx<R>* __restr
   if (threadIdx.x == 0) part[((int64_t)c * TT_RMAX + j3) * nchunk + ch] = cx<R>{rr[0], ri[0]};
 }
 
-// t3[c][j2][i3] = sum_j3 G3[j2][i3][j3] t4[j3], t4 summed from the partials
+// t3[c][row] = sum_j3 G3[row][j3] t4[j3] over rows (j2, i3) of G3; t4 summed from the partials
+// into LDS first; 16 lanes per row read it contiguously, 16 rows per block
 template <typename R>
-__global__ void k_tt_f3(TTDesc<R> T, const cx<R>* __restrict__ part, int nchunk, int n3, cx<R>* __restrict__ t3) {
-  const int c = blockIdx.z;
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_tt_f3(TTDesc<R> T, const cx<R>* __restrict__ part, int nchunk, int n3,
+                                               cx<R>* __restrict__ t3) {
+  __shared__ cx<R> t4[TT_RMAX];
+  const int c = blockIdx.y;
   const int r2 = T.r2[c], r3 = T.r3[c];
-  if (id >= r2 * n3) return;
-  cx<R> acc = {0, 0};
-  for (int j3 = 0; j3 < r3; ++j3) {
-    cx<R> t4 = {0, 0};
-    for (int ch = 0; ch < nchunk; ++ch) t4 += part[((int64_t)c * TT_RMAX + j3) * nchunk + ch];
-    acc += T.G3[c][(int64_t)id * r3 + j3] * t4;
+  for (int j3 = threadIdx.x; j3 < r3; j3 += 256) {
+    cx<R> acc = {0, 0};
+    for (int ch = 0; ch < nchunk; ++ch) acc += part[((int64_t)c * TT_RMAX + j3) * nchunk + ch];
+    t4[j3] = acc;
   }
-  t3[(int64_t)c * TT_RMAX * n3 + id] = acc;
+  __syncthreads();
+  const int row = blockIdx.x * 16 + threadIdx.x / 16;
+  const int lane = threadIdx.x % 16;
+  cx<R> acc = {0, 0};
+  if (row < r2 * n3) {
+    const cx<R>* g = T.G3[c] + (int64_t)row * r3;
+    for (int j3 = lane; j3 < r3; j3 += 16) acc += g[j3] * t4[j3];
+  }
+  for (int off = 8; off > 0; off >>= 1) {
+    acc.re += __shfl_xor(acc.re, off, 16);
+    acc.im += __shfl_xor(acc.im, off, 16);
+  }
+  if (lane == 0 && row < r2 * n3) t3[(int64_t)c * TT_RMAX * n3 + row] = acc;
 }
 
-// s3[c][j3] = sum_{j2, i3} G3[j2][i3][j3] S2[c][j2][i3]; one block per component
+// partial sums of s3[c][j3] = sum_k G3[k][j3] S2[c][k] over rows k = (j2, i3) of G3, TT_KROWS rows
+// per block: part[blk][c TT_RMAX + j3] (zero for j3 >= r3)
+constexpr int TT_KROWS = 64;
 template <typename R>
 __global__ __launch_bounds__(256) void k_ttT_3(TTDesc<R> T, const cx<R>* __restrict__ s2, int n3,
-                                               cx<R>* __restrict__ s3) {
-  __shared__ R rr[256], ri[256];
-  const int c = blockIdx.z;
+                                               cx<R>* __restrict__ part) {
+  __shared__ R rr[4][TT_RMAX], ri[4][TT_RMAX];
+  const int c = blockIdx.y;
   const int r2 = T.r2[c], r3 = T.r3[c];
-  const int lane = threadIdx.x % 32, slice = threadIdx.x / 32;
   const int K = r2 * n3;
+  const int lane = threadIdx.x % 64, sl = threadIdx.x / 64;
+  const int k0 = blockIdx.x * TT_KROWS;
   const cx<R>* sv = s2 + (int64_t)c * TT_RMAX * n3;
-  for (int j0 = 0; j0 < r3; j0 += 32) {
-    const int j3 = j0 + lane;
+  for (int j3 = lane; j3 < TT_RMAX; j3 += 64) {
     cx<R> acc = {0, 0};
     if (j3 < r3)
-      for (int k = slice; k < K; k += 8) acc += T.G3[c][(int64_t)k * r3 + j3] * sv[k];
-    rr[threadIdx.x] = acc.re;
-    ri[threadIdx.x] = acc.im;
-    __syncthreads();
-    if (slice == 0 && j3 < r3) {
-      cx<R> s = {0, 0};
-      for (int q = 0; q < 8; ++q) s += cx<R>{rr[q * 32 + lane], ri[q * 32 + lane]};
-      s3[c * TT_RMAX + j3] = s;
-    }
-    __syncthreads();
+      for (int k = k0 + sl; k < k0 + TT_KROWS && k < K; k += 4) acc += T.G3[c][(int64_t)k * r3 + j3] * sv[k];
+    rr[sl][j3] = acc.re;
+    ri[sl][j3] = acc.im;
   }
+  __syncthreads();
+  for (int j3 = threadIdx.x; j3 < TT_RMAX; j3 += 256)
+    part[(int64_t)blockIdx.x * 3 * TT_RMAX + c * TT_RMAX + j3] =
+        cx<R>{(rr[0][j3] + rr[1][j3]) + (rr[2][j3] + rr[3][j3]), (ri[0][j3] + ri[1][j3]) + (ri[2][j3] + ri[3][j3])};
 }
 
-// y_f[i4] += sum_c sum_j3 G4[c][j3][i4] s3[c][j3]
+// y_f[i4] += sum_c sum_j3 G4[c][j3][i4] s3[c][j3]; 64 rows per block, four wavefronts split j3
 template <typename R>
-__global__ void k_ttT_4(TTDesc<R> T, const cx<R>* __restrict__ s3, int mf, cx<R>* __restrict__ yf) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= mf) return;
+__global__ __launch_bounds__(256) void k_ttT_4(TTDesc<R> T, const cx<R>* __restrict__ s3, int mf,
+                                               cx<R>* __restrict__ yf) {
+  __shared__ cx<R> sv[3 * TT_RMAX];
+  __shared__ R rr[4][64], ri[4][64];
+  for (int l = threadIdx.x; l < 3 * TT_RMAX; l += 256) sv[l] = s3[l];
+  __syncthreads();
+  const int row = threadIdx.x % 64, sl = threadIdx.x / 64;
+  const int64_t i = (int64_t)blockIdx.x * 64 + row;
   cx<R> acc = {0, 0};
-  for (int c = 0; c < 3; ++c)
-    for (int j3 = 0; j3 < T.r3[c]; ++j3) acc += T.G4[c][(int64_t)j3 * mf + i] * s3[c * TT_RMAX + j3];
-  yf[i] += acc;
+  if (i < mf)
+    for (int c = 0; c < 3; ++c)
+      for (int j3 = sl; j3 < T.r3[c]; j3 += 4) acc += T.G4[c][(int64_t)j3 * mf + i] * sv[c * TT_RMAX + j3];
+  rr[sl][row] = acc.re;
+  ri[sl][row] = acc.im;
+  __syncthreads();
+  if (sl == 0 && i < mf)
+    yf[i] += cx<R>{(rr[0][row] + rr[1][row]) + (rr[2][row] + rr[3][row]),
+                   (ri[0][row] + ri[1][row]) + (ri[2][row] + ri[3][row])};
 }
 
 // =============================================================================================
@@ -1241,7 +1595,8 @@ template <typename R> void launch_gemv_rows(hipStream_t st, const cx<R>* A, cons
 template <typename R> void launch_tt(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
                                      const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* yb, cx<R>* work) {
   const int n1 = n[0], n2 = n[1], n3 = n[2];
-  const int64_t nq = (int64_t)n2 * n3, nv = (int64_t)n1 * nq;
+  const int n12 = n1 * n2;
+  const int64_t nv = (int64_t)n12 * n3;
   int rmax2 = 1, rmax3 = 1;
   for (int c = 0; c < 3; ++c) {
     rmax2 = std::max(rmax2, T.r2[c]);
@@ -1249,66 +1604,56 @@ template <typename R> void launch_tt(hipStream_t st, const TTDesc<R>& T, const i
   }
   const int chunk = 4096;
   const int nchunk = (mf + chunk - 1) / chunk;
+  const int kc = TT_KCHUNK;
+  const int nkc = (n12 + kc - 1) / kc;
   cx<R>* part = work;                                    // 3 * RMAX * nchunk
   cx<R>* t3 = part + 3LL * TT_RMAX * nchunk;             // 3 * RMAX * n3
-  cx<R>* big = t3 + 3LL * TT_RMAX * n3;                  // RMAX * nq (one component at a time)
-  // forward (eqs. (16)-(17)): G4 x first, then G3, G2, G1
+  cx<R>* kpart = t3 + 3LL * TT_RMAX * n3;                // 3 * nkc * RMAX * n3
+  // forward (eqs. (16)-(17)): G4 x first, then G3, then the merged first two cores
   hipLaunchKernelGGL(k_tt_f4<R>, dim3(nchunk, rmax3, 3), dim3(256), 0, st, T, xf, mf, chunk, part, nchunk);
-  hipLaunchKernelGGL(k_tt_f3<R>, dim3((rmax2 * n3 + 255) / 256, 1, 3), dim3(256), 0, st, T, part, nchunk, n3, t3);
+  hipLaunchKernelGGL(k_tt_f3<R>, dim3((rmax2 * n3 + 15) / 16, 3), dim3(256), 0, st, T, part, nchunk, n3, t3);
+  GemmSet<R> F{};
+  F.nprob = 3;
   for (int c = 0; c < 3; ++c) {
-    const int r1 = T.r1[c], r2 = T.r2[c];
-    // T2[j1][i3][i2] (= T2[j1][q], q = i2 + n2 i3) = sum_j2 t3[j2][i3] G2[j1][i2][j2], batched over j1:
-    // C(i3, i2) = A(i3, j2) B(j2, i2), stores along i2
-    GemmArgs<R> g2{t3 + (int64_t)c * TT_RMAX * n3, 1, n3, 0,
-                   T.G2[c], 1, r2, (int64_t)n2 * r2,
-                   big, n2, 1, nq, n3, n2, r2, nullptr, nullptr, 0};
-    gemm<R>(st, g2, r1);
-    // y_b[c][i1 + n1 q] += mask * sum_j1 T2[j1][q] G1[i1][j1]: C(q, i1) = A(q, j1) B(j1, i1)
-    GemmArgs<R> g1{big, 1, nq, 0, T.G1[c], 1, r1, 0, yb + (int64_t)c * nv, n1, 1, 0, (int)nq, n1, r1, nullptr, mask, 1};
-    gemm<R>(st, g1, 1);
+    // C(p, i3) = y_b[c][p + n12 i3] += mask * sum_j2 M[j2][p] t3[j2][i3]
+    F.g[c] = GemmArgs<R>{T.M[c], 1, n12, 0, t3 + (int64_t)c * TT_RMAX * n3, n3, 1, 0, yb + (int64_t)c * nv, 1, n12, 0,
+                         n12, n3, T.r2[c], 0, nullptr, mask, 1};
+    F.nbatch[c] = 1;
   }
-  // transpose (eqs. (18)-(19)): G1 first, summed over the components into y_f
+  zgemm<R>(st, F);
+  // transpose (eqs. (18)-(19)), summed over the components into y_f:
+  // S2(j2, i3) = sum_p M[j2][p] mask x_b[c][p + n12 i3], split over p in chunks of kc
+  GemmSet<R> B{};
+  B.nprob = 3;
+  for (int c = 0; c < 3; ++c) {
+    B.g[c] = GemmArgs<R>{T.M[c], n12, 1, kc, xb + (int64_t)c * nv, 1, n12, kc,
+                         kpart + (int64_t)c * nkc * TT_RMAX * n3, n3, 1, (int64_t)TT_RMAX * n3,
+                         T.r2[c], n3, kc, n12, mask, nullptr, 0};
+    B.nbatch[c] = nkc;
+  }
+  zgemm<R>(st, B);
   cx<R>* s2 = t3;
   cx<R>* s3 = part;
-  cx<R>* kpart = big + (int64_t)TT_RMAX * nq;            // split-K partials
-  for (int c = 0; c < 3; ++c) {
-    const int r1 = T.r1[c], r2 = T.r2[c];
-    // S1[i3][j1][i2] = sum_i1 G1[i1][j1] mask x_b[c][i1 + n1 (i2 + n2 i3)]   (batched over i3)
-    GemmArgs<R> h1{T.G1[c], 1, r1, 0, xb + (int64_t)c * nv, 1, n1, (int64_t)n1 * n2,
-                   big, n2, 1, (int64_t)r1 * n2, r1, n2, n1, mask, nullptr, 0};
-    gemm<R>(st, h1, n3);
-    // S2^T(i3, j2) = sum_k S1[i3][k] G2[k][j2], k = j1 n2 + i2, split over K in chunks of 128
-    const int K = r1 * n2;
-    const int kc = 128;
-    const int nb = (K + kc - 1) / kc;
-    GemmArgs<R> h2{big, (int64_t)K, 1, kc, T.G2[c], r2, 1, (int64_t)kc * r2,
-                   kpart, r2, 1, (int64_t)n3 * r2, n3, r2, kc, nullptr, nullptr, 0};
-    // the last chunk may be short: run full chunks, then the tail
-    gemm<R>(st, h2, K / kc);
-    if (K % kc) {
-      GemmArgs<R> tail = h2;
-      tail.A = big + (int64_t)(K / kc) * kc;
-      tail.B = T.G2[c] + (int64_t)(K / kc) * kc * r2;
-      tail.C = kpart + (int64_t)(K / kc) * n3 * r2;
-      tail.K = K % kc;
-      gemm<R>(st, tail, 1);
-    }
-    hipLaunchKernelGGL(k_splitk_reduce<R>, dim3((n3 * r2 + 255) / 256), dim3(256), 0, st, kpart, nb, n3, r2,
-                       s2 + (int64_t)c * TT_RMAX * n3);
-  }
-  hipLaunchKernelGGL(k_ttT_3<R>, dim3(1, 1, 3), dim3(256), 0, st, T, s2, n3, s3);
-  hipLaunchKernelGGL(k_ttT_4<R>, dim3((mf + 255) / 256), dim3(256), 0, st, T, s3, mf, yf);
+  hipLaunchKernelGGL(k_tt_ksum<R>, dim3((rmax2 * n3 + 31) / 32, 3), dim3(256), 0, st, T, kpart, nkc, n3, s2);
+  const int nk3 = (rmax2 * n3 + TT_KROWS - 1) / TT_KROWS;
+  cx<R>* s3part = kpart + 3LL * nkc * TT_RMAX * n3;   // nk3 x 3 RMAX
+  hipLaunchKernelGGL(k_ttT_3<R>, dim3(nk3, 3), dim3(256), 0, st, T, s2, n3, s3part);
+  hipLaunchKernelGGL(k_sum_partials<R>, dim3(3 * TT_RMAX), dim3(256), 0, st, s3part, nk3, 3 * TT_RMAX, s3);
+  hipLaunchKernelGGL(k_ttT_4<R>, dim3((mf + 63) / 64), dim3(256), 0, st, T, s3, mf, yf);
 }
 int64_t tt_work_elems(const int n[3], int mf) {
   const int nchunk = (mf + 4095) / 4096;
-  const int64_t kparts = (int64_t)((TT_RMAX * n[1] + 127) / 128) * n[2] * TT_RMAX;
-  return 3LL * TT_RMAX * nchunk + 3LL * TT_RMAX * n[2] + (int64_t)TT_RMAX * n[1] * n[2] + kparts;
+  const int nkc = (n[0] * n[1] + TT_KCHUNK - 1) / TT_KCHUNK;
+  const int nk3 = (TT_RMAX * n[2] + TT_KROWS - 1) / TT_KROWS;
+  return 3LL * TT_RMAX * nchunk + 3LL * TT_RMAX * n[2] + 3LL * nkc * TT_RMAX * n[2] + 3LL * TT_RMAX * nk3;
 }
-template <typename R> void launch_symv(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x, int m,
-                                       cx<R>* part, cx<R>* y) {
+template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
+                                             int m, cx<R>* part) {
   const int64_t nt = (int64_t)T * (T + 1) / 2;
   hipLaunchKernelGGL(k_symv_tiles<R>, dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, m, part);
-  hipLaunchKernelGGL(k_symv_reduce<R>, dim3((m + 255) / 256), dim3(256), 0, st, part, T, m, y, 0);
+}
+template <typename R> void launch_symv_reduce(hipStream_t st, const cx<R>* part, int T, int m, cx<R>* y) {
+  hipLaunchKernelGGL(k_symv_reduce<R>, dim3((m + 63) / 64), dim3(256), 0, st, part, T, m, y, 0);
 }
 template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, const double* vre, const double* vim,
                                              int ne, cx<R>* b) {
@@ -1329,7 +1674,8 @@ template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, co
   template void launch_tt<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*, const cx<R>*,           \
                              const uint8_t*, cx<R>*, cx<R>*, cx<R>*);                                                 \
   template void launch_scatter_rhs<R>(hipStream_t, const int*, const double*, const double*, int, cx<R>*);         \
-  template void launch_symv<R>(hipStream_t, const cx<R>*, const int*, int, const cx<R>*, int, cx<R>*, cx<R>*);
+  template void launch_symv_tiles<R>(hipStream_t, const cx<R>*, const int*, int, const cx<R>*, int, cx<R>*);      \
+  template void launch_symv_reduce<R>(hipStream_t, const cx<R>*, int, int, cx<R>*);
 VSIE_INST(double)
 VSIE_INST(float)
 

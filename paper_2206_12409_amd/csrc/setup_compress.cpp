@@ -6,7 +6,8 @@
 // maximum-volume rows give the next index set. Cores follow from the cross interpolation
 // formula G_k = Q_k Q_k[rows]^{-1}, G_4 = A(I_3, i_4). Ranks grow (with random enrichment of the
 // index sets) until the relative error measured on random held-out entries is below the
-// tolerance or the rank cap is reached. The paper uses the two-site DMRG variant of TT-cross;
+// tolerance or the rank cap is reached; a rank stops growing once its fibre matrix is
+// numerically rank deficient at the tolerance. The paper uses the two-site DMRG variant of TT-cross;
 // this one-site variant with explicit rank growth reaches the same accuracy target.
 #include <algorithm>
 #include <cmath>
@@ -43,6 +44,63 @@ void fibre(EntryFn& f, const std::vector<std::vector<int>>& left, int nk, int k,
         for (int q = 0; q < 4; ++q) idx.push_back(t[q]);
       }
   f.eval(idx, C);   // C[(a * nk + i) * rr + b]
+}
+
+// sigma_min / sigma_max of an m x n complex matrix (row-major, m >= n) from the eigenvalues of
+// its Gram matrix C^H C, computed by cyclic Jacobi on the equivalent real symmetric 2n x 2n
+// matrix [[Re, -Im], [Im, Re]] (each eigenvalue appears twice). Resolves ratios down to ~1e-7.
+double sv_ratio(const std::vector<cxd>& C, int m, int n) {
+  if (n <= 1) return 1.0;
+  std::vector<cxd> G((size_t)n * n, cxd{0, 0});
+  for (int r = 0; r < m; ++r) {
+    const cxd* row = &C[(size_t)r * n];
+    for (int a = 0; a < n; ++a)
+      for (int b = a; b < n; ++b) G[(size_t)a * n + b] += mul_conj_a(row[a], row[b]);
+  }
+  const int N2 = 2 * n;
+  std::vector<double> S((size_t)N2 * N2);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const cxd g = a <= b ? G[(size_t)a * n + b] : cxd{G[(size_t)b * n + a].re, -G[(size_t)b * n + a].im};
+      S[(size_t)a * N2 + b] = g.re;
+      S[(size_t)(a + n) * N2 + (b + n)] = g.re;
+      S[(size_t)(a + n) * N2 + b] = g.im;
+      S[(size_t)a * N2 + (b + n)] = -g.im;
+    }
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0, diag = 0;
+    for (int i = 0; i < N2; ++i) {
+      diag += S[(size_t)i * N2 + i] * S[(size_t)i * N2 + i];
+      for (int j = i + 1; j < N2; ++j) off += S[(size_t)i * N2 + j] * S[(size_t)i * N2 + j];
+    }
+    if (off <= 1e-30 * diag) break;
+    for (int p = 0; p < N2; ++p)
+      for (int q = p + 1; q < N2; ++q) {
+        const double apq = S[(size_t)p * N2 + q];
+        if (apq == 0) continue;
+        const double app = S[(size_t)p * N2 + p], aqq = S[(size_t)q * N2 + q];
+        const double theta = (aqq - app) / (2 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
+        const double c = 1 / std::sqrt(t * t + 1), sn = t * c;
+        for (int k = 0; k < N2; ++k) {   // S <- J^T S J on rows/columns p, q
+          const double skp = S[(size_t)k * N2 + p], skq = S[(size_t)k * N2 + q];
+          S[(size_t)k * N2 + p] = c * skp - sn * skq;
+          S[(size_t)k * N2 + q] = sn * skp + c * skq;
+        }
+        for (int k = 0; k < N2; ++k) {
+          const double spk = S[(size_t)p * N2 + k], sqk = S[(size_t)q * N2 + k];
+          S[(size_t)p * N2 + k] = c * spk - sn * sqk;
+          S[(size_t)q * N2 + k] = sn * spk + c * sqk;
+        }
+      }
+  }
+  double lmax = 0, lmin = 1e300;
+  for (int i = 0; i < N2; ++i) {
+    lmax = std::max(lmax, S[(size_t)i * N2 + i]);
+    lmin = std::min(lmin, S[(size_t)i * N2 + i]);
+  }
+  if (lmax <= 0) return 0.0;
+  return std::sqrt(std::max(lmin, 0.0) / lmax);
 }
 
 }  // namespace
@@ -142,13 +200,16 @@ void tt_cross(EntryFn& f, const int n[4], double tol, int rmax, uint64_t seed, s
         }
       }
     }
-    // cores from the final left-to-right pass
+    // cores from the final left-to-right pass; an unfolding whose fibre matrix already has a
+    // numerically dependent column (sigma_min / sigma_max below tol / 4) keeps its rank
+    bool saturated[3] = {false, false, false};
     std::vector<std::vector<int>> left0(1);
     const std::vector<std::vector<int>>* left = &left0;
     for (int k = 0; k < 3; ++k) {
       fibre(f, *left, n[k], k, J[k], C);
       int m = (int)left->size() * n[k];
       int rk = (int)J[k].size();
+      saturated[k] = sv_ratio(C, m, rk) < 0.25 * tol;
       Q = C;
       qr_mgs2(Q, m, rk, Rm);
       std::vector<int> rows = maxvol(Q, m, rk);
@@ -200,7 +261,9 @@ void tt_cross(EntryFn& f, const int n[4], double tol, int rmax, uint64_t seed, s
     err = tnorm > 0 ? sqrt(e2 / tnorm) : 0.0;
     if (err <= tol) break;
     int old[3] = {r[0], r[1], r[2]};
-    for (int k = 0; k < 3; ++k) r[k] = r[k] + std::max(2, r[k] / 2);
+    const bool all_sat = saturated[0] && saturated[1] && saturated[2];
+    for (int k = 0; k < 3; ++k)
+      if (!saturated[k] || all_sat) r[k] = r[k] + std::max(2, r[k] / 2);
     cap(r);
     if (r[0] == old[0] && r[1] == old[1] && r[2] == old[2]) break;   // rank cap reached
     grow_right();

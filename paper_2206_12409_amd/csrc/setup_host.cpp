@@ -61,7 +61,7 @@ void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int
   for (auto& x : th) x.join();
 }
 
-static int host_threads() {
+int host_threads() {
   unsigned hc = std::thread::hardware_concurrency();
   if (hc == 0) hc = 4;
   return (int)std::min<unsigned>(hc, 16);

@@ -105,6 +105,10 @@ template <typename R> cx<R>* twiddles(Handle& H, int L) {
 // volume convolution data: generator on the extended-grid octant, circulant spectra
 void setup_volume(Handle& H) {
   hipStream_t st = H.stream;
+  for (int v = 0; v < 2; ++v) {
+    const std::vector<int> ord = zconv_order(H.P[2], H.P[0], H.P[1], v == 0);
+    if (!ord.empty()) H.d_zorder[v] = upload<int>(H, ord);
+  }
   GaussTab gt_h;
   fill_gauss_table(&gt_h);
   GaussTab* gt = H.dalloc<GaussTab>(1);
@@ -501,8 +505,30 @@ void setup_tt(Handle& H) {
   }
 }
 
+// Device copies of G3, G4 and of the contraction of the first two cores over j1,
+// M[j2][i1 + n1 i2] = sum_j1 G1[i1][j1] G2[j1][i2][j2] (eq. (14) with cores 1 and 2 merged).
 void upload_tt(Handle& H, int chi) {
-  for (int k = 0; k < 4; ++k) {
+  const int n1 = H.n[0], n2 = H.n[1];
+  const int r1 = H.tt_r[chi][0], r2 = H.tt_r[chi][1];
+  const std::vector<cxd>& G1 = H.tt_host[chi][0];
+  const std::vector<cxd>& G2 = H.tt_host[chi][1];
+  const int64_t n12 = (int64_t)n1 * n2;
+  std::vector<cxd> M((size_t)r2 * n12);
+  parallel_for((int64_t)r2 * n2, host_threads(), [&](int64_t b, int64_t e) {
+    for (int64_t q = b; q < e; ++q) {
+      const int64_t j2 = q / n2;
+      const int i2 = (int)(q % n2);
+      for (int i1 = 0; i1 < n1; ++i1) {
+          cxd acc{0, 0};
+          for (int j1 = 0; j1 < r1; ++j1)
+            acc += G1[(size_t)i1 * r1 + j1] * G2[((size_t)j1 * n2 + i2) * r2 + j2];
+        M[(size_t)j2 * n12 + (size_t)i2 * n1 + i1] = acc;
+      }
+    }
+  });
+  H.d64.G12[chi] = upload_cx<double>(H, M);
+  if (H.opts.build_c64) H.d32.G12[chi] = upload_cx<float>(H, M);
+  for (int k = 2; k < 4; ++k) {
     H.d64.G[chi][k] = upload_cx<double>(H, H.tt_host[chi][k]);
     if (H.opts.build_c64) H.d32.G[chi][k] = upload_cx<float>(H, H.tt_host[chi][k]);
   }
@@ -517,9 +543,9 @@ template <typename R> void alloc_work(Handle& H, OpData<R>& D) {
 }
 
 // ---------------------------------------------------------------------------------------------
-const char* const kStageNames[Handle::NSTAGE] = {"build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv",
-                                                 "fft_y_inv", "fft_x_inv", "body_out", "pfft_gather",
-                                                 "gemv_far", "precorrect", "aca", "tt"};
+const char* const kStageNames[Handle::NSTAGE] = {"build_grid", "fft_x_fwd", "fft_y_fwd",  "fft_z_conv", "fft_y_inv",
+                                                 "fft_x_inv",  "body_out",  "pfft_gather", "gemv_far",  "precorrect",
+                                                 "aca",        "tt",        "gemv_far_reduce"};
 
 struct StageTimer {
   Handle& H;
@@ -573,7 +599,7 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
   fft_strided<R>(st, P2, true, D.bufB, D.bufC, ne2, P2, P1, P1, P1, 3LL * ne3, (int64_t)ne2 * P1, (int64_t)P2 * P1, D.tw[1]);
   T.end(2);
   T.begin(3);
-  fft_z_conv<R>(st, P3, D.bufC, ne3, P1, P2, D.spec, D.tw[2]);
+  fft_z_conv<R>(st, P3, D.bufC, ne3, P1, P2, D.spec, D.tw[2], H.d_zorder[sizeof(R) == 8 ? 0 : 1]);
   T.end(3);
   T.begin(4);
   fft_strided<R>(st, P2, false, D.bufC, D.bufB, P2, ne2, P1, P1, P1, 3LL * ne3, (int64_t)P2 * P1, (int64_t)ne2 * P1, D.tw[1]);
@@ -592,8 +618,11 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
   // dense far block (writes y_f)
   if (mf) {
     T.begin(8);
-    launch_symv<R>(st, D.Zff, H.d_tiles, H.sym_T, xf, mf, D.sym_part, yf);
+    launch_symv_tiles<R>(st, D.Zff, H.d_tiles, H.sym_T, xf, mf, D.sym_part);
     T.end(8);
+    T.begin(12);
+    launch_symv_reduce<R>(st, D.sym_part, H.sym_T, mf, yf);
+    T.end(12);
   }
   // precorrection
   T.begin(9);
@@ -611,15 +640,13 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
     T.end(10);
   }
   // TT far coupling (eqs. (16)-(19))
-  if (mf && D.G[0][0] && D.G[1][0] && D.G[2][0]) {
+  if (mf && D.G12[0] && D.G12[1] && D.G12[2]) {
     T.begin(11);
     TTDesc<R> td;
     for (int c = 0; c < 3; ++c) {
-      td.G1[c] = D.G[c][0];
-      td.G2[c] = D.G[c][1];
+      td.M[c] = D.G12[c];
       td.G3[c] = D.G[c][2];
       td.G4[c] = D.G[c][3];
-      td.r1[c] = H.tt_r[c][0];
       td.r2[c] = H.tt_r[c][1];
       td.r3[c] = H.tt_r[c][2];
     }
@@ -631,6 +658,13 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
 
 // ---------------------------------------------------------------------------------------------
 // GMRES (FP64 Arnoldi, CGS2) with a matvec callback on FP64 vectors
+static bool verbose() {
+  static const bool on = getenv("VSIE_VERBOSE") != nullptr;
+  return on;
+}
+
+constexpr int IR_OUTER_M = 20;   // FP64 flexible-GMRES steps per cycle of the mixed-precision solver
+
 struct Solver {
   Handle& H;
   hipStream_t st;
@@ -682,6 +716,10 @@ struct Solver {
       double nr[4];
       norms(w, nr);
       *relres = nr[3] / bnorm;
+      if (verbose()) {
+        fprintf(stderr, "[vsie] gmres: %d iterations, true relative residual %.3e\n", it, *relres);
+        fflush(stderr);
+      }
       if (*relres <= tol || it >= max_iter) break;
       ++*restarts;
       const double beta = nr[3];
@@ -737,6 +775,85 @@ struct Solver {
     }
     return it;
   }
+
+  // Flexible GMRES in FP64 whose preconditioner P(v, z) may change from step to step (here an
+  // inner complex64 GMRES solve of Z z = v). Vb holds m + 1 basis vectors, Zb the m
+  // preconditioned ones; x = sum_j Zb_j y_j minimises the FP64 residual over their span. With an
+  // exact inner solve one step is one refinement x += Z^{-1} r. P returns false when the inner
+  // iteration budget is spent.
+  template <class MV, class PC>
+  int fgmres(MV&& A, PC&& P, const cxd* b, cxd* x, double tol, int m, int* steps, double* relres, cxd* Vb, cxd* Zb,
+             cxd* w, cxd* hvec_dev) {
+    VSIE_HIP(hipMemsetAsync(x, 0, sizeof(cxd) * N, st));
+    double nb[4];
+    norms(b, nb);
+    const double bnorm = nb[3];
+    *relres = 0;
+    if (bnorm == 0) return 0;
+    std::vector<cxd> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h, h2;
+    bool budget = true;
+    int cycles = 0;
+    for (;;) {
+      A(x, w);
+      launch_sub(st, b, w, w, N);
+      double nr[4];
+      norms(w, nr);
+      *relres = nr[3] / bnorm;
+      if (verbose()) {
+        fprintf(stderr, "[vsie] flexible GMRES: %d FP64 steps, true relative residual %.3e\n", *steps, *relres);
+        fflush(stderr);
+      }
+      if (*relres <= tol || !budget || cycles >= 100) break;
+      ++cycles;
+      const double beta = nr[3];
+      launch_scale_copy(st, w, 1.0 / beta, Vb, N);
+      std::fill(g.begin(), g.end(), cxd{0, 0});
+      g[0] = {beta, 0};
+      int jend = 0;
+      for (int j = 0; j < m; ++j) {
+        cxd* z = Zb + (int64_t)j * N;
+        budget = P(Vb + (int64_t)j * N, z);
+        A(z, w);
+        dots(Vb, j + 1, w, h);
+        VSIE_HIP(hipMemcpyAsync(hvec_dev, h.data(), sizeof(cxd) * (j + 1), hipMemcpyHostToDevice, st));
+        launch_multiaxpy(st, Vb, N, j + 1, hvec_dev, w, N);
+        dots(Vb, j + 1, w, h2);
+        VSIE_HIP(hipMemcpyAsync(hvec_dev, h2.data(), sizeof(cxd) * (j + 1), hipMemcpyHostToDevice, st));
+        launch_multiaxpy(st, Vb, N, j + 1, hvec_dev, w, N);
+        double nw[4];
+        norms(w, nw);
+        for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h[i] + h2[i];
+        Hm[(size_t)(j + 1) * m + j] = {nw[3], 0};
+        if (nw[3] > 0) launch_scale_copy(st, w, 1.0 / nw[3], Vb + (int64_t)(j + 1) * N, N);
+        for (int i = 0; i < j; ++i) {
+          cxd a = Hm[(size_t)i * m + j], bb = Hm[(size_t)(i + 1) * m + j];
+          Hm[(size_t)i * m + j] = conj(cs[i]) * a + conj(sn[i]) * bb;
+          Hm[(size_t)(i + 1) * m + j] = cxd{-sn[i].re, -sn[i].im} * a + cs[i] * bb;
+        }
+        cxd a = Hm[(size_t)j * m + j], bb = Hm[(size_t)(j + 1) * m + j];
+        double den = sqrt(a.re * a.re + a.im * a.im + bb.re * bb.re + bb.im * bb.im);
+        cs[j] = den > 0 ? (1.0 / den) * a : cxd{1, 0};
+        sn[j] = den > 0 ? (1.0 / den) * bb : cxd{0, 0};
+        Hm[(size_t)j * m + j] = conj(cs[j]) * a + conj(sn[j]) * bb;
+        Hm[(size_t)(j + 1) * m + j] = {0, 0};
+        g[j + 1] = cxd{-sn[j].re, -sn[j].im} * g[j];
+        g[j] = conj(cs[j]) * g[j];
+        ++*steps;
+        jend = j + 1;
+        double est = sqrt(g[j + 1].re * g[j + 1].re + g[j + 1].im * g[j + 1].im) / bnorm;
+        if (est <= tol || !budget || nw[3] == 0) break;
+      }
+      std::vector<cxd> y(jend);
+      for (int i = jend - 1; i >= 0; --i) {
+        cxd sacc = g[i];
+        for (int k = i + 1; k < jend; ++k) sacc -= Hm[(size_t)i * m + k] * y[k];
+        y[i] = sacc * cinv(Hm[(size_t)i * m + i]);
+      }
+      VSIE_HIP(hipMemcpyAsync(hvec_dev, y.data(), sizeof(cxd) * jend, hipMemcpyHostToDevice, st));
+      launch_combine_add(st, Zb, N, jend, hvec_dev, x, N);
+    }
+    return *steps;
+  }
 };
 
 void ensure_solver_ws(Handle& H, int restart) {
@@ -765,7 +882,7 @@ extern "C" {
 int vsie_default_options(vsie_options* o) {
   if (!o) return fail(VSIE_E_ARG, "null options");
   o->tt_tol = 1e-3;
-  o->tt_rank_max = 64;
+  o->tt_rank_max = 96;
   o->aca_tol = 1e-3;
   o->aca_rank_max = 128;
   o->precorrect_dist = 2;
@@ -786,8 +903,7 @@ int vsie_default_solve_opts(vsie_solve_opts* o) {
 }
 
 static void progress(const char* what, std::chrono::steady_clock::time_point t0) {
-  static const bool on = getenv("VSIE_VERBOSE") != nullptr;
-  if (!on) return;
+  if (!verbose()) return;
   double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fprintf(stderr, "[vsie] %7.2f s  %s\n", s, what);
   fflush(stderr);
@@ -992,9 +1108,15 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
     VSIE_HIP(hipMalloc(&r, sizeof(cxd) * N));
     VSIE_HIP(hipMalloc(&d, sizeof(cxd) * N));
     VSIE_HIP(hipMalloc(&hv, sizeof(cxd) * 1100));
+    cxd* Vout = nullptr;
+    cxd* Zout = nullptr;
+    cxd* hv2 = nullptr;
     if (so.method == VSIE_IR_MIXED) {
       VSIE_HIP(hipMalloc(&x32, sizeof(cxf) * N));
       VSIE_HIP(hipMalloc(&y32, sizeof(cxf) * N));
+      VSIE_HIP(hipMalloc(&Vout, sizeof(cxd) * N * (IR_OUTER_M + 1)));
+      VSIE_HIP(hipMalloc(&Zout, sizeof(cxd) * N * IR_OUTER_M));
+      VSIE_HIP(hipMalloc(&hv2, sizeof(cxd) * 1100));
     }
     Solver S(H, st);
     auto A64 = [&](const cxd* in, cxd* out) { matvec_one<double>(H, H.d64, in, out, st); };
@@ -1013,25 +1135,16 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       if (so.method == VSIE_GMRES64) {
         s.iterations = S.gmres(A64, b, x, so.tol, so.restart, so.max_iter, &s.restarts, &rel, H.d_krylov, w, hv);
       } else {
-        VSIE_HIP(hipMemsetAsync(x, 0, sizeof(cxd) * N, st));
-        double nb[4];
-        S.norms(b, nb);
         int total = 0;
-        for (int outer = 0; outer < 50; ++outer) {
-          A64(x, w);
-          launch_sub(st, b, w, r, N);
-          double nr[4];
-          S.norms(r, nr);
-          rel = nb[3] > 0 ? nr[3] / nb[3] : 0;
-          if (rel <= so.tol || total >= so.max_iter) break;
+        // preconditioner: at most one cycle (restart iterations) of complex64 GMRES on Z z = v
+        auto P32 = [&](const cxd* v, cxd* z) {
           double inner_rel = 0;
-          int used = S.gmres(A32, r, d, std::max(so.inner_tol, so.tol / rel * 0.5), so.restart, so.max_iter - total,
-                             &s.restarts, &inner_rel, H.d_krylov, w, hv);
+          int used = S.gmres(A32, v, z, so.inner_tol, so.restart, std::max(1, std::min(so.restart, so.max_iter - total)),
+                             &s.restarts, &inner_rel, H.d_krylov, d, hv2);
           total += used;
-          launch_add(st, x, d, N);
-          ++s.refinements;
-          if (used == 0) break;
-        }
+          return total < so.max_iter;
+        };
+        S.fgmres(A64, P32, b, x, so.tol, IR_OUTER_M, &s.refinements, &rel, Vout, Zout, w, hv);
         s.iterations = total;
       }
       // true FP64 residual and per-block residuals
@@ -1053,6 +1166,9 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
     (void)hipFree(hv);
     if (x32) (void)hipFree(x32);
     if (y32) (void)hipFree(y32);
+    if (Vout) (void)hipFree(Vout);
+    if (Zout) (void)hipFree(Zout);
+    if (hv2) (void)hipFree(hv2);
   });
   if (rc != VSIE_OK) return rc;
   if (status != VSIE_OK) return fail(status, "solver did not reach the requested tolerance");

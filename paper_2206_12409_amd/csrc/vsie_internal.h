@@ -69,8 +69,9 @@ template <typename R> struct OpData {
   // ACA
   cx<R>* U = nullptr;          // [m_n][k]
   cx<R>* V = nullptr;          // [m_f][k]
-  // TT cores per component
+  // TT cores per component (G3, G4) and the first two cores contracted, [r2][n1 n2]
   cx<R>* G[3][4] = {};
+  cx<R>* G12[3] = {};
   // dense far block
   cx<R>* Zff = nullptr;        // upper-triangle tiles of the symmetric far block
   cx<R>* sym_part = nullptr;   // per-tile partial sums
@@ -119,6 +120,7 @@ struct Handle {
   int* d_tiles = nullptr;         // [ntiles][2] (I, J), I <= J
   // body mask
   uint8_t* d_mask = nullptr;
+  int* d_zorder[2] = {};       // z-pass block order, FP64 / FP32 variants
   // TT
   int tt_r[3][3] = {};
   double tt_err[3] = {0, 0, 0};
@@ -141,7 +143,7 @@ struct Handle {
   hipStream_t stream = nullptr;
   std::vector<void*> allocations;
   // per-stage timing of the matrix-vector product (HIP events on the caller's stream)
-  static constexpr int NSTAGE = 12;
+  static constexpr int NSTAGE = 13;
   bool prof = false;
   hipEvent_t ev[2 * NSTAGE] = {};
   bool ev_used[NSTAGE] = {};
@@ -170,6 +172,7 @@ void build_rwg(const vsie_problem* p, int domain, Rwg& out,
 void stencil_setup(Handle& H);
 void fill_gauss_table(GaussTab* t);
 void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int64_t)>& fn);
+int host_threads();   // worker threads for host setup loops (hardware concurrency, at most 16)
 
 // dense host linear algebra (setup_linalg.cpp)
 void qr_mgs2(std::vector<cxd>& A, int m, int n, std::vector<cxd>& R);   // A (m x n, row-major) -> Q

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(vs):
 
 def test_default_options(vs):
     o = vs.default_options()
-    assert o.tt_tol == 1e-3 and o.aca_tol == 1e-3 and o.tt_rank_max == 64 and o.precorrect_dist == 2
+    assert o.tt_tol == 1e-3 and o.aca_tol == 1e-3 and o.tt_rank_max == 96 and o.precorrect_dist == 2
 
 
 def _expect(vs, problem, code):
