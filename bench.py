@@ -63,12 +63,31 @@ KERNEL_OF_STAGE = {   # stages that are a single kernel launch, and that kernel'
 }
 
 
+def kernel_source_sha(kernel):
+    """sha256 over the kernel's own source, its launcher(s) and the shared kernel header: the
+    traffic figure is void once any of them changes."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2206_12409_amd", "csrc")
+    text = open(os.path.join(csrc, "kernels.hip")).read()
+    parts = []
+    for key in ("void %s(" % kernel, "void launch_%s" % kernel.replace("k_", "", 1)):
+        at = text.find(key)
+        while at >= 0:
+            brace, semi = text.find("{", at), text.find(";", at)
+            if 0 <= brace < semi:   # a definition, not a declaration or instantiation
+                start = text.rfind("\ntemplate", 0, at)
+                start = start if start >= 0 else at
+                end = text.find("\n}\n", at)
+                parts.append(text[start:end])
+            at = text.find(key, at + len(key))
+    parts.append(open(os.path.join(csrc, "kernels.h")).read())
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on the
-    kernel source as it is now (sha256 of the HIP kernel file); else None."""
-    import hashlib
+    kernel as it is now; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_2mm.txt" % kernel)
-    src = os.path.join(ROOT, "paper_2206_12409_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -76,10 +95,72 @@ def measured_traffic(kernel):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("source_sha256") != sha or "traffic_bytes" not in kv:
+    if kv.get("source_sha256") != kernel_source_sha(kernel) or "traffic_bytes" not in kv:
         return None
     return float(kv["traffic_bytes"])
+
+
+def _pmc_rows(db, counter):
+    import re
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                       (counter,)).fetchall()
+    con.close()
+    return [(re.sub(r"\(.*", "", n), float(v)) for n, v in rows]
+
+
+def write_traffic(kernel, fetch_db, write_db, commands):
+    """profiles/traffic_<kernel>_2mm.txt from a FETCH_SIZE run and a WRITE_SIZE run (KiB per
+    dispatch), each scaled by what the counter reads for the calibration copy (512 MiB read,
+    1 GiB written, float32 -> float64)."""
+    copy_read, copy_written = float(1 << 29), float(1 << 30)
+    out = {}
+    for name, db, ref in (("fetch", fetch_db, copy_read), ("write", write_db, copy_written)):
+        counter = "FETCH_SIZE" if name == "fetch" else "WRITE_SIZE"
+        rows = _pmc_rows(db, counter)
+        kv = [v for n, v in rows if n.endswith(kernel + "<double>")]
+        cv = [v for n, v in rows if "direct_copy" in n and v * 1024 > 0.25 * ref]
+        if not kv or not cv:
+            raise SystemExit("no %s dispatches of %s or of the calibration copy in %s" % (counter, kernel, db))
+        k_kib = sum(kv) / len(kv)
+        c_kib = sum(cv) / len(cv)
+        factor = ref / (c_kib * 1024)
+        out[name] = (k_kib, len(kv), c_kib, factor, k_kib * 1024 * factor)
+    traffic = out["fetch"][4] + out["write"][4]
+    path = os.path.join(ROOT, "profiles", "traffic_%s_2mm.txt" % kernel)
+    with open(path, "w") as f:
+        f.write("# HBM traffic per launch of %s<double> on the 2 mm workload (MI355X)\n" % kernel)
+        for c in commands:
+            f.write("# command: %s\n" % c)
+        for name in ("fetch", "write"):
+            k_kib, n, c_kib, factor, b = out[name]
+            f.write("# %s: kernel %.1f KiB/dispatch (%d dispatches), calibration copy %.1f KiB for %d B "
+                    "-> factor %.4f -> %.4e B\n" % (name.upper(), k_kib, n, c_kib,
+                                                     copy_read if name == "fetch" else copy_written, factor, b))
+        f.write("kernel=%s\n" % kernel)
+        f.write("fetch_bytes=%.6e\n" % out["fetch"][4])
+        f.write("write_bytes=%.6e\n" % out["write"][4])
+        f.write("traffic_bytes=%.6e\n" % traffic)
+        f.write("source_sha256=%s\n" % kernel_source_sha(kernel))
+    print(open(path).read())
+
+
+def write_trace_summary(stats_csv, out_name, command, top=25):
+    """profiles/<out_name>.txt: the top kernels of a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    import re
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    path = os.path.join(ROOT, "profiles", out_name + ".txt")
+    with open(path, "w") as f:
+        f.write("# rocprofv3 kernel statistics (MI355X)\n# command: %s\n" % command)
+        f.write("%-64s %7s %11s %11s %7s\n" % ("kernel", "calls", "total_ms", "avg_us", "pct"))
+        for r in rows[:top]:
+            name = re.sub(r"\(.*", "", r["Name"])[:64]
+            f.write("%-64s %7s %11.3f %11.2f %7.2f\n" % (name, r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                                                        float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    print(open(path).read())
 
 
 def copy_calibration():
@@ -138,7 +219,18 @@ def main():
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--max-iter", type=int, default=2000)
     ap.add_argument("--calib-copy", action="store_true", help="run the copy used to scale HBM counters")
+    ap.add_argument("--write-traffic", nargs=3, metavar=("KERNEL", "FETCH_DB", "WRITE_DB"),
+                    help="write profiles/traffic_<KERNEL>_2mm.txt from two rocprofv3 --pmc databases")
+    ap.add_argument("--write-trace", nargs=2, metavar=("STATS_CSV", "NAME"),
+                    help="write profiles/NAME.txt from a rocprofv3 --kernel-trace --stats CSV")
+    ap.add_argument("--command", action="append", default=[], help="command line recorded in the summary")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.write_traffic[2], args.command)
+        return
+    if args.write_trace:
+        write_trace_summary(args.write_trace[0], args.write_trace[1], " ; ".join(args.command))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the path has no multi-GPU mode); got --gpus %d" % args.gpus,
               file=sys.stderr)

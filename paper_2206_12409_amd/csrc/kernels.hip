@@ -673,8 +673,13 @@ __device__ inline void zfft(cx<R>* Sp, cx<R>* v, int j, const cx<R>* __restrict_
   }
 }
 
+#ifdef ZCONV_WAVES
+#define ZCONV_ATTR __attribute__((amdgpu_waves_per_eu(ZCONV_WAVES, 8)))
+#else
+#define ZCONV_ATTR
+#endif
 template <typename R, int L, int V, int NP>
-__global__ __launch_bounds__(NP * L / V) void k_zconv3(cx<R>* __restrict__ buf, int n3, int P1, int P2,
+__global__ __launch_bounds__(NP * L / V) ZCONV_ATTR void k_zconv3(cx<R>* __restrict__ buf, int n3, int P1, int P2,
                                                        const cx<R>* __restrict__ spec, const cx<R>* __restrict__ tw,
                                                        const int* __restrict__ order) {
   constexpr int T = L / V;
@@ -728,6 +733,9 @@ __global__ __launch_bounds__(NP * L / V) void k_zconv3(cx<R>* __restrict__ buf, 
         H[0][e] = Txx * x + Txy * y + Txz * z;
         H[1][e] = Txy * x + Tyy * y + Tyz * z;
         H[2][e] = Txz * x + Tyz * y + Tzz * z;
+#ifdef ZCONV_SB
+        __builtin_amdgcn_sched_barrier(0);   // keeps the spectral loads of one frequency at a time
+#endif
       }
   }
 #pragma unroll
