@@ -81,6 +81,7 @@ template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, co
 
 // solver
 void launch_multidot(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* w, int64_t n, cxd* part, int nblk);
+void launch_sum_partials(hipStream_t st, const cxd* part, int nblk, int K, cxd* out);
 void launch_multiaxpy(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* h, cxd* w, int64_t n);
 void launch_combine_add(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* y, cxd* x, int64_t n);
 void launch_scale_copy(hipStream_t st, const cxd* a, double s, cxd* b, int64_t n);

@@ -733,8 +733,9 @@ __global__ __launch_bounds__(NP * L / V) ZCONV_ATTR void k_zconv3(cx<R>* __restr
         H[0][e] = Txx * x + Txy * y + Txz * z;
         H[1][e] = Txy * x + Tyy * y + Tyz * z;
         H[2][e] = Txz * x + Tyz * y + Tzz * z;
-#ifdef ZCONV_SB
-        __builtin_amdgcn_sched_barrier(0);   // keeps the spectral loads of one frequency at a time
+#ifndef ZCONV_NO_SB
+        // FP64: keep the spectral loads of one frequency at a time (fewer live registers)
+        if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
 #endif
       }
   }
@@ -1104,8 +1105,16 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const cx<R>* __restrict__ A, 
 // Thread (rg, cg): 32 column groups of 4 columns (64-byte FP64 segments, a 2 KB row per 32
 // lanes) x 8 row groups of 16 rows. Row sums reduce across the 32 column lanes by shuffles;
 // column sums across row groups by one shuffle and LDS.
+#ifdef SYMV_WAVES
+#define SYMV_ATTR __attribute__((amdgpu_waves_per_eu(SYMV_WAVES, 8)))
+#else
+#define SYMV_ATTR
+#endif
+#ifndef SYMV_UNROLL
+#define SYMV_UNROLL 4
+#endif
 template <typename R>
-__global__ __launch_bounds__(256) void k_symv_tiles(const cx<R>* __restrict__ Zp, const int* __restrict__ tiles,
+__global__ __launch_bounds__(256) SYMV_ATTR void k_symv_tiles(const cx<R>* __restrict__ Zp, const int* __restrict__ tiles,
                                                     const cx<R>* __restrict__ x, int m, cx<R>* __restrict__ part) {
   __shared__ R cr[4][SYM_TB], ci[4][SYM_TB];
   __shared__ cx<R> xs[SYM_TB];
@@ -1126,7 +1135,7 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const cx<R>* __restrict__ Zp
   }
   __syncthreads();
   cx<R>* out = part + t * 2 * SYM_TB;
-#pragma unroll 4
+#pragma unroll SYMV_UNROLL
   for (int r = 0; r < 16; ++r) {
     const int row = rg * 16 + r;
     const cx<R>* zr = Z + (int64_t)row * SYM_TB + cg * 4;
@@ -1220,11 +1229,32 @@ template <typename R> struct GemmSet {
   int nprob;
 };
 
-// 64 x 64 output tile per block of 256 threads, 4 x 4 outputs per thread (rows ty + 16u, columns
-// tx + 16v); K staged through LDS in chunks of 16. Tile loaders walk each operand's unit-stride
-// dimension fastest; neighbouring threads store along C's unit-stride dimension.
+// 64 x 64 output tile per block of 256 threads on the matrix cores: each wavefront owns a 32 x 32
+// quadrant as 2 x 2 tiles of the 16 x 16 x 4 MFMA (FP64: v_mfma_f64_16x16x4f64, FP32:
+// v_mfma_f32_16x16x4f32); K is staged through LDS in chunks of 16, tile loaders walking each
+// operand's unit-stride dimension.
+// A complex product is four real MFMAs (re re, -im im into the real part; re im, im re into the
+// imaginary part). Operand lane layout: A[row l % 16][k l / 16], B[k l / 16][col l % 16]; result
+// lane l, register v: FP64 row l / 16 + 4 v, FP32 row 4 (l / 16) + v, column l % 16 (both
+// checked on the device). Columns run along lanes, so C is best given with unit column stride.
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+template <typename R> struct Mfma16;
+template <> struct Mfma16<double> {
+  typedef dvec4 V;
+  __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int v) { return lane / 16 + 4 * v; }
+};
+template <> struct Mfma16<float> {
+  typedef fvec4 V;
+  __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int v) { return 4 * (lane / 16) + v; }
+};
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_zgemm64(GemmSet<R> S) {
+__global__ __launch_bounds__(256) void k_zgemm_mfma(GemmSet<R> S) {
+  using MM = Mfma16<R>;
+  using V = typename MM::V;
   __shared__ cx<R> As[64][17];
   __shared__ cx<R> Bs[16][65];
   int z = blockIdx.z, pi = 0;
@@ -1237,19 +1267,22 @@ __global__ __launch_bounds__(256) void k_zgemm64(GemmSet<R> S) {
   int K = g.K;
   if (g.ktot > 0) K = (int)(g.ktot - (int64_t)z * g.K < g.K ? g.ktot - (int64_t)z * g.K : g.K);
   if (i0 >= g.M || j0 >= g.N || K <= 0) return;
-  const bool c_rowfast = g.scc != 1 && g.scr == 1;
-  const int tx = c_rowfast ? threadIdx.x / 16 : threadIdx.x % 16;
-  const int ty = c_rowfast ? threadIdx.x % 16 : threadIdx.x / 16;
   const bool a_rowfast = g.sac != 1 && g.sar == 1;
   const bool b_rowfast = g.sbc != 1 && g.sbr == 1;
   const cx<R>* A = g.A + z * g.sab;
   const cx<R>* B = g.B + z * g.sbb;
   const uint8_t* mB = g.maskB ? g.maskB + z * g.sbb : nullptr;
-  cx<R> acc[4][4];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
+  const int li = lane % 16, lk = lane / 16;
+  V cr[2][2], ci[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = cx<R>{0, 0};
+    for (int v = 0; v < 2; ++v) {
+      cr[u][v] = V{0, 0, 0, 0};
+      ci[u][v] = V{0, 0, 0, 0};
+    }
   for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1268,37 +1301,45 @@ __global__ __launch_bounds__(256) void k_zgemm64(GemmSet<R> S) {
       Bs[rb][cb] = v;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < 16; ++k) {
-      cx<R> a[4], b[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = As[ty + 16 * u][k];
+    for (int ks = 0; ks < 16; ks += 4) {
+      cx<R> a[2], b[2];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) b[v] = Bs[k][tx + 16 * v];
+      for (int u = 0; u < 2; ++u) a[u] = As[wm + 16 * u + li][ks + lk];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int v = 0; v < 2; ++v) b[v] = Bs[ks + lk][wn + 16 * v + li];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          cr[u][v] = MM::mma(a[u].re, b[v].re, cr[u][v]);
+          cr[u][v] = MM::mma(-a[u].im, b[v].im, cr[u][v]);
+          ci[u][v] = MM::mma(a[u].re, b[v].im, ci[u][v]);
+          ci[u][v] = MM::mma(a[u].im, b[v].re, ci[u][v]);
+        }
     }
     __syncthreads();
   }
   cx<R>* C = g.C + z * g.scb;
   const uint8_t* mC = g.maskC;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + ty + 16 * u, j = j0 + tx + 16 * v;
-      if (i >= g.M || j >= g.N) continue;
-      const int64_t idx = i * g.scr + j * g.scc;
-      if (mC) {
-        if (mC[idx]) C[idx] += acc[u][v];
-      } else if (g.accumulate) {
-        C[idx] += acc[u][v];
-      } else {
-        C[idx] = acc[u][v];
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + wm + 16 * u + MM::row(lane, e), j = j0 + wn + 16 * v + li;
+        if (i >= g.M || j >= g.N) continue;
+        const cx<R> val = {cr[u][v][e], ci[u][v][e]};
+        const int64_t idx = i * g.scr + j * g.scc;
+        if (mC) {
+          if (mC[idx]) C[idx] += val;
+        } else if (g.accumulate) {
+          C[idx] += val;
+        } else {
+          C[idx] = val;
+        }
       }
-    }
 }
 
 template <typename R> static void zgemm(hipStream_t st, const GemmSet<R>& S) {
@@ -1309,7 +1350,7 @@ template <typename R> static void zgemm(hipStream_t st, const GemmSet<R>& S) {
     nz += S.nbatch[p];
   }
   if (mx <= 0 || nx <= 0 || nz <= 0) return;
-  hipLaunchKernelGGL(k_zgemm64<R>, dim3((nx + 63) / 64, (mx + 63) / 64, nz), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(k_zgemm_mfma<R>, dim3((nx + 63) / 64, (mx + 63) / 64, nz), dim3(256), 0, st, S);
 }
 
 // s2[c][j2][i3] = sum_b part[c][b][j2][i3]  (split-K reduction of the transpose contraction);
@@ -1450,28 +1491,41 @@ __global__ __launch_bounds__(256) void k_ttT_4(TTDesc<R> T, const cx<R>* __restr
 // Solver helpers (FP64 Arnoldi) and conversions
 // =============================================================================================
 
-// partial sums of V[i]^H w for i < nvec over a fixed number of blocks: part[blk][nvec]
+// partial sums of V[i]^H w for i < nvec: part[blk][nvec]. Grid-stride over rows; vectors in
+// groups of eight per block reduction (w is re-read per group from cache).
 __global__ __launch_bounds__(256) void k_multidot_partial(const cxd* __restrict__ V, int64_t ld, int nvec,
                                                           const cxd* __restrict__ w, int64_t n, cxd* __restrict__ part) {
-  __shared__ double rr[256], ri[256];
-  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = blockIdx.x * per;
-  const int64_t r1 = r0 + per < n ? r0 + per : n;
-  for (int i = 0; i < nvec; ++i) {
-    cxd acc = {0, 0};
-    const cxd* v = V + (int64_t)i * ld;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) acc += mul_conj_a(v[r], w[r]);
-    rr[threadIdx.x] = acc.re;
-    ri[threadIdx.x] = acc.im;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        rr[threadIdx.x] += rr[threadIdx.x + s];
-        ri[threadIdx.x] += ri[threadIdx.x + s];
-      }
-      __syncthreads();
+  __shared__ double rr[8][4], ri[8][4];
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  for (int i0 = 0; i0 < nvec; i0 += 8) {
+    const int g = nvec - i0 < 8 ? nvec - i0 : 8;
+    cxd acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = cxd{0, 0};
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += stride) {
+      const cxd wr = w[r];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < g) acc[q] += mul_conj_a(V[(int64_t)(i0 + q) * ld + r], wr);
     }
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nvec + i] = cxd{rr[0], ri[0]};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double re = acc[q].re, im = acc[q].im;
+      for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_down(re, off, 64);
+        im += __shfl_down(im, off, 64);
+      }
+      if (lane == 0) {
+        rr[q][wave] = re;
+        ri[q][wave] = im;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < g)
+      part[(int64_t)blockIdx.x * nvec + i0 + threadIdx.x] =
+          cxd{(rr[threadIdx.x][0] + rr[threadIdx.x][1]) + (rr[threadIdx.x][2] + rr[threadIdx.x][3]),
+              (ri[threadIdx.x][0] + ri[threadIdx.x][1]) + (ri[threadIdx.x][2] + ri[threadIdx.x][3])};
     __syncthreads();
   }
 }
@@ -1623,9 +1677,9 @@ template <typename R> void launch_tt(hipStream_t st, const TTDesc<R>& T, const i
   GemmSet<R> F{};
   F.nprob = 3;
   for (int c = 0; c < 3; ++c) {
-    // C(p, i3) = y_b[c][p + n12 i3] += mask * sum_j2 M[j2][p] t3[j2][i3]
-    F.g[c] = GemmArgs<R>{T.M[c], 1, n12, 0, t3 + (int64_t)c * TT_RMAX * n3, n3, 1, 0, yb + (int64_t)c * nv, 1, n12, 0,
-                         n12, n3, T.r2[c], 0, nullptr, mask, 1};
+    // C(i3, p) = y_b[c][p + n12 i3] += mask * sum_j2 t3[j2][i3] M[j2][p]  (p along the columns)
+    F.g[c] = GemmArgs<R>{t3 + (int64_t)c * TT_RMAX * n3, 1, n3, 0, T.M[c], n12, 1, 0, yb + (int64_t)c * nv, n12, 1, 0,
+                         n3, n12, T.r2[c], 0, nullptr, mask, 1};
     F.nbatch[c] = 1;
   }
   zgemm<R>(st, F);
@@ -1737,6 +1791,9 @@ void launch_zbc_near(hipStream_t st, const RwgDev& B, const double* centres, con
 
 void launch_multidot(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* w, int64_t n, cxd* part, int nblk) {
   hipLaunchKernelGGL(k_multidot_partial, dim3(nblk), dim3(256), 0, st, V, ld, nvec, w, n, part);
+}
+void launch_sum_partials(hipStream_t st, const cxd* part, int nblk, int K, cxd* out) {
+  if (K > 0) hipLaunchKernelGGL(k_sum_partials<double>, dim3(K), dim3(256), 0, st, part, nblk, K, out);
 }
 void launch_multiaxpy(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* h, cxd* w, int64_t n) {
   hipLaunchKernelGGL(k_multiaxpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, V, ld, nvec, h, w, n);

@@ -672,6 +672,8 @@ struct Solver {
   cxd* part;     // multidot partials
   double* npart;
   static constexpr int NBLK = 256;
+  static constexpr int MDOT_BLK = 1024;
+  static constexpr int MAX_BASIS = 1024;
   Solver(Handle& h, hipStream_t s) : H(h), st(s), N(h.N) {
     part = H.d_solve_work;
     npart = H.d_red;
@@ -689,14 +691,34 @@ struct Solver {
     out[2] = sqrt(s[2]);
     out[3] = sqrt(s[0] + s[1] + s[2]);
   }
+  // h = V^H w for the first nvec basis vectors (partials per block, summed on the device)
   void dots(const cxd* V, int nvec, const cxd* w, std::vector<cxd>& h) {
-    launch_multidot(st, V, N, nvec, w, N, part, NBLK);
-    std::vector<cxd> p((size_t)NBLK * nvec);
-    VSIE_HIP(hipMemcpyAsync(p.data(), part, sizeof(cxd) * NBLK * nvec, hipMemcpyDeviceToHost, st));
+    cxd* sum = part + (int64_t)MDOT_BLK * MAX_BASIS;
+    launch_multidot(st, V, N, nvec, w, N, part, MDOT_BLK);
+    launch_sum_partials(st, part, MDOT_BLK, nvec, sum);
+    h.resize(nvec);
+    VSIE_HIP(hipMemcpyAsync(h.data(), sum, sizeof(cxd) * nvec, hipMemcpyDeviceToHost, st));
     VSIE_HIP(hipStreamSynchronize(st));
-    h.assign(nvec, cxd{0, 0});
-    for (int b = 0; b < NBLK; ++b)
-      for (int i = 0; i < nvec; ++i) h[i] += p[(size_t)b * nvec + i];
+  }
+  // classical Gram-Schmidt of w against V[0..nvec), repeated once when the first pass removed more
+  // than 1 - 1/sqrt(2) of the norm of w (DGKS criterion); h receives the projection
+  // coefficients, the return value is ||w|| afterwards
+  double orthogonalize(const cxd* V, int nvec, cxd* w, cxd* hvec_dev, std::vector<cxd>& h) {
+    double n0[4], n1[4];
+    norms(w, n0);
+    dots(V, nvec, w, h);
+    VSIE_HIP(hipMemcpyAsync(hvec_dev, h.data(), sizeof(cxd) * nvec, hipMemcpyHostToDevice, st));
+    launch_multiaxpy(st, V, N, nvec, hvec_dev, w, N);
+    norms(w, n1);
+    if (n1[3] < 0.70710678118654752 * n0[3]) {
+      std::vector<cxd> h2;
+      dots(V, nvec, w, h2);
+      VSIE_HIP(hipMemcpyAsync(hvec_dev, h2.data(), sizeof(cxd) * nvec, hipMemcpyHostToDevice, st));
+      launch_multiaxpy(st, V, N, nvec, hvec_dev, w, N);
+      for (int i = 0; i < nvec; ++i) h[i] += h2[i];
+      norms(w, n1);
+    }
+    return n1[3];
   }
   // solve A x = b to relative residual tol (x initialised to zero). Returns iterations used.
   template <typename MV>
@@ -709,7 +731,7 @@ struct Solver {
     *relres = 0;
     if (bnorm == 0) return 0;
     int it = 0;
-    std::vector<cxd> Hm((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h, h2;
+    std::vector<cxd> Hm((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h;
     for (;;) {
       A(x, w);
       launch_sub(st, b, w, w, N);      // r = b - A x
@@ -730,15 +752,8 @@ struct Solver {
       bool done = false;
       for (int j = 0; j < restart; ++j) {
         A(Vbuf + (int64_t)j * N, w);
-        dots(Vbuf, j + 1, w, h);
-        VSIE_HIP(hipMemcpyAsync(hvec_dev, h.data(), sizeof(cxd) * (j + 1), hipMemcpyHostToDevice, st));
-        launch_multiaxpy(st, Vbuf, N, j + 1, hvec_dev, w, N);
-        dots(Vbuf, j + 1, w, h2);
-        VSIE_HIP(hipMemcpyAsync(hvec_dev, h2.data(), sizeof(cxd) * (j + 1), hipMemcpyHostToDevice, st));
-        launch_multiaxpy(st, Vbuf, N, j + 1, hvec_dev, w, N);
-        double nw[4];
-        norms(w, nw);
-        for (int i = 0; i <= j; ++i) Hm[(size_t)i * restart + j] = h[i] + h2[i];
+        double nw[4] = {0, 0, 0, orthogonalize(Vbuf, j + 1, w, hvec_dev, h)};
+        for (int i = 0; i <= j; ++i) Hm[(size_t)i * restart + j] = h[i];
         Hm[(size_t)(j + 1) * restart + j] = {nw[3], 0};
         if (nw[3] > 0) launch_scale_copy(st, w, 1.0 / nw[3], Vbuf + (int64_t)(j + 1) * N, N);
         for (int i = 0; i < j; ++i) {
@@ -790,7 +805,7 @@ struct Solver {
     const double bnorm = nb[3];
     *relres = 0;
     if (bnorm == 0) return 0;
-    std::vector<cxd> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h, h2;
+    std::vector<cxd> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h;
     bool budget = true;
     int cycles = 0;
     for (;;) {
@@ -814,15 +829,8 @@ struct Solver {
         cxd* z = Zb + (int64_t)j * N;
         budget = P(Vb + (int64_t)j * N, z);
         A(z, w);
-        dots(Vb, j + 1, w, h);
-        VSIE_HIP(hipMemcpyAsync(hvec_dev, h.data(), sizeof(cxd) * (j + 1), hipMemcpyHostToDevice, st));
-        launch_multiaxpy(st, Vb, N, j + 1, hvec_dev, w, N);
-        dots(Vb, j + 1, w, h2);
-        VSIE_HIP(hipMemcpyAsync(hvec_dev, h2.data(), sizeof(cxd) * (j + 1), hipMemcpyHostToDevice, st));
-        launch_multiaxpy(st, Vb, N, j + 1, hvec_dev, w, N);
-        double nw[4];
-        norms(w, nw);
-        for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h[i] + h2[i];
+        double nw[4] = {0, 0, 0, orthogonalize(Vb, j + 1, w, hvec_dev, h)};
+        for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h[i];
         Hm[(size_t)(j + 1) * m + j] = {nw[3], 0};
         if (nw[3] > 0) launch_scale_copy(st, w, 1.0 / nw[3], Vb + (int64_t)(j + 1) * N, N);
         for (int i = 0; i < j; ++i) {
@@ -858,7 +866,7 @@ struct Solver {
 
 void ensure_solver_ws(Handle& H, int restart) {
   if (!H.d_solve_work) {
-    H.d_solve_work = H.dalloc<cxd>(256LL * 1100);
+    H.d_solve_work = H.dalloc<cxd>((int64_t)(Solver::MDOT_BLK + 1) * Solver::MAX_BASIS);
     H.d_red = H.dalloc<double>(256 * 4);
   }
   if (H.krylov_cols < restart + 1) {
