@@ -50,9 +50,10 @@ def stage_bytes(info, s):
         "aca": 2 * c * (mf + mn) * info["aca_rank"],
     }
     r = info["tt_rank"]
-    # per component: G4 and the merged first-two-core block read in both directions, y_b read and
-    # written (forward), x_b read (transpose)
-    b["tt"] = sum(c * (2 * r[a][2] * mf + 2 * r[a][1] * n1 * n2 + 3 * nv) for a in range(3))
+    # per component: x-only part reads G4 (with x_f), the merged first-two-core block and x_b;
+    # the accumulation part reads G4 and the merged block again and updates y_b
+    b["tt_pre"] = sum(c * (r[a][2] * mf + r[a][1] * n1 * n2 + nv) for a in range(3))
+    b["tt_post"] = sum(c * (r[a][2] * mf + r[a][1] * n1 * n2 + 2 * nv) for a in range(3))
     return b.get(s)
 
 
@@ -146,6 +147,45 @@ def write_traffic(kernel, fetch_db, write_db, commands):
     print(open(path).read())
 
 
+def write_pmc_summary(kernel, db, out_name, commands):
+    """profiles/<out_name>.txt: mean counter values per dispatch of `kernel` (each instantiation)
+    from a rocprofv3 --pmc database, with the matrix-core rate derived from the MFMA op counters
+    (512 flops per counted op) and the kernel's duration."""
+    import re
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, counter_name, value, duration from counters_collection").fetchall()
+    con.close()
+    agg = {}
+    for n, c, v, d in rows:
+        name = re.sub(r"\(.*", "", n)
+        if kernel not in name:
+            continue
+        a = agg.setdefault(name, {})
+        a.setdefault(c, []).append(float(v))
+        a.setdefault("_dur", []).append(float(d))
+    peaks = {"double": 78.6, "float": 157.3}
+    path = os.path.join(ROOT, "profiles", out_name + ".txt")
+    with open(path, "w") as f:
+        f.write("# rocprofv3 counters per dispatch (MI355X, 2 mm workload)\n")
+        for c in commands:
+            f.write("# command: %s\n" % c)
+        for name, a in sorted(agg.items()):
+            dur = sum(a["_dur"]) / len(a["_dur"])
+            ndisp = max(len(v) for c, v in a.items() if c != "_dur")
+            f.write("%s: %d dispatches, mean duration %.1f us\n" % (name, ndisp, dur / 1e3))
+            for c, vals in sorted(a.items()):
+                if c != "_dur":
+                    f.write("  %-32s %.6g\n" % (c, sum(vals) / len(vals)))
+            for prec, key in (("double", "SQ_INSTS_VALU_MFMA_MOPS_F64"), ("float", "SQ_INSTS_VALU_MFMA_MOPS_F32")):
+                if prec in name and key in a:
+                    flops = 512 * sum(a[key]) / len(a[key])
+                    rate = flops / (dur * 1e-9) / 1e12
+                    f.write("  matrix-core flops per dispatch %.4g -> %.2f TFLOP/s = %.3f of the %.1f TFLOP/s "
+                            "dense peak\n" % (flops, rate, rate / peaks[prec], peaks[prec]))
+    print(open(path).read())
+
+
 def write_trace_summary(stats_csv, out_name, command, top=25):
     """profiles/<out_name>.txt: the top kernels of a rocprofv3 --kernel-trace --stats run."""
     import csv
@@ -223,10 +263,15 @@ def main():
                     help="write profiles/traffic_<KERNEL>_2mm.txt from two rocprofv3 --pmc databases")
     ap.add_argument("--write-trace", nargs=2, metavar=("STATS_CSV", "NAME"),
                     help="write profiles/NAME.txt from a rocprofv3 --kernel-trace --stats CSV")
+    ap.add_argument("--write-pmc", nargs=3, metavar=("KERNEL", "DB", "NAME"),
+                    help="write profiles/NAME.txt with the counters of KERNEL from a rocprofv3 --pmc database")
     ap.add_argument("--command", action="append", default=[], help="command line recorded in the summary")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args.write_traffic[0], args.write_traffic[1], args.write_traffic[2], args.command)
+        return
+    if args.write_pmc:
+        write_pmc_summary(args.write_pmc[0], args.write_pmc[1], args.write_pmc[2], args.command)
         return
     if args.write_trace:
         write_trace_summary(args.write_trace[0], args.write_trace[1], " ; ".join(args.command))
@@ -257,11 +302,15 @@ def main():
     for _ in range(args.warmup):
         op.matvec(x, out=y)
     torch.cuda.synchronize()
+    # stage events are recorded during the timed products and read back after the timed region
+    op.profile(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         op.matvec(x, out=y)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    stages = op.profile_read()
+    op.profile(False)
     value = args.steps / el
     print("fp64: %.1f matvec/s (%.3f ms)" % (value, 1e3 * el / args.steps), file=sys.stderr, flush=True)
 
@@ -279,13 +328,6 @@ def main():
     err32 = float(torch.linalg.norm(y32.to(torch.complex128) - y) / torch.linalg.norm(y))
     print("fp32: %.1f matvec/s, rel err vs fp64 %.2e" % (value32, err32), file=sys.stderr, flush=True)
 
-    # per-stage timing with HIP events recorded on the stream the kernels run on
-    op.profile(True)
-    nprof = 20
-    for _ in range(nprof):
-        op.matvec(x, out=y)
-    stages = op.profile_read()
-    op.profile(False)
     per_stage = {k: v[0] / v[1] for k, v in stages.items()}
     print("stage ms: %s" % json.dumps({k: round(v, 4) for k, v in per_stage.items()}), file=sys.stderr, flush=True)
     dom = max((k for k in per_stage if k in KERNEL_OF_STAGE), key=per_stage.get)

@@ -156,12 +156,13 @@ int vsie_rhs(const struct vsie_handle* h, int port, int dtype, void* b_dev, void
 int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, void* y_dev,
                 void* stream);
 
-/* Solve Z x = b for nrhs right-hand sides (device, [nrhs][N] complex128) with restarted GMRES
- * (Sec. III-A: zero initial guess, FP64 classical Gram-Schmidt applied twice) or the mixed-
- * precision solver IR_MIXED: FP64 flexible GMRES (20 steps per cycle) on the FP64 operator whose
- * preconditioner is one cycle (at most `restart` iterations, stopping early at inner_tol) of
- * complex64 GMRES on Z z = v; with an exact inner solve each outer step is one refinement
- * x += Z^{-1}(b - Zx). x_dev receives complex128. Blocks.
+/* Solve Z x = b for nrhs right-hand sides (device, [nrhs][N] complex128).
+ * GMRES64: restarted GMRES (Sec. III-A), zero initial guess, FP64 classical Gram-Schmidt repeated
+ * when the first pass loses more than 1 - 1/sqrt(2) of the norm.
+ * IR_MIXED: FP64 flexible GMRES (20 steps per cycle) on the FP64 operator whose preconditioner is
+ * one cycle (at most `restart` iterations, stopping early at inner_tol) of complex64 GMRES on
+ * Z z = v; with an exact inner solve each outer step is one refinement x += Z^{-1}(b - Zx).
+ * x_dev receives complex128. Blocks.
  * Allocates its work vectors (IR_MIXED: 41 FP64 vectors of length N besides the Krylov basis).
  * stats (array of nrhs, may be NULL) are filled even on E_NOCONV. */
 int vsie_solve(struct vsie_handle* h, const vsie_solve_opts* opts, int nrhs, const void* b_dev,
@@ -193,12 +194,15 @@ int vsie_export(const struct vsie_handle* h, int what, int index, void* host, si
  * vsie_export. Errors: E_ARG (size mismatch). */
 int vsie_import(struct vsie_handle* h, int what, int index, const void* host, size_t nbytes);
 
-/* Per-stage timing of vsie_matvec with HIP events recorded on the caller's stream (the stream
- * each kernel runs on). enable != 0 creates the events and resets the totals; while enabled,
- * every matvec synchronises its stream once at the end. Stages: build_grid, fft_x_fwd,
- * fft_y_fwd, fft_z_conv, fft_y_inv, fft_x_inv, body_out, pfft_gather, gemv_far, precorrect,
- * aca, tt. vsie_profile_read returns up to max_stages entries (names are static strings),
- * the summed milliseconds and the number of timed calls per stage, and the stage count. */
+/* Per-stage timing of vsie_matvec with HIP events recorded on the stream each stage runs on
+ * (the caller's stream, or the handle's second stream for gemv_far, gemv_far_reduce and tt_pre,
+ * which run concurrently with the volume stages). enable != 0 creates the events and resets the
+ * totals; the events of up to 256 products are kept and read back by vsie_profile_read (which
+ * waits for them) or when that ring is full, so products are not synchronised while profiled.
+ * Stages: build_grid, fft_x_fwd, fft_y_fwd, fft_z_conv, fft_y_inv, fft_x_inv, body_out,
+ * pfft_gather, gemv_far, precorrect, aca, tt_pre, gemv_far_reduce, tt_post. vsie_profile_read
+ * returns up to max_stages entries (names are static strings), the summed milliseconds and the
+ * number of timed calls per stage, and the stage count. */
 int vsie_profile(struct vsie_handle* h, int enable);
 int vsie_profile_read(const struct vsie_handle* h, int max_stages, const char** names, double* total_ms,
                       int64_t* calls, int* n_stages);

@@ -69,8 +69,10 @@ template <typename R> struct TTDesc {
 };
 // forward and transpose far coupling of all three components: y_b += mask Zt x_f,
 // y_f += sum_c Zt_c^T (mask x_b)
-template <typename R> void launch_tt(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
-                                     const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* yb, cx<R>* work);
+template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
+                                         const cx<R>* xb, const uint8_t* mask, cx<R>* work);
+template <typename R> void launch_tt_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
+                                          const uint8_t* mask, cx<R>* yf, cx<R>* yb, const cx<R>* work);
 int64_t tt_work_elems(const int n[3], int mf);
 // y = Z x for the symmetric far block stored as upper-triangle tiles (part: 2 SYM_TB per tile)
 template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,

@@ -1102,19 +1102,11 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const cx<R>* __restrict__ A, 
 
 // Symmetric far block from its upper-triangle tiles: one block per tile (I, J) reads the tile
 // once and produces both the row sums Z_IJ x_J and (for I < J) the column sums Z_IJ^T x_I.
-// Thread (rg, cg): 32 column groups of 4 columns (64-byte FP64 segments, a 2 KB row per 32
-// lanes) x 8 row groups of 16 rows. Row sums reduce across the 32 column lanes by shuffles;
-// column sums across row groups by one shuffle and LDS.
-#ifdef SYMV_WAVES
-#define SYMV_ATTR __attribute__((amdgpu_waves_per_eu(SYMV_WAVES, 8)))
-#else
-#define SYMV_ATTR
-#endif
-#ifndef SYMV_UNROLL
-#define SYMV_UNROLL 4
-#endif
+// Thread (rg, cg): column lane cg owns columns cg + 32 c, c < 4, so each load instruction of a
+// half-wavefront reads 512 contiguous bytes of one row; 8 row groups of 16 rows. Row sums reduce
+// across the 32 column lanes by shuffles; column sums across row groups by one shuffle and LDS.
 template <typename R>
-__global__ __launch_bounds__(256) SYMV_ATTR void k_symv_tiles(const cx<R>* __restrict__ Zp, const int* __restrict__ tiles,
+__global__ __launch_bounds__(256) void k_symv_tiles(const cx<R>* __restrict__ Zp, const int* __restrict__ tiles,
                                                     const cx<R>* __restrict__ x, int m, cx<R>* __restrict__ part) {
   __shared__ R cr[4][SYM_TB], ci[4][SYM_TB];
   __shared__ cx<R> xs[SYM_TB];
@@ -1129,21 +1121,21 @@ __global__ __launch_bounds__(256) SYMV_ATTR void k_symv_tiles(const cx<R>* __res
   cx<R> xJ[4], ca[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    int n = J * SYM_TB + cg * 4 + c;
+    int n = J * SYM_TB + cg + 32 * c;
     xJ[c] = n < m ? x[n] : cx<R>{0, 0};
     ca[c] = {0, 0};
   }
   __syncthreads();
   cx<R>* out = part + t * 2 * SYM_TB;
-#pragma unroll SYMV_UNROLL
+#pragma unroll 4
   for (int r = 0; r < 16; ++r) {
     const int row = rg * 16 + r;
-    const cx<R>* zr = Z + (int64_t)row * SYM_TB + cg * 4;
+    const cx<R>* zr = Z + (int64_t)row * SYM_TB + cg;
     const cx<R> xi = xs[row];
     cx<R> rd = {0, 0};
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      cx<R> z = zr[c];
+      cx<R> z = zr[32 * c];
       rd += z * xJ[c];
       ca[c] += z * xi;
     }
@@ -1163,8 +1155,8 @@ __global__ __launch_bounds__(256) SYMV_ATTR void k_symv_tiles(const cx<R>* __res
   if ((threadIdx.x % 64) < 32)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      cr[wave][cg * 4 + c] = ca[c].re;
-      ci[wave][cg * 4 + c] = ca[c].im;
+      cr[wave][cg + 32 * c] = ca[c].re;
+      ci[wave][cg + 32 * c] = ca[c].im;
     }
   __syncthreads();
   if (threadIdx.x < SYM_TB) {
@@ -1654,60 +1646,86 @@ template <typename R> void launch_gemv_rows(hipStream_t st, const cx<R>* A, cons
                                             cx<R>* out, int accumulate) {
   if (nrow > 0) hipLaunchKernelGGL(k_gemv_rows<R>, dim3((unsigned)nrow), dim3(256), 0, st, A, x, ncol, out, accumulate);
 }
-template <typename R> void launch_tt(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
-                                     const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* yb, cx<R>* work) {
-  const int n1 = n[0], n2 = n[1], n3 = n[2];
-  const int n12 = n1 * n2;
-  const int64_t nv = (int64_t)n12 * n3;
-  int rmax2 = 1, rmax3 = 1;
+// TT work layout: part (3 RMAX nchunk; later s3) | t3 (3 RMAX n3) | s2 (3 RMAX n3) |
+// split-K partials (3 nkc RMAX n3) | s3 partials (nk3 3 RMAX)
+struct TTWork {
+  int n1, n2, n3, n12, mf, nchunk, nkc, nk3, rmax2, rmax3;
+  int64_t nv;
+};
+template <typename R> static TTWork tt_layout(const TTDesc<R>& T, const int n[3], int mf) {
+  TTWork w;
+  w.n1 = n[0];
+  w.n2 = n[1];
+  w.n3 = n[2];
+  w.n12 = n[0] * n[1];
+  w.nv = (int64_t)w.n12 * w.n3;
+  w.mf = mf;
+  w.rmax2 = 1;
+  w.rmax3 = 1;
   for (int c = 0; c < 3; ++c) {
-    rmax2 = std::max(rmax2, T.r2[c]);
-    rmax3 = std::max(rmax3, T.r3[c]);
+    w.rmax2 = std::max(w.rmax2, T.r2[c]);
+    w.rmax3 = std::max(w.rmax3, T.r3[c]);
   }
-  const int chunk = 4096;
-  const int nchunk = (mf + chunk - 1) / chunk;
+  w.nchunk = (mf + 4095) / 4096;
+  w.nkc = (w.n12 + TT_KCHUNK - 1) / TT_KCHUNK;
+  w.nk3 = (w.rmax2 * w.n3 + TT_KROWS - 1) / TT_KROWS;
+  return w;
+}
+
+// Everything of the TT coupling that reads only x: forward G4 x_f then G3 (eqs. (16)-(17)) into
+// t3, and the transpose (eqs. (18)-(19)) S2 = M (mask x_b) over the merged first two cores, then
+// G3 into s3. Writes the work buffer only.
+template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
+                                         const cx<R>* xb, const uint8_t* mask, cx<R>* work) {
+  const TTWork w = tt_layout(T, n, mf);
   const int kc = TT_KCHUNK;
-  const int nkc = (n12 + kc - 1) / kc;
-  cx<R>* part = work;                                    // 3 * RMAX * nchunk
-  cx<R>* t3 = part + 3LL * TT_RMAX * nchunk;             // 3 * RMAX * n3
-  cx<R>* kpart = t3 + 3LL * TT_RMAX * n3;                // 3 * nkc * RMAX * n3
-  // forward (eqs. (16)-(17)): G4 x first, then G3, then the merged first two cores
-  hipLaunchKernelGGL(k_tt_f4<R>, dim3(nchunk, rmax3, 3), dim3(256), 0, st, T, xf, mf, chunk, part, nchunk);
-  hipLaunchKernelGGL(k_tt_f3<R>, dim3((rmax2 * n3 + 15) / 16, 3), dim3(256), 0, st, T, part, nchunk, n3, t3);
-  GemmSet<R> F{};
-  F.nprob = 3;
-  for (int c = 0; c < 3; ++c) {
-    // C(i3, p) = y_b[c][p + n12 i3] += mask * sum_j2 t3[j2][i3] M[j2][p]  (p along the columns)
-    F.g[c] = GemmArgs<R>{t3 + (int64_t)c * TT_RMAX * n3, 1, n3, 0, T.M[c], n12, 1, 0, yb + (int64_t)c * nv, n12, 1, 0,
-                         n3, n12, T.r2[c], 0, nullptr, mask, 1};
-    F.nbatch[c] = 1;
-  }
-  zgemm<R>(st, F);
-  // transpose (eqs. (18)-(19)), summed over the components into y_f:
+  cx<R>* part = work;
+  cx<R>* t3 = part + 3LL * TT_RMAX * w.nchunk;
+  cx<R>* s2 = t3 + 3LL * TT_RMAX * w.n3;
+  cx<R>* kpart = s2 + 3LL * TT_RMAX * w.n3;
+  cx<R>* s3part = kpart + 3LL * w.nkc * TT_RMAX * w.n3;
+  cx<R>* s3 = part;
+  hipLaunchKernelGGL(k_tt_f4<R>, dim3(w.nchunk, w.rmax3, 3), dim3(256), 0, st, T, xf, mf, 4096, part, w.nchunk);
+  hipLaunchKernelGGL(k_tt_f3<R>, dim3((w.rmax2 * w.n3 + 15) / 16, 3), dim3(256), 0, st, T, part, w.nchunk, w.n3, t3);
   // S2(j2, i3) = sum_p M[j2][p] mask x_b[c][p + n12 i3], split over p in chunks of kc
   GemmSet<R> B{};
   B.nprob = 3;
   for (int c = 0; c < 3; ++c) {
-    B.g[c] = GemmArgs<R>{T.M[c], n12, 1, kc, xb + (int64_t)c * nv, 1, n12, kc,
-                         kpart + (int64_t)c * nkc * TT_RMAX * n3, n3, 1, (int64_t)TT_RMAX * n3,
-                         T.r2[c], n3, kc, n12, mask, nullptr, 0};
-    B.nbatch[c] = nkc;
+    B.g[c] = GemmArgs<R>{T.M[c], w.n12, 1, kc, xb + (int64_t)c * w.nv, 1, w.n12, kc,
+                         kpart + (int64_t)c * w.nkc * TT_RMAX * w.n3, w.n3, 1, (int64_t)TT_RMAX * w.n3,
+                         T.r2[c], w.n3, kc, w.n12, mask, nullptr, 0};
+    B.nbatch[c] = w.nkc;
   }
   zgemm<R>(st, B);
-  cx<R>* s2 = t3;
-  cx<R>* s3 = part;
-  hipLaunchKernelGGL(k_tt_ksum<R>, dim3((rmax2 * n3 + 31) / 32, 3), dim3(256), 0, st, T, kpart, nkc, n3, s2);
-  const int nk3 = (rmax2 * n3 + TT_KROWS - 1) / TT_KROWS;
-  cx<R>* s3part = kpart + 3LL * nkc * TT_RMAX * n3;   // nk3 x 3 RMAX
-  hipLaunchKernelGGL(k_ttT_3<R>, dim3(nk3, 3), dim3(256), 0, st, T, s2, n3, s3part);
-  hipLaunchKernelGGL(k_sum_partials<R>, dim3(3 * TT_RMAX), dim3(256), 0, st, s3part, nk3, 3 * TT_RMAX, s3);
+  hipLaunchKernelGGL(k_tt_ksum<R>, dim3((w.rmax2 * w.n3 + 31) / 32, 3), dim3(256), 0, st, T, kpart, w.nkc, w.n3, s2);
+  hipLaunchKernelGGL(k_ttT_3<R>, dim3(w.nk3, 3), dim3(256), 0, st, T, s2, w.n3, s3part);
+  hipLaunchKernelGGL(k_sum_partials<R>, dim3(3 * TT_RMAX), dim3(256), 0, st, s3part, w.nk3, 3 * TT_RMAX, s3);
+}
+
+// The accumulations: y_b[c] += mask * (merged core) t3 (forward) and y_f += sum_c G4^T s3
+// (transpose), from the work buffer filled by launch_tt_pre.
+template <typename R> void launch_tt_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
+                                          const uint8_t* mask, cx<R>* yf, cx<R>* yb, const cx<R>* work) {
+  const TTWork w = tt_layout(T, n, mf);
+  const cx<R>* t3 = work + 3LL * TT_RMAX * w.nchunk;
+  const cx<R>* s3 = work;
+  GemmSet<R> F{};
+  F.nprob = 3;
+  for (int c = 0; c < 3; ++c) {
+    // C(i3, p) = y_b[c][p + n12 i3] += mask * sum_j2 t3[j2][i3] M[j2][p]  (p along the columns)
+    F.g[c] = GemmArgs<R>{t3 + (int64_t)c * TT_RMAX * w.n3, 1, w.n3, 0, T.M[c], w.n12, 1, 0, yb + (int64_t)c * w.nv,
+                         w.n12, 1, 0, w.n3, w.n12, T.r2[c], 0, nullptr, mask, 1};
+    F.nbatch[c] = 1;
+  }
+  zgemm<R>(st, F);
   hipLaunchKernelGGL(k_ttT_4<R>, dim3((mf + 63) / 64), dim3(256), 0, st, T, s3, mf, yf);
 }
 int64_t tt_work_elems(const int n[3], int mf) {
   const int nchunk = (mf + 4095) / 4096;
   const int nkc = (n[0] * n[1] + TT_KCHUNK - 1) / TT_KCHUNK;
   const int nk3 = (TT_RMAX * n[2] + TT_KROWS - 1) / TT_KROWS;
-  return 3LL * TT_RMAX * nchunk + 3LL * TT_RMAX * n[2] + 3LL * nkc * TT_RMAX * n[2] + 3LL * TT_RMAX * nk3;
+  return 3LL * TT_RMAX * std::max(nchunk, 1) + 6LL * TT_RMAX * n[2] + 3LL * nkc * TT_RMAX * n[2] +
+         3LL * TT_RMAX * nk3;
 }
 template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
                                              int m, cx<R>* part) {
@@ -1733,8 +1751,10 @@ template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, co
   template void launch_lr_t<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*, int, cx<R>*);      \
   template void launch_lr_n_add<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*);              \
   template void launch_gemv_rows<R>(hipStream_t, const cx<R>*, const cx<R>*, int64_t, int64_t, cx<R>*, int);          \
-  template void launch_tt<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*, const cx<R>*,           \
-                             const uint8_t*, cx<R>*, cx<R>*, cx<R>*);                                                 \
+  template void launch_tt_pre<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*, const cx<R>*,       \
+                                 const uint8_t*, cx<R>*);                                                             \
+  template void launch_tt_post<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const uint8_t*, cx<R>*, cx<R>*,   \
+                                  const cx<R>*);                                                                      \
   template void launch_scatter_rhs<R>(hipStream_t, const int*, const double*, const double*, int, cx<R>*);         \
   template void launch_symv_tiles<R>(hipStream_t, const cx<R>*, const int*, int, const cx<R>*, int, cx<R>*);      \
   template void launch_symv_reduce<R>(hipStream_t, const cx<R>*, int, int, cx<R>*);

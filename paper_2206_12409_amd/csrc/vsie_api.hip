@@ -543,40 +543,63 @@ template <typename R> void alloc_work(Handle& H, OpData<R>& D) {
 }
 
 // ---------------------------------------------------------------------------------------------
-const char* const kStageNames[Handle::NSTAGE] = {"build_grid", "fft_x_fwd", "fft_y_fwd",  "fft_z_conv", "fft_y_inv",
-                                                 "fft_x_inv",  "body_out",  "pfft_gather", "gemv_far",  "precorrect",
-                                                 "aca",        "tt",        "gemv_far_reduce"};
+const char* const kStageNames[Handle::NSTAGE] = {
+    "build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv",       "fft_x_inv", "body_out",
+    "pfft_gather", "gemv_far", "precorrect", "aca",       "tt_pre",    "gemv_far_reduce", "tt_post"};
 
-struct StageTimer {
-  Handle& H;
-  hipStream_t st;
-  StageTimer(Handle& h, hipStream_t s) : H(h), st(s) {
-    for (int i = 0; i < Handle::NSTAGE; ++i) H.ev_used[i] = false;
-  }
-  void begin(int s) {
-    if (H.prof) {
-      VSIE_HIP(hipEventRecord(H.ev[2 * s], st));
-      H.ev_used[s] = true;
-    }
-  }
-  void end(int s) {
-    if (H.prof) VSIE_HIP(hipEventRecord(H.ev[2 * s + 1], st));
-  }
-  void collect() {
-    if (!H.prof) return;
-    VSIE_HIP(hipStreamSynchronize(st));
+// Accumulate the stage times of every pending product (waits for their events).
+static void drain_profile(Handle& H) {
+  for (int k = H.ring_count; k > 0; --k) {
+    const int slot = (H.ring_head - k + Handle::PROF_RING) % Handle::PROF_RING;
     for (int s = 0; s < Handle::NSTAGE; ++s)
-      if (H.ev_used[s]) {
+      if (H.ev_mask[slot] & (1u << s)) {
+        VSIE_HIP(hipEventSynchronize(H.ev[slot][2 * s + 1]));
         float ms = 0;
-        VSIE_HIP(hipEventElapsedTime(&ms, H.ev[2 * s], H.ev[2 * s + 1]));
+        VSIE_HIP(hipEventElapsedTime(&ms, H.ev[slot][2 * s], H.ev[slot][2 * s + 1]));
         H.prof_ms[s] += ms;
         H.prof_calls[s] += 1;
       }
   }
+  H.ring_count = 0;
+}
+
+// Per-stage HIP events of one product, recorded on the stream the stage runs on.
+struct StageTimer {
+  Handle& H;
+  hipStream_t st;
+  int slot = -1;
+  StageTimer(Handle& h, hipStream_t s) : H(h), st(s) {
+    if (!H.prof) return;
+    if (H.ring_count == Handle::PROF_RING) drain_profile(H);
+    slot = H.ring_head;
+    H.ev_mask[slot] = 0;
+  }
+  void begin(int s, hipStream_t on = nullptr) {
+    if (slot < 0) return;
+    VSIE_HIP(hipEventRecord(H.ev[slot][2 * s], on ? on : st));
+    H.ev_mask[slot] |= 1u << s;
+  }
+  void end(int s, hipStream_t on = nullptr) {
+    if (slot >= 0) VSIE_HIP(hipEventRecord(H.ev[slot][2 * s + 1], on ? on : st));
+  }
+  void collect() {
+    if (slot < 0) return;
+    H.ring_head = (slot + 1) % Handle::PROF_RING;
+    ++H.ring_count;
+  }
 };
 
+// One product (eq. (15)). The dense far block only reads x_f and writes y_f, so it runs on a
+// second stream (default priority, forked from and joined back into the caller's stream by
+// events) concurrently with the volume convolution and pFFT chain; everything that accumulates
+// into y_f, y_n or y_b after both runs on the caller's stream.
 template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t st) {
   StageTimer T(H, st);
+  if (!H.side) {
+    VSIE_HIP(hipStreamCreateWithFlags(&H.side, hipStreamNonBlocking));
+    VSIE_HIP(hipEventCreateWithFlags(&H.fork, hipEventDisableTiming));
+    VSIE_HIP(hipEventCreateWithFlags(&H.join, hipEventDisableTiming));
+  }
   const int mf = H.mf, mn = H.mn;
   const cx<R>* xf = x;
   const cx<R>* xn = x + mf;
@@ -587,6 +610,33 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
   GridDims g = grid_dims(H);
   const int P1 = H.P[0], P2 = H.P[1], P3 = H.P[2];
   const int ne1 = H.ne[0], ne2 = H.ne[1], ne3 = H.ne[2];
+  const bool have_tt = mf && D.G12[0] && D.G12[1] && D.G12[2];
+  TTDesc<R> td;
+  if (have_tt)
+    for (int c = 0; c < 3; ++c) {
+      td.M[c] = D.G12[c];
+      td.G3[c] = D.G[c][2];
+      td.G4[c] = D.G[c][3];
+      td.r2[c] = H.tt_r[c][1];
+      td.r3[c] = H.tt_r[c][2];
+    }
+  // side stream: dense far block (writes y_f), then the parts of the TT coupling that read only x
+  if (mf) {
+    VSIE_HIP(hipEventRecord(H.fork, st));
+    VSIE_HIP(hipStreamWaitEvent(H.side, H.fork, 0));
+    T.begin(8, H.side);
+    launch_symv_tiles<R>(H.side, D.Zff, H.d_tiles, H.sym_T, xf, mf, D.sym_part);
+    T.end(8, H.side);
+    T.begin(12, H.side);
+    launch_symv_reduce<R>(H.side, D.sym_part, H.sym_T, mf, yf);
+    T.end(12, H.side);
+    if (have_tt) {
+      T.begin(11, H.side);
+      launch_tt_pre<R>(H.side, td, H.n, mf, xf, xb, H.d_mask, D.tt_work);
+      T.end(11, H.side);
+    }
+    VSIE_HIP(hipEventRecord(H.join, H.side));
+  }
   // volume convolution and pFFT (Sec. II-B, eq. (13))
   T.begin(0);
   launch_build_grid<R>(st, xb, mn ? xn : nullptr, H.d_mask, mn ? H.d_vox2row : nullptr, H.d_rowptr, H.d_rowrwg, D.roww,
@@ -615,15 +665,7 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
     launch_pfft_gather<R>(st, D.W, H.d_base, D.gridA, yn, mn, g);
     T.end(7);
   }
-  // dense far block (writes y_f)
-  if (mf) {
-    T.begin(8);
-    launch_symv_tiles<R>(st, D.Zff, H.d_tiles, H.sym_T, xf, mf, D.sym_part);
-    T.end(8);
-    T.begin(12);
-    launch_symv_reduce<R>(st, D.sym_part, H.sym_T, mf, yf);
-    T.end(12);
-  }
+  if (mf) VSIE_HIP(hipStreamWaitEvent(st, H.join, 0));
   // precorrection
   T.begin(9);
   launch_csr_add<R>(st, H.d_pc_rowid, H.d_pc_rowptr, H.d_pc_col, D.pc_val, x, y, H.n_pcrows);
@@ -639,25 +681,18 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
     launch_lr_n_add<R>(st, true, D.V, t, mf, H.aca_k, yf);
     T.end(10);
   }
-  // TT far coupling (eqs. (16)-(19))
-  if (mf && D.G12[0] && D.G12[1] && D.G12[2]) {
-    T.begin(11);
-    TTDesc<R> td;
-    for (int c = 0; c < 3; ++c) {
-      td.M[c] = D.G12[c];
-      td.G3[c] = D.G[c][2];
-      td.G4[c] = D.G[c][3];
-      td.r2[c] = H.tt_r[c][1];
-      td.r3[c] = H.tt_r[c][2];
-    }
-    launch_tt<R>(st, td, H.n, mf, xf, xb, H.d_mask, yf, yb, D.tt_work);
-    T.end(11);
+  // TT far coupling (eqs. (16)-(19)): the accumulations into y_b and y_f
+  if (have_tt) {
+    T.begin(13);
+    launch_tt_post<R>(st, td, H.n, mf, H.d_mask, yf, yb, D.tt_work);
+    T.end(13);
   }
   T.collect();
 }
 
 // ---------------------------------------------------------------------------------------------
-// GMRES (FP64 Arnoldi, CGS2) with a matvec callback on FP64 vectors
+// GMRES (FP64 Arnoldi, classical Gram-Schmidt with selective reorthogonalisation) with a matvec
+// callback on FP64 vectors
 static bool verbose() {
   static const bool on = getenv("VSIE_VERBOSE") != nullptr;
   return on;
@@ -1300,8 +1335,11 @@ int vsie_profile(vsie_handle* hd, int enable) {
   if (!hd) return fail(VSIE_E_ARG, "null handle");
   Handle& H = hd->H;
   return guarded([&]() {
-    if (enable && !H.ev[0])
-      for (auto& e : H.ev) VSIE_HIP(hipEventCreate(&e));
+    if (enable && !H.ev[0][0])
+      for (auto& slot : H.ev)
+        for (auto& e : slot) VSIE_HIP(hipEventCreate(&e));
+    if (H.prof) drain_profile(H);
+    H.ring_count = 0;
     H.prof = enable != 0;
     for (int s = 0; s < Handle::NSTAGE; ++s) {
       H.prof_ms[s] = 0;
@@ -1313,7 +1351,9 @@ int vsie_profile(vsie_handle* hd, int enable) {
 int vsie_profile_read(const vsie_handle* hd, int max_stages, const char** names, double* total_ms, int64_t* calls,
                       int* n_stages) {
   if (!hd || !n_stages) return fail(VSIE_E_ARG, "null argument");
-  const Handle& H = hd->H;
+  Handle& H = const_cast<vsie_handle*>(hd)->H;   // reading back pending events updates only the totals
+  const int rc = guarded([&]() { drain_profile(H); });
+  if (rc != VSIE_OK) return rc;
   *n_stages = Handle::NSTAGE;
   for (int s = 0; s < Handle::NSTAGE && s < max_stages; ++s) {
     if (names) names[s] = kStageNames[s];

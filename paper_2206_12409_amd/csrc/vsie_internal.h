@@ -143,10 +143,16 @@ struct Handle {
   hipStream_t stream = nullptr;
   std::vector<void*> allocations;
   // per-stage timing of the matrix-vector product (HIP events on the caller's stream)
-  static constexpr int NSTAGE = 13;
+  static constexpr int NSTAGE = 14;
+  hipStream_t side = nullptr;    // second stream of the product (dense far block)
+  hipEvent_t fork = nullptr, join = nullptr;
   bool prof = false;
-  hipEvent_t ev[2 * NSTAGE] = {};
-  bool ev_used[NSTAGE] = {};
+  // stage events of the last PROF_RING products, read back only by vsie_profile_read (or when the
+  // ring wraps), so profiling adds no synchronisation to the products themselves
+  static constexpr int PROF_RING = 256;
+  hipEvent_t ev[PROF_RING][2 * NSTAGE] = {};
+  uint32_t ev_mask[PROF_RING] = {};
+  int ring_head = 0, ring_count = 0;
   double prof_ms[NSTAGE] = {};
   int64_t prof_calls[NSTAGE] = {};
 
@@ -160,9 +166,14 @@ struct Handle {
     return (T*)p;
   }
   ~Handle() {
+    if (side) (void)hipStreamSynchronize(side);
     for (void* p : allocations) (void)hipFree(p);
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
+    for (auto& slot : ev)
+      for (auto& e : slot)
+        if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
   }
 };
 
