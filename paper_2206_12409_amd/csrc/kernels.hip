@@ -1100,68 +1100,73 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const cx<R>* __restrict__ A, 
   }
 }
 
-// Symmetric far block from its upper-triangle tiles: one block per tile (I, J) reads the tile
-// once and produces both the row sums Z_IJ x_J and (for I < J) the column sums Z_IJ^T x_I.
+// Symmetric far block from its upper-triangle tiles: each tile (I, J) is read once (blocks step
+// over the tiles, one per block at the default grid) and yields both the row sums Z_IJ x_J and
+// (for I < J) the column sums Z_IJ^T x_I.
 // Thread (rg, cg): column lane cg owns columns cg + 32 c, c < 4, so each load instruction of a
 // half-wavefront reads 512 contiguous bytes of one row; 8 row groups of 16 rows. Row sums reduce
 // across the 32 column lanes by shuffles; column sums across row groups by one shuffle and LDS.
 template <typename R>
 __global__ __launch_bounds__(256) void k_symv_tiles(const cx<R>* __restrict__ Zp, const int* __restrict__ tiles,
-                                                    const cx<R>* __restrict__ x, int m, cx<R>* __restrict__ part) {
+                                                    const cx<R>* __restrict__ x, int m, int64_t ntiles,
+                                                    cx<R>* __restrict__ part) {
   __shared__ R cr[4][SYM_TB], ci[4][SYM_TB];
   __shared__ cx<R> xs[SYM_TB];
-  const int64_t t = blockIdx.x;
-  const int I = tiles[2 * t], J = tiles[2 * t + 1];
   const int cg = threadIdx.x % 32, rg = threadIdx.x / 32;
-  const cx<R>* Z = Zp + t * (int64_t)SYM_TB * SYM_TB;
-  if (threadIdx.x < SYM_TB) {
-    int mm = I * SYM_TB + threadIdx.x;
-    xs[threadIdx.x] = mm < m ? x[mm] : cx<R>{0, 0};
-  }
-  cx<R> xJ[4], ca[4];
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int I = tiles[2 * t], J = tiles[2 * t + 1];
+    const cx<R>* Z = Zp + t * (int64_t)SYM_TB * SYM_TB;
+    if (threadIdx.x < SYM_TB) {
+      int mm = I * SYM_TB + threadIdx.x;
+      xs[threadIdx.x] = mm < m ? x[mm] : cx<R>{0, 0};
+    }
+    cx<R> xJ[4], ca[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    int n = J * SYM_TB + cg + 32 * c;
-    xJ[c] = n < m ? x[n] : cx<R>{0, 0};
-    ca[c] = {0, 0};
-  }
-  __syncthreads();
-  cx<R>* out = part + t * 2 * SYM_TB;
+    for (int c = 0; c < 4; ++c) {
+      int n = J * SYM_TB + cg + 32 * c;
+      xJ[c] = n < m ? x[n] : cx<R>{0, 0};
+      ca[c] = {0, 0};
+    }
+    __syncthreads();
+    cx<R>* out = part + t * 2 * SYM_TB;
 #pragma unroll 4
-  for (int r = 0; r < 16; ++r) {
-    const int row = rg * 16 + r;
-    const cx<R>* zr = Z + (int64_t)row * SYM_TB + cg;
-    const cx<R> xi = xs[row];
-    cx<R> rd = {0, 0};
+    for (int r = 0; r < 16; ++r) {
+      const int row = rg * 16 + r;
+      const cx<R>* zr = Z + (int64_t)row * SYM_TB + cg;
+      const cx<R> xi = xs[row];
+      cx<R> rd = {0, 0};
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      cx<R> z = zr[32 * c];
-      rd += z * xJ[c];
-      ca[c] += z * xi;
+      for (int c = 0; c < 4; ++c) {
+        cx<R> z = zr[32 * c];
+        rd += z * xJ[c];
+        ca[c] += z * xi;
+      }
+      for (int off = 16; off > 0; off >>= 1) {
+        rd.re += __shfl_xor(rd.re, off, 32);
+        rd.im += __shfl_xor(rd.im, off, 32);
+      }
+      if (cg == 0) out[row] = rd;
     }
-    for (int off = 16; off > 0; off >>= 1) {
-      rd.re += __shfl_xor(rd.re, off, 32);
-      rd.im += __shfl_xor(rd.im, off, 32);
-    }
-    if (cg == 0) out[row] = rd;
-  }
-  if (I == J) return;
+    if (I != J) {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    ca[c].re += __shfl_xor(ca[c].re, 32, 64);
-    ca[c].im += __shfl_xor(ca[c].im, 32, 64);
-  }
-  const int wave = threadIdx.x / 64;
-  if ((threadIdx.x % 64) < 32)
+      for (int c = 0; c < 4; ++c) {
+        ca[c].re += __shfl_xor(ca[c].re, 32, 64);
+        ca[c].im += __shfl_xor(ca[c].im, 32, 64);
+      }
+      const int wave = threadIdx.x / 64;
+      if ((threadIdx.x % 64) < 32)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      cr[wave][cg + 32 * c] = ca[c].re;
-      ci[wave][cg + 32 * c] = ca[c].im;
+        for (int c = 0; c < 4; ++c) {
+          cr[wave][cg + 32 * c] = ca[c].re;
+          ci[wave][cg + 32 * c] = ca[c].im;
+        }
+      __syncthreads();
+      if (threadIdx.x < SYM_TB) {
+        int c = threadIdx.x;
+        out[SYM_TB + c] = cx<R>{cr[0][c] + cr[1][c] + cr[2][c] + cr[3][c], ci[0][c] + ci[1][c] + ci[2][c] + ci[3][c]};
+      }
     }
-  __syncthreads();
-  if (threadIdx.x < SYM_TB) {
-    int c = threadIdx.x;
-    out[SYM_TB + c] = cx<R>{cr[0][c] + cr[1][c] + cr[2][c] + cr[3][c], ci[0][c] + ci[1][c] + ci[2][c] + ci[3][c]};
+    __syncthreads();   // xs, cr and ci are rewritten by the next tile
   }
 }
 
@@ -1730,7 +1735,7 @@ int64_t tt_work_elems(const int n[3], int mf) {
 template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
                                              int m, cx<R>* part) {
   const int64_t nt = (int64_t)T * (T + 1) / 2;
-  hipLaunchKernelGGL(k_symv_tiles<R>, dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, m, part);
+  hipLaunchKernelGGL(k_symv_tiles<R>, dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, m, nt, part);
 }
 template <typename R> void launch_symv_reduce(hipStream_t st, const cx<R>* part, int T, int m, cx<R>* y) {
   hipLaunchKernelGGL(k_symv_reduce<R>, dim3((m + 63) / 64), dim3(256), 0, st, part, T, m, y, 0);

@@ -593,13 +593,15 @@ struct StageTimer {
 // second stream (default priority, forked from and joined back into the caller's stream by
 // events) concurrently with the volume convolution and pFFT chain; everything that accumulates
 // into y_f, y_n or y_b after both runs on the caller's stream.
+static void make_streams(Handle& H) {
+  VSIE_HIP(hipStreamCreateWithFlags(&H.side, hipStreamNonBlocking));
+  VSIE_HIP(hipEventCreateWithFlags(&H.fork, hipEventDisableTiming));
+  VSIE_HIP(hipEventCreateWithFlags(&H.join, hipEventDisableTiming));
+}
+
 template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t st) {
+  if (!H.side) make_streams(H);
   StageTimer T(H, st);
-  if (!H.side) {
-    VSIE_HIP(hipStreamCreateWithFlags(&H.side, hipStreamNonBlocking));
-    VSIE_HIP(hipEventCreateWithFlags(&H.fork, hipEventDisableTiming));
-    VSIE_HIP(hipEventCreateWithFlags(&H.join, hipEventDisableTiming));
-  }
   const int mf = H.mf, mn = H.mn;
   const cx<R>* xf = x;
   const cx<R>* xn = x + mf;
@@ -638,32 +640,32 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
     VSIE_HIP(hipEventRecord(H.join, H.side));
   }
   // volume convolution and pFFT (Sec. II-B, eq. (13))
-  T.begin(0);
+  T.begin(0, st);
   launch_build_grid<R>(st, xb, mn ? xn : nullptr, H.d_mask, mn ? H.d_vox2row : nullptr, H.d_rowptr, H.d_rowrwg, D.roww,
                        D.gridA, g);
-  T.end(0);
-  T.begin(1);
+  T.end(0, st);
+  T.begin(1, st);
   fft_rows<R>(st, P1, true, D.gridA, D.bufB, ne1, P1, ne1, P1, 3LL * ne3 * ne2, D.tw[0]);
-  T.end(1);
-  T.begin(2);
+  T.end(1, st);
+  T.begin(2, st);
   fft_strided<R>(st, P2, true, D.bufB, D.bufC, ne2, P2, P1, P1, P1, 3LL * ne3, (int64_t)ne2 * P1, (int64_t)P2 * P1, D.tw[1]);
-  T.end(2);
-  T.begin(3);
+  T.end(2, st);
+  T.begin(3, st);
   fft_z_conv<R>(st, P3, D.bufC, ne3, P1, P2, D.spec, D.tw[2], H.d_zorder[sizeof(R) == 8 ? 0 : 1]);
-  T.end(3);
-  T.begin(4);
+  T.end(3, st);
+  T.begin(4, st);
   fft_strided<R>(st, P2, false, D.bufC, D.bufB, P2, ne2, P1, P1, P1, 3LL * ne3, (int64_t)P2 * P1, (int64_t)ne2 * P1, D.tw[1]);
-  T.end(4);
-  T.begin(5);
+  T.end(4, st);
+  T.begin(5, st);
   fft_rows<R>(st, P1, false, D.bufB, D.gridA, P1, ne1, P1, ne1, 3LL * ne3 * ne2, D.tw[0]);
-  T.end(5);
-  T.begin(6);
+  T.end(5, st);
+  T.begin(6, st);
   launch_body_out<R>(st, xb, D.gridA, D.dv_chi, H.d_mask, yb, g);
-  T.end(6);
+  T.end(6, st);
   if (mn) {
-    T.begin(7);
+    T.begin(7, st);
     launch_pfft_gather<R>(st, D.W, H.d_base, D.gridA, yn, mn, g);
-    T.end(7);
+    T.end(7, st);
   }
   if (mf) VSIE_HIP(hipStreamWaitEvent(st, H.join, 0));
   // precorrection
