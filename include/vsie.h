@@ -194,16 +194,26 @@ int vsie_export(const struct vsie_handle* h, int what, int index, void* host, si
  * vsie_export. Errors: E_ARG (size mismatch). */
 int vsie_import(struct vsie_handle* h, int what, int index, const void* host, size_t nbytes);
 
-/* Per-stage timing of vsie_matvec with HIP events recorded on the stream each stage runs on
- * (the caller's stream, or the handle's second stream for gemv_far, gemv_far_reduce and tt_pre,
- * which run concurrently with the volume stages). enable != 0 creates the events and resets the
- * totals; the events of up to 256 products are kept and read back by vsie_profile_read (which
- * waits for them) or when that ring is full, so products are not synchronised while profiled.
- * Stages: build_grid, fft_x_fwd, fft_y_fwd, fft_z_conv, fft_y_inv, fft_x_inv, body_out,
- * pfft_gather, gemv_far, precorrect, aca, tt_pre, gemv_far_reduce, tt_post. vsie_profile_read
- * returns up to max_stages entries (names are static strings), the summed milliseconds and the
- * number of timed calls per stage, and the stage count. */
+/* Concurrency of one product: enable != 0 runs the far-block chain (gemv_far, gemv_far_reduce,
+ * tt_pre: the dense far block and the TT stages that read only x) on a second non-blocking stream
+ * of default priority, forked from and joined back into the caller's stream with events, while the
+ * volume/pFFT chain runs on the caller's stream; 0 (the default) runs every stage in order on the
+ * caller's stream. Results are identical either way. Waits for the second stream before it
+ * returns. Errors: E_ARG, E_HIP. */
+int vsie_set_concurrency(struct vsie_handle* h, int enable);
+
+/* Per-stage timing of vsie_matvec with HIP events recorded on the stream each stage runs on.
+ * vsie_profile_mask(h, stages) times the stages whose bit (1 << stage index) is set and resets the
+ * totals (0 turns profiling off); vsie_profile(h, enable) is the same with all stages or none.
+ * Event creation happens on first use. The events of up to 256 products are kept and read back by
+ * vsie_profile_read (which waits for them) or when that ring is full, so products are not
+ * synchronised while profiled. Stage indices: 0 build_grid, 1 fft_x_fwd, 2 fft_y_fwd,
+ * 3 fft_z_conv, 4 fft_y_inv, 5 fft_x_inv, 6 body_out, 7 pfft_gather, 8 gemv_far, 9 precorrect,
+ * 10 aca, 11 tt_pre, 12 gemv_far_reduce, 13 tt_post. vsie_profile_read returns up to max_stages
+ * entries (names are static strings), the summed milliseconds and the number of timed calls per
+ * stage, and the stage count. */
 int vsie_profile(struct vsie_handle* h, int enable);
+int vsie_profile_mask(struct vsie_handle* h, uint32_t stages);
 int vsie_profile_read(const struct vsie_handle* h, int max_stages, const char** names, double* total_ms,
                       int64_t* calls, int* n_stages);
 

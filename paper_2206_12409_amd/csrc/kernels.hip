@@ -488,7 +488,10 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
                                                  const cx<R>* __restrict__ tw) {
   constexpr int L = A * B;
   __shared__ cx<R> S[NP * B * (A + 1)];
+  __shared__ cx<R> twl[L];   // twiddles staged once per block
   const int t = threadIdx.x;
+  for (int k = t; k < L; k += NP * A) twl[k] = tw[k];
+  __syncthreads();
   int p, u;
   const cx<R>* ib;
   cx<R>* ob;
@@ -519,10 +522,10 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
       const int n = j + B * m;
       v[bitrev_of(m, A)] = (valid && n < n_in) ? ib[(int64_t)n * in_stride] : cx<R>{0, 0};
     }
-    reg_dft<R, A, L, FWD>(v, tw);
+    reg_dft<R, A, L, FWD>(v, twl);
 #pragma unroll
     for (int k1 = 0; k1 < A; ++k1) {
-      cx<R> w = tw[(j * k1) & (L - 1)];
+      cx<R> w = twl[(j * k1) & (L - 1)];
       if (!FWD) w.im = -w.im;
       Sp[j * (A + 1) + k1] = (k1 == 0) ? v[k1] : v[k1] * w;
     }
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
     cx<R> v[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) v[bitrev_of(j, B)] = Sp[j * (A + 1) + k1];
-    reg_dft<R, B, L, FWD>(v, tw);
+    reg_dft<R, B, L, FWD>(v, twl);
 #pragma unroll
     for (int k2 = 0; k2 < B; ++k2) {
       const int k = k1 + A * k2;
@@ -632,42 +635,54 @@ __device__ inline void zload(const cx<R>* Sp, cx<R>* v, int j) {
     for (int q = 0; q < RAD; ++q) v[i * RAD + q] = Sp[j + T * i + (L / RAD) * q];
 }
 
-template <typename R, int L, int V, bool FWD, int RAD>
+// exchange barrier: the whole block, or only the wavefront when each pencil lives in one
+// wavefront (LDS accesses of one wavefront complete in order; the fence keeps the compiler from
+// moving them across)
+template <bool WAVE> __device__ inline void zsync() {
+  if (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
+template <typename R, int L, int V, bool FWD, int RAD, bool WAVE>
 __device__ inline void zstep(cx<R>* Sp, cx<R>* v, int j, int Ls, bool load, bool store,
                              const cx<R>* __restrict__ tw) {
   if (load) {
-    __syncthreads();
+    zsync<WAVE>();
     zload<R, L, V, RAD>(Sp, v, j);
   }
   zstage<R, L, V, RAD, FWD>(v, j, Ls, tw);
   if (store) {
-    if (load) __syncthreads();
+    if (load) zsync<WAVE>();
     zstore<R, L, V, RAD>(Sp, v, j, Ls);
   }
 }
-template <typename R, int L, int V, bool FWD>
+template <typename R, int L, int V, bool FWD, bool WAVE>
 __device__ inline void zstep_any(int rad, cx<R>* Sp, cx<R>* v, int j, int Ls, bool load, bool store,
                                  const cx<R>* __restrict__ tw) {
-  if (rad == V) zstep<R, L, V, FWD, V>(Sp, v, j, Ls, load, store, tw);
-  else if (rad == V / 2 && V >= 4) zstep<R, L, V, FWD, (V >= 4 ? V / 2 : 2)>(Sp, v, j, Ls, load, store, tw);
-  else if (rad == V / 4 && V >= 8) zstep<R, L, V, FWD, (V >= 8 ? V / 4 : 2)>(Sp, v, j, Ls, load, store, tw);
+  if (rad == V) zstep<R, L, V, FWD, V, WAVE>(Sp, v, j, Ls, load, store, tw);
+  else if (rad == V / 2 && V >= 4) zstep<R, L, V, FWD, (V >= 4 ? V / 2 : 2), WAVE>(Sp, v, j, Ls, load, store, tw);
+  else if (rad == V / 4 && V >= 8) zstep<R, L, V, FWD, (V >= 8 ? V / 4 : 2), WAVE>(Sp, v, j, Ls, load, store, tw);
 }
 
 // all stages of one transform; the first forward (last inverse) stage works on registers only
-template <typename R, int L, int V, bool FWD>
+template <typename R, int L, int V, bool FWD, bool WAVE = false>
 __device__ inline void zfft(cx<R>* Sp, cx<R>* v, int j, const cx<R>* __restrict__ tw) {
   using Z = ZRad<L, V>;
   int Ls = 1;
   if (FWD) {
 #pragma unroll
     for (int s = 0; s < Z::nst; ++s) {
-      zstep_any<R, L, V, true>(Z::rad(s), Sp, v, j, Ls, s > 0, s + 1 < Z::nst, tw);
+      zstep_any<R, L, V, true, WAVE>(Z::rad(s), Sp, v, j, Ls, s > 0, s + 1 < Z::nst, tw);
       Ls *= Z::rad(s);
     }
   } else {
 #pragma unroll
     for (int s = Z::nst - 1; s >= 0; --s) {
-      zstep_any<R, L, V, false>(Z::rad(s), Sp, v, j, Ls, s < Z::nst - 1, s > 0, tw);
+      zstep_any<R, L, V, false, WAVE>(Z::rad(s), Sp, v, j, Ls, s < Z::nst - 1, s > 0, tw);
       Ls *= Z::rad(s);
     }
   }
@@ -686,7 +701,9 @@ __global__ __launch_bounds__(NP * L / V) ZCONV_ATTR void k_zconv3(cx<R>* __restr
   constexpr int RAD_LAST = ZRad<L, V>::rad(ZRad<L, V>::nst - 1);
   constexpr int NB_LAST = V / RAD_LAST;
   __shared__ cx<R> S[NP * (L + 1)];
+  __shared__ cx<R> twl[L];   // twiddles w_L^k staged once per block (LDS latency in every stage)
   const int t = threadIdx.x;
+  for (int k = t; k < L; k += NP * L / V) twl[k] = tw[k];
   const int p = t % NP, j = t / NP;
   // the block order puts the (up to four) blocks that read the same folded spectra next to
   // each other: k2 with P2 - k2 and each k1 tile with its mirror tile
@@ -705,8 +722,8 @@ __global__ __launch_bounds__(NP * L / V) ZCONV_ATTR void k_zconv3(cx<R>* __restr
       const int n = j + T * q;
       H[c][q] = (2 * q < V && valid && n < n3) ? col[c * comp + (int64_t)n * plane] : cx<R>{0, 0};
     }
-    if (c > 0) __syncthreads();   // the previous component's last exchange has been read
-    zfft<R, L, V, true>(Sp, H[c], j, tw);
+    __syncthreads();   // twiddle table ready; the previous component's last exchange has been read
+    zfft<R, L, V, true>(Sp, H[c], j, twl);
   }
   // spectral 3 x 3 multiply: H[c][i RAD_LAST + q] is X[k3], k3 = j + T i + (L / RAD_LAST) q
   {
@@ -742,7 +759,7 @@ __global__ __launch_bounds__(NP * L / V) ZCONV_ATTR void k_zconv3(cx<R>* __restr
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     __syncthreads();   // LDS free for this component's exchanges
-    zfft<R, L, V, false>(Sp, H[c], j, tw);
+    zfft<R, L, V, false>(Sp, H[c], j, twl);
     // last inverse stage output: thread holds x[j + T q]
 #pragma unroll
     for (int q = 0; q < V / 2; ++q) {
@@ -752,8 +769,103 @@ __global__ __launch_bounds__(NP * L / V) ZCONV_ATTR void k_zconv3(cx<R>* __restr
   }
 }
 
+// Fused z pass, one wavefront (or part of one) per pencil: T = L / V <= 64 threads own a pencil,
+// so the FFT exchanges only synchronise the wavefront. The block's NP pencils (adjacent k1) are
+// loaded and stored through an LDS staging area [NP][3][L + 1] with neighbouring threads on
+// neighbouring pencils (coalesced), the only two block-wide barriers.
+template <typename R, int L, int V, int NP>
+__global__ __launch_bounds__(NP * L / V) void k_zconv4(cx<R>* __restrict__ buf, int n3, int P1, int P2,
+                                                       const cx<R>* __restrict__ spec, const cx<R>* __restrict__ tw,
+                                                       const int* __restrict__ order) {
+  constexpr int T = L / V;
+  constexpr int NT = NP * T;
+  constexpr int LP = L + 1;
+  constexpr int RAD_LAST = ZRad<L, V>::rad(ZRad<L, V>::nst - 1);
+  constexpr int NB_LAST = V / RAD_LAST;
+  static_assert(T <= 64, "a pencil must fit one wavefront");
+  __shared__ cx<R> S[NP * 3 * LP];
+  __shared__ cx<R> twl[L];   // twiddles w_L^k staged once per block
+  const int t = threadIdx.x;
+  for (int k = t; k < L; k += NT) twl[k] = tw[k];
+  const int k2 = order[2 * blockIdx.x];
+  const int k10 = order[2 * blockIdx.x + 1] * NP;
+  const int64_t plane = (int64_t)P1 * P2, comp = plane * n3;
+  cx<R>* base = buf + (int64_t)k2 * P1 + k10;
+  // staging load: element (c, n, p), pencils fastest
+  for (int e = t; e < 3 * n3 * NP; e += NT) {
+    const int p = e % NP, n = (e / NP) % n3, c = e / (NP * n3);
+    S[(p * 3 + c) * LP + n] = (k10 + p < P1) ? base[c * comp + (int64_t)n * plane + p] : cx<R>{0, 0};
+  }
+  __syncthreads();
+  const int p = t / T, j = t % T;
+  const int k1 = k10 + p;
+  const bool valid = k1 < P1;
+  cx<R>* Sp = S + p * 3 * LP;
+  cx<R> H[3][V];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int n = j + T * q;
+      H[c][q] = (2 * q < V && n < n3) ? Sp[c * LP + n] : cx<R>{0, 0};
+    }
+  zsync<true>();   // the staged inputs of this pencil are in registers; its LDS rows are free
+#pragma unroll
+  for (int c = 0; c < 3; ++c) zfft<R, L, V, true, true>(Sp + c * LP, H[c], j, twl);
+  {
+    const int S1 = P1 / 2 + 1, S3 = L / 2 + 1;
+    const int f1 = k1 <= P1 / 2 ? k1 : P1 - k1;
+    const int f2 = k2 <= P2 / 2 ? k2 : P2 - k2;
+    const R s1 = k1 <= P1 / 2 ? (R)1 : (R)-1;
+    const R s2 = k2 <= P2 / 2 ? (R)1 : (R)-1;
+    const cx<R>* sp = spec + (valid ? 6 * ((int64_t)f2 * S1 + f1) * S3 : 0);
+#pragma unroll
+    for (int i = 0; i < NB_LAST; ++i)
+#pragma unroll
+      for (int q = 0; q < RAD_LAST; ++q) {
+        const int k3 = j + T * i + (L / RAD_LAST) * q;
+        const int f3 = k3 <= L / 2 ? k3 : L - k3;
+        const R s3 = k3 <= L / 2 ? (R)1 : (R)-1;
+        const cx<R>* rec = sp + 6 * f3;
+        const cx<R> Txx = rec[0], Tyy = rec[1], Tzz = rec[2];
+        const cx<R> Txy = (s1 * s2) * rec[3];
+        const cx<R> Txz = (s1 * s3) * rec[4];
+        const cx<R> Tyz = (s2 * s3) * rec[5];
+        const int e = i * RAD_LAST + q;
+        const cx<R> x = H[0][e], y = H[1][e], z = H[2][e];
+        H[0][e] = Txx * x + Txy * y + Txz * z;
+        H[1][e] = Txy * x + Tyy * y + Tyz * z;
+        H[2][e] = Txz * x + Tyz * y + Tzz * z;
+#ifndef ZCONV_NO_SB
+        if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
+#endif
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    zsync<true>();
+    zfft<R, L, V, false, true>(Sp + c * LP, H[c], j, twl);
+  }
+  zsync<true>();   // every exchange of this pencil is read before the outputs overwrite the rows
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int q = 0; q < V / 2; ++q) {
+      const int n = j + T * q;
+      if (n < n3) Sp[c * LP + n] = H[c][q];
+    }
+  __syncthreads();
+  for (int e = t; e < 3 * n3 * NP; e += NT) {
+    const int pp = e % NP, n = (e / NP) % n3, c = e / (NP * n3);
+    if (k10 + pp < P1) base[c * comp + (int64_t)n * plane + pp] = S[(pp * 3 + c) * LP + n];
+  }
+}
+
 #ifndef ZCONV_V64
 #define ZCONV_V64 4
+#endif
+#ifndef ZCONV_FORCE3
+#define ZCONV_FORCE3 0
 #endif
 template <int L> struct Split;
 template <> struct Split<8> { static constexpr int A = 4, B = 2; };
@@ -889,8 +1001,14 @@ void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const
         constexpr int V = sizeof(R) == 8 ? ZCONV_V64 : 8;
         constexpr int NP = 256 * V / LL;
         dim3 grid((unsigned)(P2 * ((P1 + NP - 1) / NP)));
-        hipLaunchKernelGGL((k_zconv3<R, LL, V, NP>), grid, dim3(NP * LL / V), 0, st, buf, n3, P1, P2, spec, tw,
-                           order);
+        // FP64: one pencil per wavefront (measured faster at 2 mm); complex64: pencils across the
+        // block's wavefronts
+        if constexpr (LL / V <= 64 && sizeof(R) == 8 && !ZCONV_FORCE3)
+          hipLaunchKernelGGL((k_zconv4<R, LL, V, NP>), grid, dim3(NP * LL / V), 0, st, buf, n3, P1, P2, spec, tw,
+                             order);
+        else
+          hipLaunchKernelGGL((k_zconv3<R, LL, V, NP>), grid, dim3(NP * LL / V), 0, st, buf, n3, P1, P2, spec, tw,
+                             order);
       }
     });
     return;

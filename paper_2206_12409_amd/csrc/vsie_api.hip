@@ -575,12 +575,12 @@ struct StageTimer {
     H.ev_mask[slot] = 0;
   }
   void begin(int s, hipStream_t on = nullptr) {
-    if (slot < 0) return;
+    if (slot < 0 || !(H.prof_stages & (1u << s))) return;
     VSIE_HIP(hipEventRecord(H.ev[slot][2 * s], on ? on : st));
     H.ev_mask[slot] |= 1u << s;
   }
   void end(int s, hipStream_t on = nullptr) {
-    if (slot >= 0) VSIE_HIP(hipEventRecord(H.ev[slot][2 * s + 1], on ? on : st));
+    if (slot >= 0 && (H.prof_stages & (1u << s))) VSIE_HIP(hipEventRecord(H.ev[slot][2 * s + 1], on ? on : st));
   }
   void collect() {
     if (slot < 0) return;
@@ -600,7 +600,11 @@ static void make_streams(Handle& H) {
 }
 
 template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t st) {
-  if (!H.side) make_streams(H);
+  if (H.concurrent && !H.side) make_streams(H);
+  // far-block chain: the second stream when concurrent, else the caller's stream after the
+  // volume chain
+  const bool conc = H.concurrent && H.mf;
+  hipStream_t fs = conc ? H.side : st;
   StageTimer T(H, st);
   const int mf = H.mf, mn = H.mn;
   const cx<R>* xf = x;
@@ -622,21 +626,24 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
       td.r2[c] = H.tt_r[c][1];
       td.r3[c] = H.tt_r[c][2];
     }
-  // side stream: dense far block (writes y_f), then the parts of the TT coupling that read only x
-  if (mf) {
+  // dense far block (writes y_f), then the parts of the TT coupling that read only x
+  auto far_chain = [&]() {
+    T.begin(8, fs);
+    launch_symv_tiles<R>(fs, D.Zff, H.d_tiles, H.sym_T, xf, mf, D.sym_part);
+    T.end(8, fs);
+    T.begin(12, fs);
+    launch_symv_reduce<R>(fs, D.sym_part, H.sym_T, mf, yf);
+    T.end(12, fs);
+    if (have_tt) {
+      T.begin(11, fs);
+      launch_tt_pre<R>(fs, td, H.n, mf, xf, xb, H.d_mask, D.tt_work);
+      T.end(11, fs);
+    }
+  };
+  if (conc) {
     VSIE_HIP(hipEventRecord(H.fork, st));
     VSIE_HIP(hipStreamWaitEvent(H.side, H.fork, 0));
-    T.begin(8, H.side);
-    launch_symv_tiles<R>(H.side, D.Zff, H.d_tiles, H.sym_T, xf, mf, D.sym_part);
-    T.end(8, H.side);
-    T.begin(12, H.side);
-    launch_symv_reduce<R>(H.side, D.sym_part, H.sym_T, mf, yf);
-    T.end(12, H.side);
-    if (have_tt) {
-      T.begin(11, H.side);
-      launch_tt_pre<R>(H.side, td, H.n, mf, xf, xb, H.d_mask, D.tt_work);
-      T.end(11, H.side);
-    }
+    far_chain();
     VSIE_HIP(hipEventRecord(H.join, H.side));
   }
   // volume convolution and pFFT (Sec. II-B, eq. (13))
@@ -667,7 +674,10 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
     launch_pfft_gather<R>(st, D.W, H.d_base, D.gridA, yn, mn, g);
     T.end(7, st);
   }
-  if (mf) VSIE_HIP(hipStreamWaitEvent(st, H.join, 0));
+  if (conc)
+    VSIE_HIP(hipStreamWaitEvent(st, H.join, 0));
+  else if (mf)
+    far_chain();
   // precorrection
   T.begin(9);
   launch_csr_add<R>(st, H.d_pc_rowid, H.d_pc_rowptr, H.d_pc_col, D.pc_val, x, y, H.n_pcrows);
@@ -1333,9 +1343,22 @@ int vsie_import(vsie_handle* hd, int what, int index, const void* host, size_t n
   });
 }
 
-int vsie_profile(vsie_handle* hd, int enable) {
+int vsie_set_concurrency(vsie_handle* hd, int enable) {
+  if (!hd) return fail(VSIE_E_ARG, "null handle");
+  return guarded([&]() {
+    Handle& H = hd->H;
+    if (H.side) VSIE_HIP(hipStreamSynchronize(H.side));
+    H.concurrent = enable != 0;
+  });
+}
+
+int vsie_profile(vsie_handle* hd, int enable) { return vsie_profile_mask(hd, enable ? 0xFFFFFFFFu : 0u); }
+
+int vsie_profile_mask(vsie_handle* hd, uint32_t stages) {
   if (!hd) return fail(VSIE_E_ARG, "null handle");
   Handle& H = hd->H;
+  const int enable = stages != 0;
+  H.prof_stages = stages;
   return guarded([&]() {
     if (enable && !H.ev[0][0])
       for (auto& slot : H.ev)

@@ -147,6 +147,8 @@ struct Handle {
   hipStream_t side = nullptr;    // second stream of the product (dense far block)
   hipEvent_t fork = nullptr, join = nullptr;
   bool prof = false;
+  uint32_t prof_stages = 0;      // stages timed while profiling
+  bool concurrent = false;       // far-block chain on the second stream
   // stage events of the last PROF_RING products, read back only by vsie_profile_read (or when the
   // ring wraps), so profiling adds no synchronisation to the products themselves
   static constexpr int PROF_RING = 256;

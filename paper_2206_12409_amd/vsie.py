@@ -19,8 +19,12 @@ VSIE_GMRES64, VSIE_IR_MIXED = 0, 1
 X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
 
 EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_sizes", "vsie_rhs",
-            "vsie_matvec", "vsie_solve", "vsie_port_current", "vsie_export", "vsie_import", "vsie_profile",
-            "vsie_profile_read", "vsie_destroy", "vsie_last_error"]
+            "vsie_matvec", "vsie_solve", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
+            "vsie_profile", "vsie_profile_mask", "vsie_profile_read", "vsie_destroy", "vsie_last_error"]
+
+
+STAGES = ["build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "body_out", "pfft_gather",
+          "gemv_far", "precorrect", "aca", "tt_pre", "gemv_far_reduce", "tt_post"]
 
 
 class Mesh(C.Structure):
@@ -81,6 +85,8 @@ def load(path=LIB_PATH):
     lib.vsie_export.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(C.c_size_t)]
     lib.vsie_import.argtypes = [vp, C.c_int, C.c_int, vp, C.c_size_t]
     lib.vsie_profile.argtypes = [vp, C.c_int]
+    lib.vsie_profile_mask.argtypes = [vp, C.c_uint32]
+    lib.vsie_set_concurrency.argtypes = [vp, C.c_int]
     lib.vsie_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64), C.POINTER(C.c_int)]
     lib.vsie_destroy.argtypes = [vp]
@@ -229,9 +235,20 @@ class Operator:
                       converged=rc == VSIE_OK) for s in st]
         return x, stats
 
-    def profile(self, enable=True):
-        """Enable (and reset) or disable per-stage event timing of matvec."""
-        _check(load().vsie_profile(self._h, 1 if enable else 0))
+    def profile(self, enable=True, stages=None):
+        """Enable (and reset) or disable per-stage event timing of matvec; `stages` (names) limits
+        the timing to those stages."""
+        if stages is None:
+            _check(load().vsie_profile(self._h, 1 if enable else 0))
+        else:
+            mask = 0
+            for st in stages:
+                mask |= 1 << STAGES.index(st)
+            _check(load().vsie_profile_mask(self._h, C.c_uint32(mask if enable else 0)))
+
+    def set_concurrency(self, enable=True):
+        """Run the far-block chain of each product on a second stream (see vsie_set_concurrency)."""
+        _check(load().vsie_set_concurrency(self._h, 1 if enable else 0))
 
     def profile_read(self):
         """{stage: (total_ms, calls)} for stages that ran."""

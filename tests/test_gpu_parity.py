@@ -85,6 +85,26 @@ def test_full_matvec_fp64_and_reciprocity(small):
     del rng
 
 
+def test_concurrent_far_block_is_identical(small):
+    """The far-block chain on a second stream gives the bitwise same product; stage profiling
+    restricted to one stage times only that stage."""
+    p, op, d, _, S_same, _ = small
+    x = to_dev(synth.complex_normal(op.N, 77))
+    y0 = op.matvec(x)
+    op.set_concurrency(True)
+    try:
+        op.profile(True, stages=["gemv_far"])
+        ys = [op.matvec(x) for _ in range(3)]
+        prof = op.profile_read()
+        op.profile(False)
+    finally:
+        op.set_concurrency(False)
+    for y in ys:
+        assert torch.equal(y, y0)
+    assert set(prof) == {"gemv_far"} and prof["gemv_far"][1] == 3 and prof["gemv_far"][0] > 0
+    assert rel(y0.cpu().numpy(), S_same.matvec(x.cpu().numpy())) < 1e-10
+
+
 def test_batched_columns_match(small):
     p, op, d, _, S_same, _ = small
     X = np.stack([synth.complex_normal(op.N, s) for s in (1, 2, 3)])
