@@ -12,6 +12,13 @@
 
 namespace vsie {
 
+// Loads of data read once per product (the far-block tiles): the non-temporal hint keeps them
+// from displacing reused data (x, partial sums) in the caches.
+template <typename R> __device__ inline cx<R> ld_stream(const cx<R>* p) {
+  return cx<R>{__builtin_nontemporal_load(&p->re), __builtin_nontemporal_load(&p->im)};
+}
+
+
 // =============================================================================================
 // Setup kernels
 // =============================================================================================
@@ -1255,7 +1262,7 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const cx<R>* __restrict__ Zp
       cx<R> rd = {0, 0};
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        cx<R> z = zr[32 * c];
+        const cx<R> z = ld_stream(zr + 32 * c);   // each tile is read once per product
         rd += z * xJ[c];
         ca[c] += z * xi;
       }
