@@ -65,8 +65,9 @@ KERNEL_OF_STAGE = {   # stages that are a single kernel launch, and that kernel'
 
 
 def kernel_source_sha(kernel):
-    """sha256 over the kernel's own source, its launcher(s) and the shared kernel header: the
-    traffic figure is void once any of them changes."""
+    """sha256 over the kernel's own source, its launcher(s) and the compile-time constants of the
+    shared kernel header (tile sizes and layouts): the traffic figure is void once any of them
+    changes."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2206_12409_amd", "csrc")
     text = open(os.path.join(csrc, "kernels.hip")).read()
@@ -81,7 +82,7 @@ def kernel_source_sha(kernel):
                 end = text.find("\n}\n", at)
                 parts.append(text[start:end])
             at = text.find(key, at + len(key))
-    parts.append(open(os.path.join(csrc, "kernels.h")).read())
+    parts += [ln for ln in open(os.path.join(csrc, "kernels.h")) if ln.startswith("constexpr")]
     return hashlib.sha256("\n".join(parts).encode()).hexdigest()
 
 
