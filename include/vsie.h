@@ -53,7 +53,8 @@ enum vsie_status {
   VSIE_E_NOCONV = 7,       /* solver hit max_iter; statistics are still filled */
   VSIE_E_BREAKDOWN = 8,    /* Arnoldi breakdown without convergence */
   VSIE_E_UNSUPPORTED = 9,  /* option not supported (e.g. piecewise-linear basis) */
-  VSIE_E_STATE = 10        /* operation not valid for this handle (e.g. precision not built) */
+  VSIE_E_STATE = 10,       /* operation not valid for this handle (e.g. precision not built) */
+  VSIE_E_SINGULAR = 11     /* dense factorisation met an exactly zero pivot column */
 };
 
 enum vsie_domain { VSIE_NEAR = 0, VSIE_FAR = 1 };
@@ -114,11 +115,12 @@ typedef struct {
   double tol;                 /* relative residual ||b - Ax|| / ||b||, default 1e-6 */
   int32_t restart;            /* GMRES restart length, default 50 (Sec. IV-C) */
   int32_t max_iter;           /* GMRES64: iterations; IR_MIXED: total inner complex64 iterations */
-  int32_t method;             /* VSIE_GMRES64 or VSIE_IR_MIXED */
+  int32_t method;             /* VSIE_GMRES64, VSIE_IR_MIXED or VSIE_SCHUR */
   double inner_tol;           /* IR_MIXED: inner complex64 solve tolerance, default 1e-3 */
+  int32_t precond;            /* SCHUR: 1 (default) right-preconditions the reduced system, 0 none */
 } vsie_solve_opts;
 
-enum vsie_method { VSIE_GMRES64 = 0, VSIE_IR_MIXED = 1 };
+enum vsie_method { VSIE_GMRES64 = 0, VSIE_IR_MIXED = 1, VSIE_SCHUR = 2 };
 
 typedef struct {
   int32_t iterations;         /* Krylov iterations (IR_MIXED: inner complex64 iterations) */
@@ -162,6 +164,10 @@ int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, v
  * IR_MIXED: FP64 flexible GMRES (20 steps per cycle) on the FP64 operator whose preconditioner is
  * one cycle (at most `restart` iterations, stopping early at inner_tol) of complex64 GMRES on
  * Z z = v; with an exact inner solve each outer step is one refinement x += Z^{-1}(b - Zx).
+ * SCHUR: the far-conductor currents are eliminated first (see vsie_schur_setup) and FP64 GMRES
+ * runs on the reduced system (near currents and body) with zero initial guess, right-preconditioned
+ * by the block-diagonal operator of vsie_schur_precond; the far currents are recovered afterwards.
+ * The residual test is on the full system's relative residual.
  * x_dev receives complex128. Blocks.
  * Allocates its work vectors (IR_MIXED: 41 FP64 vectors of length N besides the Krylov basis).
  * stats (array of nrhs, may be NULL) are filled even on E_NOCONV. */
@@ -216,6 +222,38 @@ int vsie_profile(struct vsie_handle* h, int enable);
 int vsie_profile_mask(struct vsie_handle* h, uint32_t stages);
 int vsie_profile_read(const struct vsie_handle* h, int max_stages, const char** names, double* total_ms,
                       int64_t* calls, int* n_stages);
+
+/* Elimination of the far-conductor currents (the Schur complement of the dense far block; the
+ * paper's conclusion proposes solving for the other unknowns first). The far conductor couples to
+ * the rest only through the ACA factors (eq. (12)) and the TT cores (eq. (14)), so with
+ * L = [conj(V) | G4^T of each component] (m_f x K, K = ACA rank + the three TT ranks r3) the
+ * reduced operator on the near currents and the body is
+ *     A_S = Z_rr - Z_rf Z_ff^-1 Z_fr = Z_rr - R^T (L^T Z_ff^-1 L) R,
+ * R the maps of eqs. (12) and (18)-(19) from x_r to the K proxies. vsie_schur_setup unpacks the
+ * dense far block (m_f^2 complex128 held on the device), factors it (vsie_dense_lu_solve's
+ * method), forms W = Z_ff^-1 L and the K x K matrix L^T W. With precond != 0 it also builds the
+ * right preconditioner of vsie_schur_precond: the inverse of the reduced near block
+ * (direct Galerkin entries of the near coils minus U (L^T W)_aa U^T; m_n^2 complex128 while
+ * building) and the inverse body diagonal (h^3 / chi + h^3 T_aa(0)). Blocks; later calls only
+ * add what is missing. Errors: E_NOMEM, E_SINGULAR, E_HIP, E_ARG (K > 640). */
+int vsie_schur_setup(struct vsie_handle* h, int precond);
+/* K (0 before setup or without far conductors), setup seconds so far, and whether the
+ * elimination (bit 0) and the preconditioner (bit 1) are built. */
+int vsie_schur_info(const struct vsie_handle* h, int32_t* n_proxy, double* seconds, int32_t* built);
+/* y = A_S x on device vectors of length N (complex128, layout as vsie_matvec): the far part of x
+ * is not read and the far part of y is set to zero. Asynchronous. Errors: E_STATE (no setup). */
+int vsie_schur_matvec(struct vsie_handle* h, const void* x_dev, void* y_dev, void* stream);
+/* y = M x, M = block diagonal: inverse reduced near block on the near currents, inverse body
+ * diagonal on the body (1 on air voxels), zero on the far currents. Asynchronous.
+ * Errors: E_STATE (preconditioner not built). */
+int vsie_schur_precond(struct vsie_handle* h, const void* x_dev, void* y_dev, void* stream);
+
+/* Dense complex128 solve A X = B on the device, row-major, A (n x n, row stride lda >= n)
+ * overwritten by its LU factors (P A = L U, partial pivoting by |re| + |im|), B (n x nrhs, row
+ * stride ldb >= nrhs) overwritten by X. Blocked right-looking factorisation with panels of 64
+ * columns whose trailing updates run on the matrix cores. Caller-owned buffers; allocates its
+ * scratch; blocks. Errors: E_ARG, E_SINGULAR (exactly zero pivot column), E_NOMEM, E_HIP. */
+int vsie_dense_lu_solve(int n, void* A_dev, int64_t lda, void* B_dev, int64_t ldb, int nrhs, void* stream);
 
 void vsie_destroy(struct vsie_handle* h);
 const char* vsie_last_error(void);

@@ -59,6 +59,33 @@ template <typename R> void launch_lr_n_add(hipStream_t st, bool conj, const cx<R
                                            int K, cx<R>* y);
 template <typename R> void launch_gemv_rows(hipStream_t st, const cx<R>* A, const cx<R>* x, int64_t nrow, int64_t ncol,
                                             cx<R>* out, int accumulate);
+// Batched strided complex GEMM, C(i,j) = sum_k A(i,k) B(k,j), with element (i,j) of batch b at
+// X[i sr + j sc + b sb]. Up to three independent problems share one launch (blockIdx.z runs over
+// their batches in turn). Optional mask on B (mask index = B's element index relative to the
+// batch) and masked accumulation into C. Split-K use: batch b covers K indices [b K, b K + K)
+// of a contraction of length ktot, the last batch taking the remainder.
+template <typename R> struct GemmArgs {
+  const cx<R>* A;
+  int64_t sar, sac, sab;
+  const cx<R>* B;
+  int64_t sbr, sbc, sbb;
+  cx<R>* C;
+  int64_t scr, scc, scb;
+  int M, N, K;
+  int64_t ktot;           // > 0: split-K over batches
+  const uint8_t* maskB;
+  const uint8_t* maskC;   // non-null: C += maskC * AB (mask index = C's element index)
+  int accumulate;
+  int negate;             // store -AB (with accumulate: C -= AB)
+};
+template <typename R> struct GemmSet {
+  GemmArgs<R> g[3];
+  int nbatch[3];
+  int nprob;
+};
+
+template <typename R> void launch_zgemm(hipStream_t st, const GemmSet<R>& S);
+
 constexpr int TT_RMAX = 128;
 constexpr int TT_KCHUNK = 64;   // split-K chunk of the transpose contraction over n1 n2
 template <typename R> struct TTDesc {
@@ -73,6 +100,15 @@ template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, con
                                          const cx<R>* xb, const uint8_t* mask, cx<R>* work);
 template <typename R> void launch_tt_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
                                           const uint8_t* mask, cx<R>* yf, cx<R>* yb, const cx<R>* work);
+// the halves used by the reduced (far-eliminated) operator: the transpose chain alone (s3 at the
+// start of the work buffer), the forward chain from given rank vectors u3[c][TT_RMAX] instead of
+// G4 x_f, and the forward accumulation into y_b alone
+template <typename R> void launch_tt_transpose_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
+                                                   const cx<R>* xb, const uint8_t* mask, cx<R>* work);
+template <typename R> void launch_tt_forward_from(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
+                                                  const cx<R>* u3, cx<R>* work);
+template <typename R> void launch_tt_forward_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
+                                                  const uint8_t* mask, cx<R>* yb, const cx<R>* work);
 int64_t tt_work_elems(const int n[3], int mf);
 // y = Z x for the symmetric far block stored as upper-triangle tiles (part: 2 SYM_TB per tile)
 template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
@@ -80,6 +116,19 @@ template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, co
 template <typename R> void launch_symv_reduce(hipStream_t st, const cx<R>* part, int T, int m, cx<R>* y);
 template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, const double* vre, const double* vim,
                                              int ne, cx<R>* b);
+
+// elimination of the far currents (FP64)
+void launch_set_identity(hipStream_t st, cxd* X, int n);
+void launch_unpack_sym(hipStream_t st, const cxd* Zp, int T, int m, cxd* out);
+void launch_pack_sym(hipStream_t st, const cxd* X, int m, const int* tiles, int64_t ntiles, cxd* Zp);
+void launch_build_far_factors(hipStream_t st, const cxd* V, int ka, const TTDesc<double>& T, int mf, int K, cxd* L);
+void launch_schur_apply(hipStream_t st, const cxd* S, int K, int ka, const int r3[3], const cxd* ta, const cxd* s3,
+                        double sign, cxd* pa, cxd* p3);
+void launch_schur_gather(hipStream_t st, int K, int ka, const int r3[3], const cxd* ta, const cxd* s3, double sign,
+                         cxd* out);
+void launch_schur_scatter(hipStream_t st, int K, int ka, const int r3[3], const cxd* in, double sign, cxd* pa,
+                          cxd* p3);
+void launch_mul_diag(hipStream_t st, const cxd* x, const cxd* d, cxd* y, int64_t n);
 
 // solver
 void launch_multidot(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* w, int64_t n, cxd* part, int nblk);

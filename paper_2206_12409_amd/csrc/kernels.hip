@@ -1327,30 +1327,6 @@ __global__ __launch_bounds__(256) void k_symv_reduce(const cx<R>* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------------------------
-// Batched strided complex GEMM, C(i,j) = sum_k A(i,k) B(k,j), with element (i,j) of batch b at
-// X[i sr + j sc + b sb]. Up to three independent problems share one launch (blockIdx.z runs over
-// their batches in turn). Optional mask on B (mask index = B's element index relative to the
-// batch) and masked accumulation into C. Split-K use: batch b covers K indices [b K, b K + K)
-// of a contraction of length ktot, the last batch taking the remainder.
-template <typename R> struct GemmArgs {
-  const cx<R>* A;
-  int64_t sar, sac, sab;
-  const cx<R>* B;
-  int64_t sbr, sbc, sbb;
-  cx<R>* C;
-  int64_t scr, scc, scb;
-  int M, N, K;
-  int64_t ktot;           // > 0: split-K over batches
-  const uint8_t* maskB;
-  const uint8_t* maskC;   // non-null: C += maskC * AB (mask index = C's element index)
-  int accumulate;
-};
-template <typename R> struct GemmSet {
-  GemmArgs<R> g[3];
-  int nbatch[3];
-  int nprob;
-};
-
 // 64 x 64 output tile per block of 256 threads on the matrix cores: each wavefront owns a 32 x 32
 // quadrant as 2 x 2 tiles of the 16 x 16 x 4 MFMA (FP64: v_mfma_f64_16x16x4f64, FP32:
 // v_mfma_f32_16x16x4f32); K is staged through LDS in chunks of 16, tile loaders walking each
@@ -1452,7 +1428,7 @@ __global__ __launch_bounds__(256) void k_zgemm_mfma(GemmSet<R> S) {
       for (int e = 0; e < 4; ++e) {
         const int i = i0 + wm + 16 * u + MM::row(lane, e), j = j0 + wn + 16 * v + li;
         if (i >= g.M || j >= g.N) continue;
-        const cx<R> val = {cr[u][v][e], ci[u][v][e]};
+        const cx<R> val = g.negate ? cx<R>{-cr[u][v][e], -ci[u][v][e]} : cx<R>{cr[u][v][e], ci[u][v][e]};
         const int64_t idx = i * g.scr + j * g.scc;
         if (mC) {
           if (mC[idx]) C[idx] += val;
@@ -1464,7 +1440,7 @@ __global__ __launch_bounds__(256) void k_zgemm_mfma(GemmSet<R> S) {
       }
 }
 
-template <typename R> static void zgemm(hipStream_t st, const GemmSet<R>& S) {
+template <typename R> void launch_zgemm(hipStream_t st, const GemmSet<R>& S) {
   int mx = 0, nx = 0, nz = 0;
   for (int p = 0; p < S.nprob; ++p) {
     mx = std::max(mx, S.g[p].M);
@@ -1474,6 +1450,8 @@ template <typename R> static void zgemm(hipStream_t st, const GemmSet<R>& S) {
   if (mx <= 0 || nx <= 0 || nz <= 0) return;
   hipLaunchKernelGGL(k_zgemm_mfma<R>, dim3((nx + 63) / 64, (mx + 63) / 64, nz), dim3(256), 0, st, S);
 }
+template void launch_zgemm<double>(hipStream_t, const GemmSet<double>&);
+template void launch_zgemm<float>(hipStream_t, const GemmSet<float>&);
 
 // s2[c][j2][i3] = sum_b part[c][b][j2][i3]  (split-K reduction of the transpose contraction);
 // a block covers 32 outputs with 8 slices over b
@@ -1808,6 +1786,17 @@ template <typename R> static TTWork tt_layout(const TTDesc<R>& T, const int n[3]
 template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
                                          const cx<R>* xb, const uint8_t* mask, cx<R>* work) {
   const TTWork w = tt_layout(T, n, mf);
+  cx<R>* part = work;
+  cx<R>* t3 = part + 3LL * TT_RMAX * w.nchunk;
+  hipLaunchKernelGGL(k_tt_f4<R>, dim3(w.nchunk, w.rmax3, 3), dim3(256), 0, st, T, xf, mf, 4096, part, w.nchunk);
+  hipLaunchKernelGGL(k_tt_f3<R>, dim3((w.rmax2 * w.n3 + 15) / 16, 3), dim3(256), 0, st, T, part, w.nchunk, w.n3, t3);
+  launch_tt_transpose_pre<R>(st, T, n, mf, xb, mask, work);
+}
+
+// The transpose half of launch_tt_pre: s3[c][j3] (at the start of the work buffer) from x_b.
+template <typename R> void launch_tt_transpose_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
+                                                   const cx<R>* xb, const uint8_t* mask, cx<R>* work) {
+  const TTWork w = tt_layout(T, n, mf);
   const int kc = TT_KCHUNK;
   cx<R>* part = work;
   cx<R>* t3 = part + 3LL * TT_RMAX * w.nchunk;
@@ -1815,8 +1804,6 @@ template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, con
   cx<R>* kpart = s2 + 3LL * TT_RMAX * w.n3;
   cx<R>* s3part = kpart + 3LL * w.nkc * TT_RMAX * w.n3;
   cx<R>* s3 = part;
-  hipLaunchKernelGGL(k_tt_f4<R>, dim3(w.nchunk, w.rmax3, 3), dim3(256), 0, st, T, xf, mf, 4096, part, w.nchunk);
-  hipLaunchKernelGGL(k_tt_f3<R>, dim3((w.rmax2 * w.n3 + 15) / 16, 3), dim3(256), 0, st, T, part, w.nchunk, w.n3, t3);
   // S2(j2, i3) = sum_p M[j2][p] mask x_b[c][p + n12 i3], split over p in chunks of kc
   GemmSet<R> B{};
   B.nprob = 3;
@@ -1826,10 +1813,18 @@ template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, con
                          T.r2[c], w.n3, kc, w.n12, mask, nullptr, 0};
     B.nbatch[c] = w.nkc;
   }
-  zgemm<R>(st, B);
+  launch_zgemm<R>(st, B);
   hipLaunchKernelGGL(k_tt_ksum<R>, dim3((w.rmax2 * w.n3 + 31) / 32, 3), dim3(256), 0, st, T, kpart, w.nkc, w.n3, s2);
   hipLaunchKernelGGL(k_ttT_3<R>, dim3(w.nk3, 3), dim3(256), 0, st, T, s2, w.n3, s3part);
   hipLaunchKernelGGL(k_sum_partials<R>, dim3(3 * TT_RMAX), dim3(256), 0, st, s3part, w.nk3, 3 * TT_RMAX, s3);
+}
+
+// Forward chain from given rank-r3 vectors u3[c][j3] (in place of G4 x_f): t3 = G3 u3.
+template <typename R> void launch_tt_forward_from(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
+                                                  const cx<R>* u3, cx<R>* work) {
+  const TTWork w = tt_layout(T, n, mf);
+  cx<R>* t3 = work + 3LL * TT_RMAX * w.nchunk;
+  hipLaunchKernelGGL(k_tt_f3<R>, dim3((w.rmax2 * w.n3 + 15) / 16, 3), dim3(256), 0, st, T, u3, 1, w.n3, t3);
 }
 
 // The accumulations: y_b[c] += mask * (merged core) t3 (forward) and y_f += sum_c G4^T s3
@@ -1837,8 +1832,16 @@ template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, con
 template <typename R> void launch_tt_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
                                           const uint8_t* mask, cx<R>* yf, cx<R>* yb, const cx<R>* work) {
   const TTWork w = tt_layout(T, n, mf);
-  const cx<R>* t3 = work + 3LL * TT_RMAX * w.nchunk;
   const cx<R>* s3 = work;
+  launch_tt_forward_post<R>(st, T, n, mf, mask, yb, work);
+  hipLaunchKernelGGL(k_ttT_4<R>, dim3((mf + 63) / 64), dim3(256), 0, st, T, s3, mf, yf);
+}
+
+// The forward half of launch_tt_post: y_b[c] += mask * (merged core) t3.
+template <typename R> void launch_tt_forward_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
+                                                  const uint8_t* mask, cx<R>* yb, const cx<R>* work) {
+  const TTWork w = tt_layout(T, n, mf);
+  const cx<R>* t3 = work + 3LL * TT_RMAX * w.nchunk;
   GemmSet<R> F{};
   F.nprob = 3;
   for (int c = 0; c < 3; ++c) {
@@ -1847,8 +1850,7 @@ template <typename R> void launch_tt_post(hipStream_t st, const TTDesc<R>& T, co
                          w.n12, 1, 0, w.n3, w.n12, T.r2[c], 0, nullptr, mask, 1};
     F.nbatch[c] = 1;
   }
-  zgemm<R>(st, F);
-  hipLaunchKernelGGL(k_ttT_4<R>, dim3((mf + 63) / 64), dim3(256), 0, st, T, s3, mf, yf);
+  launch_zgemm<R>(st, F);
 }
 int64_t tt_work_elems(const int n[3], int mf) {
   const int nchunk = (mf + 4095) / 4096;
@@ -1870,6 +1872,183 @@ template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, co
   if (ne > 0) hipLaunchKernelGGL(k_scatter_rhs<R>, dim3((ne + 255) / 256), dim3(256), 0, st, idx, vre, vim, ne, b);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Elimination of the far-conductor currents (Schur complement of the dense far block) and the
+// block-Jacobi preconditioner of the reduced system, FP64.
+//
+// The far currents couple to the rest only through low-rank factors: Z_fr x_r = L t(x_r) with
+// L = [conj(V) | G4_0^T | G4_1^T | G4_2^T] (m_f x K) and t = [U^T x_n ; s3_0 ; s3_1 ; s3_2], the
+// ACA (eq. (12)) and the transpose TT chain (eqs. (18)-(19)). With W = Z_ff^-1 L and
+// S = L^T W (K x K), the reduced operator is Z_rr x_r - R^T (S t(x_r)), where R^T injects proxy
+// values through the same factors in the forward direction (U p_a into y_n, the forward TT chain
+// from p_c into y_b, eqs. (16)-(17)).
+
+// dense row-major m x m copy of a symmetric block held as upper-triangle tiles
+__global__ void k_unpack_sym(const cxd* __restrict__ Zp, int T, int m, cxd* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  const int i = (int)(e / m), j = (int)(e % m);
+  int I = i / SYM_TB, J = j / SYM_TB, a = i % SYM_TB, b = j % SYM_TB;
+  if (I > J) {
+    const int t0 = I, t1 = a;
+    I = J;
+    J = t0;
+    a = b;
+    b = t1;
+  }
+  const int64_t t = (int64_t)I * T - (int64_t)I * (I - 1) / 2 + (J - I);
+  out[e] = Zp[t * SYM_TB * SYM_TB + a * SYM_TB + b];
+}
+
+// upper-triangle tiles (tile list as for the far block) of a dense row-major m x m matrix
+__global__ void k_pack_sym(const cxd* __restrict__ X, int m, const int* __restrict__ tiles, int64_t ntiles,
+                           cxd* __restrict__ Zp) {
+  const int64_t per = (int64_t)SYM_TB * SYM_TB;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ntiles * per) return;
+  const int64_t t = e / per;
+  const int a = (int)((e % per) / SYM_TB), b = (int)(e % SYM_TB);
+  const int i = tiles[2 * t] * SYM_TB + a, j = tiles[2 * t + 1] * SYM_TB + b;
+  Zp[e] = (i < m && j < m) ? X[(int64_t)i * m + j] : cxd{0, 0};
+}
+
+// L[i][l], row-major m_f x K: conj(V[l][i]) for the ka ACA columns, then G4_c[r][i] per component
+__global__ void k_build_far_factors(const cxd* __restrict__ V, int ka, TTDesc<double> T, int mf, int K,
+                                    cxd* __restrict__ L) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)mf * K) return;
+  const int i = (int)(e / K), l = (int)(e % K);
+  cxd v;
+  if (l < ka) {
+    v = conj(V[(int64_t)l * mf + i]);
+  } else {
+    int q = l - ka, c = 0;
+    while (c < 2 && q >= T.r3[c]) q -= T.r3[c++];
+    v = T.G4[c][(int64_t)q * mf + i];
+  }
+  L[e] = v;
+}
+
+// p = sign * S t, t = [ta (ka values) | s3[0][0..r3_0) | s3[1][..] | s3[2][..]] (s3 rows of
+// length TT_RMAX); p is scattered the same way into pa and p3. One wavefront per row of S.
+constexpr int SCHUR_KMAX = 256 + 3 * TT_RMAX;
+__global__ __launch_bounds__(256) void k_schur_apply(const cxd* __restrict__ S, int K, int ka, int r30, int r31,
+                                                     int r32, const cxd* __restrict__ ta, const cxd* __restrict__ s3,
+                                                     double sign, cxd* __restrict__ pa, cxd* __restrict__ p3) {
+  __shared__ cxd t[SCHUR_KMAX];
+  for (int l = threadIdx.x; l < K; l += 256) {
+    if (l < ka) {
+      t[l] = ta[l];
+    } else {
+      const int q = l - ka;
+      const int c = q < r30 ? 0 : (q < r30 + r31 ? 1 : 2);
+      const int r = q - (c > 0 ? r30 : 0) - (c > 1 ? r31 : 0);
+      t[l] = s3[c * TT_RMAX + r];
+    }
+  }
+  __syncthreads();
+  const int row = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (row >= K) return;
+  cxd acc = {0, 0};
+  for (int m = lane; m < K; m += 64) acc += S[(int64_t)row * K + m] * t[m];
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.re += __shfl_xor(acc.re, off, 64);
+    acc.im += __shfl_xor(acc.im, off, 64);
+  }
+  if (lane != 0) return;
+  acc = sign * acc;
+  if (row < ka) {
+    pa[row] = acc;
+  } else {
+    const int q = row - ka;
+    const int c = q < r30 ? 0 : (q < r30 + r31 ? 1 : 2);
+    const int r = q - (c > 0 ? r30 : 0) - (c > 1 ? r31 : 0);
+    p3[c * TT_RMAX + r] = acc;
+  }
+}
+
+// out[l] = sign * t[l] with t laid out as for k_schur_apply (compact proxy vector)
+__global__ void k_schur_gather(int K, int ka, int r30, int r31, const cxd* __restrict__ ta,
+                               const cxd* __restrict__ s3, double sign, cxd* __restrict__ out) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= K) return;
+  cxd v;
+  if (l < ka) {
+    v = ta[l];
+  } else {
+    const int q = l - ka;
+    const int c = q < r30 ? 0 : (q < r30 + r31 ? 1 : 2);
+    const int r = q - (c > 0 ? r30 : 0) - (c > 1 ? r31 : 0);
+    v = s3[c * TT_RMAX + r];
+  }
+  out[l] = sign * v;
+}
+
+// pa / p3 (layout as in k_schur_apply) = sign * in, in compact (K values)
+__global__ void k_schur_scatter(int K, int ka, int r30, int r31, const cxd* __restrict__ in, double sign,
+                                cxd* __restrict__ pa, cxd* __restrict__ p3) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= K) return;
+  const cxd v = sign * in[l];
+  if (l < ka) {
+    pa[l] = v;
+  } else {
+    const int q = l - ka;
+    const int c = q < r30 ? 0 : (q < r30 + r31 ? 1 : 2);
+    const int r = q - (c > 0 ? r30 : 0) - (c > 1 ? r31 : 0);
+    p3[c * TT_RMAX + r] = v;
+  }
+}
+
+// y = d * x elementwise
+__global__ void k_mul_diag(const cxd* __restrict__ x, const cxd* __restrict__ d, cxd* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = d[i] * x[i];
+}
+
+// X = identity (n x n, row-major)
+__global__ void k_set_identity(cxd* __restrict__ X, int n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  X[e] = cxd{e / n == e % n ? 1.0 : 0.0, 0.0};
+}
+
+void launch_set_identity(hipStream_t st, cxd* X, int n) {
+  const int64_t m = (int64_t)n * n;
+  if (m > 0) hipLaunchKernelGGL(k_set_identity, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, X, n);
+}
+void launch_unpack_sym(hipStream_t st, const cxd* Zp, int T, int m, cxd* out) {
+  const int64_t n = (int64_t)m * m;
+  if (n > 0) hipLaunchKernelGGL(k_unpack_sym, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Zp, T, m, out);
+}
+void launch_pack_sym(hipStream_t st, const cxd* X, int m, const int* tiles, int64_t ntiles, cxd* Zp) {
+  const int64_t n = ntiles * SYM_TB * SYM_TB;
+  if (n > 0) hipLaunchKernelGGL(k_pack_sym, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, m, tiles, ntiles, Zp);
+}
+void launch_build_far_factors(hipStream_t st, const cxd* V, int ka, const TTDesc<double>& T, int mf, int K, cxd* L) {
+  const int64_t n = (int64_t)mf * K;
+  if (n > 0)
+    hipLaunchKernelGGL(k_build_far_factors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, V, ka, T, mf, K, L);
+}
+void launch_schur_apply(hipStream_t st, const cxd* S, int K, int ka, const int r3[3], const cxd* ta, const cxd* s3,
+                        double sign, cxd* pa, cxd* p3) {
+  if (K > SCHUR_KMAX) throw Error(VSIE_E_ARG, "more than " + std::to_string(SCHUR_KMAX) + " far-coupling proxies");
+  if (K > 0)
+    hipLaunchKernelGGL(k_schur_apply, dim3((K + 3) / 4), dim3(256), 0, st, S, K, ka, r3[0], r3[1], r3[2], ta, s3, sign,
+                       pa, p3);
+}
+void launch_schur_gather(hipStream_t st, int K, int ka, const int r3[3], const cxd* ta, const cxd* s3, double sign,
+                         cxd* out) {
+  if (K > 0) hipLaunchKernelGGL(k_schur_gather, dim3((K + 255) / 256), dim3(256), 0, st, K, ka, r3[0], r3[1], ta, s3, sign, out);
+}
+void launch_schur_scatter(hipStream_t st, int K, int ka, const int r3[3], const cxd* in, double sign, cxd* pa,
+                          cxd* p3) {
+  if (K > 0) hipLaunchKernelGGL(k_schur_scatter, dim3((K + 255) / 256), dim3(256), 0, st, K, ka, r3[0], r3[1], in, sign, pa, p3);
+}
+void launch_mul_diag(hipStream_t st, const cxd* x, const cxd* d, cxd* y, int64_t n) {
+  if (n > 0) hipLaunchKernelGGL(k_mul_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, d, y, n);
+}
+
 #define VSIE_INST(R)                                                                                                  \
   template void launch_build_grid<R>(hipStream_t, const cx<R>*, const cx<R>*, const uint8_t*, const int*, const int*, \
                                      const int*, const R*, cx<R>*, const GridDims&);                                  \
@@ -1885,6 +2064,11 @@ template <typename R> void launch_scatter_rhs(hipStream_t st, const int* idx, co
                                  const uint8_t*, cx<R>*);                                                             \
   template void launch_tt_post<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const uint8_t*, cx<R>*, cx<R>*,   \
                                   const cx<R>*);                                                                      \
+  template void launch_tt_transpose_pre<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*,          \
+                                           const uint8_t*, cx<R>*);                                             \
+  template void launch_tt_forward_from<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*, cx<R>*); \
+  template void launch_tt_forward_post<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const uint8_t*,        \
+                                          cx<R>*, const cx<R>*);                                                \
   template void launch_scatter_rhs<R>(hipStream_t, const int*, const double*, const double*, int, cx<R>*);         \
   template void launch_symv_tiles<R>(hipStream_t, const cx<R>*, const int*, int, const cx<R>*, int, cx<R>*);      \
   template void launch_symv_reduce<R>(hipStream_t, const cx<R>*, int, int, cx<R>*);

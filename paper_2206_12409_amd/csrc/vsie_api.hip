@@ -5,6 +5,7 @@
 #include <cstring>
 #include <numeric>
 
+#include "dense_lu.h"
 #include "kernels.h"
 
 using namespace vsie;
@@ -599,6 +600,44 @@ static void make_streams(Handle& H) {
   VSIE_HIP(hipEventCreateWithFlags(&H.join, hipEventDisableTiming));
 }
 
+// Volume convolution with the pFFT projection and interpolation of the near currents
+// (Sec. II-B, eq. (13)): y_b and y_n from x_b and x_n (x_n null when there are no near currents).
+template <typename R>
+static void volume_chain(Handle& H, OpData<R>& D, const cx<R>* xn, const cx<R>* xb, cx<R>* yn, cx<R>* yb,
+                         hipStream_t st, StageTimer& T) {
+  GridDims g = grid_dims(H);
+  const int mn = H.mn;
+  const int P1 = H.P[0], P2 = H.P[1], P3 = H.P[2];
+  const int ne1 = H.ne[0], ne2 = H.ne[1], ne3 = H.ne[2];
+  T.begin(0, st);
+  launch_build_grid<R>(st, xb, mn ? xn : nullptr, H.d_mask, mn ? H.d_vox2row : nullptr, H.d_rowptr, H.d_rowrwg, D.roww,
+                       D.gridA, g);
+  T.end(0, st);
+  T.begin(1, st);
+  fft_rows<R>(st, P1, true, D.gridA, D.bufB, ne1, P1, ne1, P1, 3LL * ne3 * ne2, D.tw[0]);
+  T.end(1, st);
+  T.begin(2, st);
+  fft_strided<R>(st, P2, true, D.bufB, D.bufC, ne2, P2, P1, P1, P1, 3LL * ne3, (int64_t)ne2 * P1, (int64_t)P2 * P1, D.tw[1]);
+  T.end(2, st);
+  T.begin(3, st);
+  fft_z_conv<R>(st, P3, D.bufC, ne3, P1, P2, D.spec, D.tw[2], H.d_zorder[sizeof(R) == 8 ? 0 : 1]);
+  T.end(3, st);
+  T.begin(4, st);
+  fft_strided<R>(st, P2, false, D.bufC, D.bufB, P2, ne2, P1, P1, P1, 3LL * ne3, (int64_t)P2 * P1, (int64_t)ne2 * P1, D.tw[1]);
+  T.end(4, st);
+  T.begin(5, st);
+  fft_rows<R>(st, P1, false, D.bufB, D.gridA, P1, ne1, P1, ne1, 3LL * ne3 * ne2, D.tw[0]);
+  T.end(5, st);
+  T.begin(6, st);
+  launch_body_out<R>(st, xb, D.gridA, D.dv_chi, H.d_mask, yb, g);
+  T.end(6, st);
+  if (mn) {
+    T.begin(7, st);
+    launch_pfft_gather<R>(st, D.W, H.d_base, D.gridA, yn, mn, g);
+    T.end(7, st);
+  }
+}
+
 template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t st) {
   if (H.concurrent && !H.side) make_streams(H);
   // far-block chain: the second stream when concurrent, else the caller's stream after the
@@ -613,9 +652,6 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
   cx<R>* yf = y;
   cx<R>* yn = y + mf;
   cx<R>* yb = y + mf + mn;
-  GridDims g = grid_dims(H);
-  const int P1 = H.P[0], P2 = H.P[1], P3 = H.P[2];
-  const int ne1 = H.ne[0], ne2 = H.ne[1], ne3 = H.ne[2];
   const bool have_tt = mf && D.G12[0] && D.G12[1] && D.G12[2];
   TTDesc<R> td;
   if (have_tt)
@@ -646,34 +682,7 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
     far_chain();
     VSIE_HIP(hipEventRecord(H.join, H.side));
   }
-  // volume convolution and pFFT (Sec. II-B, eq. (13))
-  T.begin(0, st);
-  launch_build_grid<R>(st, xb, mn ? xn : nullptr, H.d_mask, mn ? H.d_vox2row : nullptr, H.d_rowptr, H.d_rowrwg, D.roww,
-                       D.gridA, g);
-  T.end(0, st);
-  T.begin(1, st);
-  fft_rows<R>(st, P1, true, D.gridA, D.bufB, ne1, P1, ne1, P1, 3LL * ne3 * ne2, D.tw[0]);
-  T.end(1, st);
-  T.begin(2, st);
-  fft_strided<R>(st, P2, true, D.bufB, D.bufC, ne2, P2, P1, P1, P1, 3LL * ne3, (int64_t)ne2 * P1, (int64_t)P2 * P1, D.tw[1]);
-  T.end(2, st);
-  T.begin(3, st);
-  fft_z_conv<R>(st, P3, D.bufC, ne3, P1, P2, D.spec, D.tw[2], H.d_zorder[sizeof(R) == 8 ? 0 : 1]);
-  T.end(3, st);
-  T.begin(4, st);
-  fft_strided<R>(st, P2, false, D.bufC, D.bufB, P2, ne2, P1, P1, P1, 3LL * ne3, (int64_t)P2 * P1, (int64_t)ne2 * P1, D.tw[1]);
-  T.end(4, st);
-  T.begin(5, st);
-  fft_rows<R>(st, P1, false, D.bufB, D.gridA, P1, ne1, P1, ne1, 3LL * ne3 * ne2, D.tw[0]);
-  T.end(5, st);
-  T.begin(6, st);
-  launch_body_out<R>(st, xb, D.gridA, D.dv_chi, H.d_mask, yb, g);
-  T.end(6, st);
-  if (mn) {
-    T.begin(7, st);
-    launch_pfft_gather<R>(st, D.W, H.d_base, D.gridA, yn, mn, g);
-    T.end(7, st);
-  }
+  volume_chain<R>(H, D, mn ? xn : nullptr, xb, yn, yb, st, T);
   if (conc)
     VSIE_HIP(hipStreamWaitEvent(st, H.join, 0));
   else if (mf)
@@ -700,6 +709,242 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
     T.end(13);
   }
   T.collect();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Elimination of the far currents. The far conductor couples to the near currents and the body
+// only through the ACA factors (eq. (12)) and the TT cores (eq. (14)), so its unknowns leave the
+// system exactly through a K x K matrix, K = ACA rank + TT ranks r3 (the elimination the paper's
+// conclusion proposes): Z_fr x_r = L t(x_r), L = [conj(V) | G4_0^T | G4_1^T | G4_2^T], and the
+// reduced operator is Z_rr x_r - R^T S t(x_r) with S = L^T Z_ff^-1 L; R^T injects proxy values
+// through the same factors in the forward direction.
+
+// device buffer released at scope exit (setup temporaries)
+struct Scratch {
+  void* p = nullptr;
+  explicit Scratch(size_t bytes) {
+    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+      p = nullptr;
+      throw Error(VSIE_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  ~Scratch() {
+    if (p) (void)hipFree(p);
+  }
+  template <typename T> T* as() const { return (T*)p; }
+};
+
+static bool tt_desc(const Handle& H, const OpData<double>& D, TTDesc<double>& td, int r3[3]) {
+  const bool have = H.mf && D.G12[0] && D.G12[1] && D.G12[2];
+  for (int c = 0; c < 3; ++c) {
+    td.M[c] = D.G12[c];
+    td.G3[c] = D.G[c][2];
+    td.G4[c] = D.G[c][3];
+    td.r2[c] = have ? H.tt_r[c][1] : 0;
+    td.r3[c] = have ? H.tt_r[c][2] : 0;
+    r3[c] = td.r3[c];
+  }
+  return have;
+}
+static int aca_rank(const Handle& H) { return (H.mf > 0 && H.mn > 0 && H.aca_k > 0) ? H.aca_k : 0; }
+
+// C (M x N) = A B with explicit element strides (row, column) of each operand
+static void gemm_strided(hipStream_t st, int M, int N, int K, const cxd* A, int64_t sar, int64_t sac, const cxd* B,
+                         int64_t sbr, int64_t sbc, cxd* C, int64_t scr, int64_t scc, int accumulate, int negate) {
+  GemmSet<double> G{};
+  G.nprob = 1;
+  G.nbatch[0] = 1;
+  G.g[0] = GemmArgs<double>{A, sar, sac, 0, B, sbr, sbc, 0, C, scr, scc, 0, M, N, K, 0, nullptr, nullptr, accumulate,
+                            negate};
+  launch_zgemm<double>(st, G);
+}
+
+// y_n += U p_a and y_b += forward TT chain of p3 (eqs. (16)-(17) from the rank-r3 stage on)
+static void inject_proxies(Handle& H, const cxd* pa, const cxd* p3, cxd* yn, cxd* yb, hipStream_t st) {
+  OpData<double>& D = H.d64;
+  TTDesc<double> td;
+  int r3[3];
+  const bool have_tt = tt_desc(H, D, td, r3);
+  const int ka = aca_rank(H);
+  if (ka) launch_lr_n_add<double>(st, false, D.U, pa, H.mn, ka, yn);
+  if (have_tt) {
+    launch_tt_forward_from<double>(st, td, H.n, H.mf, p3, D.tt_work);
+    launch_tt_forward_post<double>(st, td, H.n, H.mf, H.d_mask, yb, D.tt_work);
+  }
+}
+
+// ta = U^T x_n and s3 (start of the TT work buffer) = transpose TT chain of x_b: the proxies t(x_r)
+static void far_proxies(Handle& H, const cxd* xn, const cxd* xb, hipStream_t st) {
+  OpData<double>& D = H.d64;
+  TTDesc<double> td;
+  int r3[3];
+  const bool have_tt = tt_desc(H, D, td, r3);
+  const int ka = aca_rank(H);
+  if (ka) launch_lr_t<double>(st, false, D.U, xn, H.mn, ka, D.small_work, 512, H.schur.ta);
+  if (have_tt) launch_tt_transpose_pre<double>(st, td, H.n, H.mf, xb, H.d_mask, D.tt_work);
+}
+
+// Reduced product y_r = Z_rr x_r - R^T S t(x_r) on the near and body unknowns (x_f is not read,
+// y_f is set to zero).
+static void matvec_schur(Handle& H, const cxd* x, cxd* y, hipStream_t st) {
+  OpData<double>& D = H.d64;
+  Handle::Schur& Sc = H.schur;
+  StageTimer T(H, st);
+  const int mf = H.mf, mn = H.mn;
+  const cxd* xn = x + mf;
+  const cxd* xb = x + mf + mn;
+  cxd* yn = y + mf;
+  cxd* yb = y + mf + mn;
+  volume_chain<double>(H, D, mn ? xn : nullptr, xb, yn, yb, st, T);
+  T.begin(9);
+  launch_csr_add<double>(st, H.d_pc_rowid, H.d_pc_rowptr, H.d_pc_col, D.pc_val, x, y, H.n_pcrows);
+  T.end(9);
+  if (Sc.K > 0) {
+    T.begin(10);
+    far_proxies(H, xn, xb, st);
+    TTDesc<double> td;
+    int r3[3];
+    tt_desc(H, D, td, r3);
+    launch_schur_apply(st, Sc.S, Sc.K, aca_rank(H), r3, Sc.ta, D.tt_work, -1.0, Sc.pa, Sc.p3);
+    inject_proxies(H, Sc.pa, Sc.p3, yn, yb, st);
+    T.end(10);
+  }
+  if (mf) VSIE_HIP(hipMemsetAsync(y, 0, sizeof(cxd) * mf, st));
+  T.collect();
+}
+
+// Right preconditioner of the reduced system: the inverse of its near block (direct Galerkin
+// entries of the near coils minus the eliminated far block's ACA term) on the near currents, the
+// inverse diagonal on the body unknowns, zero on the far currents. Identity when not built.
+static void precond_apply(Handle& H, const cxd* v, cxd* w, hipStream_t st) {
+  Handle::Schur& Sc = H.schur;
+  const int mf = H.mf, mn = H.mn;
+  if (!Sc.precond) {
+    VSIE_HIP(hipMemcpyAsync(w, v, sizeof(cxd) * H.N, hipMemcpyDeviceToDevice, st));
+    if (mf) VSIE_HIP(hipMemsetAsync(w, 0, sizeof(cxd) * mf, st));
+    return;
+  }
+  if (mf) VSIE_HIP(hipMemsetAsync(w, 0, sizeof(cxd) * mf, st));
+  if (mn) {
+    launch_symv_tiles<double>(st, Sc.Xn, Sc.d_tiles_n, Sc.Tn, v + mf, mn, Sc.part_n);
+    launch_symv_reduce<double>(st, Sc.part_n, Sc.Tn, mn, w + mf);
+  }
+  launch_mul_diag(st, v + mf + mn, Sc.invdiag, w + mf + mn, 3LL * H.nv);
+}
+
+static std::vector<int> upper_tiles(int T) {
+  std::vector<int> tiles;
+  for (int I = 0; I < T; ++I)
+    for (int J = I; J < T; ++J) {
+      tiles.push_back(I);
+      tiles.push_back(J);
+    }
+  return tiles;
+}
+
+static void setup_schur(Handle& H, bool precond) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = H.stream;
+  OpData<double>& D = H.d64;
+  Handle::Schur& Sc = H.schur;
+  const int mf = H.mf, mn = H.mn;
+  TTDesc<double> td;
+  int r3[3];
+  tt_desc(H, D, td, r3);
+  const int ka = aca_rank(H);
+  if (!Sc.ready) {
+    Sc.K = mf ? ka + r3[0] + r3[1] + r3[2] : 0;
+    if (Sc.K > 256 + 3 * TT_RMAX) throw Error(VSIE_E_ARG, "too many far-coupling proxies");
+    Sc.ta = H.dalloc<cxd>(256);
+    Sc.pa = H.dalloc<cxd>(256);
+    Sc.p3 = H.dalloc<cxd>(3 * TT_RMAX);
+    Sc.tc = H.dalloc<cxd>(std::max(Sc.K, 1));
+    for (auto& v : Sc.vec) v = H.dalloc<cxd>(H.N);
+    if (mf) {
+      // dense far block from its tiles, factored in place
+      Sc.zf = H.dalloc<cxd>(mf);
+      DenseLU& F = Sc.ff;
+      F.n = mf;
+      F.lda = mf;
+      F.A = H.dalloc<cxd>((int64_t)mf * mf);
+      F.Linv = H.dalloc<cxd>(lu_blocks_elems(mf));
+      F.Uinv = H.dalloc<cxd>(lu_blocks_elems(mf));
+      F.d_ipiv = H.dalloc<int>(mf);
+      F.d_perm = H.dalloc<int>(mf);
+      F.d_info = H.dalloc<int>(1);
+      launch_unpack_sym(st, D.Zff, H.sym_T, mf, F.A);
+      {
+        Scratch work(sizeof(cxd) * lu_work_elems(mf));
+        lu_factor(st, F, work.as<cxd>());
+      }
+      if (Sc.K > 0) {
+        const int K = Sc.K;
+        Scratch L(sizeof(cxd) * mf * K), Wt(sizeof(cxd) * mf * K);
+        launch_build_far_factors(st, D.V, ka, td, mf, K, L.as<cxd>());
+        Sc.W = H.dalloc<cxd>((int64_t)mf * K);
+        VSIE_HIP(hipMemcpyAsync(Sc.W, L.p, sizeof(cxd) * mf * K, hipMemcpyDeviceToDevice, st));
+        lu_solve(st, F, Sc.W, K, K, Wt.as<cxd>());
+        // S = L^T W
+        Sc.S = H.dalloc<cxd>((int64_t)K * K);
+        gemm_strided(st, K, K, mf, L.as<cxd>(), 1, K, Sc.W, K, 1, Sc.S, K, 1, 0, 0);
+        VSIE_HIP(hipGetLastError());
+        VSIE_HIP(hipStreamSynchronize(st));
+      }
+    }
+    Sc.ready = true;
+  }
+  if (precond && !Sc.precond) {
+    if (mn) {
+      // reduced near block: direct Galerkin entries minus U S_aa U^T, inverted through its LU
+      Scratch Zn(sizeof(cxd) * mn * mn), X(sizeof(cxd) * mn * mn);
+      launch_zcc_dense(st, H.dnear, H.dnear, H.k0, 0, mn, Zn.as<cxd>());
+      if (ka && Sc.K > 0) {
+        Scratch T1(sizeof(cxd) * mn * ka);
+        gemm_strided(st, mn, ka, ka, D.U, 1, mn, Sc.S, Sc.K, 1, T1.as<cxd>(), ka, 1, 0, 0);
+        gemm_strided(st, mn, mn, ka, T1.as<cxd>(), ka, 1, D.U, mn, 1, Zn.as<cxd>(), mn, 1, 1, 1);
+        VSIE_HIP(hipStreamSynchronize(st));
+      }
+      DenseLU F;
+      F.n = mn;
+      F.lda = mn;
+      F.A = Zn.as<cxd>();
+      Scratch Li(sizeof(cxd) * lu_blocks_elems(mn)), Ui(sizeof(cxd) * lu_blocks_elems(mn)),
+          ip(sizeof(int) * mn), pm(sizeof(int) * mn), inf(sizeof(int)), work(sizeof(cxd) * lu_work_elems(mn));
+      F.Linv = Li.as<cxd>();
+      F.Uinv = Ui.as<cxd>();
+      F.d_ipiv = ip.as<int>();
+      F.d_perm = pm.as<int>();
+      F.d_info = inf.as<int>();
+      lu_factor(st, F, work.as<cxd>());
+      launch_set_identity(st, X.as<cxd>(), mn);
+      {
+        Scratch Wn(sizeof(cxd) * mn * mn);
+        lu_solve(st, F, X.as<cxd>(), mn, mn, Wn.as<cxd>());
+        VSIE_HIP(hipStreamSynchronize(st));
+      }
+      Sc.Tn = (mn + SYM_TB - 1) / SYM_TB;
+      const std::vector<int> tiles = upper_tiles(Sc.Tn);
+      const int64_t nt = (int64_t)tiles.size() / 2;
+      Sc.d_tiles_n = upload(H, tiles);
+      Sc.Xn = H.dalloc<cxd>(nt * SYM_TB * SYM_TB);
+      Sc.part_n = H.dalloc<cxd>(nt * 2 * SYM_TB);
+      launch_pack_sym(st, X.as<cxd>(), mn, Sc.d_tiles_n, nt, Sc.Xn);
+      VSIE_HIP(hipGetLastError());
+      VSIE_HIP(hipStreamSynchronize(st));
+    }
+    // body diagonal: h^3 / chi + h^3 T_aa(0) (the self term of the convolution), 1 in air
+    cxd T0[3];
+    for (int a = 0; a < 3; ++a)
+      VSIE_HIP(hipMemcpy(&T0[a], H.d_oct + (int64_t)a * H.Ne, sizeof(cxd), hipMemcpyDeviceToHost));
+    const double h3 = H.h * H.h * H.h;
+    std::vector<cxd> inv(3 * (size_t)H.nv, cxd{1, 0});
+    for (int p = 0; p < H.nv; ++p)
+      if (H.chi[p].re != 0 || H.chi[p].im != 0)
+        for (int a = 0; a < 3; ++a) inv[(size_t)a * H.nv + p] = cinv(h3 * cinv(H.chi[p]) + h3 * T0[a]);
+    Sc.invdiag = upload_cx<double>(H, inv);
+    Sc.precond = true;
+  }
+  Sc.seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -929,6 +1174,56 @@ void ensure_solver_ws(Handle& H, int restart) {
   }
 }
 
+// GMRES on the reduced system (far currents eliminated), right-preconditioned when the
+// preconditioner is built: solve (A_S M) u = b_r - Z_rf Z_ff^-1 b_f, x_r = M u, then recover
+// x_f = Z_ff^-1 (b_f - L t(x_r)). Returns the iterations.
+int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, const cxd* b, cxd* x, cxd* w, cxd* hv, int* restarts,
+                double* rel, hipStream_t st) {
+  Handle::Schur& Sc = H.schur;
+  OpData<double>& D = H.d64;
+  const int64_t N = H.N;
+  const int mf = H.mf, mn = H.mn, K = Sc.K, ka = aca_rank(H);
+  TTDesc<double> td;
+  int r3[3];
+  tt_desc(H, D, td, r3);
+  cxd* bred = Sc.vec[0];
+  cxd* tmp = Sc.vec[1];
+  double nb[4], nbr[4];
+  S.norms(b, nb);
+  const bool bf = mf > 0 && nb[0] > 0;
+  VSIE_HIP(hipMemcpyAsync(bred, b, sizeof(cxd) * N, hipMemcpyDeviceToDevice, st));
+  if (mf) VSIE_HIP(hipMemsetAsync(bred, 0, sizeof(cxd) * mf, st));
+  if (bf) {
+    VSIE_HIP(hipMemcpyAsync(Sc.zf, b, sizeof(cxd) * mf, hipMemcpyDeviceToDevice, st));
+    lu_solve(st, Sc.ff, Sc.zf, 1, 1, tmp);
+    if (K) {
+      // proxies of Z_ff^-1 b_f: L^T Z_ff^-1 b_f = W^T b_f, injected with a minus sign
+      gemm_strided(st, K, 1, mf, Sc.W, 1, K, b, 1, 1, Sc.tc, 1, 1, 0, 0);
+      launch_schur_scatter(st, K, ka, r3, Sc.tc, -1.0, Sc.pa, Sc.p3);
+      inject_proxies(H, Sc.pa, Sc.p3, bred + mf, bred + mf + mn, st);
+    }
+  }
+  S.norms(bred, nbr);
+  const double tol = nbr[3] > 0 ? so.tol * nb[3] / nbr[3] : so.tol;
+  auto AM = [&](const cxd* in, cxd* out) {
+    precond_apply(H, in, tmp, st);
+    matvec_schur(H, tmp, out, st);
+  };
+  const int it = S.gmres(AM, bred, x, tol, so.restart, so.max_iter, restarts, rel, H.d_krylov, w, hv);
+  precond_apply(H, x, tmp, st);
+  VSIE_HIP(hipMemcpyAsync(x, tmp, sizeof(cxd) * N, hipMemcpyDeviceToDevice, st));
+  if (mf) {
+    if (bf) VSIE_HIP(hipMemcpyAsync(x, Sc.zf, sizeof(cxd) * mf, hipMemcpyDeviceToDevice, st));
+    if (K) {
+      far_proxies(H, x + mf, x + mf + mn, st);
+      launch_schur_gather(st, K, ka, r3, Sc.ta, D.tt_work, -1.0, Sc.tc);
+      launch_gemv_rows<double>(st, Sc.W, Sc.tc, mf, K, x, 1);
+    }
+  }
+  VSIE_HIP(hipGetLastError());
+  return it;
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -954,6 +1249,7 @@ int vsie_default_solve_opts(vsie_solve_opts* o) {
   o->max_iter = 5000;
   o->method = VSIE_GMRES64;
   o->inner_tol = 1e-3;
+  o->precond = 1;
   return VSIE_OK;
 }
 
@@ -1146,6 +1442,7 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
   if (o) so = *o;
   else vsie_default_solve_opts(&so);
   if (so.restart < 1 || so.restart > 1000 || so.max_iter < 1 || !(so.tol > 0)) return fail(VSIE_E_ARG, "bad solve options");
+  if (so.method < VSIE_GMRES64 || so.method > VSIE_SCHUR) return fail(VSIE_E_ARG, "unknown solve method");
   if (so.method == VSIE_IR_MIXED && !hd->H.have32) return fail(VSIE_E_STATE, "complex64 operator data not built");
   Handle& H = hd->H;
   int status = VSIE_OK;
@@ -1180,6 +1477,7 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       matvec_one<float>(H, H.d32, x32, y32, st);
       launch_f2d(st, y32, out, N);
     };
+    if (so.method == VSIE_SCHUR) setup_schur(H, so.precond != 0);
     for (int c = 0; c < nrhs; ++c) {
       auto t0 = std::chrono::steady_clock::now();
       const cxd* b = (const cxd*)b_dev + c * N;
@@ -1189,6 +1487,8 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       double rel = 0;
       if (so.method == VSIE_GMRES64) {
         s.iterations = S.gmres(A64, b, x, so.tol, so.restart, so.max_iter, &s.restarts, &rel, H.d_krylov, w, hv);
+      } else if (so.method == VSIE_SCHUR) {
+        s.iterations = solve_schur(H, S, so, b, x, w, hv, &s.restarts, &rel, st);
       } else {
         int total = 0;
         // preconditioner: at most one cycle (restart iterations) of complex64 GMRES on Z z = v
@@ -1339,6 +1639,67 @@ int vsie_import(vsie_handle* hd, int what, int index, const void* host, size_t n
       upload_aca(H);
     } else {
       throw Error(VSIE_E_ARG, "unsupported import kind");
+    }
+  });
+}
+
+int vsie_schur_setup(vsie_handle* hd, int precond) {
+  if (!hd) return fail(VSIE_E_ARG, "null handle");
+  Handle& H = hd->H;
+  return guarded([&]() { setup_schur(H, precond != 0); });
+}
+
+int vsie_schur_info(const vsie_handle* hd, int32_t* n_proxy, double* seconds, int32_t* built) {
+  if (!hd) return fail(VSIE_E_ARG, "null handle");
+  const Handle::Schur& Sc = hd->H.schur;
+  if (n_proxy) *n_proxy = Sc.K;
+  if (seconds) *seconds = Sc.seconds;
+  if (built) *built = (Sc.ready ? 1 : 0) | (Sc.precond ? 2 : 0);
+  return VSIE_OK;
+}
+
+int vsie_schur_matvec(vsie_handle* hd, const void* x_dev, void* y_dev, void* stream) {
+  if (!hd || !x_dev || !y_dev || x_dev == y_dev) return fail(VSIE_E_ARG, "bad argument");
+  Handle& H = hd->H;
+  if (!H.schur.ready) return fail(VSIE_E_STATE, "far elimination not set up (vsie_schur_setup)");
+  return guarded([&]() {
+    matvec_schur(H, (const cxd*)x_dev, (cxd*)y_dev, (hipStream_t)stream);
+    VSIE_HIP(hipGetLastError());
+  });
+}
+
+int vsie_schur_precond(vsie_handle* hd, const void* x_dev, void* y_dev, void* stream) {
+  if (!hd || !x_dev || !y_dev || x_dev == y_dev) return fail(VSIE_E_ARG, "bad argument");
+  Handle& H = hd->H;
+  if (!H.schur.precond) return fail(VSIE_E_STATE, "preconditioner not built (vsie_schur_setup with precond)");
+  return guarded([&]() {
+    precond_apply(H, (const cxd*)x_dev, (cxd*)y_dev, (hipStream_t)stream);
+    VSIE_HIP(hipGetLastError());
+  });
+}
+
+int vsie_dense_lu_solve(int n, void* A_dev, int64_t lda, void* B_dev, int64_t ldb, int nrhs, void* stream) {
+  if (n < 0 || nrhs < 0 || lda < n || ldb < nrhs || (n > 0 && (!A_dev || (nrhs > 0 && !B_dev))))
+    return fail(VSIE_E_ARG, "bad argument");
+  if (n == 0) return VSIE_OK;
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    DenseLU F;
+    F.n = n;
+    F.lda = lda;
+    F.A = (cxd*)A_dev;
+    Scratch Li(sizeof(cxd) * lu_blocks_elems(n)), Ui(sizeof(cxd) * lu_blocks_elems(n)), ip(sizeof(int) * n),
+        pm(sizeof(int) * n), inf(sizeof(int)), work(sizeof(cxd) * lu_work_elems(n));
+    F.Linv = Li.as<cxd>();
+    F.Uinv = Ui.as<cxd>();
+    F.d_ipiv = ip.as<int>();
+    F.d_perm = pm.as<int>();
+    F.d_info = inf.as<int>();
+    lu_factor(st, F, work.as<cxd>());
+    if (nrhs > 0) {
+      Scratch W(sizeof(cxd) * (size_t)n * nrhs);
+      lu_solve(st, F, (cxd*)B_dev, ldb, nrhs, W.as<cxd>());
+      VSIE_HIP(hipStreamSynchronize(st));
     }
   });
 }

@@ -83,6 +83,23 @@ template <typename R> struct OpData {
   cx<R>* small_work = nullptr; // ACA / reductions
 };
 
+constexpr int LU_NB = 64;   // panel width of the dense LU
+
+// Factors of P A = L U, in place in A (row-major, leading dimension lda). The caller provides the
+// device buffers: d_ipiv and d_perm (n ints each), d_info (1 int), Linv and Uinv
+// (ceil(n / LU_NB) blocks of LU_NB x LU_NB): the inverted unit-lower and upper diagonal blocks.
+struct DenseLU {
+  int n = 0;
+  int64_t lda = 0;
+  cxd* A = nullptr;
+  cxd* Linv = nullptr;
+  cxd* Uinv = nullptr;
+  int* d_ipiv = nullptr;
+  int* d_perm = nullptr;
+  int* d_info = nullptr;
+  std::vector<int> perm;   // row i of L U is row perm[i] of A
+};
+
 struct Handle {
   // problem
   int n[3];
@@ -157,6 +174,29 @@ struct Handle {
   int ring_head = 0, ring_count = 0;
   double prof_ms[NSTAGE] = {};
   int64_t prof_calls[NSTAGE] = {};
+
+  // elimination of the far currents (Schur complement of the dense far block) and the right
+  // preconditioner of the reduced system, built on first use
+  struct Schur {
+    bool ready = false;
+    bool precond = false;
+    int K = 0;                   // far-coupling proxies: ACA rank + the three TT ranks r3
+    DenseLU ff;                  // LU of the dense far block (m_f x m_f, row-major)
+    cxd* W = nullptr;            // Z_ff^-1 L, row-major [m_f][K]
+    cxd* S = nullptr;            // L^T Z_ff^-1 L, [K][K]
+    cxd* ta = nullptr;           // U^T x_n (256)
+    cxd* pa = nullptr;           // ACA proxies to inject (256)
+    cxd* p3 = nullptr;           // TT proxies to inject, [3][128]
+    cxd* tc = nullptr;           // compact proxy vector (K)
+    cxd* zf = nullptr;           // Z_ff^-1 b_f (m_f)
+    cxd* vec[3] = {};            // N-length work vectors of the solver
+    int Tn = 0;                  // inverse of the reduced near block as upper-triangle tiles
+    int* d_tiles_n = nullptr;
+    cxd* Xn = nullptr;
+    cxd* part_n = nullptr;
+    cxd* invdiag = nullptr;      // inverse body diagonal, 3 n_v (1 for air voxels)
+    double seconds = 0;          // setup time
+  } schur;
 
   template <typename T> T* dalloc(int64_t count) {
     if (count <= 0) count = 1;

@@ -15,12 +15,14 @@ LIB_PATH = os.path.join(HERE, "libvsie.so")
 VSIE_OK, VSIE_E_NOCONV = 0, 7
 VSIE_NEAR, VSIE_FAR = 0, 1
 VSIE_C128, VSIE_C64 = 0, 1
-VSIE_GMRES64, VSIE_IR_MIXED = 0, 1
+VSIE_GMRES64, VSIE_IR_MIXED, VSIE_SCHUR = 0, 1, 2
+VSIE_E_SINGULAR = 11
 X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
 
 EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_sizes", "vsie_rhs",
             "vsie_matvec", "vsie_solve", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
-            "vsie_profile", "vsie_profile_mask", "vsie_profile_read", "vsie_destroy", "vsie_last_error"]
+            "vsie_profile", "vsie_profile_mask", "vsie_profile_read", "vsie_schur_setup", "vsie_schur_info",
+            "vsie_schur_matvec", "vsie_schur_precond", "vsie_dense_lu_solve", "vsie_destroy", "vsie_last_error"]
 
 
 STAGES = ["build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "body_out", "pfft_gather",
@@ -54,7 +56,7 @@ class Sizes(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("method", C.c_int32),
-                ("inner_tol", C.c_double)]
+                ("inner_tol", C.c_double), ("precond", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -89,6 +91,11 @@ def load(path=LIB_PATH):
     lib.vsie_set_concurrency.argtypes = [vp, C.c_int]
     lib.vsie_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64), C.POINTER(C.c_int)]
+    lib.vsie_schur_setup.argtypes = [vp, C.c_int]
+    lib.vsie_schur_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+    lib.vsie_schur_matvec.argtypes = [vp, vp, vp, vp]
+    lib.vsie_schur_precond.argtypes = [vp, vp, vp, vp]
+    lib.vsie_dense_lu_solve.argtypes = [C.c_int, vp, C.c_int64, vp, C.c_int64, C.c_int, vp]
     lib.vsie_destroy.argtypes = [vp]
     lib.vsie_destroy.restype = None
     lib.vsie_last_error.restype = C.c_char_p
@@ -218,13 +225,13 @@ class Operator:
         return b
 
     def solve(self, b, tol=1e-6, restart=50, max_iter=5000, method=VSIE_GMRES64, inner_tol=1e-3, stream=None,
-              allow_noconv=False):
+              allow_noconv=False, precond=True):
         import torch
         nrhs = 1 if b.dim() == 1 else b.shape[0]
         if b.dtype != torch.complex128 or not b.is_cuda:
             raise ValueError("b must be a complex128 device tensor")
         x = torch.empty_like(b)
-        o = SolveOpts(tol, restart, max_iter, method, inner_tol)
+        o = SolveOpts(tol, restart, max_iter, method, inner_tol, 1 if precond else 0)
         st = (SolveStats * nrhs)()
         rc = load().vsie_solve(self._h, C.byref(o), nrhs, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), st,
                                _stream_ptr(stream))
@@ -234,6 +241,35 @@ class Operator:
                       rel_residual=s.rel_residual, block_residual=list(s.block_residual), seconds=s.seconds,
                       converged=rc == VSIE_OK) for s in st]
         return x, stats
+
+    def schur_setup(self, precond=True):
+        """Eliminate the far-conductor currents (and build the reduced system's preconditioner)."""
+        _check(load().vsie_schur_setup(self._h, 1 if precond else 0))
+        return self.schur_info()
+
+    def schur_info(self):
+        k = C.c_int32(0)
+        sec = C.c_double(0)
+        built = C.c_int32(0)
+        _check(load().vsie_schur_info(self._h, C.byref(k), C.byref(sec), C.byref(built)))
+        return dict(n_proxy=k.value, seconds=sec.value, eliminated=bool(built.value & 1),
+                    preconditioner=bool(built.value & 2))
+
+    def _vec_op(self, fn, x, stream):
+        import torch
+        if x.dtype != torch.complex128 or not x.is_cuda or not x.is_contiguous() or x.shape != (self.N,):
+            raise ValueError("x must be a contiguous complex128 device vector of length N")
+        y = torch.empty_like(x)
+        _check(fn(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
+        return y
+
+    def schur_matvec(self, x, stream=None):
+        """Reduced operator (far currents eliminated) on the near and body parts of x."""
+        return self._vec_op(load().vsie_schur_matvec, x, stream)
+
+    def schur_precond(self, x, stream=None):
+        """Block-diagonal right preconditioner of the reduced system."""
+        return self._vec_op(load().vsie_schur_precond, x, stream)
 
     def profile(self, enable=True, stages=None):
         """Enable (and reset) or disable per-stage event timing of matvec; `stages` (names) limits
@@ -326,3 +362,19 @@ class Operator:
         blob = k.tobytes() + U.tobytes() + V.tobytes()
         buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
         _check(load().vsie_import(self._h, X_ACA, 0, buf, len(blob)))
+
+
+def dense_lu_solve(A, B, stream=None):
+    """Solve A X = B on the device (complex128, row-major). A is overwritten by its LU factors and
+    B by X; both are returned."""
+    import torch
+    if A.dtype != torch.complex128 or B.dtype != torch.complex128 or not (A.is_cuda and B.is_cuda):
+        raise ValueError("complex128 device tensors only")
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
+        raise ValueError("A must be square with unit column stride")
+    Bm = B if B.dim() == 2 else B.view(-1, 1)
+    if Bm.shape[0] != A.shape[0] or Bm.stride(1) != 1:
+        raise ValueError("B must have n rows and unit column stride")
+    _check(load().vsie_dense_lu_solve(A.shape[0], C.c_void_p(A.data_ptr()), A.stride(0), C.c_void_p(Bm.data_ptr()),
+                                      Bm.stride(0), Bm.shape[1], _stream_ptr(stream)))
+    return A, B
