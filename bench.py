@@ -250,6 +250,43 @@ def cpu_baseline(problem, budget_s=12.0):
     return macs_per_s, S.Z.shape[0], reps
 
 
+def other_precisions(op, x, y, args):
+    """complex64 product rate and error, and the FP64 rate with the far-block chain on a second
+    stream (checked to give the identical result)."""
+    import torch
+    x32 = x.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    for _ in range(args.warmup):
+        op.matvec(x32, out=y32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n32 = max(10, args.steps // 2)
+    for _ in range(n32):
+        op.matvec(x32, out=y32)
+    torch.cuda.synchronize()
+    value32 = n32 / (time.perf_counter() - t0)
+    err32 = float(torch.linalg.norm(y32.to(torch.complex128) - y) / torch.linalg.norm(y))
+    print("fp32: %.1f matvec/s, rel err vs fp64 %.2e" % (value32, err32), file=sys.stderr, flush=True)
+
+    # the same product with the far-block chain on a second stream
+    op.set_concurrency(True)
+    yc = torch.empty_like(x)
+    for _ in range(args.warmup):
+        op.matvec(x, out=yc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        op.matvec(x, out=yc)
+    torch.cuda.synchronize()
+    value_conc = args.steps / (time.perf_counter() - t0)
+    same = bool(torch.equal(yc, y))
+    op.set_concurrency(False)
+    print("fp64 concurrent far block: %.1f matvec/s (identical result: %s)" % (value_conc, same), file=sys.stderr,
+          flush=True)
+
+    return value32, err32, value_conc, same
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,7 +295,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--restart", type=int, default=50)
-    ap.add_argument("--max-iter", type=int, default=1000)
+    ap.add_argument("--max-iter", type=int, default=1000, help="iterations of the preconditioned solve")
+    ap.add_argument("--plain-max-iter", type=int, default=500, help="iterations of plain GMRES and mixed IR")
+    ap.add_argument("--only-fp64", action="store_true", help="skip the complex64 and concurrent-product runs")
     ap.add_argument("--calib-copy", action="store_true", help="run the copy used to scale HBM counters")
     ap.add_argument("--write-traffic", nargs=3, metavar=("KERNEL", "FETCH_DB", "WRITE_DB"),
                     help="write profiles/traffic_<KERNEL>_2mm.txt from two rocprofv3 --pmc databases")
@@ -324,35 +363,9 @@ def main():
     value = args.steps / el
     print("fp64: %.1f matvec/s (%.3f ms)" % (value, 1e3 * el / args.steps), file=sys.stderr, flush=True)
 
-    x32 = x.to(torch.complex64)
-    y32 = torch.empty_like(x32)
-    for _ in range(args.warmup):
-        op.matvec(x32, out=y32)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n32 = max(10, args.steps // 2)
-    for _ in range(n32):
-        op.matvec(x32, out=y32)
-    torch.cuda.synchronize()
-    value32 = n32 / (time.perf_counter() - t0)
-    err32 = float(torch.linalg.norm(y32.to(torch.complex128) - y) / torch.linalg.norm(y))
-    print("fp32: %.1f matvec/s, rel err vs fp64 %.2e" % (value32, err32), file=sys.stderr, flush=True)
-
-    # the same product with the far-block chain on a second stream
-    op.set_concurrency(True)
-    yc = torch.empty_like(x)
-    for _ in range(args.warmup):
-        op.matvec(x, out=yc)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        op.matvec(x, out=yc)
-    torch.cuda.synchronize()
-    value_conc = args.steps / (time.perf_counter() - t0)
-    same = bool(torch.equal(yc, y))
-    op.set_concurrency(False)
-    print("fp64 concurrent far block: %.1f matvec/s (identical result: %s)" % (value_conc, same), file=sys.stderr,
-          flush=True)
+    value32 = err32 = value_conc = same = None
+    if not args.only_fp64:
+        value32, err32, value_conc, same = other_precisions(op, x, y, args)
 
     per_stage = pre
     print("stage ms: %s" % json.dumps({k: round(v, 4) for k, v in per_stage.items()}), file=sys.stderr, flush=True)
@@ -372,27 +385,55 @@ def main():
 
     solve = {}
     if not args.no_solve:
-        # every port right-hand side, plain FP64 GMRES(restart) (Sec. IV-C uses restart 50)
         B = torch.stack([op.rhs(pt) for pt in range(op.n_ports)])
+        # far currents eliminated, reduced system right-preconditioned (block diagonal), GMRES(restart)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        X, sts = op.solve(B, tol=1e-6, restart=args.restart, max_iter=args.max_iter, allow_noconv=True)
+        sinfo = op.schur_setup(precond=True)
+        schur_setup_s = time.perf_counter() - t0
+        for _ in range(3):
+            op.schur_matvec(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            op.schur_matvec(x)
+        torch.cuda.synchronize()
+        red_ms = (time.perf_counter() - t0) / 20 * 1e3
+        t0 = time.perf_counter()
+        Xs, sts = op.solve(B, tol=1e-6, restart=args.restart, max_iter=args.max_iter, method=2, allow_noconv=True)
+        wall = time.perf_counter() - t0
+        its = [s_["iterations"] for s_ in sts]
+        conv = [s_["rel_residual"] <= 1e-6 for s_ in sts]
+        solve["schur_precond"] = dict(
+            method="far currents eliminated (Schur complement through the ACA/TT factors), GMRES on the reduced "
+                   "system right-preconditioned by its near-block inverse and the body diagonal",
+            restart=args.restart, max_iter=args.max_iter, ports=op.n_ports, setup_seconds=round(schur_setup_s, 3),
+            n_proxy=sinfo["n_proxy"], reduced_matvec_ms=round(red_ms, 4), seconds_total=round(wall, 3),
+            converged_ports=int(sum(conv)), mean_iterations=float(np.mean(its)),
+            max_rel_residual=float(max(s_["rel_residual"] for s_ in sts)),
+            ms_per_iteration=round(1e3 * sum(s_["seconds"] for s_ in sts) / max(1, sum(its)), 3),
+            time_to_1e6_mean_s=(round(float(np.mean([s_["seconds"] for s_ in sts])), 4) if all(conv) else None))
+        print("schur_precond: %s" % solve["schur_precond"], file=sys.stderr, flush=True)
+        # plain FP64 GMRES(restart) on the full system (Sec. IV-C uses restart 50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, sts = op.solve(B, tol=1e-6, restart=args.restart, max_iter=args.plain_max_iter, allow_noconv=True)
         wall = time.perf_counter() - t0
         its = [s_["iterations"] for s_ in sts]
         conv = [s_["rel_residual"] <= 1e-6 for s_ in sts]
         solve["gmres64"] = dict(
-            restart=args.restart, max_iter=args.max_iter, ports=op.n_ports, seconds_total=round(wall, 3),
+            restart=args.restart, max_iter=args.plain_max_iter, ports=op.n_ports, seconds_total=round(wall, 3),
             converged_ports=int(sum(conv)), mean_iterations=float(np.mean(its)),
             max_rel_residual=float(max(s_["rel_residual"] for s_ in sts)),
             ms_per_iteration=round(1e3 * sum(s_["seconds"] for s_ in sts) / max(1, sum(its)), 3),
             time_to_1e6_mean_s=(round(float(np.mean([s_["seconds"] for s_ in sts])), 3) if all(conv) else None))
         print("gmres64: %s" % solve["gmres64"], file=sys.stderr, flush=True)
-        xm, sm = op.solve(B[0], tol=1e-6, restart=args.restart, max_iter=args.max_iter, method=1, inner_tol=1e-3,
-                          allow_noconv=True)
-        diff = float(torch.linalg.norm(xm - X[0]) / torch.linalg.norm(X[0]))
+        xm, sm = op.solve(B[0], tol=1e-6, restart=args.restart, max_iter=args.plain_max_iter, method=1,
+                          inner_tol=1e-3, allow_noconv=True)
+        diff = float(torch.linalg.norm(xm - Xs[0]) / torch.linalg.norm(Xs[0]))
         solve["ir_mixed_port0"] = dict(seconds=round(sm[0]["seconds"], 3), inner_iterations=sm[0]["iterations"],
                                        fp64_steps=sm[0]["refinements"], rel_residual=sm[0]["rel_residual"],
-                                       converged=sm[0]["rel_residual"] <= 1e-6, rel_diff_vs_gmres64=diff)
+                                       converged=sm[0]["rel_residual"] <= 1e-6, rel_diff_vs_schur=diff)
         print("ir_mixed: %s" % solve["ir_mixed_port0"], file=sys.stderr, flush=True)
 
     cpu = None
@@ -439,8 +480,9 @@ def main():
                         "gbs": round(conv_b / (conv_ms * 1e-3) / 1e9, 1) if conv_ms else None},
         "stages": rl,
         "three_parts": three,
-        "c64": {"value": round(value32, 3), "unit": "matvec/s", "rel_err_vs_c128": err32},
-        "concurrent_far_block": {"value": round(value_conc, 3), "unit": "matvec/s", "identical_result": same},
+        "c64": {"value": round(value32, 3) if value32 else None, "unit": "matvec/s", "rel_err_vs_c128": err32},
+        "concurrent_far_block": {"value": round(value_conc, 3) if value_conc else None, "unit": "matvec/s",
+                                 "identical_result": same},
         "solve": solve,
         "setup_seconds": round(setup_s, 2),
         "cpu_baseline": cpu,
