@@ -131,9 +131,13 @@ void launch_schur_scatter(hipStream_t st, int K, int ka, const int r3[3], const 
 void launch_mul_diag(hipStream_t st, const cxd* x, const cxd* d, cxd* y, int64_t n);
 
 // solver
-void launch_multidot(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* w, int64_t n, cxd* part, int nblk);
+// part[blk][nvec (+3)]: partial V^H w, and with_norm the partial |w|^2 of [0, s1), [s1, s2), [s2, n)
+void launch_multidot(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* w, int64_t n, int64_t s1,
+                     int64_t s2, int with_norm, cxd* part, int nblk);
 void launch_sum_partials(hipStream_t st, const cxd* part, int nblk, int K, cxd* out);
-void launch_multiaxpy(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* h, cxd* w, int64_t n);
+// w -= V h (h on the device, nvec <= 1024) with part[blk][3] = partial |w|^2 of the three segments
+void launch_multiaxpy_norm(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* h, cxd* w, int64_t n,
+                          int64_t s1, int64_t s2, cxd* part, int nblk);
 void launch_combine_add(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* y, cxd* x, int64_t n);
 void launch_scale_copy(hipStream_t st, const cxd* a, double s, cxd* b, int64_t n);
 void launch_sub(hipStream_t st, const cxd* a, const cxd* b, cxd* c, int64_t n);

@@ -1594,24 +1594,30 @@ __global__ __launch_bounds__(256) void k_ttT_4(TTDesc<R> T, const cx<R>* __restr
 // partial sums of V[i]^H w for i < nvec: part[blk][nvec]. Grid-stride over rows; vectors in
 // groups of eight per block reduction (w is re-read per group from cache).
 __global__ __launch_bounds__(256) void k_multidot_partial(const cxd* __restrict__ V, int64_t ld, int nvec,
-                                                          const cxd* __restrict__ w, int64_t n, cxd* __restrict__ part) {
-  __shared__ double rr[8][4], ri[8][4];
+                                                          const cxd* __restrict__ w, int64_t n, int64_t s1, int64_t s2,
+                                                          int with_norm, cxd* __restrict__ part) {
+  constexpr int G = 8;
+  __shared__ double rr[G + 3][4], ri[G + 3][4];
   const int64_t stride = (int64_t)gridDim.x * 256;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  for (int i0 = 0; i0 < nvec; i0 += 8) {
-    const int g = nvec - i0 < 8 ? nvec - i0 : 8;
-    cxd acc[8];
+  const int K = nvec + (with_norm ? 3 : 0);
+  for (int i0 = 0; i0 < nvec || (i0 == 0 && with_norm); i0 += G) {
+    const int g = nvec - i0 < G ? nvec - i0 : G;
+    const bool nrm = with_norm && i0 == 0;
+    cxd acc[G];
+    double sq[3] = {0, 0, 0};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = cxd{0, 0};
+    for (int q = 0; q < G; ++q) acc[q] = cxd{0, 0};
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += stride) {
       const cxd wr = w[r];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
+      for (int q = 0; q < G; ++q)
         if (q < g) acc[q] += mul_conj_a(V[(int64_t)(i0 + q) * ld + r], wr);
+      if (nrm) sq[r < s1 ? 0 : (r < s2 ? 1 : 2)] += wr.re * wr.re + wr.im * wr.im;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      double re = acc[q].re, im = acc[q].im;
+    for (int q = 0; q < G + 3; ++q) {
+      double re = q < G ? acc[q].re : sq[q - G], im = q < G ? acc[q].im : 0.0;
       for (int off = 32; off > 0; off >>= 1) {
         re += __shfl_down(re, off, 64);
         im += __shfl_down(im, off, 64);
@@ -1622,22 +1628,43 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const cxd* __restrict_
       }
     }
     __syncthreads();
-    if (threadIdx.x < g)
-      part[(int64_t)blockIdx.x * nvec + i0 + threadIdx.x] =
-          cxd{(rr[threadIdx.x][0] + rr[threadIdx.x][1]) + (rr[threadIdx.x][2] + rr[threadIdx.x][3]),
-              (ri[threadIdx.x][0] + ri[threadIdx.x][1]) + (ri[threadIdx.x][2] + ri[threadIdx.x][3])};
+    const int t = threadIdx.x;
+    const auto sum4 = [&](int q) {
+      return cxd{(rr[q][0] + rr[q][1]) + (rr[q][2] + rr[q][3]), (ri[q][0] + ri[q][1]) + (ri[q][2] + ri[q][3])};
+    };
+    if (t < g) part[(int64_t)blockIdx.x * K + i0 + t] = sum4(t);
+    if (nrm && t >= 64 && t < 67) part[(int64_t)blockIdx.x * K + nvec + (t - 64)] = sum4(G + t - 64);
     __syncthreads();
   }
 }
 
-// w -= sum_i h[i] V[i]
-__global__ void k_multiaxpy(const cxd* __restrict__ V, int64_t ld, int nvec, const cxd* __restrict__ h,
-                            cxd* __restrict__ w, int64_t n) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  cxd acc = w[r];
-  for (int i = 0; i < nvec; ++i) acc -= h[i] * V[(int64_t)i * ld + r];
-  w[r] = acc;
+// w -= sum_i h[i] V[i], and per-block partial sums of |w|^2 over [0, s1), [s1, s2), [s2, n)
+// after the update (part[blk][3], real parts)
+__global__ __launch_bounds__(256) void k_multiaxpy_norm(const cxd* __restrict__ V, int64_t ld, int nvec,
+                                                        const cxd* __restrict__ h, cxd* __restrict__ w, int64_t n,
+                                                        int64_t s1, int64_t s2, cxd* __restrict__ part) {
+  __shared__ cxd hs[1024];
+  __shared__ double red[3][4];
+  for (int i = threadIdx.x; i < nvec; i += 256) hs[i] = h[i];
+  __syncthreads();
+  double sq[3] = {0, 0, 0};
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += stride) {
+    cxd acc = w[r];
+    for (int i = 0; i < nvec; ++i) acc -= hs[i] * V[(int64_t)i * ld + r];
+    w[r] = acc;
+    sq[r < s1 ? 0 : (r < s2 ? 1 : 2)] += acc.re * acc.re + acc.im * acc.im;
+  }
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  for (int s = 0; s < 3; ++s) {
+    double v = sq[s];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[s][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3)
+    part[(int64_t)blockIdx.x * 3 + threadIdx.x] =
+        cxd{(red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]), 0.0};
 }
 
 // x += sum_i y[i] V[i]
@@ -2123,14 +2150,17 @@ void launch_zbc_near(hipStream_t st, const RwgDev& B, const double* centres, con
     hipLaunchKernelGGL(k_zbc_near_pairs, dim3((unsigned)((np + 127) / 128)), dim3(128), 0, st, B, centres, pn, np, h, k, out);
 }
 
-void launch_multidot(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* w, int64_t n, cxd* part, int nblk) {
-  hipLaunchKernelGGL(k_multidot_partial, dim3(nblk), dim3(256), 0, st, V, ld, nvec, w, n, part);
+void launch_multidot(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* w, int64_t n, int64_t s1,
+                     int64_t s2, int with_norm, cxd* part, int nblk) {
+  hipLaunchKernelGGL(k_multidot_partial, dim3(nblk), dim3(256), 0, st, V, ld, nvec, w, n, s1, s2, with_norm, part);
 }
 void launch_sum_partials(hipStream_t st, const cxd* part, int nblk, int K, cxd* out) {
   if (K > 0) hipLaunchKernelGGL(k_sum_partials<double>, dim3(K), dim3(256), 0, st, part, nblk, K, out);
 }
-void launch_multiaxpy(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* h, cxd* w, int64_t n) {
-  hipLaunchKernelGGL(k_multiaxpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, V, ld, nvec, h, w, n);
+void launch_multiaxpy_norm(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* h, cxd* w, int64_t n,
+                          int64_t s1, int64_t s2, cxd* part, int nblk) {
+  if (nvec > 1024) throw Error(VSIE_E_ARG, "Krylov basis wider than 1024");
+  hipLaunchKernelGGL(k_multiaxpy_norm, dim3(nblk), dim3(256), 0, st, V, ld, nvec, h, w, n, s1, s2, part);
 }
 void launch_combine_add(hipStream_t st, const cxd* V, int64_t ld, int nvec, const cxd* y, cxd* x, int64_t n) {
   hipLaunchKernelGGL(k_combine_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, V, ld, nvec, y, x, n);

@@ -961,13 +961,21 @@ struct Solver {
   Handle& H;
   hipStream_t st;
   int64_t N;
-  cxd* part;     // multidot partials
+  cxd* part;     // multidot partials [MDOT_BLK][MAX_BASIS + 3]
+  cxd* sum;      // their sums (h, then the segment norms)
+  cxd* npart2;   // norm partials of the update [NB2][3]
+  cxd* nsum;
   double* npart;
   static constexpr int NBLK = 256;
   static constexpr int MDOT_BLK = 1024;
+  static constexpr int NB2 = 1024;
   static constexpr int MAX_BASIS = 1024;
+  static int64_t work_elems() { return (int64_t)MDOT_BLK * (MAX_BASIS + 3) + (MAX_BASIS + 3) + 3 * NB2 + 3; }
   Solver(Handle& h, hipStream_t s) : H(h), st(s), N(h.N) {
     part = H.d_solve_work;
+    sum = part + (int64_t)MDOT_BLK * (MAX_BASIS + 3);
+    npart2 = sum + MAX_BASIS + 3;
+    nsum = npart2 + 3 * NB2;
     npart = H.d_red;
   }
   void norms(const cxd* a, double out[4]) {
@@ -983,34 +991,32 @@ struct Solver {
     out[2] = sqrt(s[2]);
     out[3] = sqrt(s[0] + s[1] + s[2]);
   }
-  // h = V^H w for the first nvec basis vectors (partials per block, summed on the device)
-  void dots(const cxd* V, int nvec, const cxd* w, std::vector<cxd>& h) {
-    cxd* sum = part + (int64_t)MDOT_BLK * MAX_BASIS;
-    launch_multidot(st, V, N, nvec, w, N, part, MDOT_BLK);
-    launch_sum_partials(st, part, MDOT_BLK, nvec, sum);
-    h.resize(nvec);
-    VSIE_HIP(hipMemcpyAsync(h.data(), sum, sizeof(cxd) * nvec, hipMemcpyDeviceToHost, st));
-    VSIE_HIP(hipStreamSynchronize(st));
-  }
-  // classical Gram-Schmidt of w against V[0..nvec), repeated once when the first pass removed more
-  // than 1 - 1/sqrt(2) of the norm of w (DGKS criterion); h receives the projection
-  // coefficients, the return value is ||w|| afterwards
-  double orthogonalize(const cxd* V, int nvec, cxd* w, cxd* hvec_dev, std::vector<cxd>& h) {
-    double n0[4], n1[4];
-    norms(w, n0);
-    dots(V, nvec, w, h);
-    VSIE_HIP(hipMemcpyAsync(hvec_dev, h.data(), sizeof(cxd) * nvec, hipMemcpyHostToDevice, st));
-    launch_multiaxpy(st, V, N, nvec, hvec_dev, w, N);
-    norms(w, n1);
-    if (n1[3] < 0.70710678118654752 * n0[3]) {
-      std::vector<cxd> h2;
-      dots(V, nvec, w, h2);
-      VSIE_HIP(hipMemcpyAsync(hvec_dev, h2.data(), sizeof(cxd) * nvec, hipMemcpyHostToDevice, st));
-      launch_multiaxpy(st, V, N, nvec, hvec_dev, w, N);
-      for (int i = 0; i < nvec; ++i) h[i] += h2[i];
-      norms(w, n1);
+  // Classical Gram-Schmidt of w against V[0..nvec): one pass forms h = V^H w (with the segment
+  // norms of w on the first pass), a second applies w -= V h with the device copy of h and forms
+  // the norms of the result; repeated once when the first pass removed more than 1 - 1/sqrt(2) of
+  // the norm of w (DGKS criterion). One host synchronisation per pass. h receives the projection
+  // coefficients; the return value is ||w|| afterwards.
+  double orthogonalize(const cxd* V, int nvec, cxd* w, std::vector<cxd>& h) {
+    if (nvec > MAX_BASIS) throw Error(VSIE_E_ARG, "Krylov basis larger than 1024 vectors");
+    const int64_t s1 = H.mf, s2 = (int64_t)H.mf + H.mn;
+    h.assign(nvec, cxd{0, 0});
+    double n0 = 0, n1 = 0;
+    std::vector<cxd> hh(MAX_BASIS + 3), nn(3);
+    for (int pass = 0; pass < 2; ++pass) {
+      const int K = nvec + (pass == 0 ? 3 : 0);
+      launch_multidot(st, V, N, nvec, w, N, s1, s2, pass == 0, part, MDOT_BLK);
+      launch_sum_partials(st, part, MDOT_BLK, K, sum);
+      launch_multiaxpy_norm(st, V, N, nvec, sum, w, N, s1, s2, npart2, NB2);
+      launch_sum_partials(st, npart2, NB2, 3, nsum);
+      VSIE_HIP(hipMemcpyAsync(hh.data(), sum, sizeof(cxd) * K, hipMemcpyDeviceToHost, st));
+      VSIE_HIP(hipMemcpyAsync(nn.data(), nsum, sizeof(cxd) * 3, hipMemcpyDeviceToHost, st));
+      VSIE_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < nvec; ++i) h[i] += hh[i];
+      if (pass == 0) n0 = sqrt(hh[nvec].re + hh[nvec + 1].re + hh[nvec + 2].re);
+      n1 = sqrt(nn[0].re + nn[1].re + nn[2].re);
+      if (n1 >= 0.70710678118654752 * n0) break;
     }
-    return n1[3];
+    return n1;
   }
   // solve A x = b to relative residual tol (x initialised to zero). Returns iterations used.
   template <typename MV>
@@ -1044,7 +1050,7 @@ struct Solver {
       bool done = false;
       for (int j = 0; j < restart; ++j) {
         A(Vbuf + (int64_t)j * N, w);
-        double nw[4] = {0, 0, 0, orthogonalize(Vbuf, j + 1, w, hvec_dev, h)};
+        double nw[4] = {0, 0, 0, orthogonalize(Vbuf, j + 1, w, h)};
         for (int i = 0; i <= j; ++i) Hm[(size_t)i * restart + j] = h[i];
         Hm[(size_t)(j + 1) * restart + j] = {nw[3], 0};
         if (nw[3] > 0) launch_scale_copy(st, w, 1.0 / nw[3], Vbuf + (int64_t)(j + 1) * N, N);
@@ -1121,7 +1127,7 @@ struct Solver {
         cxd* z = Zb + (int64_t)j * N;
         budget = P(Vb + (int64_t)j * N, z);
         A(z, w);
-        double nw[4] = {0, 0, 0, orthogonalize(Vb, j + 1, w, hvec_dev, h)};
+        double nw[4] = {0, 0, 0, orthogonalize(Vb, j + 1, w, h)};
         for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h[i];
         Hm[(size_t)(j + 1) * m + j] = {nw[3], 0};
         if (nw[3] > 0) launch_scale_copy(st, w, 1.0 / nw[3], Vb + (int64_t)(j + 1) * N, N);
@@ -1158,7 +1164,7 @@ struct Solver {
 
 void ensure_solver_ws(Handle& H, int restart) {
   if (!H.d_solve_work) {
-    H.d_solve_work = H.dalloc<cxd>((int64_t)(Solver::MDOT_BLK + 1) * Solver::MAX_BASIS);
+    H.d_solve_work = H.dalloc<cxd>(Solver::work_elems());
     H.d_red = H.dalloc<double>(256 * 4);
   }
   if (H.krylov_cols < restart + 1) {
