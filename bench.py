@@ -364,8 +364,23 @@ def main():
     print("fp64: %.1f matvec/s (%.3f ms)" % (value, 1e3 * el / args.steps), file=sys.stderr, flush=True)
 
     value32 = err32 = value_conc = same = None
+    batched = None
     if not args.only_fp64:
         value32, err32, value_conc, same = other_precisions(op, x, y, args)
+        # eight right-hand sides per call: the far block is read once per four of them
+        X8 = torch.stack([torch.from_numpy(synth.complex_normal(op.N, 2000 + s)) for s in range(8)]).cuda()
+        Y8 = torch.empty_like(X8)
+        for _ in range(2):
+            op.matvec(X8, out=Y8)
+        torch.cuda.synchronize()
+        nb = max(5, args.steps // 8)
+        t0 = time.perf_counter()
+        for _ in range(nb):
+            op.matvec(X8, out=Y8)
+        torch.cuda.synchronize()
+        batched = dict(nrhs=8, value=round(8 * nb / (time.perf_counter() - t0), 3), unit="RHS matvec/s",
+                       dtype="c128")
+        print("fp64 batched: %s" % batched, file=sys.stderr, flush=True)
 
     per_stage = pre
     print("stage ms: %s" % json.dumps({k: round(v, 4) for k, v in per_stage.items()}), file=sys.stderr, flush=True)
@@ -483,6 +498,7 @@ def main():
         "c64": {"value": round(value32, 3) if value32 else None, "unit": "matvec/s", "rel_err_vs_c128": err32},
         "concurrent_far_block": {"value": round(value_conc, 3) if value_conc else None, "unit": "matvec/s",
                                  "identical_result": same},
+        "batched_rhs": batched,
         "solve": solve,
         "setup_seconds": round(setup_s, 2),
         "cpu_baseline": cpu,

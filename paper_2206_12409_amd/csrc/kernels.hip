@@ -1295,6 +1295,91 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const cx<R>* __restrict__ Zp
   }
 }
 
+// The same tile pass for NB right-hand sides at once (column b of x at x + b ldx): every tile is
+// read once for all of them and yields NB row-sum and column-sum partials (column b at
+// part + b ldp). Per right-hand side the arithmetic and its order are those of k_symv_tiles.
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_symv_multi(const cx<R>* __restrict__ Zp, const int* __restrict__ tiles,
+                                                    const cx<R>* __restrict__ x, int64_t ldx, int m, int64_t ntiles,
+                                                    cx<R>* __restrict__ part, int64_t ldp) {
+  __shared__ R cr[4][SYM_TB], ci[4][SYM_TB];
+  __shared__ cx<R> xs[NB][SYM_TB];
+  const int cg = threadIdx.x % 32, rg = threadIdx.x / 32;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int I = tiles[2 * t], J = tiles[2 * t + 1];
+    const cx<R>* Z = Zp + t * (int64_t)SYM_TB * SYM_TB;
+    if (threadIdx.x < SYM_TB) {
+      const int mm = I * SYM_TB + threadIdx.x;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) xs[b][threadIdx.x] = mm < m ? x[b * ldx + mm] : cx<R>{0, 0};
+    }
+    cx<R> xJ[NB][4], ca[NB][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int n = J * SYM_TB + cg + 32 * c;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        xJ[b][c] = n < m ? x[b * ldx + n] : cx<R>{0, 0};
+        ca[b][c] = {0, 0};
+      }
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int r = 0; r < 16; ++r) {
+      const int row = rg * 16 + r;
+      const cx<R>* zr = Z + (int64_t)row * SYM_TB + cg;
+      cx<R> rd[NB], xi[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        xi[b] = xs[b][row];
+        rd[b] = {0, 0};
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const cx<R> z = ld_stream(zr + 32 * c);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          rd[b] += z * xJ[b][c];
+          ca[b][c] += z * xi[b];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        for (int off = 16; off > 0; off >>= 1) {
+          rd[b].re += __shfl_xor(rd[b].re, off, 32);
+          rd[b].im += __shfl_xor(rd[b].im, off, 32);
+        }
+        if (cg == 0) part[b * ldp + t * 2 * SYM_TB + row] = rd[b];
+      }
+    }
+    if (I != J) {
+      const int wave = threadIdx.x / 64;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          ca[b][c].re += __shfl_xor(ca[b][c].re, 32, 64);
+          ca[b][c].im += __shfl_xor(ca[b][c].im, 32, 64);
+        }
+        if ((threadIdx.x % 64) < 32)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            cr[wave][cg + 32 * c] = ca[b][c].re;
+            ci[wave][cg + 32 * c] = ca[b][c].im;
+          }
+        __syncthreads();
+        if (threadIdx.x < SYM_TB) {
+          const int c = threadIdx.x;
+          part[b * ldp + t * 2 * SYM_TB + SYM_TB + c] =
+              cx<R>{cr[0][c] + cr[1][c] + cr[2][c] + cr[3][c], ci[0][c] + ci[1][c] + ci[2][c] + ci[3][c]};
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();   // xs is rewritten by the next tile
+  }
+}
+
 // y[i] = sum_{J >= I} rowpart(I, J)[i] + sum_{J < I} colpart(J, I)[i], I = i / SYM_TB; a block
 // covers 64 outputs with four wavefronts taking every fourth J (fixed order)
 template <typename R>
@@ -1891,6 +1976,20 @@ template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, co
   const int64_t nt = (int64_t)T * (T + 1) / 2;
   hipLaunchKernelGGL(k_symv_tiles<R>, dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, m, nt, part);
 }
+template <typename R> void launch_symv_multi(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
+                                             int64_t ldx, int m, int nrhs, cx<R>* part, int64_t ldp) {
+  const int64_t nt = (int64_t)T * (T + 1) / 2;
+  if (nrhs == 4)
+    hipLaunchKernelGGL((k_symv_multi<R, 4>), dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, ldx, m, nt, part, ldp);
+  else if (nrhs == 3)
+    hipLaunchKernelGGL((k_symv_multi<R, 3>), dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, ldx, m, nt, part, ldp);
+  else if (nrhs == 2)
+    hipLaunchKernelGGL((k_symv_multi<R, 2>), dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, ldx, m, nt, part, ldp);
+  else if (nrhs == 1)
+    hipLaunchKernelGGL((k_symv_multi<R, 1>), dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, ldx, m, nt, part, ldp);
+  else
+    throw Error(VSIE_E_ARG, "symv_multi takes 1 to 4 right-hand sides");
+}
 template <typename R> void launch_symv_reduce(hipStream_t st, const cx<R>* part, int T, int m, cx<R>* y) {
   hipLaunchKernelGGL(k_symv_reduce<R>, dim3((m + 63) / 64), dim3(256), 0, st, part, T, m, y, 0);
 }
@@ -2098,7 +2197,9 @@ void launch_mul_diag(hipStream_t st, const cxd* x, const cxd* d, cxd* y, int64_t
                                           cx<R>*, const cx<R>*);                                                \
   template void launch_scatter_rhs<R>(hipStream_t, const int*, const double*, const double*, int, cx<R>*);         \
   template void launch_symv_tiles<R>(hipStream_t, const cx<R>*, const int*, int, const cx<R>*, int, cx<R>*);      \
-  template void launch_symv_reduce<R>(hipStream_t, const cx<R>*, int, int, cx<R>*);
+  template void launch_symv_reduce<R>(hipStream_t, const cx<R>*, int, int, cx<R>*);                                            \
+  template void launch_symv_multi<R>(hipStream_t, const cx<R>*, const int*, int, const cx<R>*, int64_t, int, int, cx<R>*, \
+                                     int64_t);
 VSIE_INST(double)
 VSIE_INST(float)
 

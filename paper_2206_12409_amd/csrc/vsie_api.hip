@@ -638,7 +638,9 @@ static void volume_chain(Handle& H, OpData<R>& D, const cx<R>* xn, const cx<R>* 
   }
 }
 
-template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t st) {
+// far_done: y_f already holds Z_ff x_f (the batched tile pass of vsie_matvec)
+template <typename R>
+void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t st, bool far_done = false) {
   if (H.concurrent && !H.side) make_streams(H);
   // far-block chain: the second stream when concurrent, else the caller's stream after the
   // volume chain
@@ -664,12 +666,14 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
     }
   // dense far block (writes y_f), then the parts of the TT coupling that read only x
   auto far_chain = [&]() {
-    T.begin(8, fs);
-    launch_symv_tiles<R>(fs, D.Zff, H.d_tiles, H.sym_T, xf, mf, D.sym_part);
-    T.end(8, fs);
-    T.begin(12, fs);
-    launch_symv_reduce<R>(fs, D.sym_part, H.sym_T, mf, yf);
-    T.end(12, fs);
+    if (!far_done) {
+      T.begin(8, fs);
+      launch_symv_tiles<R>(fs, D.Zff, H.d_tiles, H.sym_T, xf, mf, D.sym_part);
+      T.end(8, fs);
+      T.begin(12, fs);
+      launch_symv_reduce<R>(fs, D.sym_part, H.sym_T, mf, yf);
+      T.end(12, fs);
+    }
     if (have_tt) {
       T.begin(11, fs);
       launch_tt_pre<R>(fs, td, H.n, mf, xf, xb, H.d_mask, D.tt_work);
@@ -709,6 +713,26 @@ template <typename R> void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, c
     T.end(13);
   }
   T.collect();
+}
+
+// nrhs products: the dense far block, the largest operand, is read once per group of up to four
+// right-hand sides (each tile yields the partial sums of every column of the group); the rest
+// of each product runs per column.
+template <typename R> void matvec_batch(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, int nrhs, hipStream_t st) {
+  constexpr int kGroup = 4;
+  const int64_t N = H.N;
+  const bool batched = nrhs > 1 && H.mf > 0;
+  if (batched) {
+    const int64_t nt = (int64_t)H.sym_T * (H.sym_T + 1) / 2;
+    const int64_t ldp = nt * 2 * SYM_TB;
+    if (!D.multi_part) D.multi_part = H.dalloc<cx<R>>(kGroup * ldp);
+    for (int c0 = 0; c0 < nrhs; c0 += kGroup) {
+      const int nb = std::min(kGroup, nrhs - c0);
+      launch_symv_multi<R>(st, D.Zff, H.d_tiles, H.sym_T, x + c0 * N, N, H.mf, nb, D.multi_part, ldp);
+      for (int b = 0; b < nb; ++b) launch_symv_reduce<R>(st, D.multi_part + b * ldp, H.sym_T, H.mf, y + (c0 + b) * N);
+    }
+  }
+  for (int c = 0; c < nrhs; ++c) matvec_one<R>(H, D, x + c * N, y + c * N, st, batched);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1427,15 +1451,13 @@ int vsie_matvec(vsie_handle* hd, int dtype, int nrhs, const void* x_dev, void* y
   Handle& H = hd->H;
   return guarded([&]() {
     hipStream_t st = (hipStream_t)stream;
-    for (int c = 0; c < nrhs; ++c) {
-      if (dtype == VSIE_C128) {
-        matvec_one<double>(H, H.d64, (const cxd*)x_dev + c * H.N, (cxd*)y_dev + c * H.N, st);
-      } else if (dtype == VSIE_C64) {
-        if (!H.have32) throw Error(VSIE_E_STATE, "complex64 operator data not built");
-        matvec_one<float>(H, H.d32, (const cxf*)x_dev + c * H.N, (cxf*)y_dev + c * H.N, st);
-      } else {
-        throw Error(VSIE_E_ARG, "bad dtype");
-      }
+    if (dtype == VSIE_C128) {
+      matvec_batch<double>(H, H.d64, (const cxd*)x_dev, (cxd*)y_dev, nrhs, st);
+    } else if (dtype == VSIE_C64) {
+      if (!H.have32) throw Error(VSIE_E_STATE, "complex64 operator data not built");
+      matvec_batch<float>(H, H.d32, (const cxf*)x_dev, (cxf*)y_dev, nrhs, st);
+    } else {
+      throw Error(VSIE_E_ARG, "bad dtype");
     }
     VSIE_HIP(hipGetLastError());
   });

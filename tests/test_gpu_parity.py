@@ -113,6 +113,20 @@ def test_batched_columns_match(small):
         assert rel(Y[c], S_same.matvec(X[c])) < 1e-10
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batched_far_block_matches_single_columns(small, dtype):
+    """Six right-hand sides (groups of four and two in the batched far-block pass) give the
+    single-column products."""
+    p, op, d, _, S_same, _ = small
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    X = to_dev(np.stack([synth.complex_normal(op.N, 10 + s) for s in range(6)]), tdt)
+    Y = op.matvec(X)
+    for c in range(6):
+        y1 = op.matvec(X[c].contiguous())
+        e = float(torch.linalg.norm(Y[c] - y1) / torch.linalg.norm(y1))
+        assert e <= (1e-14 if dtype == "c128" else 1e-6)
+
+
 def test_complex64_matvec_error(small):
     """complex64 storage and FP32 arithmetic: error against the FP64 oracle stated and bounded."""
     p, op, d, _, S_same, _ = small
