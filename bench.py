@@ -298,6 +298,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=1000, help="iterations of the preconditioned solve")
     ap.add_argument("--plain-max-iter", type=int, default=500, help="iterations of plain GMRES and mixed IR")
     ap.add_argument("--only-fp64", action="store_true", help="skip the complex64 and concurrent-product runs")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="set up, then only the preconditioned far-eliminated solve of every port (for profiling)")
     ap.add_argument("--calib-copy", action="store_true", help="run the copy used to scale HBM counters")
     ap.add_argument("--write-traffic", nargs=3, metavar=("KERNEL", "FETCH_DB", "WRITE_DB"),
                     help="write profiles/traffic_<KERNEL>_2mm.txt from two rocprofv3 --pmc databases")
@@ -335,6 +337,17 @@ def main():
     info["n"] = tuple(int(v) for v in problem.grid.n)
     print("setup %.1f s: %s" % (setup_s, json.dumps(info)), file=sys.stderr, flush=True)
 
+    if args.solve_only:
+        B = torch.stack([op.rhs(pt) for pt in range(op.n_ports)])
+        sinfo = op.schur_setup(precond=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, sts = op.solve(B, tol=1e-6, restart=args.restart, max_iter=args.max_iter, method=2, allow_noconv=True)
+        wall = time.perf_counter() - t0
+        print(json.dumps({"solve_only": dict(ports=op.n_ports, seconds=round(wall, 3), n_proxy=sinfo["n_proxy"],
+                                             iterations=[s_["iterations"] for s_ in sts],
+                                             converged=all(s_["rel_residual"] <= 1e-6 for s_ in sts))}), flush=True)
+        return
     if args.calib_copy:
         copy_calibration()
     x = torch.from_numpy(synth.complex_normal(op.N, 1234)).cuda()
