@@ -169,7 +169,9 @@ int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, v
  * by the block-diagonal operator of vsie_schur_precond; the far currents are recovered afterwards.
  * The residual test is on the full system's relative residual.
  * x_dev receives complex128. Blocks.
- * Allocates its work vectors (IR_MIXED: 41 FP64 vectors of length N besides the Krylov basis).
+ * The Krylov basis and work vectors hold only the unknowns that couple (far and near currents,
+ * tissue voxels): air voxels carry identity rows and columns, so their solution is b there.
+ * Allocates its work vectors (IR_MIXED: 41 FP64 vectors of that length besides the basis).
  * stats (array of nrhs, may be NULL) are filled even on E_NOCONV. */
 int vsie_solve(struct vsie_handle* h, const vsie_solve_opts* opts, int nrhs, const void* b_dev,
                void* x_dev, vsie_solve_stats* stats, void* stream);

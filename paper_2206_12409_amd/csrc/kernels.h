@@ -133,6 +133,8 @@ void launch_schur_gather(hipStream_t st, int K, int ka, const int r3[3], const c
 void launch_schur_scatter(hipStream_t st, int K, int ka, const int r3[3], const cxd* in, double sign, cxd* pa,
                           cxd* p3);
 void launch_mul_diag(hipStream_t st, const cxd* x, const cxd* d, cxd* y, int64_t n);
+void launch_gather_idx(hipStream_t st, const cxd* src, const int* idx, int64_t n, cxd* dst);
+void launch_scatter_idx(hipStream_t st, const cxd* src, const int* idx, int64_t n, cxd* dst);
 
 // solver
 // part[blk][nvec (+3)]: partial V^H w, and with_norm the partial |w|^2 of [0, s1), [s1, s2), [s2, n)

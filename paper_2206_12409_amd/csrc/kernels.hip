@@ -2126,6 +2126,17 @@ __global__ void k_schur_scatter(int K, int ka, int r30, int r31, const cxd* __re
   }
 }
 
+// dst[i] = src[idx[i]] and dst[idx[i]] = src[i]: the unknowns that couple (conductor currents
+// and tissue voxels) packed into and out of a compact vector
+__global__ void k_gather_idx(const cxd* __restrict__ src, const int* __restrict__ idx, int64_t n, cxd* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+__global__ void k_scatter_idx(const cxd* __restrict__ src, const int* __restrict__ idx, int64_t n, cxd* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[idx[i]] = src[i];
+}
+
 // y = d * x elementwise
 __global__ void k_mul_diag(const cxd* __restrict__ x, const cxd* __restrict__ d, cxd* __restrict__ y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2170,6 +2181,12 @@ void launch_schur_gather(hipStream_t st, int K, int ka, const int r3[3], const c
 void launch_schur_scatter(hipStream_t st, int K, int ka, const int r3[3], const cxd* in, double sign, cxd* pa,
                           cxd* p3) {
   if (K > 0) hipLaunchKernelGGL(k_schur_scatter, dim3((K + 255) / 256), dim3(256), 0, st, K, ka, r3[0], r3[1], in, sign, pa, p3);
+}
+void launch_gather_idx(hipStream_t st, const cxd* src, const int* idx, int64_t n, cxd* dst) {
+  if (n > 0) hipLaunchKernelGGL(k_gather_idx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, idx, n, dst);
+}
+void launch_scatter_idx(hipStream_t st, const cxd* src, const int* idx, int64_t n, cxd* dst) {
+  if (n > 0) hipLaunchKernelGGL(k_scatter_idx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, idx, n, dst);
 }
 void launch_mul_diag(hipStream_t st, const cxd* x, const cxd* d, cxd* y, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_mul_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, d, y, n);

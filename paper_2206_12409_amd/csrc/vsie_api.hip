@@ -752,6 +752,9 @@ struct Scratch {
       throw Error(VSIE_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     }
   }
+  Scratch(Scratch&& o) noexcept : p(o.p) { o.p = nullptr; }
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
   ~Scratch() {
     if (p) (void)hipFree(p);
   }
@@ -995,15 +998,16 @@ struct Solver {
   static constexpr int NB2 = 1024;
   static constexpr int MAX_BASIS = 1024;
   static int64_t work_elems() { return (int64_t)MDOT_BLK * (MAX_BASIS + 3) + (MAX_BASIS + 3) + 3 * NB2 + 3; }
-  Solver(Handle& h, hipStream_t s) : H(h), st(s), N(h.N) {
+  Solver(Handle& h, hipStream_t s) : H(h), st(s), N(h.n_active) {
     part = H.d_solve_work;
     sum = part + (int64_t)MDOT_BLK * (MAX_BASIS + 3);
     npart2 = sum + MAX_BASIS + 3;
     nsum = npart2 + 3 * NB2;
     npart = H.d_red;
   }
-  void norms(const cxd* a, double out[4]) {
-    launch_norm_partial(st, a, N, H.mf, (int64_t)H.mf + H.mn, npart, NBLK);
+  // segment norms (far, near, body) and the total of a compact (n < 0) or full-length vector
+  void norms(const cxd* a, double out[4], int64_t n = -1) {
+    launch_norm_partial(st, a, n < 0 ? N : n, H.mf, (int64_t)H.mf + H.mn, npart, NBLK);
     std::vector<double> p(3 * NBLK);
     VSIE_HIP(hipMemcpyAsync(p.data(), npart, sizeof(double) * 3 * NBLK, hipMemcpyDeviceToHost, st));
     VSIE_HIP(hipStreamSynchronize(st));
@@ -1191,35 +1195,50 @@ void ensure_solver_ws(Handle& H, int restart) {
     H.d_solve_work = H.dalloc<cxd>(Solver::work_elems());
     H.d_red = H.dalloc<double>(256 * 4);
   }
+  if (!H.d_active) {
+    std::vector<int> act;
+    act.reserve((size_t)H.mf + H.mn + 3 * H.tissue.size());
+    for (int i = 0; i < H.mf + H.mn; ++i) act.push_back(i);
+    for (int c = 0; c < 3; ++c)
+      for (int p = 0; p < H.nv; ++p)
+        if (H.chi[p].re != 0 || H.chi[p].im != 0) act.push_back((int)(H.mf + H.mn + (int64_t)c * H.nv + p));
+    H.n_active = (int64_t)act.size();
+    H.d_active = upload(H, act);
+    for (auto& v : H.d_full) v = H.dalloc<cxd>(H.N);
+    VSIE_HIP(hipMemset(H.d_full[0], 0, sizeof(cxd) * H.N));
+  }
   if (H.krylov_cols < restart + 1) {
     if (H.d_krylov) {
       auto it = std::find(H.allocations.begin(), H.allocations.end(), (void*)H.d_krylov);
       if (it != H.allocations.end()) H.allocations.erase(it);
-      H.device_bytes -= (int64_t)sizeof(cxd) * H.krylov_cols * H.N;
+      H.device_bytes -= (int64_t)sizeof(cxd) * H.krylov_cols * H.n_active;
       VSIE_HIP(hipFree(H.d_krylov));
       H.d_krylov = nullptr;
     }
-    H.d_krylov = H.dalloc<cxd>((int64_t)(restart + 1) * H.N);
+    H.d_krylov = H.dalloc<cxd>((int64_t)(restart + 1) * H.n_active);
     H.krylov_cols = restart + 1;
   }
 }
 
 // GMRES on the reduced system (far currents eliminated), right-preconditioned when the
-// preconditioner is built: solve (A_S M) u = b_r - Z_rf Z_ff^-1 b_f, x_r = M u, then recover
-// x_f = Z_ff^-1 (b_f - L t(x_r)). Returns the iterations.
-int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, const cxd* b, cxd* x, cxd* w, cxd* hv, int* restarts,
-                double* rel, hipStream_t st) {
+// preconditioner is built: solve (A_S M) u = b_r - Z_rf Z_ff^-1 b_f on the compact unknowns,
+// x_r = M u, then recover x_f = Z_ff^-1 (b_f - L t(x_r)); air voxels take x = b. bc, uc, wc:
+// compact work vectors. Returns the iterations.
+int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, const cxd* b, cxd* x, cxd* bc, cxd* uc, cxd* wc,
+                cxd* hv, int* restarts, double* rel, hipStream_t st) {
   Handle::Schur& Sc = H.schur;
   OpData<double>& D = H.d64;
-  const int64_t N = H.N;
+  const int64_t N = H.N, Nc = H.n_active;
   const int mf = H.mf, mn = H.mn, K = Sc.K, ka = aca_rank(H);
   TTDesc<double> td;
   int r3[3];
   tt_desc(H, D, td, r3);
   cxd* bred = Sc.vec[0];
   cxd* tmp = Sc.vec[1];
+  cxd* fin = H.d_full[0];
+  cxd* fout = H.d_full[1];
   double nb[4], nbr[4];
-  S.norms(b, nb);
+  S.norms(b, nb, N);
   const bool bf = mf > 0 && nb[0] > 0;
   VSIE_HIP(hipMemcpyAsync(bred, b, sizeof(cxd) * N, hipMemcpyDeviceToDevice, st));
   if (mf) VSIE_HIP(hipMemsetAsync(bred, 0, sizeof(cxd) * mf, st));
@@ -1233,15 +1252,22 @@ int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, const cxd* b, c
       inject_proxies(H, Sc.pa, Sc.p3, bred + mf, bred + mf + mn, st);
     }
   }
-  S.norms(bred, nbr);
+  launch_gather_idx(st, bred, H.d_active, Nc, bc);
+  S.norms(bc, nbr);
   const double tol = nbr[3] > 0 ? so.tol * nb[3] / nbr[3] : so.tol;
   auto AM = [&](const cxd* in, cxd* out) {
-    precond_apply(H, in, tmp, st);
-    matvec_schur(H, tmp, out, st);
+    launch_scatter_idx(st, in, H.d_active, Nc, fin);
+    precond_apply(H, fin, tmp, st);
+    matvec_schur(H, tmp, fout, st);
+    launch_gather_idx(st, fout, H.d_active, Nc, out);
   };
-  const int it = S.gmres(AM, bred, x, tol, so.restart, so.max_iter, restarts, rel, H.d_krylov, w, hv);
-  precond_apply(H, x, tmp, st);
-  VSIE_HIP(hipMemcpyAsync(x, tmp, sizeof(cxd) * N, hipMemcpyDeviceToDevice, st));
+  const int it = S.gmres(AM, bc, uc, tol, so.restart, so.max_iter, restarts, rel, H.d_krylov, wc, hv);
+  // x = M u on the coupled unknowns, b on the air voxels
+  launch_scatter_idx(st, uc, H.d_active, Nc, fin);
+  precond_apply(H, fin, tmp, st);
+  launch_gather_idx(st, tmp, H.d_active, Nc, wc);
+  VSIE_HIP(hipMemcpyAsync(x, b, sizeof(cxd) * N, hipMemcpyDeviceToDevice, st));
+  launch_scatter_idx(st, wc, H.d_active, Nc, x);
   if (mf) {
     if (bf) VSIE_HIP(hipMemcpyAsync(x, Sc.zf, sizeof(cxd) * mf, hipMemcpyDeviceToDevice, st));
     if (K) {
@@ -1477,33 +1503,45 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
   int rc = guarded([&]() {
     hipStream_t st = (hipStream_t)stream;
     ensure_solver_ws(H, so.restart);
-    const int64_t N = H.N;
-    cxd* w = nullptr;
-    cxd* r = nullptr;
-    cxd* d = nullptr;
+    // Krylov work runs on the compact vector of coupled unknowns (conductor currents and tissue
+    // voxels; air voxels decouple with identity rows and columns and take x = b); products
+    // scatter into and gather from full-length vectors
+    const int64_t N = H.N, Nc = H.n_active;
+    std::vector<Scratch> bufs;
+    auto vec = [&](int64_t n, size_t elem) { bufs.emplace_back(elem * (size_t)n); return bufs.back().p; };
+    bufs.reserve(12);
+    cxd* wc = (cxd*)vec(Nc, sizeof(cxd));
+    cxd* bc = (cxd*)vec(Nc, sizeof(cxd));
+    cxd* xc = (cxd*)vec(Nc, sizeof(cxd));
+    cxd* dc = (cxd*)vec(Nc, sizeof(cxd));
+    cxd* r = (cxd*)vec(N, sizeof(cxd));
+    cxd* hv = (cxd*)vec(1100, sizeof(cxd));
     cxf* x32 = nullptr;
     cxf* y32 = nullptr;
-    cxd* hv = nullptr;
-    VSIE_HIP(hipMalloc(&w, sizeof(cxd) * N));
-    VSIE_HIP(hipMalloc(&r, sizeof(cxd) * N));
-    VSIE_HIP(hipMalloc(&d, sizeof(cxd) * N));
-    VSIE_HIP(hipMalloc(&hv, sizeof(cxd) * 1100));
     cxd* Vout = nullptr;
     cxd* Zout = nullptr;
     cxd* hv2 = nullptr;
     if (so.method == VSIE_IR_MIXED) {
-      VSIE_HIP(hipMalloc(&x32, sizeof(cxf) * N));
-      VSIE_HIP(hipMalloc(&y32, sizeof(cxf) * N));
-      VSIE_HIP(hipMalloc(&Vout, sizeof(cxd) * N * (IR_OUTER_M + 1)));
-      VSIE_HIP(hipMalloc(&Zout, sizeof(cxd) * N * IR_OUTER_M));
-      VSIE_HIP(hipMalloc(&hv2, sizeof(cxd) * 1100));
+      x32 = (cxf*)vec(N, sizeof(cxf));
+      y32 = (cxf*)vec(N, sizeof(cxf));
+      Vout = (cxd*)vec(Nc * (IR_OUTER_M + 1), sizeof(cxd));
+      Zout = (cxd*)vec(Nc * IR_OUTER_M, sizeof(cxd));
+      hv2 = (cxd*)vec(1100, sizeof(cxd));
     }
+    cxd* fin = H.d_full[0];
+    cxd* fout = H.d_full[1];
     Solver S(H, st);
-    auto A64 = [&](const cxd* in, cxd* out) { matvec_one<double>(H, H.d64, in, out, st); };
+    auto A64 = [&](const cxd* in, cxd* out) {
+      launch_scatter_idx(st, in, H.d_active, Nc, fin);
+      matvec_one<double>(H, H.d64, fin, fout, st);
+      launch_gather_idx(st, fout, H.d_active, Nc, out);
+    };
     auto A32 = [&](const cxd* in, cxd* out) {
-      launch_d2f(st, in, x32, N);
+      launch_scatter_idx(st, in, H.d_active, Nc, fin);
+      launch_d2f(st, fin, x32, N);
       matvec_one<float>(H, H.d32, x32, y32, st);
-      launch_f2d(st, y32, out, N);
+      launch_f2d(st, y32, fout, N);
+      launch_gather_idx(st, fout, H.d_active, Nc, out);
     };
     if (so.method == VSIE_SCHUR) setup_schur(H, so.precond != 0);
     for (int c = 0; c < nrhs; ++c) {
@@ -1513,29 +1551,35 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       vsie_solve_stats s;
       std::memset(&s, 0, sizeof(s));
       double rel = 0;
-      if (so.method == VSIE_GMRES64) {
-        s.iterations = S.gmres(A64, b, x, so.tol, so.restart, so.max_iter, &s.restarts, &rel, H.d_krylov, w, hv);
-      } else if (so.method == VSIE_SCHUR) {
-        s.iterations = solve_schur(H, S, so, b, x, w, hv, &s.restarts, &rel, st);
+      if (so.method == VSIE_SCHUR) {
+        s.iterations = solve_schur(H, S, so, b, x, bc, xc, wc, hv, &s.restarts, &rel, st);
       } else {
-        int total = 0;
-        // preconditioner: at most one cycle (restart iterations) of complex64 GMRES on Z z = v
-        auto P32 = [&](const cxd* v, cxd* z) {
-          double inner_rel = 0;
-          int used = S.gmres(A32, v, z, so.inner_tol, so.restart, std::max(1, std::min(so.restart, so.max_iter - total)),
-                             &s.restarts, &inner_rel, H.d_krylov, d, hv2);
-          total += used;
-          return total < so.max_iter;
-        };
-        S.fgmres(A64, P32, b, x, so.tol, IR_OUTER_M, &s.refinements, &rel, Vout, Zout, w, hv);
-        s.iterations = total;
+        launch_gather_idx(st, b, H.d_active, Nc, bc);
+        if (so.method == VSIE_GMRES64) {
+          s.iterations = S.gmres(A64, bc, xc, so.tol, so.restart, so.max_iter, &s.restarts, &rel, H.d_krylov, wc, hv);
+        } else {
+          int total = 0;
+          // preconditioner: at most one cycle (restart iterations) of complex64 GMRES on Z z = v
+          auto P32 = [&](const cxd* v, cxd* z) {
+            double inner_rel = 0;
+            int used = S.gmres(A32, v, z, so.inner_tol, so.restart,
+                               std::max(1, std::min(so.restart, so.max_iter - total)), &s.restarts, &inner_rel,
+                               H.d_krylov, dc, hv2);
+            total += used;
+            return total < so.max_iter;
+          };
+          S.fgmres(A64, P32, bc, xc, so.tol, IR_OUTER_M, &s.refinements, &rel, Vout, Zout, wc, hv);
+          s.iterations = total;
+        }
+        VSIE_HIP(hipMemcpyAsync(x, b, sizeof(cxd) * N, hipMemcpyDeviceToDevice, st));
+        launch_scatter_idx(st, xc, H.d_active, Nc, x);
       }
-      // true FP64 residual and per-block residuals
-      A64(x, w);
-      launch_sub(st, b, w, r, N);
+      // true FP64 residual of the full system and per-block residuals
+      matvec_one<double>(H, H.d64, x, fout, st);
+      launch_sub(st, b, fout, r, N);
       double nr[4], nb[4];
-      S.norms(r, nr);
-      S.norms(b, nb);
+      S.norms(r, nr, N);
+      S.norms(b, nb, N);
       s.rel_residual = nb[3] > 0 ? nr[3] / nb[3] : 0;
       for (int q = 0; q < 3; ++q) s.block_residual[q] = nb[3] > 0 ? nr[q] / nb[3] : 0;
       VSIE_HIP(hipStreamSynchronize(st));
@@ -1543,15 +1587,7 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       if (s.rel_residual > so.tol) status = VSIE_E_NOCONV;
       if (stats) stats[c] = s;
     }
-    (void)hipFree(w);
-    (void)hipFree(r);
-    (void)hipFree(d);
-    (void)hipFree(hv);
-    if (x32) (void)hipFree(x32);
-    if (y32) (void)hipFree(y32);
-    if (Vout) (void)hipFree(Vout);
-    if (Zout) (void)hipFree(Zout);
-    if (hv2) (void)hipFree(hv2);
+    VSIE_HIP(hipStreamSynchronize(st));
   });
   if (rc != VSIE_OK) return rc;
   if (status != VSIE_OK) return fail(status, "solver did not reach the requested tolerance");

@@ -152,6 +152,11 @@ struct Handle {
   OpData<float> d32;
   bool have32 = false;
   // GMRES workspace (lazily sized)
+  // unknowns that couple (conductor currents, tissue voxels), in unknown order: the Krylov vectors
+  // hold only these (air voxels carry identity rows and columns and decouple)
+  int* d_active = nullptr;
+  int64_t n_active = 0;
+  cxd* d_full[2] = {};         // full-length product input (zero at air voxels) and output
   cxd* d_krylov = nullptr;
   int64_t krylov_cols = 0;
   cxd* d_solve_work = nullptr;
