@@ -115,12 +115,12 @@ typedef struct {
   double tol;                 /* relative residual ||b - Ax|| / ||b||, default 1e-6 */
   int32_t restart;            /* GMRES restart length, default 50 (Sec. IV-C) */
   int32_t max_iter;           /* GMRES64: iterations; IR_MIXED: total inner complex64 iterations */
-  int32_t method;             /* VSIE_GMRES64, VSIE_IR_MIXED or VSIE_SCHUR */
+  int32_t method;             /* VSIE_GMRES64, VSIE_IR_MIXED, VSIE_SCHUR or VSIE_SCHUR_MIXED */
   double inner_tol;           /* IR_MIXED: inner complex64 solve tolerance, default 1e-3 */
   int32_t precond;            /* SCHUR: 1 (default) right-preconditions the reduced system, 0 none */
 } vsie_solve_opts;
 
-enum vsie_method { VSIE_GMRES64 = 0, VSIE_IR_MIXED = 1, VSIE_SCHUR = 2 };
+enum vsie_method { VSIE_GMRES64 = 0, VSIE_IR_MIXED = 1, VSIE_SCHUR = 2, VSIE_SCHUR_MIXED = 3 };
 
 typedef struct {
   int32_t iterations;         /* Krylov iterations (IR_MIXED: inner complex64 iterations) */
@@ -168,6 +168,9 @@ int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, v
  * runs on the reduced system (near currents and body) with zero initial guess, right-preconditioned
  * by the block-diagonal operator of vsie_schur_precond; the far currents are recovered afterwards.
  * The residual test is on the full system's relative residual.
+ * SCHUR_MIXED: the same reduced, preconditioned system solved as IR_MIXED does: FP64 flexible
+ * GMRES (20 steps per cycle) whose preconditioner is one complex64 GMRES cycle on the complex64
+ * reduced operator (iterations count the inner ones, refinements the FP64 steps).
  * x_dev receives complex128. Blocks.
  * The Krylov basis and work vectors hold only the unknowns that couple (far and near currents,
  * tissue voxels): air voxels carry identity rows and columns, so their solution is b there.
@@ -199,7 +202,8 @@ int vsie_export(const struct vsie_handle* h, int what, int index, void* host, si
 
 /* Replace a compressed block with stored data (the "store and recycle" use of the compressed
  * coupling, Sec. VI): VSIE_X_TT_CORES (one component per call) or VSIE_X_ACA, same layout as
- * vsie_export. Errors: E_ARG (size mismatch). */
+ * vsie_export. Errors: E_ARG (size mismatch), E_STATE (after vsie_schur_setup, whose matrices
+ * were formed from the factors in place). */
 int vsie_import(struct vsie_handle* h, int what, int index, const void* host, size_t nbytes);
 
 /* Concurrency of one product: enable != 0 runs the far-block chain (gemv_far, gemv_far_reduce,

@@ -126,13 +126,14 @@ void launch_set_identity(hipStream_t st, cxd* X, int n);
 void launch_unpack_sym(hipStream_t st, const cxd* Zp, int T, int m, cxd* out);
 void launch_pack_sym(hipStream_t st, const cxd* X, int m, const int* tiles, int64_t ntiles, cxd* Zp);
 void launch_build_far_factors(hipStream_t st, const cxd* V, int ka, const TTDesc<double>& T, int mf, int K, cxd* L);
-void launch_schur_apply(hipStream_t st, const cxd* S, int K, int ka, const int r3[3], const cxd* ta, const cxd* s3,
-                        double sign, cxd* pa, cxd* p3);
+template <typename R>
+void launch_schur_apply(hipStream_t st, const cx<R>* S, int K, int ka, const int r3[3], const cx<R>* ta,
+                        const cx<R>* s3, R sign, cx<R>* pa, cx<R>* p3);
 void launch_schur_gather(hipStream_t st, int K, int ka, const int r3[3], const cxd* ta, const cxd* s3, double sign,
                          cxd* out);
 void launch_schur_scatter(hipStream_t st, int K, int ka, const int r3[3], const cxd* in, double sign, cxd* pa,
                           cxd* p3);
-void launch_mul_diag(hipStream_t st, const cxd* x, const cxd* d, cxd* y, int64_t n);
+template <typename R> void launch_mul_diag(hipStream_t st, const cx<R>* x, const cx<R>* d, cx<R>* y, int64_t n);
 void launch_gather_idx(hipStream_t st, const cxd* src, const int* idx, int64_t n, cxd* dst);
 void launch_scatter_idx(hipStream_t st, const cxd* src, const int* idx, int64_t n, cxd* dst);
 

@@ -2058,10 +2058,12 @@ __global__ void k_build_far_factors(const cxd* __restrict__ V, int ka, TTDesc<do
 // p = sign * S t, t = [ta (ka values) | s3[0][0..r3_0) | s3[1][..] | s3[2][..]] (s3 rows of
 // length TT_RMAX); p is scattered the same way into pa and p3. One wavefront per row of S.
 constexpr int SCHUR_KMAX = 256 + 3 * TT_RMAX;
-__global__ __launch_bounds__(256) void k_schur_apply(const cxd* __restrict__ S, int K, int ka, int r30, int r31,
-                                                     int r32, const cxd* __restrict__ ta, const cxd* __restrict__ s3,
-                                                     double sign, cxd* __restrict__ pa, cxd* __restrict__ p3) {
-  __shared__ cxd t[SCHUR_KMAX];
+template <typename R>
+__global__ __launch_bounds__(256) void k_schur_apply(const cx<R>* __restrict__ S, int K, int ka, int r30, int r31,
+                                                     int r32, const cx<R>* __restrict__ ta,
+                                                     const cx<R>* __restrict__ s3, R sign, cx<R>* __restrict__ pa,
+                                                     cx<R>* __restrict__ p3) {
+  __shared__ cx<R> t[SCHUR_KMAX];
   for (int l = threadIdx.x; l < K; l += 256) {
     if (l < ka) {
       t[l] = ta[l];
@@ -2075,7 +2077,7 @@ __global__ __launch_bounds__(256) void k_schur_apply(const cxd* __restrict__ S, 
   __syncthreads();
   const int row = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
   if (row >= K) return;
-  cxd acc = {0, 0};
+  cx<R> acc = {0, 0};
   for (int m = lane; m < K; m += 64) acc += S[(int64_t)row * K + m] * t[m];
   for (int off = 32; off > 0; off >>= 1) {
     acc.re += __shfl_xor(acc.re, off, 64);
@@ -2138,7 +2140,8 @@ __global__ void k_scatter_idx(const cxd* __restrict__ src, const int* __restrict
 }
 
 // y = d * x elementwise
-__global__ void k_mul_diag(const cxd* __restrict__ x, const cxd* __restrict__ d, cxd* __restrict__ y, int64_t n) {
+template <typename R>
+__global__ void k_mul_diag(const cx<R>* __restrict__ x, const cx<R>* __restrict__ d, cx<R>* __restrict__ y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = d[i] * x[i];
 }
@@ -2167,11 +2170,12 @@ void launch_build_far_factors(hipStream_t st, const cxd* V, int ka, const TTDesc
   if (n > 0)
     hipLaunchKernelGGL(k_build_far_factors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, V, ka, T, mf, K, L);
 }
-void launch_schur_apply(hipStream_t st, const cxd* S, int K, int ka, const int r3[3], const cxd* ta, const cxd* s3,
-                        double sign, cxd* pa, cxd* p3) {
+template <typename R>
+void launch_schur_apply(hipStream_t st, const cx<R>* S, int K, int ka, const int r3[3], const cx<R>* ta,
+                        const cx<R>* s3, R sign, cx<R>* pa, cx<R>* p3) {
   if (K > SCHUR_KMAX) throw Error(VSIE_E_ARG, "more than " + std::to_string(SCHUR_KMAX) + " far-coupling proxies");
   if (K > 0)
-    hipLaunchKernelGGL(k_schur_apply, dim3((K + 3) / 4), dim3(256), 0, st, S, K, ka, r3[0], r3[1], r3[2], ta, s3, sign,
+    hipLaunchKernelGGL(k_schur_apply<R>, dim3((K + 3) / 4), dim3(256), 0, st, S, K, ka, r3[0], r3[1], r3[2], ta, s3, sign,
                        pa, p3);
 }
 void launch_schur_gather(hipStream_t st, int K, int ka, const int r3[3], const cxd* ta, const cxd* s3, double sign,
@@ -2188,9 +2192,15 @@ void launch_gather_idx(hipStream_t st, const cxd* src, const int* idx, int64_t n
 void launch_scatter_idx(hipStream_t st, const cxd* src, const int* idx, int64_t n, cxd* dst) {
   if (n > 0) hipLaunchKernelGGL(k_scatter_idx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, idx, n, dst);
 }
-void launch_mul_diag(hipStream_t st, const cxd* x, const cxd* d, cxd* y, int64_t n) {
-  if (n > 0) hipLaunchKernelGGL(k_mul_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, d, y, n);
+template <typename R> void launch_mul_diag(hipStream_t st, const cx<R>* x, const cx<R>* d, cx<R>* y, int64_t n) {
+  if (n > 0) hipLaunchKernelGGL(k_mul_diag<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, d, y, n);
 }
+template void launch_schur_apply<double>(hipStream_t, const cxd*, int, int, const int[3], const cxd*, const cxd*,
+                                         double, cxd*, cxd*);
+template void launch_schur_apply<float>(hipStream_t, const cxf*, int, int, const int[3], const cxf*, const cxf*, float,
+                                        cxf*, cxf*);
+template void launch_mul_diag<double>(hipStream_t, const cxd*, const cxd*, cxd*, int64_t);
+template void launch_mul_diag<float>(hipStream_t, const cxf*, const cxf*, cxf*, int64_t);
 
 #define VSIE_INST(R)                                                                                                  \
   template void launch_build_grid<R>(hipStream_t, const cx<R>*, const cx<R>*, const uint8_t*, const int*, const int*, \

@@ -761,7 +761,7 @@ struct Scratch {
   template <typename T> T* as() const { return (T*)p; }
 };
 
-static bool tt_desc(const Handle& H, const OpData<double>& D, TTDesc<double>& td, int r3[3]) {
+template <typename R> static bool tt_desc(const Handle& H, const OpData<R>& D, TTDesc<R>& td, int r3[3]) {
   const bool have = H.mf && D.G12[0] && D.G12[1] && D.G12[2];
   for (int c = 0; c < 3; ++c) {
     td.M[c] = D.G12[c];
@@ -774,6 +774,10 @@ static bool tt_desc(const Handle& H, const OpData<double>& D, TTDesc<double>& td
   return have;
 }
 static int aca_rank(const Handle& H) { return (H.mf > 0 && H.mn > 0 && H.aca_k > 0) ? H.aca_k : 0; }
+static OpData<double>& opdata(Handle& H, double) { return H.d64; }
+static OpData<float>& opdata(Handle& H, float) { return H.d32; }
+static Handle::SchurOp<double>& schurop(Handle& H, double) { return H.schur.d64; }
+static Handle::SchurOp<float>& schurop(Handle& H, float) { return H.schur.d32; }
 
 // C (M x N) = A B with explicit element strides (row, column) of each operand
 static void gemm_strided(hipStream_t st, int M, int N, int K, const cxd* A, int64_t sar, int64_t sac, const cxd* B,
@@ -787,76 +791,79 @@ static void gemm_strided(hipStream_t st, int M, int N, int K, const cxd* A, int6
 }
 
 // y_n += U p_a and y_b += forward TT chain of p3 (eqs. (16)-(17) from the rank-r3 stage on)
-static void inject_proxies(Handle& H, const cxd* pa, const cxd* p3, cxd* yn, cxd* yb, hipStream_t st) {
-  OpData<double>& D = H.d64;
-  TTDesc<double> td;
+template <typename R>
+static void inject_proxies(Handle& H, const cx<R>* pa, const cx<R>* p3, cx<R>* yn, cx<R>* yb, hipStream_t st) {
+  OpData<R>& D = opdata(H, R());
+  TTDesc<R> td;
   int r3[3];
   const bool have_tt = tt_desc(H, D, td, r3);
   const int ka = aca_rank(H);
-  if (ka) launch_lr_n_add<double>(st, false, D.U, pa, H.mn, ka, yn);
+  if (ka) launch_lr_n_add<R>(st, false, D.U, pa, H.mn, ka, yn);
   if (have_tt) {
-    launch_tt_forward_from<double>(st, td, H.n, H.mf, p3, D.tt_work);
-    launch_tt_forward_post<double>(st, td, H.n, H.mf, H.d_mask, yb, D.tt_work);
+    launch_tt_forward_from<R>(st, td, H.n, H.mf, p3, D.tt_work);
+    launch_tt_forward_post<R>(st, td, H.n, H.mf, H.d_mask, yb, D.tt_work);
   }
 }
 
 // ta = U^T x_n and s3 (start of the TT work buffer) = transpose TT chain of x_b: the proxies t(x_r)
-static void far_proxies(Handle& H, const cxd* xn, const cxd* xb, hipStream_t st) {
-  OpData<double>& D = H.d64;
-  TTDesc<double> td;
+template <typename R> static void far_proxies(Handle& H, const cx<R>* xn, const cx<R>* xb, hipStream_t st) {
+  OpData<R>& D = opdata(H, R());
+  TTDesc<R> td;
   int r3[3];
   const bool have_tt = tt_desc(H, D, td, r3);
   const int ka = aca_rank(H);
-  if (ka) launch_lr_t<double>(st, false, D.U, xn, H.mn, ka, D.small_work, 512, H.schur.ta);
-  if (have_tt) launch_tt_transpose_pre<double>(st, td, H.n, H.mf, xb, H.d_mask, D.tt_work);
+  if (ka) launch_lr_t<R>(st, false, D.U, xn, H.mn, ka, D.small_work, 512, schurop(H, R()).ta);
+  if (have_tt) launch_tt_transpose_pre<R>(st, td, H.n, H.mf, xb, H.d_mask, D.tt_work);
 }
 
 // Reduced product y_r = Z_rr x_r - R^T S t(x_r) on the near and body unknowns (x_f is not read,
-// y_f is set to zero).
-static void matvec_schur(Handle& H, const cxd* x, cxd* y, hipStream_t st) {
-  OpData<double>& D = H.d64;
-  Handle::Schur& Sc = H.schur;
+// y_f is set to zero), in FP64 or complex64.
+template <typename R> static void matvec_schur(Handle& H, const cx<R>* x, cx<R>* y, hipStream_t st) {
+  OpData<R>& D = opdata(H, R());
+  Handle::SchurOp<R>& P = schurop(H, R());
+  const int K = H.schur.K;
   StageTimer T(H, st);
   const int mf = H.mf, mn = H.mn;
-  const cxd* xn = x + mf;
-  const cxd* xb = x + mf + mn;
-  cxd* yn = y + mf;
-  cxd* yb = y + mf + mn;
-  volume_chain<double>(H, D, mn ? xn : nullptr, xb, yn, yb, st, T);
+  const cx<R>* xn = x + mf;
+  const cx<R>* xb = x + mf + mn;
+  cx<R>* yn = y + mf;
+  cx<R>* yb = y + mf + mn;
+  volume_chain<R>(H, D, mn ? xn : nullptr, xb, yn, yb, st, T);
   T.begin(9);
-  launch_csr_add<double>(st, H.d_pc_rowid, H.d_pc_rowptr, H.d_pc_col, D.pc_val, x, y, H.n_pcrows);
+  launch_csr_add<R>(st, H.d_pc_rowid, H.d_pc_rowptr, H.d_pc_col, D.pc_val, x, y, H.n_pcrows);
   T.end(9);
-  if (Sc.K > 0) {
+  if (K > 0) {
     T.begin(10);
-    far_proxies(H, xn, xb, st);
-    TTDesc<double> td;
+    far_proxies<R>(H, xn, xb, st);
+    TTDesc<R> td;
     int r3[3];
     tt_desc(H, D, td, r3);
-    launch_schur_apply(st, Sc.S, Sc.K, aca_rank(H), r3, Sc.ta, D.tt_work, -1.0, Sc.pa, Sc.p3);
-    inject_proxies(H, Sc.pa, Sc.p3, yn, yb, st);
+    launch_schur_apply<R>(st, P.S, K, aca_rank(H), r3, P.ta, D.tt_work, (R)-1, P.pa, P.p3);
+    inject_proxies<R>(H, P.pa, P.p3, yn, yb, st);
     T.end(10);
   }
-  if (mf) VSIE_HIP(hipMemsetAsync(y, 0, sizeof(cxd) * mf, st));
+  if (mf) VSIE_HIP(hipMemsetAsync(y, 0, sizeof(cx<R>) * mf, st));
   T.collect();
 }
 
 // Right preconditioner of the reduced system: the inverse of its near block (direct Galerkin
 // entries of the near coils minus the eliminated far block's ACA term) on the near currents, the
 // inverse diagonal on the body unknowns, zero on the far currents. Identity when not built.
-static void precond_apply(Handle& H, const cxd* v, cxd* w, hipStream_t st) {
+template <typename R> static void precond_apply(Handle& H, const cx<R>* v, cx<R>* w, hipStream_t st) {
   Handle::Schur& Sc = H.schur;
+  Handle::SchurOp<R>& P = schurop(H, R());
   const int mf = H.mf, mn = H.mn;
   if (!Sc.precond) {
-    VSIE_HIP(hipMemcpyAsync(w, v, sizeof(cxd) * H.N, hipMemcpyDeviceToDevice, st));
-    if (mf) VSIE_HIP(hipMemsetAsync(w, 0, sizeof(cxd) * mf, st));
+    VSIE_HIP(hipMemcpyAsync(w, v, sizeof(cx<R>) * H.N, hipMemcpyDeviceToDevice, st));
+    if (mf) VSIE_HIP(hipMemsetAsync(w, 0, sizeof(cx<R>) * mf, st));
     return;
   }
-  if (mf) VSIE_HIP(hipMemsetAsync(w, 0, sizeof(cxd) * mf, st));
+  if (mf) VSIE_HIP(hipMemsetAsync(w, 0, sizeof(cx<R>) * mf, st));
   if (mn) {
-    launch_symv_tiles<double>(st, Sc.Xn, Sc.d_tiles_n, Sc.Tn, v + mf, mn, Sc.part_n);
-    launch_symv_reduce<double>(st, Sc.part_n, Sc.Tn, mn, w + mf);
+    launch_symv_tiles<R>(st, P.Xn, Sc.d_tiles_n, Sc.Tn, v + mf, mn, P.part_n);
+    launch_symv_reduce<R>(st, P.part_n, Sc.Tn, mn, w + mf);
   }
-  launch_mul_diag(st, v + mf + mn, Sc.invdiag, w + mf + mn, 3LL * H.nv);
+  launch_mul_diag<R>(st, v + mf + mn, P.invdiag, w + mf + mn, 3LL * H.nv);
 }
 
 static std::vector<int> upper_tiles(int T) {
@@ -882,9 +889,9 @@ static void setup_schur(Handle& H, bool precond) {
   if (!Sc.ready) {
     Sc.K = mf ? ka + r3[0] + r3[1] + r3[2] : 0;
     if (Sc.K > 256 + 3 * TT_RMAX) throw Error(VSIE_E_ARG, "too many far-coupling proxies");
-    Sc.ta = H.dalloc<cxd>(256);
-    Sc.pa = H.dalloc<cxd>(256);
-    Sc.p3 = H.dalloc<cxd>(3 * TT_RMAX);
+    Sc.d64.ta = H.dalloc<cxd>(256);
+    Sc.d64.pa = H.dalloc<cxd>(256);
+    Sc.d64.p3 = H.dalloc<cxd>(3 * TT_RMAX);
     Sc.tc = H.dalloc<cxd>(std::max(Sc.K, 1));
     for (auto& v : Sc.vec) v = H.dalloc<cxd>(H.N);
     if (mf) {
@@ -912,8 +919,8 @@ static void setup_schur(Handle& H, bool precond) {
         VSIE_HIP(hipMemcpyAsync(Sc.W, L.p, sizeof(cxd) * mf * K, hipMemcpyDeviceToDevice, st));
         lu_solve(st, F, Sc.W, K, K, Wt.as<cxd>());
         // S = L^T W
-        Sc.S = H.dalloc<cxd>((int64_t)K * K);
-        gemm_strided(st, K, K, mf, L.as<cxd>(), 1, K, Sc.W, K, 1, Sc.S, K, 1, 0, 0);
+        Sc.d64.S = H.dalloc<cxd>((int64_t)K * K);
+        gemm_strided(st, K, K, mf, L.as<cxd>(), 1, K, Sc.W, K, 1, Sc.d64.S, K, 1, 0, 0);
         VSIE_HIP(hipGetLastError());
         VSIE_HIP(hipStreamSynchronize(st));
       }
@@ -927,7 +934,7 @@ static void setup_schur(Handle& H, bool precond) {
       launch_zcc_dense(st, H.dnear, H.dnear, H.k0, 0, mn, Zn.as<cxd>());
       if (ka && Sc.K > 0) {
         Scratch T1(sizeof(cxd) * mn * ka);
-        gemm_strided(st, mn, ka, ka, D.U, 1, mn, Sc.S, Sc.K, 1, T1.as<cxd>(), ka, 1, 0, 0);
+        gemm_strided(st, mn, ka, ka, D.U, 1, mn, Sc.d64.S, Sc.K, 1, T1.as<cxd>(), ka, 1, 0, 0);
         gemm_strided(st, mn, mn, ka, T1.as<cxd>(), ka, 1, D.U, mn, 1, Zn.as<cxd>(), mn, 1, 1, 1);
         VSIE_HIP(hipStreamSynchronize(st));
       }
@@ -953,9 +960,9 @@ static void setup_schur(Handle& H, bool precond) {
       const std::vector<int> tiles = upper_tiles(Sc.Tn);
       const int64_t nt = (int64_t)tiles.size() / 2;
       Sc.d_tiles_n = upload(H, tiles);
-      Sc.Xn = H.dalloc<cxd>(nt * SYM_TB * SYM_TB);
-      Sc.part_n = H.dalloc<cxd>(nt * 2 * SYM_TB);
-      launch_pack_sym(st, X.as<cxd>(), mn, Sc.d_tiles_n, nt, Sc.Xn);
+      Sc.d64.Xn = H.dalloc<cxd>(nt * SYM_TB * SYM_TB);
+      Sc.d64.part_n = H.dalloc<cxd>(nt * 2 * SYM_TB);
+      launch_pack_sym(st, X.as<cxd>(), mn, Sc.d_tiles_n, nt, Sc.d64.Xn);
       VSIE_HIP(hipGetLastError());
       VSIE_HIP(hipStreamSynchronize(st));
     }
@@ -968,8 +975,29 @@ static void setup_schur(Handle& H, bool precond) {
     for (int p = 0; p < H.nv; ++p)
       if (H.chi[p].re != 0 || H.chi[p].im != 0)
         for (int a = 0; a < 3; ++a) inv[(size_t)a * H.nv + p] = cinv(h3 * cinv(H.chi[p]) + h3 * T0[a]);
-    Sc.invdiag = upload_cx<double>(H, inv);
+    Sc.d64.invdiag = upload_cx<double>(H, inv);
     Sc.precond = true;
+  }
+  // complex64 copies for the mixed-precision solve
+  if (H.have32 && !Sc.d32.ta) {
+    Sc.d32.ta = H.dalloc<cxf>(256);
+    Sc.d32.pa = H.dalloc<cxf>(256);
+    Sc.d32.p3 = H.dalloc<cxf>(3 * TT_RMAX);
+    if (Sc.K > 0) {
+      Sc.d32.S = H.dalloc<cxf>((int64_t)Sc.K * Sc.K);
+      launch_d2f(st, Sc.d64.S, Sc.d32.S, (int64_t)Sc.K * Sc.K);
+    }
+  }
+  if (H.have32 && Sc.precond && !Sc.d32.invdiag) {
+    if (mn) {
+      const int64_t nt = (int64_t)Sc.Tn * (Sc.Tn + 1) / 2;
+      Sc.d32.Xn = H.dalloc<cxf>(nt * SYM_TB * SYM_TB);
+      Sc.d32.part_n = H.dalloc<cxf>(nt * 2 * SYM_TB);
+      launch_d2f(st, Sc.d64.Xn, Sc.d32.Xn, nt * SYM_TB * SYM_TB);
+    }
+    Sc.d32.invdiag = H.dalloc<cxf>(3LL * H.nv);
+    launch_d2f(st, Sc.d64.invdiag, Sc.d32.invdiag, 3LL * H.nv);
+    VSIE_HIP(hipStreamSynchronize(st));
   }
   Sc.seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -1220,12 +1248,21 @@ void ensure_solver_ws(Handle& H, int restart) {
   }
 }
 
+// Work buffers of the solvers: compact vectors (coupled unknowns) and, for the mixed-precision
+// methods, the flexible-GMRES bases and full-length complex64 product vectors.
+struct SolveWork {
+  cxd *wc, *bc, *xc, *dc, *hv, *hv2, *Vout, *Zout;
+  cxf *x32, *y32;
+};
+
 // GMRES on the reduced system (far currents eliminated), right-preconditioned when the
 // preconditioner is built: solve (A_S M) u = b_r - Z_rf Z_ff^-1 b_f on the compact unknowns,
-// x_r = M u, then recover x_f = Z_ff^-1 (b_f - L t(x_r)); air voxels take x = b. bc, uc, wc:
-// compact work vectors. Returns the iterations.
-int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, const cxd* b, cxd* x, cxd* bc, cxd* uc, cxd* wc,
-                cxd* hv, int* restarts, double* rel, hipStream_t st) {
+// x_r = M u, then recover x_f = Z_ff^-1 (b_f - L t(x_r)); air voxels take x = b.
+// mixed: FP64 flexible GMRES whose preconditioner is one complex64 GMRES cycle on the complex64
+// reduced operator (at most `restart` iterations, stopping at inner_tol). Returns the iterations
+// (inner ones when mixed); *outer receives the FP64 flexible steps.
+int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, bool mixed, const cxd* b, cxd* x,
+                const SolveWork& ws, int* restarts, int* outer, double* rel, hipStream_t st) {
   Handle::Schur& Sc = H.schur;
   OpData<double>& D = H.d64;
   const int64_t N = H.N, Nc = H.n_active;
@@ -1248,31 +1285,53 @@ int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, const cxd* b, c
     if (K) {
       // proxies of Z_ff^-1 b_f: L^T Z_ff^-1 b_f = W^T b_f, injected with a minus sign
       gemm_strided(st, K, 1, mf, Sc.W, 1, K, b, 1, 1, Sc.tc, 1, 1, 0, 0);
-      launch_schur_scatter(st, K, ka, r3, Sc.tc, -1.0, Sc.pa, Sc.p3);
-      inject_proxies(H, Sc.pa, Sc.p3, bred + mf, bred + mf + mn, st);
+      launch_schur_scatter(st, K, ka, r3, Sc.tc, -1.0, Sc.d64.pa, Sc.d64.p3);
+      inject_proxies<double>(H, Sc.d64.pa, Sc.d64.p3, bred + mf, bred + mf + mn, st);
     }
   }
-  launch_gather_idx(st, bred, H.d_active, Nc, bc);
-  S.norms(bc, nbr);
+  launch_gather_idx(st, bred, H.d_active, Nc, ws.bc);
+  S.norms(ws.bc, nbr);
   const double tol = nbr[3] > 0 ? so.tol * nb[3] / nbr[3] : so.tol;
   auto AM = [&](const cxd* in, cxd* out) {
     launch_scatter_idx(st, in, H.d_active, Nc, fin);
-    precond_apply(H, fin, tmp, st);
-    matvec_schur(H, tmp, fout, st);
+    precond_apply<double>(H, fin, tmp, st);
+    matvec_schur<double>(H, tmp, fout, st);
     launch_gather_idx(st, fout, H.d_active, Nc, out);
   };
-  const int it = S.gmres(AM, bc, uc, tol, so.restart, so.max_iter, restarts, rel, H.d_krylov, wc, hv);
+  int it = 0;
+  if (!mixed) {
+    it = S.gmres(AM, ws.bc, ws.xc, tol, so.restart, so.max_iter, restarts, rel, H.d_krylov, ws.wc, ws.hv);
+  } else {
+    // complex64 product of the preconditioned reduced operator on compact FP64 vectors
+    auto AM32 = [&](const cxd* in, cxd* out) {
+      launch_scatter_idx(st, in, H.d_active, Nc, fin);
+      launch_d2f(st, fin, ws.x32, N);
+      precond_apply<float>(H, ws.x32, ws.y32, st);
+      matvec_schur<float>(H, ws.y32, ws.x32, st);
+      launch_f2d(st, ws.x32, fout, N);
+      launch_gather_idx(st, fout, H.d_active, Nc, out);
+    };
+    auto P32 = [&](const cxd* v, cxd* z) {
+      double inner_rel = 0;
+      const int used = S.gmres(AM32, v, z, so.inner_tol, so.restart,
+                               std::max(1, std::min(so.restart, so.max_iter - it)), restarts, &inner_rel, H.d_krylov,
+                               ws.dc, ws.hv2);
+      it += used;
+      return it < so.max_iter;
+    };
+    S.fgmres(AM, P32, ws.bc, ws.xc, tol, IR_OUTER_M, outer, rel, ws.Vout, ws.Zout, ws.wc, ws.hv);
+  }
   // x = M u on the coupled unknowns, b on the air voxels
-  launch_scatter_idx(st, uc, H.d_active, Nc, fin);
-  precond_apply(H, fin, tmp, st);
-  launch_gather_idx(st, tmp, H.d_active, Nc, wc);
+  launch_scatter_idx(st, ws.xc, H.d_active, Nc, fin);
+  precond_apply<double>(H, fin, tmp, st);
+  launch_gather_idx(st, tmp, H.d_active, Nc, ws.wc);
   VSIE_HIP(hipMemcpyAsync(x, b, sizeof(cxd) * N, hipMemcpyDeviceToDevice, st));
-  launch_scatter_idx(st, wc, H.d_active, Nc, x);
+  launch_scatter_idx(st, ws.wc, H.d_active, Nc, x);
   if (mf) {
     if (bf) VSIE_HIP(hipMemcpyAsync(x, Sc.zf, sizeof(cxd) * mf, hipMemcpyDeviceToDevice, st));
     if (K) {
-      far_proxies(H, x + mf, x + mf + mn, st);
-      launch_schur_gather(st, K, ka, r3, Sc.ta, D.tt_work, -1.0, Sc.tc);
+      far_proxies<double>(H, x + mf, x + mf + mn, st);
+      launch_schur_gather(st, K, ka, r3, Sc.d64.ta, D.tt_work, -1.0, Sc.tc);
       launch_gemv_rows<double>(st, Sc.W, Sc.tc, mf, K, x, 1);
     }
   }
@@ -1496,8 +1555,9 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
   if (o) so = *o;
   else vsie_default_solve_opts(&so);
   if (so.restart < 1 || so.restart > 1000 || so.max_iter < 1 || !(so.tol > 0)) return fail(VSIE_E_ARG, "bad solve options");
-  if (so.method < VSIE_GMRES64 || so.method > VSIE_SCHUR) return fail(VSIE_E_ARG, "unknown solve method");
-  if (so.method == VSIE_IR_MIXED && !hd->H.have32) return fail(VSIE_E_STATE, "complex64 operator data not built");
+  if (so.method < VSIE_GMRES64 || so.method > VSIE_SCHUR_MIXED) return fail(VSIE_E_ARG, "unknown solve method");
+  if ((so.method == VSIE_IR_MIXED || so.method == VSIE_SCHUR_MIXED) && !hd->H.have32)
+    return fail(VSIE_E_STATE, "complex64 operator data not built");
   Handle& H = hd->H;
   int status = VSIE_OK;
   int rc = guarded([&]() {
@@ -1507,27 +1567,27 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
     // voxels; air voxels decouple with identity rows and columns and take x = b); products
     // scatter into and gather from full-length vectors
     const int64_t N = H.N, Nc = H.n_active;
+    const bool mixed = so.method == VSIE_IR_MIXED || so.method == VSIE_SCHUR_MIXED;
     std::vector<Scratch> bufs;
     auto vec = [&](int64_t n, size_t elem) { bufs.emplace_back(elem * (size_t)n); return bufs.back().p; };
     bufs.reserve(12);
-    cxd* wc = (cxd*)vec(Nc, sizeof(cxd));
-    cxd* bc = (cxd*)vec(Nc, sizeof(cxd));
-    cxd* xc = (cxd*)vec(Nc, sizeof(cxd));
-    cxd* dc = (cxd*)vec(Nc, sizeof(cxd));
+    SolveWork ws{};
+    ws.wc = (cxd*)vec(Nc, sizeof(cxd));
+    ws.bc = (cxd*)vec(Nc, sizeof(cxd));
+    ws.xc = (cxd*)vec(Nc, sizeof(cxd));
+    ws.dc = (cxd*)vec(Nc, sizeof(cxd));
     cxd* r = (cxd*)vec(N, sizeof(cxd));
-    cxd* hv = (cxd*)vec(1100, sizeof(cxd));
-    cxf* x32 = nullptr;
-    cxf* y32 = nullptr;
-    cxd* Vout = nullptr;
-    cxd* Zout = nullptr;
-    cxd* hv2 = nullptr;
-    if (so.method == VSIE_IR_MIXED) {
-      x32 = (cxf*)vec(N, sizeof(cxf));
-      y32 = (cxf*)vec(N, sizeof(cxf));
-      Vout = (cxd*)vec(Nc * (IR_OUTER_M + 1), sizeof(cxd));
-      Zout = (cxd*)vec(Nc * IR_OUTER_M, sizeof(cxd));
-      hv2 = (cxd*)vec(1100, sizeof(cxd));
+    ws.hv = (cxd*)vec(1100, sizeof(cxd));
+    if (mixed) {
+      ws.x32 = (cxf*)vec(N, sizeof(cxf));
+      ws.y32 = (cxf*)vec(N, sizeof(cxf));
+      ws.Vout = (cxd*)vec(Nc * (IR_OUTER_M + 1), sizeof(cxd));
+      ws.Zout = (cxd*)vec(Nc * IR_OUTER_M, sizeof(cxd));
+      ws.hv2 = (cxd*)vec(1100, sizeof(cxd));
     }
+    cxd *wc = ws.wc, *bc = ws.bc, *xc = ws.xc, *dc = ws.dc, *hv = ws.hv, *hv2 = ws.hv2, *Vout = ws.Vout,
+        *Zout = ws.Zout;
+    cxf *x32 = ws.x32, *y32 = ws.y32;
     cxd* fin = H.d_full[0];
     cxd* fout = H.d_full[1];
     Solver S(H, st);
@@ -1543,7 +1603,7 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       launch_f2d(st, y32, fout, N);
       launch_gather_idx(st, fout, H.d_active, Nc, out);
     };
-    if (so.method == VSIE_SCHUR) setup_schur(H, so.precond != 0);
+    if (so.method == VSIE_SCHUR || so.method == VSIE_SCHUR_MIXED) setup_schur(H, so.precond != 0);
     for (int c = 0; c < nrhs; ++c) {
       auto t0 = std::chrono::steady_clock::now();
       const cxd* b = (const cxd*)b_dev + c * N;
@@ -1551,8 +1611,9 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       vsie_solve_stats s;
       std::memset(&s, 0, sizeof(s));
       double rel = 0;
-      if (so.method == VSIE_SCHUR) {
-        s.iterations = solve_schur(H, S, so, b, x, bc, xc, wc, hv, &s.restarts, &rel, st);
+      if (so.method == VSIE_SCHUR || so.method == VSIE_SCHUR_MIXED) {
+        s.iterations = solve_schur(H, S, so, so.method == VSIE_SCHUR_MIXED, b, x, ws, &s.restarts, &s.refinements, &rel,
+                                   st);
       } else {
         launch_gather_idx(st, b, H.d_active, Nc, bc);
         if (so.method == VSIE_GMRES64) {
@@ -1664,6 +1725,7 @@ int vsie_export(const vsie_handle* hd, int what, int index, void* host, size_t* 
 int vsie_import(vsie_handle* hd, int what, int index, const void* host, size_t nbytes) {
   if (!hd || !host) return fail(VSIE_E_ARG, "null argument");
   Handle& H = hd->H;
+  if (H.schur.ready) return fail(VSIE_E_STATE, "the far elimination was built from the current factors");
   return guarded([&]() {
     const unsigned char* c = (const unsigned char*)host;
     if (what == VSIE_X_TT_CORES) {
@@ -1727,7 +1789,7 @@ int vsie_schur_matvec(vsie_handle* hd, const void* x_dev, void* y_dev, void* str
   Handle& H = hd->H;
   if (!H.schur.ready) return fail(VSIE_E_STATE, "far elimination not set up (vsie_schur_setup)");
   return guarded([&]() {
-    matvec_schur(H, (const cxd*)x_dev, (cxd*)y_dev, (hipStream_t)stream);
+    matvec_schur<double>(H, (const cxd*)x_dev, (cxd*)y_dev, (hipStream_t)stream);
     VSIE_HIP(hipGetLastError());
   });
 }
@@ -1737,7 +1799,7 @@ int vsie_schur_precond(vsie_handle* hd, const void* x_dev, void* y_dev, void* st
   Handle& H = hd->H;
   if (!H.schur.precond) return fail(VSIE_E_STATE, "preconditioner not built (vsie_schur_setup with precond)");
   return guarded([&]() {
-    precond_apply(H, (const cxd*)x_dev, (cxd*)y_dev, (hipStream_t)stream);
+    precond_apply<double>(H, (const cxd*)x_dev, (cxd*)y_dev, (hipStream_t)stream);
     VSIE_HIP(hipGetLastError());
   });
 }

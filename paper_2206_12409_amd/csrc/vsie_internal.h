@@ -183,24 +183,28 @@ struct Handle {
 
   // elimination of the far currents (Schur complement of the dense far block) and the right
   // preconditioner of the reduced system, built on first use
+  template <typename R> struct SchurOp {
+    cx<R>* S = nullptr;          // L^T Z_ff^-1 L, [K][K]
+    cx<R>* ta = nullptr;         // U^T x_n (256)
+    cx<R>* pa = nullptr;         // ACA proxies to inject (256)
+    cx<R>* p3 = nullptr;         // TT proxies to inject, [3][128]
+    cx<R>* Xn = nullptr;         // inverse reduced near block, upper-triangle tiles
+    cx<R>* part_n = nullptr;
+    cx<R>* invdiag = nullptr;    // inverse body diagonal, 3 n_v (1 for air voxels)
+  };
   struct Schur {
     bool ready = false;
     bool precond = false;
     int K = 0;                   // far-coupling proxies: ACA rank + the three TT ranks r3
     DenseLU ff;                  // LU of the dense far block (m_f x m_f, row-major)
     cxd* W = nullptr;            // Z_ff^-1 L, row-major [m_f][K]
-    cxd* S = nullptr;            // L^T Z_ff^-1 L, [K][K]
-    cxd* ta = nullptr;           // U^T x_n (256)
-    cxd* pa = nullptr;           // ACA proxies to inject (256)
-    cxd* p3 = nullptr;           // TT proxies to inject, [3][128]
     cxd* tc = nullptr;           // compact proxy vector (K)
     cxd* zf = nullptr;           // Z_ff^-1 b_f (m_f)
     cxd* vec[3] = {};            // N-length work vectors of the solver
     int Tn = 0;                  // inverse of the reduced near block as upper-triangle tiles
     int* d_tiles_n = nullptr;
-    cxd* Xn = nullptr;
-    cxd* part_n = nullptr;
-    cxd* invdiag = nullptr;      // inverse body diagonal, 3 n_v (1 for air voxels)
+    SchurOp<double> d64;         // per precision: S, proxy buffers, preconditioner
+    SchurOp<float> d32;
     double seconds = 0;          // setup time
   } schur;
 

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libvsie.so")
 VSIE_OK, VSIE_E_NOCONV = 0, 7
 VSIE_NEAR, VSIE_FAR = 0, 1
 VSIE_C128, VSIE_C64 = 0, 1
-VSIE_GMRES64, VSIE_IR_MIXED, VSIE_SCHUR = 0, 1, 2
+VSIE_GMRES64, VSIE_IR_MIXED, VSIE_SCHUR, VSIE_SCHUR_MIXED = 0, 1, 2, 3
 VSIE_E_SINGULAR = 11
 X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
 

@@ -140,6 +140,22 @@ def test_schur_solve_all_ports(small):
         assert rel(x, S_same.solve(b)) <= 1e-5
 
 
+def test_schur_mixed_precision_solve(small):
+    """Flexible FP64 GMRES with complex64 inner cycles on the reduced system reaches 1e-8 on every
+    port; two solutions at that residual differ by at most cond(A) x 2e-8."""
+    p, op, d, _, S_same = small
+    cond = np.linalg.cond(S_same.Z)
+    for port in range(op.n_ports):
+        b = system.port_rhs(d, port)
+        x, st = op.solve(to_dev(b), tol=1e-8, restart=50, max_iter=400, method=3)
+        s = st[0]
+        print("mixed port %d: %d inner iterations, %d FP64 steps, residual %.2e"
+              % (port, s["iterations"], s["refinements"], s["rel_residual"]))
+        assert s["converged"] and s["rel_residual"] <= 1e-8
+        assert rel(S_same.matvec(x.cpu().numpy()), b) <= 2e-8
+        assert rel(x.cpu().numpy(), S_same.solve(b)) <= cond * 2e-8
+
+
 def test_schur_solve_with_far_excitation(small):
     """A right-hand side with far, near and body parts (random): exercises b_f != 0."""
     p, op, d, _, S_same = small
@@ -148,3 +164,34 @@ def test_schur_solve_with_far_excitation(small):
     x = x.cpu().numpy()
     assert st[0]["converged"]
     assert rel(S_same.matvec(x), b) <= 2e-8
+
+
+def _edge_problem(kind):
+    g = synth.sphere_phantom((9, 8, 10), 5e-3, 17e-3, 52.0, 0.55)
+    loop = synth.strip_loop_flat((25.5e-3, 0.37e-3, -0.41e-3), side=30e-3, width=5e-3, step=5e-3)
+    shield = synth.cylinder_shield(0.080, 0.160, 12, 6, closed=True, cap_rings=2)
+    meshes = {"body": [], "far": [shield], "near": [loop]}[kind]
+    return synth.Problem(g, meshes, synth.problems.LARMOR_7T_HZ, kind)
+
+
+@pytest.mark.parametrize("kind", ["body", "far", "near"])
+def test_schur_degenerate_configurations(lib, kind):
+    """Body only (nothing to eliminate, body diagonal only), body + far conductor (no ACA
+    proxies: only TT ranks), body + near coil (no far block, near-block inverse and body
+    diagonal): the reduced product equals the oracle's A_S and the preconditioned solve matches
+    the oracle's dense solve, on a ragged 9 x 8 x 10 grid."""
+    p = _edge_problem(kind)
+    op = lib.Operator(p)
+    d, _, S_same, _ = oracle_same(p, op)
+    info = op.schur_setup(precond=True)
+    mf = d.m_f
+    assert info["n_proxy"] == (sum(r[2] for r in op.info()["tt_rank"]) if mf else 0)
+    A_S, _ = schur.reduced_system(S_same.Z, np.zeros(S_same.Z.shape[0]), mf)
+    x = synth.complex_normal(op.N, 5)
+    y = op.schur_matvec(to_dev(x)).cpu().numpy()
+    idx = S_same.red_idx[mf:]
+    assert rel(y[idx], A_S @ x[idx]) <= 1e-10
+    b = system.port_rhs(d, 0) if op.n_ports else synth.complex_normal(op.N, 6)
+    xs, st = op.solve(to_dev(b), tol=1e-10, restart=50, max_iter=2000, method=2)
+    assert st[0]["converged"]
+    assert rel(xs.cpu().numpy(), S_same.solve(b)) <= 1e-7
