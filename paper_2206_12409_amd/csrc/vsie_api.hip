@@ -828,19 +828,33 @@ template <typename R> static void matvec_schur(Handle& H, const cx<R>* x, cx<R>*
   const cx<R>* xb = x + mf + mn;
   cx<R>* yn = y + mf;
   cx<R>* yb = y + mf + mn;
+  // the proxy chain reads only x and writes only its own buffers, so it runs on the second stream
+  // beside the volume chain; the injections into y_n and y_b follow the join
+  TTDesc<R> td;
+  int r3[3];
+  const bool have_tt = tt_desc(H, D, td, r3);
+  const int ka = aca_rank(H);
+  if (K > 0) {
+    if (!H.side) make_streams(H);
+    VSIE_HIP(hipEventRecord(H.fork, st));
+    VSIE_HIP(hipStreamWaitEvent(H.side, H.fork, 0));
+    T.begin(10, H.side);
+    far_proxies<R>(H, xn, xb, H.side);
+    launch_schur_apply<R>(H.side, P.S, K, ka, r3, P.ta, D.tt_work, (R)-1, P.pa, P.p3);
+    if (have_tt) launch_tt_forward_from<R>(H.side, td, H.n, H.mf, P.p3, D.tt_work);
+    T.end(10, H.side);
+    VSIE_HIP(hipEventRecord(H.join, H.side));
+  }
   volume_chain<R>(H, D, mn ? xn : nullptr, xb, yn, yb, st, T);
   T.begin(9);
   launch_csr_add<R>(st, H.d_pc_rowid, H.d_pc_rowptr, H.d_pc_col, D.pc_val, x, y, H.n_pcrows);
   T.end(9);
   if (K > 0) {
-    T.begin(10);
-    far_proxies<R>(H, xn, xb, st);
-    TTDesc<R> td;
-    int r3[3];
-    tt_desc(H, D, td, r3);
-    launch_schur_apply<R>(st, P.S, K, aca_rank(H), r3, P.ta, D.tt_work, (R)-1, P.pa, P.p3);
-    inject_proxies<R>(H, P.pa, P.p3, yn, yb, st);
-    T.end(10);
+    VSIE_HIP(hipStreamWaitEvent(st, H.join, 0));
+    T.begin(13);
+    if (ka) launch_lr_n_add<R>(st, false, D.U, P.pa, H.mn, ka, yn);
+    if (have_tt) launch_tt_forward_post<R>(st, td, H.n, H.mf, H.d_mask, yb, D.tt_work);
+    T.end(13);
   }
   if (mf) VSIE_HIP(hipMemsetAsync(y, 0, sizeof(cx<R>) * mf, st));
   T.collect();
