@@ -267,6 +267,17 @@ def other_precisions(op, x, y, args):
     value32 = n32 / (time.perf_counter() - t0)
     err32 = float(torch.linalg.norm(y32.to(torch.complex128) - y) / torch.linalg.norm(y))
     print("fp32: %.1f matvec/s, rel err vs fp64 %.2e" % (value32, err32), file=sys.stderr, flush=True)
+    # complex64 stage times (the paper's three named parts in complex64)
+    op.profile(True)
+    for _ in range(20):
+        op.matvec(x32, out=y32)
+    st32 = {k: v[0] / v[1] for k, v in op.profile_read().items()}
+    op.profile(False)
+    tp = ["build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "body_out", "pfft_gather",
+          "precorrect", "tt_pre", "tt_post"]
+    t32 = sum(st32.get(k, 0) for k in tp)
+    print("fp32 stage ms: %s" % json.dumps({k: round(v, 4) for k, v in st32.items()}), file=sys.stderr, flush=True)
+    value32 = dict(value=value32, three_parts_ms=round(t32, 4), three_parts_per_s=round(1e3 / t32, 1) if t32 else None)
 
     # the same product with the far-block chain on a second stream
     op.set_concurrency(True)
@@ -523,7 +534,9 @@ def main():
                         "gbs": round(conv_b / (conv_ms * 1e-3) / 1e9, 1) if conv_ms else None},
         "stages": rl,
         "three_parts": three,
-        "c64": {"value": round(value32, 3) if value32 else None, "unit": "matvec/s", "rel_err_vs_c128": err32},
+        "c64": {"value": round(value32["value"], 3) if value32 else None, "unit": "matvec/s", "rel_err_vs_c128": err32,
+                "three_parts_ms": value32["three_parts_ms"] if value32 else None,
+                "three_parts_per_s": value32["three_parts_per_s"] if value32 else None},
         "concurrent_far_block": {"value": round(value_conc, 3) if value_conc else None, "unit": "matvec/s",
                                  "identical_result": same},
         "batched_rhs": batched,

@@ -87,7 +87,7 @@ template <typename R> struct GemmSet {
 template <typename R> void launch_zgemm(hipStream_t st, const GemmSet<R>& S);
 
 constexpr int TT_RMAX = 128;
-constexpr int TT_KCHUNK = 64;   // split-K chunk of the transpose contraction over n1 n2
+constexpr int TT_KCHUNK = 128;  // split-K chunk of the transpose contraction over n1 n2
 template <typename R> struct TTDesc {
   const cx<R>* M[3];    // merged first two cores, [r2][n1 n2]
   const cx<R>* G3[3];   // [r2][n3][r3]

@@ -1572,28 +1572,46 @@ __global__ __launch_bounds__(256) void k_tt_ksum(TTDesc<R> T, const cx<R>* __res
 //   transpose S2[j2][i3] = sum_p M[j2][p] mask x_b[p + n1 n2 i3] -> s3[j3] -> y_f[i4]
 
 // forward, G4 first: part[c][j3][chunk] = sum_{i4 in chunk} G4[j3][i4] x_f[i4]
+constexpr int TT_F4_RB = 4;        // ranks per block of the G4 x_f partial sums
+constexpr int TT_F4_CHUNK = 2048;  // far currents per block
 template <typename R>
 __global__ __launch_bounds__(256) void k_tt_f4(TTDesc<R> T, const cx<R>* __restrict__ xf, int mf, int chunk,
                                                cx<R>* __restrict__ part, int nchunk) {
-  __shared__ R rr[256], ri[256];
-  const int c = blockIdx.z, j3 = blockIdx.y, ch = blockIdx.x;
-  cx<R> acc = {0, 0};
-  if (j3 < T.r3[c]) {
-    const cx<R>* g = T.G4[c] + (int64_t)j3 * mf;
-    const int i0 = ch * chunk, i1 = min(mf, i0 + chunk);
-    for (int i = i0 + threadIdx.x; i < i1; i += 256) acc += g[i] * xf[i];
+  // partial sums of G4[c][j3] . x_f over one chunk of the far currents, TT_F4_RB ranks per block
+  // (each x_f value loaded once for all of them)
+  constexpr int RB = TT_F4_RB;
+  __shared__ R rr[RB][4], ri[RB][4];
+  const int c = blockIdx.z, j0 = blockIdx.y * RB, ch = blockIdx.x;
+  const int r3 = T.r3[c];
+  cx<R> acc[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) acc[q] = cx<R>{0, 0};
+  const int i0 = ch * chunk, i1 = min(mf, i0 + chunk);
+  for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+    const cx<R> xv = xf[i];
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (j0 + q < r3) acc[q] += T.G4[c][(int64_t)(j0 + q) * mf + i] * xv;
   }
-  rr[threadIdx.x] = acc.re;
-  ri[threadIdx.x] = acc.im;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      rr[threadIdx.x] += rr[threadIdx.x + s];
-      ri[threadIdx.x] += ri[threadIdx.x + s];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    R re = acc[q].re, im = acc[q].im;
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_down(re, off, 64);
+      im += __shfl_down(im, off, 64);
     }
-    __syncthreads();
+    if (lane == 0) {
+      rr[q][wave] = re;
+      ri[q][wave] = im;
+    }
   }
-  if (threadIdx.x == 0) part[((int64_t)c * TT_RMAX + j3) * nchunk + ch] = cx<R>{rr[0], ri[0]};
+  __syncthreads();
+  if (threadIdx.x < RB && j0 + (int)threadIdx.x < r3) {
+    const int q = threadIdx.x;
+    part[((int64_t)c * TT_RMAX + j0 + q) * nchunk + ch] =
+        cx<R>{(rr[q][0] + rr[q][1]) + (rr[q][2] + rr[q][3]), (ri[q][0] + ri[q][1]) + (ri[q][2] + ri[q][3])};
+  }
 }
 
 // t3[c][row] = sum_j3 G3[row][j3] t4[j3] over rows (j2, i3) of G3; t4 summed from the partials
@@ -1652,24 +1670,29 @@ __global__ __launch_bounds__(256) void k_ttT_3(TTDesc<R> T, const cx<R>* __restr
 
 // y_f[i4] += sum_c sum_j3 G4[c][j3][i4] s3[c][j3]; 64 rows per block, four wavefronts split j3
 template <typename R>
-__global__ __launch_bounds__(256) void k_ttT_4(TTDesc<R> T, const cx<R>* __restrict__ s3, int mf,
-                                               cx<R>* __restrict__ yf) {
+__global__ __launch_bounds__(1024) void k_ttT_4(TTDesc<R> T, const cx<R>* __restrict__ s3, int mf,
+                                                cx<R>* __restrict__ yf) {
+  // y_f[i] += sum_c sum_j3 G4[c][j3][i] s3[c][j3]: 64 far currents per block, sixteen wavefronts
+  // taking every sixteenth rank
   __shared__ cx<R> sv[3 * TT_RMAX];
-  __shared__ R rr[4][64], ri[4][64];
-  for (int l = threadIdx.x; l < 3 * TT_RMAX; l += 256) sv[l] = s3[l];
+  __shared__ R rr[16][64], ri[16][64];
+  for (int l = threadIdx.x; l < 3 * TT_RMAX; l += 1024) sv[l] = s3[l];
   __syncthreads();
   const int row = threadIdx.x % 64, sl = threadIdx.x / 64;
   const int64_t i = (int64_t)blockIdx.x * 64 + row;
   cx<R> acc = {0, 0};
   if (i < mf)
     for (int c = 0; c < 3; ++c)
-      for (int j3 = sl; j3 < T.r3[c]; j3 += 4) acc += T.G4[c][(int64_t)j3 * mf + i] * sv[c * TT_RMAX + j3];
+      for (int j3 = sl; j3 < T.r3[c]; j3 += 16) acc += T.G4[c][(int64_t)j3 * mf + i] * sv[c * TT_RMAX + j3];
   rr[sl][row] = acc.re;
   ri[sl][row] = acc.im;
   __syncthreads();
-  if (sl == 0 && i < mf)
-    yf[i] += cx<R>{(rr[0][row] + rr[1][row]) + (rr[2][row] + rr[3][row]),
-                   (ri[0][row] + ri[1][row]) + (ri[2][row] + ri[3][row])};
+  if (sl == 0 && i < mf) {
+    cx<R> s = {0, 0};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += cx<R>{rr[q][row], ri[q][row]};
+    yf[i] += s;
+  }
 }
 
 // =============================================================================================
@@ -1886,7 +1909,7 @@ template <typename R> static TTWork tt_layout(const TTDesc<R>& T, const int n[3]
     w.rmax2 = std::max(w.rmax2, T.r2[c]);
     w.rmax3 = std::max(w.rmax3, T.r3[c]);
   }
-  w.nchunk = (mf + 4095) / 4096;
+  w.nchunk = (mf + TT_F4_CHUNK - 1) / TT_F4_CHUNK;
   w.nkc = (w.n12 + TT_KCHUNK - 1) / TT_KCHUNK;
   w.nk3 = (w.rmax2 * w.n3 + TT_KROWS - 1) / TT_KROWS;
   return w;
@@ -1900,7 +1923,8 @@ template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, con
   const TTWork w = tt_layout(T, n, mf);
   cx<R>* part = work;
   cx<R>* t3 = part + 3LL * TT_RMAX * w.nchunk;
-  hipLaunchKernelGGL(k_tt_f4<R>, dim3(w.nchunk, w.rmax3, 3), dim3(256), 0, st, T, xf, mf, 4096, part, w.nchunk);
+  hipLaunchKernelGGL(k_tt_f4<R>, dim3(w.nchunk, (w.rmax3 + TT_F4_RB - 1) / TT_F4_RB, 3), dim3(256), 0, st, T, xf, mf,
+                     TT_F4_CHUNK, part, w.nchunk);
   hipLaunchKernelGGL(k_tt_f3<R>, dim3((w.rmax2 * w.n3 + 15) / 16, 3), dim3(256), 0, st, T, part, w.nchunk, w.n3, t3);
   launch_tt_transpose_pre<R>(st, T, n, mf, xb, mask, work);
 }
@@ -1946,7 +1970,7 @@ template <typename R> void launch_tt_post(hipStream_t st, const TTDesc<R>& T, co
   const TTWork w = tt_layout(T, n, mf);
   const cx<R>* s3 = work;
   launch_tt_forward_post<R>(st, T, n, mf, mask, yb, work);
-  hipLaunchKernelGGL(k_ttT_4<R>, dim3((mf + 63) / 64), dim3(256), 0, st, T, s3, mf, yf);
+  hipLaunchKernelGGL(k_ttT_4<R>, dim3((mf + 63) / 64), dim3(1024), 0, st, T, s3, mf, yf);
 }
 
 // The forward half of launch_tt_post: y_b[c] += mask * (merged core) t3.
@@ -1965,7 +1989,7 @@ template <typename R> void launch_tt_forward_post(hipStream_t st, const TTDesc<R
   launch_zgemm<R>(st, F);
 }
 int64_t tt_work_elems(const int n[3], int mf) {
-  const int nchunk = (mf + 4095) / 4096;
+  const int nchunk = (mf + TT_F4_CHUNK - 1) / TT_F4_CHUNK;
   const int nkc = (n[0] * n[1] + TT_KCHUNK - 1) / TT_KCHUNK;
   const int nk3 = (TT_RMAX * n[2] + TT_KROWS - 1) / TT_KROWS;
   return 3LL * TT_RMAX * std::max(nchunk, 1) + 6LL * TT_RMAX * n[2] + 3LL * nkc * TT_RMAX * n[2] +
