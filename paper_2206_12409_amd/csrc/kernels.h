@@ -114,7 +114,7 @@ int64_t tt_work_elems(const int n[3], int mf);
 template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
                                              int m, cx<R>* part);
 template <typename R> void launch_symv_reduce(hipStream_t st, const cx<R>* part, int T, int m, cx<R>* y);
-// the tile pass for nrhs (1..4) right-hand sides at once: column b of x at x + b ldx, its partials
+// the tile pass for nrhs (1..16) right-hand sides at once: column b of x at x + b ldx, its partials
 // at part + b ldp (ldp >= 2 SYM_TB per tile); reduce each with launch_symv_reduce
 template <typename R> void launch_symv_multi(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
                                              int64_t ldx, int m, int nrhs, cx<R>* part, int64_t ldp);

@@ -1295,91 +1295,6 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const cx<R>* __restrict__ Zp
   }
 }
 
-// The same tile pass for NB right-hand sides at once (column b of x at x + b ldx): every tile is
-// read once for all of them and yields NB row-sum and column-sum partials (column b at
-// part + b ldp). Per right-hand side the arithmetic and its order are those of k_symv_tiles.
-template <typename R, int NB>
-__global__ __launch_bounds__(256) void k_symv_multi(const cx<R>* __restrict__ Zp, const int* __restrict__ tiles,
-                                                    const cx<R>* __restrict__ x, int64_t ldx, int m, int64_t ntiles,
-                                                    cx<R>* __restrict__ part, int64_t ldp) {
-  __shared__ R cr[4][SYM_TB], ci[4][SYM_TB];
-  __shared__ cx<R> xs[NB][SYM_TB];
-  const int cg = threadIdx.x % 32, rg = threadIdx.x / 32;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int I = tiles[2 * t], J = tiles[2 * t + 1];
-    const cx<R>* Z = Zp + t * (int64_t)SYM_TB * SYM_TB;
-    if (threadIdx.x < SYM_TB) {
-      const int mm = I * SYM_TB + threadIdx.x;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) xs[b][threadIdx.x] = mm < m ? x[b * ldx + mm] : cx<R>{0, 0};
-    }
-    cx<R> xJ[NB][4], ca[NB][4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int n = J * SYM_TB + cg + 32 * c;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        xJ[b][c] = n < m ? x[b * ldx + n] : cx<R>{0, 0};
-        ca[b][c] = {0, 0};
-      }
-    }
-    __syncthreads();
-#pragma unroll 2
-    for (int r = 0; r < 16; ++r) {
-      const int row = rg * 16 + r;
-      const cx<R>* zr = Z + (int64_t)row * SYM_TB + cg;
-      cx<R> rd[NB], xi[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        xi[b] = xs[b][row];
-        rd[b] = {0, 0};
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const cx<R> z = ld_stream(zr + 32 * c);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          rd[b] += z * xJ[b][c];
-          ca[b][c] += z * xi[b];
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        for (int off = 16; off > 0; off >>= 1) {
-          rd[b].re += __shfl_xor(rd[b].re, off, 32);
-          rd[b].im += __shfl_xor(rd[b].im, off, 32);
-        }
-        if (cg == 0) part[b * ldp + t * 2 * SYM_TB + row] = rd[b];
-      }
-    }
-    if (I != J) {
-      const int wave = threadIdx.x / 64;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          ca[b][c].re += __shfl_xor(ca[b][c].re, 32, 64);
-          ca[b][c].im += __shfl_xor(ca[b][c].im, 32, 64);
-        }
-        if ((threadIdx.x % 64) < 32)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            cr[wave][cg + 32 * c] = ca[b][c].re;
-            ci[wave][cg + 32 * c] = ca[b][c].im;
-          }
-        __syncthreads();
-        if (threadIdx.x < SYM_TB) {
-          const int c = threadIdx.x;
-          part[b * ldp + t * 2 * SYM_TB + SYM_TB + c] =
-              cx<R>{cr[0][c] + cr[1][c] + cr[2][c] + cr[3][c], ci[0][c] + ci[1][c] + ci[2][c] + ci[3][c]};
-        }
-        __syncthreads();
-      }
-    }
-    __syncthreads();   // xs is rewritten by the next tile
-  }
-}
-
 // y[i] = sum_{J >= I} rowpart(I, J)[i] + sum_{J < I} colpart(J, I)[i], I = i / SYM_TB; a block
 // covers 64 outputs with four wavefronts taking every fourth J (fixed order)
 template <typename R>
@@ -1537,6 +1452,94 @@ template <typename R> void launch_zgemm(hipStream_t st, const GemmSet<R>& S) {
 }
 template void launch_zgemm<double>(hipStream_t, const GemmSet<double>&);
 template void launch_zgemm<float>(hipStream_t, const GemmSet<float>&);
+
+// The far-block tile pass for up to 16 right-hand sides on the matrix cores (column b of x at
+// x + b ldx, its partials at part + b ldp). For a tile (I, J) the row sums Z X_J and the column
+// sums Z^T X_I are complex products of the 128 x 128 tile with 128 x nrhs slices of x, i.e. GEMMs
+// whose output columns are the right-hand sides: the 16 x 16 x 4 MFMA takes them along its
+// 16 output columns, and the reductions over the tile happen inside the matrix core. The tile
+// streams through LDS in slabs of 32 rows. Each of the four waves takes one 16-row block of the
+// slab for the row sums over one half of the columns (the halves are added through LDS), and two
+// 16-column blocks for the column sums, accumulated over all slabs in registers.
+template <typename R>
+__global__ __launch_bounds__(256) void k_symv_multi(const cx<R>* __restrict__ Zp, const int* __restrict__ tiles,
+                                                    const cx<R>* __restrict__ x, int64_t ldx, int m, int nrhs,
+                                                    int64_t ntiles, cx<R>* __restrict__ part, int64_t ldp) {
+  using MM = Mfma16<R>;
+  using V = typename MM::V;
+  constexpr int SL = 32, LD = SYM_TB + 1;
+  __shared__ cx<R> zs[SL * LD];
+  __shared__ cx<R> red[2][16][16];
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int li = lane % 16, lk = lane / 16;
+  const int kh = w / 2, rb = w % 2;   // column half and row block of this wave's row sums
+  const bool live = li < nrhs;
+  for (int64_t tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+    const int I = tiles[2 * tt], J = tiles[2 * tt + 1];
+    const cx<R>* Z = Zp + tt * (int64_t)SYM_TB * SYM_TB;
+    cx<R>* out = part + tt * 2 * SYM_TB;
+    cx<R> bj[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int mm = J * SYM_TB + kh * 64 + 4 * q + lk;
+      bj[q] = (live && mm < m) ? x[li * ldx + mm] : cx<R>{0, 0};
+    }
+    V ccr[2], cci[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      ccr[cb] = V{0, 0, 0, 0};
+      cci[cb] = V{0, 0, 0, 0};
+    }
+    for (int s = 0; s < SYM_TB / SL; ++s) {
+      __syncthreads();   // the previous slab and its row-sum exchange are consumed
+      for (int e = threadIdx.x; e < SL * SYM_TB; e += 256) {
+        const int r = e / SYM_TB, c = e % SYM_TB;
+        zs[r * LD + c] = ld_stream(Z + (int64_t)(s * SL + r) * SYM_TB + c);   // each tile is read once
+      }
+      __syncthreads();
+      V rr = V{0, 0, 0, 0}, ri = V{0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const cx<R> a = zs[(rb * 16 + li) * LD + kh * 64 + 4 * q + lk];
+        rr = MM::mma(a.re, bj[q].re, rr);
+        rr = MM::mma(-a.im, bj[q].im, rr);
+        ri = MM::mma(a.re, bj[q].im, ri);
+        ri = MM::mma(a.im, bj[q].re, ri);
+      }
+      if (kh == 1)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[rb][MM::row(lane, v)][li] = cx<R>{rr[v], ri[v]};
+      if (I != J) {
+#pragma unroll
+        for (int q = 0; q < SL / 4; ++q) {
+          const int mm = I * SYM_TB + s * SL + 4 * q + lk;
+          const cx<R> b = (live && mm < m) ? x[li * ldx + mm] : cx<R>{0, 0};
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) {
+            const cx<R> a = zs[(4 * q + lk) * LD + (2 * w + cb) * 16 + li];
+            ccr[cb] = MM::mma(a.re, b.re, ccr[cb]);
+            ccr[cb] = MM::mma(-a.im, b.im, ccr[cb]);
+            cci[cb] = MM::mma(a.re, b.im, cci[cb]);
+            cci[cb] = MM::mma(a.im, b.re, cci[cb]);
+          }
+        }
+      }
+      __syncthreads();
+      if (kh == 0 && live)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = MM::row(lane, v);
+          out[li * ldp + s * SL + rb * 16 + row] = cx<R>{rr[v], ri[v]} + red[rb][row][li];
+        }
+    }
+    if (I != J && live)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          out[li * ldp + SYM_TB + (2 * w + cb) * 16 + MM::row(lane, v)] = cx<R>{ccr[cb][v], cci[cb][v]};
+  }
+}
 
 // s2[c][j2][i3] = sum_b part[c][b][j2][i3]  (split-K reduction of the transpose contraction);
 // a block covers 32 outputs with 8 slices over b
@@ -2002,17 +2005,9 @@ template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, co
 }
 template <typename R> void launch_symv_multi(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
                                              int64_t ldx, int m, int nrhs, cx<R>* part, int64_t ldp) {
+  if (nrhs < 1 || nrhs > 16) throw Error(VSIE_E_ARG, "symv_multi takes 1 to 16 right-hand sides");
   const int64_t nt = (int64_t)T * (T + 1) / 2;
-  if (nrhs == 4)
-    hipLaunchKernelGGL((k_symv_multi<R, 4>), dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, ldx, m, nt, part, ldp);
-  else if (nrhs == 3)
-    hipLaunchKernelGGL((k_symv_multi<R, 3>), dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, ldx, m, nt, part, ldp);
-  else if (nrhs == 2)
-    hipLaunchKernelGGL((k_symv_multi<R, 2>), dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, ldx, m, nt, part, ldp);
-  else if (nrhs == 1)
-    hipLaunchKernelGGL((k_symv_multi<R, 1>), dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, ldx, m, nt, part, ldp);
-  else
-    throw Error(VSIE_E_ARG, "symv_multi takes 1 to 4 right-hand sides");
+  hipLaunchKernelGGL(k_symv_multi<R>, dim3((unsigned)nt), dim3(256), 0, st, Zp, tiles, x, ldx, m, nrhs, nt, part, ldp);
 }
 template <typename R> void launch_symv_reduce(hipStream_t st, const cx<R>* part, int T, int m, cx<R>* y) {
   hipLaunchKernelGGL(k_symv_reduce<R>, dim3((m + 63) / 64), dim3(256), 0, st, part, T, m, y, 0);

@@ -715,11 +715,11 @@ void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t s
   T.collect();
 }
 
-// nrhs products: the dense far block, the largest operand, is read once per group of up to four
+// nrhs products: the dense far block, the largest operand, is read once per group of up to 16
 // right-hand sides (each tile yields the partial sums of every column of the group); the rest
 // of each product runs per column.
 template <typename R> void matvec_batch(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, int nrhs, hipStream_t st) {
-  constexpr int kGroup = 4;
+  constexpr int kGroup = 16;
   const int64_t N = H.N;
   const bool batched = nrhs > 1 && H.mf > 0;
   if (batched) {

@@ -75,7 +75,7 @@ template <typename R> struct OpData {
   // dense far block
   cx<R>* Zff = nullptr;        // upper-triangle tiles of the symmetric far block
   cx<R>* sym_part = nullptr;   // per-tile partial sums
-  cx<R>* multi_part = nullptr; // per-tile partial sums of up to four right-hand sides
+  cx<R>* multi_part = nullptr; // per-tile partial sums of up to 16 right-hand sides
   // work buffers
   cx<R>* gridA = nullptr;      // [3][ne3][ne2][ne1] (also the convolution output)
   cx<R>* bufB = nullptr;       // [3][ne3][ne2][P1]
