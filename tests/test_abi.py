@@ -78,3 +78,26 @@ def test_rejects_bad_sizes(vs):
     p = synth.small_case()
     p.grid = synth.Grid(p.grid.n, -1.0, p.grid.origin, p.grid.eps_r, p.grid.sigma, p.grid.labels)
     _expect(vs, p, 1)
+
+
+def test_new_entry_points_reject_bad_arguments(vs):
+    """Argument checks of the elimination and dense-solve entry points happen before any device
+    work: null handles and invalid sizes give E_ARG; default solve options ask for the
+    preconditioner."""
+    import ctypes as C
+    lib = vs.load()
+    vp = C.c_void_p
+    dummy = vp(16)   # never dereferenced: every call below fails its argument check first
+    assert lib.vsie_schur_setup(None, 1) == 1
+    assert lib.vsie_schur_info(None, None, None, None) == 1
+    assert lib.vsie_schur_matvec(None, dummy, dummy, None) == 1
+    assert lib.vsie_schur_precond(None, dummy, dummy, None) == 1
+    assert lib.vsie_dense_lu_solve(-1, dummy, 1, dummy, 1, 1, None) == 1
+    assert lib.vsie_dense_lu_solve(4, dummy, 3, dummy, 1, 1, None) == 1     # lda < n
+    assert lib.vsie_dense_lu_solve(4, dummy, 4, dummy, 1, 2, None) == 1     # ldb < nrhs
+    assert lib.vsie_dense_lu_solve(4, None, 4, dummy, 1, 1, None) == 1
+    assert lib.vsie_dense_lu_solve(0, None, 0, None, 0, 0, None) == 0       # empty system: nothing to do
+    o = vs.SolveOpts()
+    lib.vsie_default_solve_opts(C.byref(o))
+    assert o.precond == 1 and o.method == vs.VSIE_GMRES64 and o.restart == 50 and o.tol == 1e-6
+    assert lib.vsie_solve(None, C.byref(o), 1, dummy, dummy, None, None) == 1
