@@ -1,8 +1,11 @@
 // Host-side setup: Gauss tables, RWG tables and ports, pFFT stencils and projection weights,
 // extended grid, small dense linear algebra, thread pool helper.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <map>
+#include <mutex>
 #include <thread>
 
 #include "vsie_internal.h"
@@ -46,19 +49,88 @@ void fill_gauss_table(GaussTab* t) {
   }
 }
 
+// Persistent workers for parallel_for: the setup loops call it thousands of times (the TT-cross
+// linear algebra once per column), so threads are started once and woken per call.
+namespace {
+thread_local bool t_in_pool = false;   // set while a thread runs parallel_for work
+class Workers {
+ public:
+  explicit Workers(int n) {
+    for (int w = 1; w < n; ++w) th_.emplace_back([this, w]() { loop(w); });
+  }
+  ~Workers() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  int size() const { return (int)th_.size() + 1; }
+  // chunk w of [0, n) for w < parts on worker w (the caller takes chunk 0); returns when all ran
+  void run(int64_t n, int parts, const std::function<void(int64_t, int64_t)>& fn) {
+    std::unique_lock<std::mutex> lk(call_mu_);   // one call at a time
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      fn_ = &fn;
+      n_ = n;
+      parts_ = parts;
+      chunk_ = (n + parts - 1) / parts;
+      pending_ = parts - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    fn(0, std::min(n, chunk_));
+    std::unique_lock<std::mutex> g(mu_);
+    done_.wait(g, [this]() { return pending_ == 0; });
+  }
+
+ private:
+  void loop(int w) {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(int64_t, int64_t)>* fn;
+      int64_t a, b;
+      {
+        std::unique_lock<std::mutex> g(mu_);
+        cv_.wait(g, [&]() { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        if (w >= parts_) continue;
+        fn = fn_;
+        a = w * chunk_;
+        b = std::min(n_, a + chunk_);
+      }
+      t_in_pool = true;
+      if (a < b) (*fn)(a, b);
+      t_in_pool = false;
+      {
+        std::lock_guard<std::mutex> g(mu_);
+        if (--pending_ == 0) done_.notify_one();
+      }
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_, call_mu_;
+  std::condition_variable cv_, done_;
+  const std::function<void(int64_t, int64_t)>* fn_ = nullptr;
+  int64_t n_ = 0, chunk_ = 0;
+  int parts_ = 0, pending_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+}  // namespace
+
 void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int64_t)>& fn) {
-  if (nthreads <= 1 || n < 64) {
+  static Workers pool(host_threads());
+  const int parts = (int)std::min<int64_t>(std::min(nthreads, pool.size()), n);
+  if (parts <= 1 || t_in_pool) {   // nested calls run inline
     fn(0, n);
     return;
   }
-  std::vector<std::thread> th;
-  int64_t chunk = (n + nthreads - 1) / nthreads;
-  for (int t = 0; t < nthreads; ++t) {
-    int64_t a = t * chunk, b = std::min(n, a + chunk);
-    if (a >= b) break;
-    th.emplace_back([&fn, a, b]() { fn(a, b); });
-  }
-  for (auto& x : th) x.join();
+  t_in_pool = true;
+  pool.run(n, parts, fn);
+  t_in_pool = false;
 }
 
 int host_threads() {
@@ -286,51 +358,92 @@ void stencil_setup(Handle& H) {
 
 // ---------------------------------------------------------------------------------------------
 // Small dense complex linear algebra for TT-cross and ACA.
+// Row chunks for the host threads of a dense kernel over m rows (at least 2048 rows each).
+static int row_threads(int64_t m) { return (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), m / 2048)); }
+
 void qr_mgs2(std::vector<cxd>& A, int m, int n, std::vector<cxd>& Rm) {
   // Classical Gram-Schmidt applied twice; a column that is numerically dependent on the previous
   // ones is replaced by a fixed pseudo-random vector (then orthogonalised), so Q always has full
-  // column rank and the maximum-volume submatrix stays invertible.
+  // column rank and the maximum-volume submatrix stays invertible. The columns are worked on in a
+  // column-major copy (contiguous dot products and updates), the rows split over host threads.
   Rm.assign((size_t)n * n, cxd{0, 0});
-  double maxnorm = 0;
-  for (int j = 0; j < n; ++j) {
-    double c = 0;
-    for (int r = 0; r < m; ++r) c += A[(size_t)r * n + j].re * A[(size_t)r * n + j].re + A[(size_t)r * n + j].im * A[(size_t)r * n + j].im;
-    maxnorm = std::max(maxnorm, sqrt(c));
-  }
-  uint64_t state = 0x9E3779B97F4A7C15ull;
-  for (int j = 0; j < n; ++j) {
-    for (int attempt = 0; attempt < 3; ++attempt) {
-      double before = 0;
-      for (int r = 0; r < m; ++r) before += A[(size_t)r * n + j].re * A[(size_t)r * n + j].re + A[(size_t)r * n + j].im * A[(size_t)r * n + j].im;
-      before = sqrt(before);
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int i = 0; i < j; ++i) {
-          cxd d = {0, 0};
-          for (int r = 0; r < m; ++r) d += mul_conj_a(A[(size_t)r * n + i], A[(size_t)r * n + j]);
-          for (int r = 0; r < m; ++r) A[(size_t)r * n + j] -= d * A[(size_t)r * n + i];
-          if (attempt == 0) Rm[(size_t)i * n + j] += d;
-        }
+  std::vector<cxd> Q((size_t)m * n);
+  for (int r = 0; r < m; ++r)
+    for (int j = 0; j < n; ++j) Q[(size_t)j * m + r] = A[(size_t)r * n + j];
+  const int nt = row_threads(m);
+  const int64_t chunk = (m + nt - 1) / nt;
+  auto norm2 = [&](const cxd* q) {
+    std::vector<double> part(nt, 0.0);
+    parallel_for(nt, nt, [&](int64_t t0, int64_t t1) {
+      for (int64_t t = t0; t < t1; ++t) {
+        double acc = 0;
+        for (int64_t r = t * chunk; r < std::min<int64_t>(m, (t + 1) * chunk); ++r) acc += q[r].re * q[r].re + q[r].im * q[r].im;
+        part[t] = acc;
       }
-      double after = 0;
-      for (int r = 0; r < m; ++r) after += A[(size_t)r * n + j].re * A[(size_t)r * n + j].re + A[(size_t)r * n + j].im * A[(size_t)r * n + j].im;
-      after = sqrt(after);
+    });
+    double s2 = 0;
+    for (double v : part) s2 += v;
+    return s2;
+  };
+  double maxnorm = 0;
+  for (int j = 0; j < n; ++j) maxnorm = std::max(maxnorm, sqrt(norm2(&Q[(size_t)j * m])));
+  uint64_t state = 0x9E3779B97F4A7C15ull;
+  std::vector<cxd> part((size_t)nt * std::max(n, 1)), d(std::max(n, 1));
+  for (int j = 0; j < n; ++j) {
+    cxd* qj = &Q[(size_t)j * m];
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      const double before = sqrt(norm2(qj));
+      for (int pass = 0; pass < 2 && j > 0; ++pass) {
+        // d = Q[:, :j]^H q_j (partial sums per row chunk), then q_j -= Q[:, :j] d
+        parallel_for(nt, nt, [&](int64_t t0, int64_t t1) {
+          for (int64_t t = t0; t < t1; ++t) {
+            const int64_t r0 = t * chunk, r1 = std::min<int64_t>(m, r0 + chunk);
+            for (int i = 0; i < j; ++i) {
+              const cxd* qi = &Q[(size_t)i * m];
+              cxd acc = {0, 0};
+              for (int64_t r = r0; r < r1; ++r) acc += mul_conj_a(qi[r], qj[r]);
+              part[(size_t)t * n + i] = acc;
+            }
+          }
+        });
+        for (int i = 0; i < j; ++i) {
+          cxd acc = {0, 0};
+          for (int t = 0; t < nt; ++t) acc += part[(size_t)t * n + i];
+          d[i] = acc;
+          if (attempt == 0) Rm[(size_t)i * n + j] += acc;
+        }
+        parallel_for(nt, nt, [&](int64_t t0, int64_t t1) {
+          for (int64_t t = t0; t < t1; ++t) {
+            const int64_t r0 = t * chunk, r1 = std::min<int64_t>(m, r0 + chunk);
+            for (int i = 0; i < j; ++i) {
+              const cxd* qi = &Q[(size_t)i * m];
+              const cxd di = d[i];
+              for (int64_t r = r0; r < r1; ++r) qj[r] -= di * qi[r];
+            }
+          }
+        });
+      }
+      const double after = sqrt(norm2(qj));
       if (after > 1e-12 * std::max(before, maxnorm) && after > 0) break;
       for (int r = 0; r < m; ++r) {
         state ^= state << 13; state ^= state >> 7; state ^= state << 17;
-        A[(size_t)r * n + j] = {(double)(state % 2001) / 1000.0 - 1.0, 0.0};
+        qj[r] = {(double)(state % 2001) / 1000.0 - 1.0, 0.0};
       }
     }
-    double nr = 0;
-    for (int r = 0; r < m; ++r) nr += A[(size_t)r * n + j].re * A[(size_t)r * n + j].re + A[(size_t)r * n + j].im * A[(size_t)r * n + j].im;
-    nr = sqrt(nr);
+    const double nr = sqrt(norm2(qj));
     Rm[(size_t)j * n + j] = {nr, 0};
-    double inv = nr > 0 ? 1.0 / nr : 0.0;
-    for (int r = 0; r < m; ++r) A[(size_t)r * n + j] = inv * A[(size_t)r * n + j];
+    const double inv = nr > 0 ? 1.0 / nr : 0.0;
+    for (int r = 0; r < m; ++r) qj[r] = inv * qj[r];
   }
+  for (int r = 0; r < m; ++r)
+    for (int j = 0; j < n; ++j) A[(size_t)r * n + j] = Q[(size_t)j * m + r];
 }
 
 bool lu_solve(std::vector<cxd> A, int n, std::vector<cxd>& B, int nrhs) {
+  // partial pivoting on A (row-major n x n); every row operation on B (n x nrhs, row-major) is a
+  // contiguous sweep, the right-hand sides split over host threads
   std::vector<int> piv(n);
+  std::vector<cxd> F((size_t)n * n, cxd{0, 0});   // multipliers, applied to B afterwards
   for (int c = 0; c < n; ++c) {
     int p = c;
     double best = -1;
@@ -339,36 +452,52 @@ bool lu_solve(std::vector<cxd> A, int n, std::vector<cxd>& B, int nrhs) {
       if (v > best) { best = v; p = r; }
     }
     if (best <= 0) return false;
-    if (p != c) {
+    piv[c] = p;
+    if (p != c)
       for (int j = 0; j < n; ++j) std::swap(A[(size_t)c * n + j], A[(size_t)p * n + j]);
-      for (int j = 0; j < nrhs; ++j) std::swap(B[(size_t)c * nrhs + j], B[(size_t)p * nrhs + j]);
-    }
-    cxd inv = cinv(A[(size_t)c * n + c]);
+    const cxd inv = cinv(A[(size_t)c * n + c]);
     for (int r = c + 1; r < n; ++r) {
-      cxd f = A[(size_t)r * n + c] * inv;
+      const cxd f = A[(size_t)r * n + c] * inv;
+      F[(size_t)r * n + c] = f;
       if (f.re == 0 && f.im == 0) continue;
       for (int j = c; j < n; ++j) A[(size_t)r * n + j] -= f * A[(size_t)c * n + j];
-      for (int j = 0; j < nrhs; ++j) B[(size_t)r * nrhs + j] -= f * B[(size_t)c * nrhs + j];
     }
   }
-  for (int c = n - 1; c >= 0; --c) {
-    cxd inv = cinv(A[(size_t)c * n + c]);
-    for (int j = 0; j < nrhs; ++j) {
-      cxd s = B[(size_t)c * nrhs + j];
-      for (int k = c + 1; k < n; ++k) s -= A[(size_t)c * n + k] * B[(size_t)k * nrhs + j];
-      B[(size_t)c * nrhs + j] = s * inv;
+  const int nt = row_threads(nrhs);
+  const int64_t chunk = (nrhs + nt - 1) / nt;
+  parallel_for(nt, nt, [&](int64_t t0, int64_t t1) {
+    for (int64_t t = t0; t < t1; ++t) {
+      const int64_t j0 = t * chunk, j1 = std::min<int64_t>(nrhs, j0 + chunk);
+      if (j0 >= j1) continue;
+      for (int c = 0; c < n; ++c) {
+        if (piv[c] != c)
+          for (int64_t j = j0; j < j1; ++j) std::swap(B[(size_t)c * nrhs + j], B[(size_t)piv[c] * nrhs + j]);
+        for (int r = c + 1; r < n; ++r) {
+          const cxd f = F[(size_t)r * n + c];
+          if (f.re == 0 && f.im == 0) continue;
+          for (int64_t j = j0; j < j1; ++j) B[(size_t)r * nrhs + j] -= f * B[(size_t)c * nrhs + j];
+        }
+      }
+      for (int c = n - 1; c >= 0; --c) {
+        for (int k = c + 1; k < n; ++k) {
+          const cxd a = A[(size_t)c * n + k];
+          for (int64_t j = j0; j < j1; ++j) B[(size_t)c * nrhs + j] -= a * B[(size_t)k * nrhs + j];
+        }
+        const cxd inv = cinv(A[(size_t)c * n + c]);
+        for (int64_t j = j0; j < j1; ++j) B[(size_t)c * nrhs + j] = B[(size_t)c * nrhs + j] * inv;
+      }
     }
-  }
+  });
   return true;
 }
 
-// maxvol: r rows of the m x r matrix Q forming a submatrix of (locally) maximal volume.
 std::vector<int> maxvol(const std::vector<cxd>& Q, int m, int r) {
   std::vector<int> rows;
-  // greedy start: pivoted Gaussian elimination on a copy
+  // greedy start: pivoted Gaussian elimination on a copy (row updates split over host threads)
   std::vector<cxd> A = Q;
   std::vector<int> perm(m);
   for (int i = 0; i < m; ++i) perm[i] = i;
+  const int nt = row_threads(m);
   for (int c = 0; c < r; ++c) {
     int p = c;
     double best = -1;
@@ -380,11 +509,13 @@ std::vector<int> maxvol(const std::vector<cxd>& Q, int m, int r) {
     std::swap(perm[c], perm[p]);
     for (int j = 0; j < r; ++j) std::swap(A[(size_t)c * r + j], A[(size_t)p * r + j]);
     if (best <= 0) continue;
-    cxd inv = cinv(A[(size_t)c * r + c]);
-    for (int i = c + 1; i < m; ++i) {
-      cxd f = A[(size_t)i * r + c] * inv;
-      for (int j = c; j < r; ++j) A[(size_t)i * r + j] -= f * A[(size_t)c * r + j];
-    }
+    const cxd inv = cinv(A[(size_t)c * r + c]);
+    parallel_for(m - c - 1, nt, [&](int64_t a0, int64_t a1) {
+      for (int64_t i = c + 1 + a0; i < c + 1 + a1; ++i) {
+        const cxd f = A[(size_t)i * r + c] * inv;
+        for (int j = c; j < r; ++j) A[(size_t)i * r + j] -= f * A[(size_t)c * r + j];
+      }
+    });
   }
   rows.assign(perm.begin(), perm.begin() + r);
   // refinement: B = Q Q_rows^{-1} (m x r); while some |B[i][j]| > 1 + 1e-2 swap row i into
@@ -395,30 +526,50 @@ std::vector<int> maxvol(const std::vector<cxd>& Q, int m, int r) {
   for (int a = 0; a < r; ++a)
     for (int i = 0; i < m; ++i) BT[(size_t)a * m + i] = Q[(size_t)i * r + a];
   if (!lu_solve(S, r, BT, m)) return rows;                                          // BT = B^T
+  // the search and the rank-one update run over rows of B^T split among host threads; ties go
+  // to the lowest (a, i) as in a sequential scan
+  const int ntr = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)host_threads(), (int64_t)r,
+                                                                (int64_t)m * r / 65536}));
+  std::vector<double> tbest(ntr);
+  std::vector<int> tbi(ntr), tbj(ntr);
+  std::vector<cxd> col(m), rowv(r);
   for (int it = 0; it < 200; ++it) {
+    parallel_for(ntr, ntr, [&](int64_t t0, int64_t t1) {
+      for (int64_t t = t0; t < t1; ++t) {
+        double best = 0;
+        int bi = -1, bj = -1;
+        for (int a = (int)(t * r / ntr); a < (int)((t + 1) * r / ntr); ++a)
+          for (int i = 0; i < m; ++i) {
+            const cxd v = BT[(size_t)a * m + i];
+            const double av = v.re * v.re + v.im * v.im;
+            if (av > best) { best = av; bi = i; bj = a; }
+          }
+        tbest[t] = best;
+        tbi[t] = bi;
+        tbj[t] = bj;
+      }
+    });
     double best = 0;
     int bi = -1, bj = -1;
-    for (int a = 0; a < r; ++a)
-      for (int i = 0; i < m; ++i) {
-        cxd v = BT[(size_t)a * m + i];
-        double av = v.re * v.re + v.im * v.im;
-        if (av > best) { best = av; bi = i; bj = a; }
-      }
+    for (int t = 0; t < ntr; ++t)
+      if (tbest[t] > best) { best = tbest[t]; bi = tbi[t]; bj = tbj[t]; }
     if (best <= (1.0 + 1e-2) * (1.0 + 1e-2) || bi < 0) break;
-    cxd piv = BT[(size_t)bj * m + bi];
-    cxd ipiv = cinv(piv);
-    std::vector<cxd> col(m), rowv(r);
+    const cxd ipiv = cinv(BT[(size_t)bj * m + bi]);
     for (int i = 0; i < m; ++i) col[i] = BT[(size_t)bj * m + i];                   // B[:, j]
     for (int a = 0; a < r; ++a) rowv[a] = BT[(size_t)a * m + bi];                  // B[i, :]
     rowv[bj] -= cxd{1.0, 0.0};
-    for (int a = 0; a < r; ++a) {
-      cxd f = rowv[a] * ipiv;
-      if (f.re == 0 && f.im == 0) continue;
-      for (int i = 0; i < m; ++i) BT[(size_t)a * m + i] -= col[i] * f;
-    }
+    parallel_for(ntr, ntr, [&](int64_t t0, int64_t t1) {
+      for (int64_t t = t0; t < t1; ++t)
+        for (int a = (int)(t * r / ntr); a < (int)((t + 1) * r / ntr); ++a) {
+          const cxd f = rowv[a] * ipiv;
+          if (f.re == 0 && f.im == 0) continue;
+          for (int i = 0; i < m; ++i) BT[(size_t)a * m + i] -= col[i] * f;
+        }
+    });
     rows[bj] = bi;
   }
   return rows;
 }
+
 
 }  // namespace vsie
