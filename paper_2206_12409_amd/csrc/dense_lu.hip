@@ -8,47 +8,51 @@
 // Right-looking blocked algorithm with panels of LU_NB columns:
 //   1. panel: for each column j, pivot search over rows j.. (|re| + |im|, ties to the lowest row),
 //      interchange of the two rows inside the panel, then one wavefront per row below scales the
-//      multiplier and applies the rank-one update to the rest of the panel row;
+//      multiplier and applies the rank-one update to the rest of the panel row; the update also
+//      reduces the next column's pivot candidates per workgroup, so only a panel's first column
+//      is searched by reading it;
 //   2. the panel's interchanges are applied to the columns left and right of it;
 //   3. the diagonal block's unit-lower and upper triangles are inverted (one workgroup, kept for
 //      the solves), U12 = L11^-1 A12 is one matrix-core GEMM;
-//   4. trailing update A22 -= L21 U12 on the matrix cores (k_zgemm_mfma, negated accumulation).
+//   4. trailing update A22 -= L21 U12 on the matrix cores (k_zgemm_mfma, negated accumulation),
+//      taken once per pair of panels (depth 2 LU_NB): the second panel of a pair is first updated
+//      by the first alone.
 // Solves gather the rows by the pivot permutation and run block forward and back substitution
 // with the inverted diagonal blocks, each block step a pair of GEMMs.
 #include "dense_lu.h"
 
 namespace vsie {
 
-// pivot of column j: row p >= j maximising |re| + |im|; rows j and p swapped inside the panel
-// columns [k, kend). One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_lu_pivot(cxd* __restrict__ A, int64_t lda, int n, int j, int k, int kend,
-                                                   int* __restrict__ ipiv, int* __restrict__ info) {
-  __shared__ double bv[1024];
-  __shared__ int bi[1024];
-  double best = -1;
-  int bidx = n;
-  for (int i = j + threadIdx.x; i < n; i += 1024) {
-    const cxd a = A[(int64_t)i * lda + j];
-    const double v = fabs(a.re) + fabs(a.im);
-    if (v > best) {
-      best = v;
-      bidx = i;
+// (best, bidx) of every thread of a 1024-thread workgroup reduced to the largest |re| + |im|, lowest
+// row among ties; then ipiv[j] = p, info set on an exactly zero (or NaN) column, rows j and p
+// swapped inside the panel columns [k, kend)
+__device__ void pivot_reduce_finish(double best, int bidx, cxd* __restrict__ A, int64_t lda, int n, int j, int k,
+                                    int kend, int* __restrict__ ipiv, int* __restrict__ info) {
+  __shared__ double bv[16];
+  __shared__ int bi[16];
+  auto combine = [&](double o, int oi) {
+    if (o > best || (o == best && oi < bidx)) {
+      best = o;
+      bidx = oi;
     }
+  };
+  for (int off = 32; off > 0; off >>= 1) combine(__shfl_xor(best, off), __shfl_xor(bidx, off));
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) {
+    bv[wave] = best;
+    bi[wave] = bidx;
   }
-  bv[threadIdx.x] = best;
-  bi[threadIdx.x] = bidx;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      const double o = bv[threadIdx.x + s];
-      const int oi = bi[threadIdx.x + s];
-      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
-        bv[threadIdx.x] = o;
-        bi[threadIdx.x] = oi;
-      }
+  if (wave == 0) {
+    best = lane < 16 ? bv[lane] : -1;
+    bidx = lane < 16 ? bi[lane] : n;
+    for (int off = 8; off > 0; off >>= 1) combine(__shfl_xor(best, off), __shfl_xor(bidx, off));
+    if (lane == 0) {
+      bv[0] = best;
+      bi[0] = bidx;
     }
-    __syncthreads();
   }
+  __syncthreads();
   const int p = bi[0];
   if (threadIdx.x == 0) {
     ipiv[j] = p;
@@ -63,18 +67,109 @@ __global__ __launch_bounds__(1024) void k_lu_pivot(cxd* __restrict__ A, int64_t 
   }
 }
 
+// pivot of the first column j of a panel: row p >= j maximising |re| + |im|, found by reading the
+// column; rows j and p swapped inside the panel columns [k, kend). One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_lu_pivot(cxd* __restrict__ A, int64_t lda, int n, int j, int k, int kend,
+                                                   int* __restrict__ ipiv, int* __restrict__ info) {
+  double best = -1;
+  int bidx = n;
+  // eight independent loads in flight per thread; within a thread rows increase, so the strict
+  // comparison keeps the lowest row among equal magnitudes (NaN never wins)
+  constexpr int U = 8;
+  for (int i0 = j + (int)threadIdx.x; i0 < n; i0 += 1024 * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 1024 * u;
+      v[u] = -1;
+      if (i < n) {
+        const cxd a = A[(int64_t)i * lda + j];
+        v[u] = fabs(a.re) + fabs(a.im);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (v[u] > best) {
+        best = v[u];
+        bidx = i0 + 1024 * u;
+      }
+  }
+  pivot_reduce_finish(best, bidx, A, lda, n, j, k, kend, ipiv, info);
+}
+
+// pivot of the other columns of a panel, from the nparts candidates the rank-one update of column
+// j - 1 left (one per workgroup, in row order): the same choice as k_lu_pivot without reading
+// a column of the matrix (one row per page at these leading dimensions).
+__global__ __launch_bounds__(1024) void k_lu_pivot_parts(cxd* __restrict__ A, int64_t lda, int n, int j, int k,
+                                                         int kend, const double* __restrict__ pv,
+                                                         const int* __restrict__ pi, int nparts,
+                                                         int* __restrict__ ipiv, int* __restrict__ info) {
+  double best = -1;
+  int bidx = n;
+  constexpr int U = 4;
+  for (int b0 = (int)threadIdx.x; b0 < nparts; b0 += 1024 * U) {
+    double v[U];
+    int r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + 1024 * u;
+      v[u] = b < nparts ? pv[b] : -1;
+      r[u] = b < nparts ? pi[b] : n;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (v[u] > best) {
+        best = v[u];
+        bidx = r[u];
+      }
+  }
+  pivot_reduce_finish(best, bidx, A, lda, n, j, k, kend, ipiv, info);
+}
+
 // rows i > j: l = A[i][j] / A[j][j], A[i][j] = l, A[i][c] -= l A[j][c] for panel columns c in
-// (j, kend). One wavefront per row, lane = column offset; 4 rows per workgroup.
-__global__ __launch_bounds__(256) void k_lu_rank1(cxd* __restrict__ A, int64_t lda, int n, int j, int kend) {
-  const int i = j + 1 + blockIdx.x * 4 + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
-  if (i >= n) return;
-  const cxd piv = A[(int64_t)j * lda + j];
-  if (piv.re == 0 && piv.im == 0) return;   // singular column, reported through info
-  const cxd l = A[(int64_t)i * lda + j] * cinv(piv);
+// (j, kend). One wavefront per row, lane = column offset; 4 rows per workgroup. With pv given, each
+// workgroup also leaves the pivot candidate of column j + 1 among its rows (largest |re| + |im| of
+// the updated entries, lowest row among ties, NaN never chosen) in pv/pi[blockIdx.x].
+__global__ __launch_bounds__(256) void k_lu_rank1(cxd* __restrict__ A, int64_t lda, int n, int j, int kend,
+                                                  double* __restrict__ pv, int* __restrict__ pi) {
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int i = j + 1 + blockIdx.x * 4 + w;
   const int c = j + 1 + lane;
-  if (c < kend) A[(int64_t)i * lda + c] -= l * A[(int64_t)j * lda + c];
-  if (lane == 0) A[(int64_t)i * lda + j] = l;
+  double v = -1;
+  if (i < n) {
+    const cxd piv = A[(int64_t)j * lda + j];
+    if (piv.re != 0 || piv.im != 0) {
+      const cxd l = A[(int64_t)i * lda + j] * cinv(piv);
+      if (c < kend) {
+        const cxd t = A[(int64_t)i * lda + c] - l * A[(int64_t)j * lda + c];
+        A[(int64_t)i * lda + c] = t;
+        v = fabs(t.re) + fabs(t.im);
+      }
+      if (lane == 0) A[(int64_t)i * lda + j] = l;
+    } else if (c < kend) {   // singular column, reported through info: entries left as they are
+      const cxd t = A[(int64_t)i * lda + c];
+      v = fabs(t.re) + fabs(t.im);
+    }
+  }
+  if (!pv) return;
+  if (lane == 0) {
+    sv[w] = v;
+    si[w] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double best = -1;
+    int bidx = n;
+    for (int q = 0; q < 4; ++q)
+      if (sv[q] > best) {
+        best = sv[q];
+        bidx = si[q];
+      }
+    pv[blockIdx.x] = best;
+    pi[blockIdx.x] = bidx;
+  }
 }
 
 // apply the interchanges j <-> ipiv[j], j in [k, kend), to every column outside [k, kend)
@@ -92,39 +187,37 @@ __global__ void k_lu_laswp(cxd* __restrict__ A, int64_t lda, int n, int k, int k
   }
 }
 
-// inverses of the unit-lower and the upper triangle of the nb x nb diagonal block at (k, k):
-// threads 0..nb-1 build the columns of L^-1, threads 64..64+nb-1 those of U^-1 (row-major,
-// leading dimension LU_NB). The block is staged in LDS; each thread writes only its own column.
-__global__ __launch_bounds__(128) void k_lu_tri_inv(const cxd* __restrict__ A, int64_t lda, int k, int nb,
-                                                    cxd* __restrict__ Linv, cxd* __restrict__ Uinv) {
+// inverses of the unit-lower and the upper triangle of the nb x nb diagonal block at (k, k) (row-major,
+// leading dimension LU_NB). The block is staged in LDS; one wavefront per column of L^-1 or U^-1
+// (16 wavefronts, 8 columns each), lane r holding entry r: the substitution runs column by column
+// of the triangle, each finished entry broadcast across the wavefront and eliminated from the rows
+// still open.
+__global__ __launch_bounds__(1024) void k_lu_tri_inv(const cxd* __restrict__ A, int64_t lda, int k, int nb,
+                                                     cxd* __restrict__ Linv, cxd* __restrict__ Uinv) {
   __shared__ cxd D[LU_NB][LU_NB + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += 128) D[e / nb][e % nb] = A[(int64_t)(k + e / nb) * lda + k + e % nb];
+  for (int e = threadIdx.x; e < nb * nb; e += 1024) D[e / nb][e % nb] = A[(int64_t)(k + e / nb) * lda + k + e % nb];
   __syncthreads();
-  const int c = threadIdx.x % 64;
-  if (c >= nb) return;
-  if (threadIdx.x < 64) {
-    // column c of L^-1: x_r = 0 (r < c), x_c = 1, x_r = -sum_{c <= s < r} L[r][s] x_s
-    for (int r = 0; r < nb; ++r) {
-      cxd x = {r == c ? 1.0 : 0.0, 0.0};
-      if (r > c) {
-        cxd s = {0, 0};
-        for (int q = c; q < r; ++q) s += D[r][q] * Linv[q * LU_NB + c];
-        x = cxd{-s.re, -s.im};
+  const int wave = threadIdx.x / 64, r = threadIdx.x % 64;
+  for (int g = wave; g < 2 * LU_NB; g += 16) {
+    const bool lower = g < LU_NB;
+    const int c = lower ? g : g - LU_NB;
+    if (c >= nb) continue;
+    cxd x = {r == c ? 1.0 : 0.0, 0.0};
+    if (lower) {
+      // L x = e_c: x_s final at step s, then x_r -= L[r][s] x_s for r > s
+      for (int s = c; s + 1 < nb; ++s) {
+        const cxd xs = {__shfl(x.re, s), __shfl(x.im, s)};
+        if (r > s && r < nb) x -= D[r][s] * xs;
       }
-      Linv[r * LU_NB + c] = x;
-    }
-  } else {
-    // column c of U^-1: x_r = 0 (r > c), x_c = 1 / U[c][c], x_r = -(sum_{r < s <= c} U[r][s] x_s) / U[r][r]
-    for (int r = nb - 1; r >= 0; --r) {
-      cxd x = {0, 0};
-      if (r == c) {
-        x = cinv(D[c][c]);
-      } else if (r < c) {
-        cxd s = {0, 0};
-        for (int q = r + 1; q <= c; ++q) s += D[r][q] * Uinv[q * LU_NB + c];
-        x = cxd{-s.re, -s.im} * cinv(D[r][r]);
+      if (r < nb) Linv[r * LU_NB + c] = x;
+    } else {
+      // U x = e_c, from the bottom: x_s /= U[s][s] at step s, then x_r -= U[r][s] x_s for r < s
+      for (int s = c; s >= 0; --s) {
+        if (r == s) x = x * cinv(D[s][s]);
+        const cxd xs = {__shfl(x.re, s), __shfl(x.im, s)};
+        if (r < s) x -= D[r][s] * xs;
       }
-      Uinv[r * LU_NB + c] = x;
+      if (r < nb) Uinv[r * LU_NB + c] = x;
     }
   }
 }
@@ -176,29 +269,67 @@ static void gemm_rm(hipStream_t st, int M, int N, int K, const cxd* A, int64_t l
 
 int64_t lu_work_elems(int n) { return (int64_t)LU_NB * std::max(n, 1); }
 
+// U rows [r0, r0 + nb) over columns [c0, c0 + w): A[r0.., c0..] = L^-1 A[r0.., c0..], L^-1 the inverted
+// unit-lower diagonal block Li (the block is copied out first: the GEMM writes where it reads)
+static void lu_urows(hipStream_t st, cxd* A, int64_t lda, int r0, int nb, int c0, int w, const cxd* Li, cxd* work) {
+  if (w <= 0) return;
+  hipLaunchKernelGGL(k_copy2d, dim3(nblocks((int64_t)nb * w, 256)), dim3(256), 0, st, A + (int64_t)r0 * lda + c0, lda,
+                     work, (int64_t)w, nb, w);
+  gemm_rm(st, nb, w, nb, Li, LU_NB, work, w, A + (int64_t)r0 * lda + c0, lda, 0, 0);
+}
+
 void lu_factor(hipStream_t st, DenseLU& F, cxd* work) {
   const int n = F.n;
   const int64_t lda = F.lda;
   cxd* A = F.A;
   VSIE_HIP(hipMemsetAsync(F.d_info, 0, sizeof(int), st));
-  for (int k = 0, p = 0; k < n; k += LU_NB, ++p) {
-    const int nb = std::min(LU_NB, n - k);
+  // one panel of nb columns at k: pivots and rank-one updates inside it, its interchanges applied
+  // to every other column, inverses of its diagonal triangles
+  auto panel = [&](int k, int nb) {
     const int kend = k + nb;
+    // pivot candidates of the next column live in the front of work (free until the U rows)
+    double* pv = reinterpret_cast<double*>(work);
+    int* pi = reinterpret_cast<int*>(pv + (n + 3) / 4);
     for (int j = k; j < kend; ++j) {
-      hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(1024), 0, st, A, lda, n, j, k, kend, F.d_ipiv, F.d_info);
-      if (j + 1 < n) hipLaunchKernelGGL(k_lu_rank1, dim3(nblocks(n - j - 1, 4)), dim3(256), 0, st, A, lda, n, j, kend);
+      if (j == k)
+        hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(1024), 0, st, A, lda, n, j, k, kend, F.d_ipiv, F.d_info);
+      else
+        hipLaunchKernelGGL(k_lu_pivot_parts, dim3(1), dim3(1024), 0, st, A, lda, n, j, k, kend, pv, pi,
+                           (int)nblocks(n - j, 4), F.d_ipiv, F.d_info);
+      if (j + 1 < n)
+        hipLaunchKernelGGL(k_lu_rank1, dim3(nblocks(n - j - 1, 4)), dim3(256), 0, st, A, lda, n, j, kend,
+                           j + 1 < kend ? pv : nullptr, pi);
     }
     if (n > nb) hipLaunchKernelGGL(k_lu_laswp, dim3(nblocks(n - nb, 256)), dim3(256), 0, st, A, lda, n, k, kend, F.d_ipiv);
-    cxd* Li = F.Linv + (int64_t)p * LU_NB * LU_NB;
-    cxd* Ui = F.Uinv + (int64_t)p * LU_NB * LU_NB;
-    hipLaunchKernelGGL(k_lu_tri_inv, dim3(1), dim3(128), 0, st, A, lda, k, nb, Li, Ui);
+    const int64_t blk = (int64_t)(k / LU_NB) * LU_NB * LU_NB;
+    hipLaunchKernelGGL(k_lu_tri_inv, dim3(1), dim3(1024), 0, st, A, lda, k, nb, F.Linv + blk, F.Uinv + blk);
+  };
+  // Two panels a = [k, km), b = [km, kend) per step: b is brought up to date by a alone, and the
+  // trailing matrix takes both in one update of depth kend - k (twice the panel width, which halves
+  // the passes over A22). Row interchanges of b reach the columns of a and of the trailing matrix
+  // through k_lu_laswp; the deferred update of those rows is row-wise, so the result is that of
+  // one-panel-at-a-time elimination.
+  for (int k = 0; k < n; k += 2 * LU_NB) {
+    const int kend = std::min(k + 2 * LU_NB, n);
+    const int km = std::min(k + LU_NB, kend), nba = km - k, nbb = kend - km;
+    const cxd* La = F.Linv + (int64_t)(k / LU_NB) * LU_NB * LU_NB;
+    const cxd* Lb = F.Linv + (int64_t)(km / LU_NB) * LU_NB * LU_NB;
+    panel(k, nba);
+    if (nbb > 0) {
+      lu_urows(st, A, lda, k, nba, km, nbb, La, work);
+      gemm_rm(st, n - km, nbb, nba, A + (int64_t)km * lda + k, lda, A + (int64_t)k * lda + km, lda,
+              A + (int64_t)km * lda + km, lda, 1, 1);
+      panel(km, nbb);
+    }
     const int nr = n - kend;
     if (nr > 0) {
-      // U12 = L11^-1 A12 (A12 copied out first), then A22 -= L21 U12
-      hipLaunchKernelGGL(k_copy2d, dim3(nblocks((int64_t)nb * nr, 256)), dim3(256), 0, st, A + (int64_t)k * lda + kend,
-                         lda, work, (int64_t)nr, nb, nr);
-      gemm_rm(st, nb, nr, nb, Li, LU_NB, work, nr, A + (int64_t)k * lda + kend, lda, 0, 0);
-      gemm_rm(st, nr, nr, nb, A + (int64_t)kend * lda + k, lda, A + (int64_t)k * lda + kend, lda,
+      lu_urows(st, A, lda, k, nba, kend, nr, La, work);
+      if (nbb > 0) {
+        gemm_rm(st, nbb, nr, nba, A + (int64_t)km * lda + k, lda, A + (int64_t)k * lda + kend, lda,
+                A + (int64_t)km * lda + kend, lda, 1, 1);
+        lu_urows(st, A, lda, km, nbb, kend, nr, Lb, work);
+      }
+      gemm_rm(st, nr, nr, kend - k, A + (int64_t)kend * lda + k, lda, A + (int64_t)k * lda + kend, lda,
               A + (int64_t)kend * lda + kend, lda, 1, 1);
     }
   }

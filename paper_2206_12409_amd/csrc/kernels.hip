@@ -1381,13 +1381,17 @@ __global__ __launch_bounds__(256) void k_zgemm_mfma(GemmSet<R> S) {
       cr[u][v] = V{0, 0, 0, 0};
       ci[u][v] = V{0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  // FP64: the next K chunk is loaded into registers while the current one is multiplied from LDS
+  // (FP32 keeps load-then-store: the extra registers would cost it a wavefront per SIMD)
+  constexpr bool prefetch = sizeof(R) == 8;
+  cx<R> pa[4], pb[4];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = threadIdx.x + 256 * q;
       const int r = a_rowfast ? e % 64 : e / 16, c = a_rowfast ? e / 64 : e % 16;
       const int i = i0 + r, k = k0 + c;
-      As[r][c] = (i < g.M && k < K) ? A[i * g.sar + k * g.sac] : cx<R>{0, 0};
+      pa[q] = (i < g.M && k < K) ? A[i * g.sar + k * g.sac] : cx<R>{0, 0};
       const int rb = b_rowfast ? e % 16 : e / 64, cb = b_rowfast ? e / 16 : e % 64;
       const int kk = k0 + rb, j = j0 + cb;
       cx<R> v = {0, 0};
@@ -1396,9 +1400,20 @@ __global__ __launch_bounds__(256) void k_zgemm_mfma(GemmSet<R> S) {
         v = B[idx];
         if (mB && !mB[idx]) v = cx<R>{0, 0};
       }
-      Bs[rb][cb] = v;
+      pb[q] = v;
+    }
+  };
+  if (prefetch) load(0);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    if (!prefetch) load(k0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      As[a_rowfast ? e % 64 : e / 16][a_rowfast ? e / 64 : e % 16] = pa[q];
+      Bs[b_rowfast ? e % 16 : e / 64][b_rowfast ? e / 16 : e % 64] = pb[q];
     }
     __syncthreads();
+    if (prefetch && k0 + 16 < K) load(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 16; ks += 4) {
       cx<R> a[2], b[2];
