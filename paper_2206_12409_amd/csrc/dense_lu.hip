@@ -15,8 +15,8 @@
 //   3. the diagonal block's unit-lower and upper triangles are inverted (one workgroup, kept for
 //      the solves), U12 = L11^-1 A12 is one matrix-core GEMM;
 //   4. trailing update A22 -= L21 U12 on the matrix cores (k_zgemm_mfma, negated accumulation),
-//      taken once per pair of panels (depth 2 LU_NB): the second panel of a pair is first updated
-//      by the first alone.
+//      taken once per group of LU_GROUP panels (depth LU_GROUP LU_NB); inside a group each panel is
+//      first updated by the group's earlier panels alone.
 // Solves gather the rows by the pivot permutation and run block forward and back substitution
 // with the inverted diagonal blocks, each block step a pair of GEMMs.
 #include "dense_lu.h"
@@ -278,6 +278,8 @@ static void lu_urows(hipStream_t st, cxd* A, int64_t lda, int r0, int nb, int c0
   gemm_rm(st, nb, w, nb, Li, LU_NB, work, w, A + (int64_t)r0 * lda + c0, lda, 0, 0);
 }
 
+constexpr int LU_GROUP = 4;
+
 void lu_factor(hipStream_t st, DenseLU& F, cxd* work) {
   const int n = F.n;
   const int64_t lda = F.lda;
@@ -304,31 +306,36 @@ void lu_factor(hipStream_t st, DenseLU& F, cxd* work) {
     const int64_t blk = (int64_t)(k / LU_NB) * LU_NB * LU_NB;
     hipLaunchKernelGGL(k_lu_tri_inv, dim3(1), dim3(1024), 0, st, A, lda, k, nb, F.Linv + blk, F.Uinv + blk);
   };
-  // Two panels a = [k, km), b = [km, kend) per step: b is brought up to date by a alone, and the
-  // trailing matrix takes both in one update of depth kend - k (twice the panel width, which halves
-  // the passes over A22). Row interchanges of b reach the columns of a and of the trailing matrix
-  // through k_lu_laswp; the deferred update of those rows is row-wise, so the result is that of
-  // one-panel-at-a-time elimination.
-  for (int k = 0; k < n; k += 2 * LU_NB) {
-    const int kend = std::min(k + 2 * LU_NB, n);
-    const int km = std::min(k + LU_NB, kend), nba = km - k, nbb = kend - km;
-    const cxd* La = F.Linv + (int64_t)(k / LU_NB) * LU_NB * LU_NB;
-    const cxd* Lb = F.Linv + (int64_t)(km / LU_NB) * LU_NB * LU_NB;
-    panel(k, nba);
-    if (nbb > 0) {
-      lu_urows(st, A, lda, k, nba, km, nbb, La, work);
-      gemm_rm(st, n - km, nbb, nba, A + (int64_t)km * lda + k, lda, A + (int64_t)k * lda + km, lda,
-              A + (int64_t)km * lda + km, lda, 1, 1);
-      panel(km, nbb);
+  // U rows of the group's panels [k, kq) over the columns [c0, c0 + w), panel by panel: each takes
+  // the earlier panels' U rows in one GEMM, then its own L^-1
+  auto group_urows = [&](int k, int kq, int c0, int w) {
+    for (int kt = k; kt < kq; kt += LU_NB) {
+      const int nbt = std::min(LU_NB, kq - kt);
+      gemm_rm(st, nbt, w, kt - k, A + (int64_t)kt * lda + k, lda, A + (int64_t)k * lda + c0, lda,
+              A + (int64_t)kt * lda + c0, lda, 1, 1);
+      lu_urows(st, A, lda, kt, nbt, c0, w, F.Linv + (int64_t)(kt / LU_NB) * LU_NB * LU_NB, work);
+    }
+  };
+  // LU_GROUP panels per step: each panel of the group is first brought up to date by the group's
+  // earlier panels alone (left-looking inside the group), and the trailing matrix takes the whole
+  // group in one update of depth kend - k, so A22 is read and written once per group instead of
+  // once per panel. Row interchanges of later panels reach the columns of earlier ones and of the
+  // trailing matrix through k_lu_laswp; the deferred updates are row-wise, so the result is that
+  // of one-panel-at-a-time elimination.
+  for (int k = 0; k < n; k += LU_GROUP * LU_NB) {
+    const int kend = std::min(k + LU_GROUP * LU_NB, n);
+    for (int kq = k; kq < kend; kq += LU_NB) {
+      const int nbq = std::min(LU_NB, kend - kq);
+      if (kq > k) {
+        group_urows(k, kq, kq, nbq);
+        gemm_rm(st, n - kq, nbq, kq - k, A + (int64_t)kq * lda + k, lda, A + (int64_t)k * lda + kq, lda,
+                A + (int64_t)kq * lda + kq, lda, 1, 1);
+      }
+      panel(kq, nbq);
     }
     const int nr = n - kend;
     if (nr > 0) {
-      lu_urows(st, A, lda, k, nba, kend, nr, La, work);
-      if (nbb > 0) {
-        gemm_rm(st, nbb, nr, nba, A + (int64_t)km * lda + k, lda, A + (int64_t)k * lda + kend, lda,
-                A + (int64_t)km * lda + kend, lda, 1, 1);
-        lu_urows(st, A, lda, km, nbb, kend, nr, Lb, work);
-      }
+      group_urows(k, kend, kend, nr);
       gemm_rm(st, nr, nr, kend - k, A + (int64_t)kend * lda + k, lda, A + (int64_t)k * lda + kend, lda,
               A + (int64_t)kend * lda + kend, lda, 1, 1);
     }
