@@ -451,6 +451,7 @@ def main():
             converged_ports=int(sum(conv)), mean_iterations=float(np.mean(its)),
             max_rel_residual=float(max(s_["rel_residual"] for s_ in sts)),
             ms_per_iteration=round(1e3 * sum(s_["seconds"] for s_ in sts) / max(1, sum(its)), 3),
+            gram_schmidt_second_passes=int(sum(s_["gs_second_passes"] for s_ in sts)),
             time_to_1e6_mean_s=(round(float(np.mean([s_["seconds"] for s_ in sts])), 4) if all(conv) else None))
         print("schur_precond: %s" % solve["schur_precond"], file=sys.stderr, flush=True)
         # the same with complex64 inner cycles under FP64 flexible GMRES

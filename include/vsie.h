@@ -118,6 +118,11 @@ typedef struct {
   int32_t method;             /* VSIE_GMRES64, VSIE_IR_MIXED, VSIE_SCHUR or VSIE_SCHUR_MIXED */
   double inner_tol;           /* IR_MIXED: inner complex64 solve tolerance, default 1e-3 */
   int32_t precond;            /* SCHUR: 1 (default) right-preconditions the reduced system, 0 none */
+  double reorth;              /* Gram-Schmidt: a second classical pass follows a first that leaves less
+                                 than this fraction of the new vector's norm (the test of Daniel, Gragg,
+                                 Kaufman and Stewart, whose classical constant is 1/sqrt(2)); default
+                                 0.1, which bounds the orthogonality lost by a single pass at about
+                                 ten roundings; 0 = always one pass; must lie in [0, 1] (else E_ARG) */
 } vsie_solve_opts;
 
 enum vsie_method { VSIE_GMRES64 = 0, VSIE_IR_MIXED = 1, VSIE_SCHUR = 2, VSIE_SCHUR_MIXED = 3 };
@@ -129,6 +134,7 @@ typedef struct {
   double rel_residual;        /* true FP64 ||b - Ax|| / ||b|| at exit */
   double block_residual[3];   /* relative residual restricted to far / near / body rows */
   double seconds;
+  int32_t gs_second_passes;   /* Arnoldi steps that took the second Gram-Schmidt pass */
 } vsie_solve_stats;
 
 /* Fill defaults: tt_tol 1e-3, tt_rank_max 96, aca_tol 1e-3, aca_rank_max 128,

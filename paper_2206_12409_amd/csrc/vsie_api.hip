@@ -1040,6 +1040,8 @@ struct Solver {
   static constexpr int NB2 = 1024;
   static constexpr int MAX_BASIS = 1024;
   static int64_t work_elems() { return (int64_t)MDOT_BLK * (MAX_BASIS + 3) + (MAX_BASIS + 3) + 3 * NB2 + 3; }
+  double kappa = 0.1;          // second Gram-Schmidt pass when a pass leaves less than kappa ||w||
+  int64_t second_passes = 0;   // Arnoldi steps that took it
   Solver(Handle& h, hipStream_t s) : H(h), st(s), N(h.n_active) {
     part = H.d_solve_work;
     sum = part + (int64_t)MDOT_BLK * (MAX_BASIS + 3);
@@ -1063,9 +1065,11 @@ struct Solver {
   }
   // Classical Gram-Schmidt of w against V[0..nvec): one pass forms h = V^H w (with the segment
   // norms of w on the first pass), a second applies w -= V h with the device copy of h and forms
-  // the norms of the result; repeated once when the first pass removed more than 1 - 1/sqrt(2) of
-  // the norm of w (DGKS criterion). One host synchronisation per pass. h receives the projection
-  // coefficients; the return value is ||w|| afterwards.
+  // the norms of the result; repeated once when the first pass left less than kappa of the norm
+  // of w (the DGKS test; its classical constant is 1/sqrt(2), the default here 0.1: a single pass
+  // that keeps a tenth of the norm loses at most about ten roundings of orthogonality). One host
+  // synchronisation per pass. h receives the projection coefficients; the return value is ||w||
+  // afterwards.
   double orthogonalize(const cxd* V, int nvec, cxd* w, std::vector<cxd>& h) {
     if (nvec > MAX_BASIS) throw Error(VSIE_E_ARG, "Krylov basis larger than 1024 vectors");
     const int64_t s1 = H.mf, s2 = (int64_t)H.mf + H.mn;
@@ -1084,7 +1088,8 @@ struct Solver {
       for (int i = 0; i < nvec; ++i) h[i] += hh[i];
       if (pass == 0) n0 = sqrt(hh[nvec].re + hh[nvec + 1].re + hh[nvec + 2].re);
       n1 = sqrt(nn[0].re + nn[1].re + nn[2].re);
-      if (n1 >= 0.70710678118654752 * n0) break;
+      if (n1 >= kappa * n0) break;
+      if (pass == 0) ++second_passes;
     }
     return n1;
   }
@@ -1379,6 +1384,7 @@ int vsie_default_solve_opts(vsie_solve_opts* o) {
   o->method = VSIE_GMRES64;
   o->inner_tol = 1e-3;
   o->precond = 1;
+  o->reorth = 0.1;
   return VSIE_OK;
 }
 
@@ -1570,6 +1576,7 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
   else vsie_default_solve_opts(&so);
   if (so.restart < 1 || so.restart > 1000 || so.max_iter < 1 || !(so.tol > 0)) return fail(VSIE_E_ARG, "bad solve options");
   if (so.method < VSIE_GMRES64 || so.method > VSIE_SCHUR_MIXED) return fail(VSIE_E_ARG, "unknown solve method");
+  if (!(so.reorth >= 0 && so.reorth <= 1)) return fail(VSIE_E_ARG, "reorth must lie in [0, 1]");
   if ((so.method == VSIE_IR_MIXED || so.method == VSIE_SCHUR_MIXED) && !hd->H.have32)
     return fail(VSIE_E_STATE, "complex64 operator data not built");
   Handle& H = hd->H;
@@ -1605,6 +1612,7 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
     cxd* fin = H.d_full[0];
     cxd* fout = H.d_full[1];
     Solver S(H, st);
+    S.kappa = so.reorth;
     auto A64 = [&](const cxd* in, cxd* out) {
       launch_scatter_idx(st, in, H.d_active, Nc, fin);
       matvec_one<double>(H, H.d64, fin, fout, st);
@@ -1624,6 +1632,7 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       cxd* x = (cxd*)x_dev + c * N;
       vsie_solve_stats s;
       std::memset(&s, 0, sizeof(s));
+      const int64_t passes0 = S.second_passes;
       double rel = 0;
       if (so.method == VSIE_SCHUR || so.method == VSIE_SCHUR_MIXED) {
         s.iterations = solve_schur(H, S, so, so.method == VSIE_SCHUR_MIXED, b, x, ws, &s.restarts, &s.refinements, &rel,
@@ -1659,6 +1668,7 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       for (int q = 0; q < 3; ++q) s.block_residual[q] = nb[3] > 0 ? nr[q] / nb[3] : 0;
       VSIE_HIP(hipStreamSynchronize(st));
       s.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      s.gs_second_passes = (int32_t)(S.second_passes - passes0);
       if (s.rel_residual > so.tol) status = VSIE_E_NOCONV;
       if (stats) stats[c] = s;
     }

@@ -56,12 +56,13 @@ class Sizes(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32), ("method", C.c_int32),
-                ("inner_tol", C.c_double), ("precond", C.c_int32)]
+                ("inner_tol", C.c_double), ("precond", C.c_int32), ("reorth", C.c_double)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("refinements", C.c_int32),
-                ("rel_residual", C.c_double), ("block_residual", C.c_double * 3), ("seconds", C.c_double)]
+                ("rel_residual", C.c_double), ("block_residual", C.c_double * 3), ("seconds", C.c_double),
+                ("gs_second_passes", C.c_int32)]
 
 
 _lib = None
@@ -225,13 +226,13 @@ class Operator:
         return b
 
     def solve(self, b, tol=1e-6, restart=50, max_iter=5000, method=VSIE_GMRES64, inner_tol=1e-3, stream=None,
-              allow_noconv=False, precond=True):
+              allow_noconv=False, precond=True, reorth=0.1):
         import torch
         nrhs = 1 if b.dim() == 1 else b.shape[0]
         if b.dtype != torch.complex128 or not b.is_cuda:
             raise ValueError("b must be a complex128 device tensor")
         x = torch.empty_like(b)
-        o = SolveOpts(tol, restart, max_iter, method, inner_tol, 1 if precond else 0)
+        o = SolveOpts(tol, restart, max_iter, method, inner_tol, 1 if precond else 0, reorth)
         st = (SolveStats * nrhs)()
         rc = load().vsie_solve(self._h, C.byref(o), nrhs, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), st,
                                _stream_ptr(stream))
@@ -239,6 +240,7 @@ class Operator:
             _check(rc)
         stats = [dict(iterations=s.iterations, restarts=s.restarts, refinements=s.refinements,
                       rel_residual=s.rel_residual, block_residual=list(s.block_residual), seconds=s.seconds,
+                      gs_second_passes=s.gs_second_passes,
                       converged=rc == VSIE_OK) for s in st]
         return x, stats
 

@@ -100,4 +100,5 @@ def test_new_entry_points_reject_bad_arguments(vs):
     o = vs.SolveOpts()
     lib.vsie_default_solve_opts(C.byref(o))
     assert o.precond == 1 and o.method == vs.VSIE_GMRES64 and o.restart == 50 and o.tol == 1e-6
+    assert o.reorth == 0.1
     assert lib.vsie_solve(None, C.byref(o), 1, dummy, dummy, None, None) == 1

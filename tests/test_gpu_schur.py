@@ -166,6 +166,32 @@ def test_schur_solve_with_far_excitation(small):
     assert rel(S_same.matvec(x), b) <= 2e-8
 
 
+def test_gram_schmidt_reorth_threshold(small, lib):
+    """The second Gram-Schmidt pass is taken by the DGKS test at the given threshold: never at 0,
+    in some steps at the classical 1/sqrt(2); each setting converges to the same solution (their
+    difference is bounded by cond(A) x the tolerance), and thresholds outside [0, 1] are refused."""
+    p, op, d, _, S_same = small
+    b = system.port_rhs(d, 0)
+    cond = np.linalg.cond(S_same.Z)
+    xs = {}
+    for kappa in (0.0, 0.1, 0.5 ** 0.5):
+        x, st = op.solve(to_dev(b), tol=1e-8, restart=50, max_iter=400, method=2, reorth=kappa)
+        s = st[0]
+        print("reorth %.3f: %d iterations, %d second passes, residual %.2e"
+              % (kappa, s["iterations"], s["gs_second_passes"], s["rel_residual"]))
+        assert s["converged"] and s["rel_residual"] <= 1e-8
+        assert 0 <= s["gs_second_passes"] <= s["iterations"]
+        xs[kappa] = x.cpu().numpy()
+        if kappa == 0.0:
+            assert s["gs_second_passes"] == 0
+    for kappa in (0.0, 0.1):
+        assert rel(xs[kappa], xs[0.5 ** 0.5]) <= cond * 2e-8
+    for bad in (-0.1, 1.5, float("nan")):
+        with pytest.raises(lib.VsieError) as e:
+            op.solve(to_dev(b), tol=1e-8, method=2, reorth=bad)
+        assert e.value.code == 1
+
+
 def _edge_problem(kind):
     g = synth.sphere_phantom((9, 8, 10), 5e-3, 17e-3, 52.0, 0.55)
     loop = synth.strip_loop_flat((25.5e-3, 0.37e-3, -0.41e-3), side=30e-3, width=5e-3, step=5e-3)
