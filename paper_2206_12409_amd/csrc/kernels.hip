@@ -1046,9 +1046,12 @@ __global__ void k_build_grid(const cx<R>* __restrict__ xb, const cx<R>* __restri
                              const uint8_t* __restrict__ mask, const int* __restrict__ vox2row,
                              const int* __restrict__ rowptr, const int* __restrict__ rowrwg,
                              const R* __restrict__ roww, cx<R>* __restrict__ grid, GridDims g) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= g.Ne) return;
-  int i1 = (int)(v % g.ne1), i2 = (int)((v / g.ne1) % g.ne2), i3 = (int)(v / ((int64_t)g.ne1 * g.ne2));
+  // 32-bit index arithmetic (the launcher checks Ne < 2^31): 64-bit division is a long software
+  // sequence on the GPU and held this kernel well below the HBM rate
+  const int vi = (int)v, t12 = vi / g.ne1;
+  const int i1 = vi - t12 * g.ne1, i3 = t12 / g.ne2, i2 = t12 - i3 * g.ne2;
   int b1 = i1 - g.ob1, b2 = i2 - g.ob2, b3 = i3 - g.ob3;
   cx<R> a[3] = {{0, 0}, {0, 0}, {0, 0}};
   if (xb && b1 >= 0 && b1 < g.n1 && b2 >= 0 && b2 < g.n2 && b3 >= 0 && b3 < g.n3) {
@@ -1865,6 +1868,7 @@ __global__ void k_scatter_rhs(const int* __restrict__ idx, const double* __restr
 template <typename R> void launch_build_grid(hipStream_t st, const cx<R>* xb, const cx<R>* xn, const uint8_t* mask,
                                              const int* vox2row, const int* rowptr, const int* rowrwg, const R* roww,
                                              cx<R>* grid, const GridDims& g) {
+  if (g.Ne >= ((int64_t)1 << 31)) throw Error(VSIE_E_GRID, "extended grid of 2^31 or more voxels");
   hipLaunchKernelGGL(k_build_grid<R>, dim3((unsigned)((g.Ne + 255) / 256)), dim3(256), 0, st, xb, xn, mask, vox2row,
                      rowptr, rowrwg, roww, grid, g);
 }

@@ -1039,6 +1039,10 @@ struct Solver {
   static constexpr int MDOT_BLK = 1024;
   static constexpr int NB2 = 1024;
   static constexpr int MAX_BASIS = 1024;
+  // layout of the page-locked buffer: projection sums [0, MAX_BASIS + 3), update norms, segment norms
+  static constexpr int PIN_NSUM = MAX_BASIS + 3;
+  static constexpr int PIN_NORMS = PIN_NSUM + 3;
+  static_assert(PIN_NORMS + (3 * NBLK + 1) / 2 <= Handle::HOST_PINNED_ELEMS, "page-locked buffer too small");
   static int64_t work_elems() { return (int64_t)MDOT_BLK * (MAX_BASIS + 3) + (MAX_BASIS + 3) + 3 * NB2 + 3; }
   double kappa = 0.1;          // second Gram-Schmidt pass when a pass leaves less than kappa ||w||
   int64_t second_passes = 0;   // Arnoldi steps that took it
@@ -1052,8 +1056,8 @@ struct Solver {
   // segment norms (far, near, body) and the total of a compact (n < 0) or full-length vector
   void norms(const cxd* a, double out[4], int64_t n = -1) {
     launch_norm_partial(st, a, n < 0 ? N : n, H.mf, (int64_t)H.mf + H.mn, npart, NBLK);
-    std::vector<double> p(3 * NBLK);
-    VSIE_HIP(hipMemcpyAsync(p.data(), npart, sizeof(double) * 3 * NBLK, hipMemcpyDeviceToHost, st));
+    const double* p = reinterpret_cast<const double*>(H.h_pinned + PIN_NORMS);
+    VSIE_HIP(hipMemcpyAsync(H.h_pinned + PIN_NORMS, npart, sizeof(double) * 3 * NBLK, hipMemcpyDeviceToHost, st));
     VSIE_HIP(hipStreamSynchronize(st));
     double s[3] = {0, 0, 0};
     for (int b = 0; b < NBLK; ++b)
@@ -1075,15 +1079,17 @@ struct Solver {
     const int64_t s1 = H.mf, s2 = (int64_t)H.mf + H.mn;
     h.assign(nvec, cxd{0, 0});
     double n0 = 0, n1 = 0;
-    std::vector<cxd> hh(MAX_BASIS + 3), nn(3);
+    // the reductions come back through page-locked memory: truly asynchronous copies, one wait
+    const cxd* hh = H.h_pinned;
+    const cxd* nn = H.h_pinned + PIN_NSUM;
     for (int pass = 0; pass < 2; ++pass) {
       const int K = nvec + (pass == 0 ? 3 : 0);
       launch_multidot(st, V, N, nvec, w, N, s1, s2, pass == 0, part, MDOT_BLK);
       launch_sum_partials(st, part, MDOT_BLK, K, sum);
       launch_multiaxpy_norm(st, V, N, nvec, sum, w, N, s1, s2, npart2, NB2);
       launch_sum_partials(st, npart2, NB2, 3, nsum);
-      VSIE_HIP(hipMemcpyAsync(hh.data(), sum, sizeof(cxd) * K, hipMemcpyDeviceToHost, st));
-      VSIE_HIP(hipMemcpyAsync(nn.data(), nsum, sizeof(cxd) * 3, hipMemcpyDeviceToHost, st));
+      VSIE_HIP(hipMemcpyAsync(H.h_pinned, sum, sizeof(cxd) * K, hipMemcpyDeviceToHost, st));
+      VSIE_HIP(hipMemcpyAsync(H.h_pinned + PIN_NSUM, nsum, sizeof(cxd) * 3, hipMemcpyDeviceToHost, st));
       VSIE_HIP(hipStreamSynchronize(st));
       for (int i = 0; i < nvec; ++i) h[i] += hh[i];
       if (pass == 0) n0 = sqrt(hh[nvec].re + hh[nvec + 1].re + hh[nvec + 2].re);
@@ -1241,6 +1247,10 @@ void ensure_solver_ws(Handle& H, int restart) {
   if (!H.d_solve_work) {
     H.d_solve_work = H.dalloc<cxd>(Solver::work_elems());
     H.d_red = H.dalloc<double>(256 * 4);
+  }
+  if (!H.h_pinned && hipHostMalloc((void**)&H.h_pinned, sizeof(cxd) * Handle::HOST_PINNED_ELEMS, hipHostMallocDefault) != hipSuccess) {
+    H.h_pinned = nullptr;
+    throw Error(VSIE_E_NOMEM, "page-locked host buffer of the solver");
   }
   if (!H.d_active) {
     std::vector<int> act;

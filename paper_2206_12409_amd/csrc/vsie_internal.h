@@ -161,6 +161,8 @@ struct Handle {
   int64_t krylov_cols = 0;
   cxd* d_solve_work = nullptr;
   double* d_red = nullptr;        // reduction scratch
+  cxd* h_pinned = nullptr;        // page-locked host copy of the solver's reductions (HOST_PINNED_ELEMS)
+  static constexpr int HOST_PINNED_ELEMS = 2048;
   int64_t device_bytes = 0;
   double setup_seconds = 0;
   hipStream_t stream = nullptr;
@@ -220,6 +222,7 @@ struct Handle {
   ~Handle() {
     if (side) (void)hipStreamSynchronize(side);
     for (void* p : allocations) (void)hipFree(p);
+    if (h_pinned) (void)hipHostFree(h_pinned);
     for (auto& slot : ev)
       for (auto& e : slot)
         if (e) (void)hipEventDestroy(e);
