@@ -30,8 +30,11 @@ def _rand(shape, seed):
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (2, 3), (63, 1), (64, 5), (65, 70), (130, 2), (257, 33)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (2, 3), (63, 1), (64, 5), (65, 70), (130, 2), (257, 33), (600, 7)])
 def test_dense_lu_solve(lib, n, nrhs):
+    """Sizes cover one column, partial and full 64-column panels, a partial group of four panels
+    (130), a group plus one column (257), and two groups with a deferred trailing update and a
+    ragged last group (600)."""
     A = _rand((n, n), n)
     B = _rand((n, nrhs), n + 1)
     X_ref = np.linalg.solve(A, B)
