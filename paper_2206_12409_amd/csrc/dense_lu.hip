@@ -13,7 +13,8 @@
 //      is searched by reading it;
 //   2. the panel's interchanges are applied to the columns left and right of it;
 //   3. the diagonal block's unit-lower and upper triangles are inverted (one workgroup, kept for
-//      the solves), U12 = L11^-1 A12 is one matrix-core GEMM;
+//      the solves); the panel's U rows to its right are L11^-1 times those rows once the U rows
+//      of the group's earlier panels have been taken out of them (two matrix-core GEMMs);
 //   4. trailing update A22 -= L21 U12 on the matrix cores (k_zgemm_mfma, negated accumulation),
 //      taken once per group of LU_GROUP panels (depth LU_GROUP LU_NB); inside a group each panel is
 //      first updated by the group's earlier panels alone.
