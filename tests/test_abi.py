@@ -102,3 +102,31 @@ def test_new_entry_points_reject_bad_arguments(vs):
     assert o.precond == 1 and o.method == vs.VSIE_GMRES64 and o.restart == 50 and o.tol == 1e-6
     assert o.reorth == 0.1
     assert lib.vsie_solve(None, C.byref(o), 1, dummy, dummy, None, None) == 1
+
+
+def test_binding_structs_match_the_header(vs, tmp_path):
+    """Every ctypes mirror in the binding has the size and field offsets that a C compiler gives
+    the structs of include/vsie.h (compiled here with gcc against the header itself)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    mirrors = {"vsie_mesh": vs.Mesh, "vsie_problem": vs.ProblemC, "vsie_options": vs.Options,
+               "vsie_sizes_t": vs.Sizes, "vsie_solve_opts": vs.SolveOpts, "vsie_solve_stats": vs.SolveStats}
+    lines = ['#include <stdio.h>', '#include "vsie.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in py._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l)}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
