@@ -227,6 +227,11 @@ class Operator:
 
     def solve(self, b, tol=1e-6, restart=50, max_iter=5000, method=VSIE_GMRES64, inner_tol=1e-3, stream=None,
               allow_noconv=False, precond=True, reorth=0.1):
+        """Solve Z x = b for each row of b (vsie_solve) from a zero start. method is VSIE_GMRES64,
+        VSIE_IR_MIXED, VSIE_SCHUR or VSIE_SCHUR_MIXED; precond right-preconditions the reduced
+        system of the SCHUR methods; reorth is the DGKS constant below which a Gram-Schmidt pass is
+        repeated. Returns x and one stats dict per right-hand side; VSIE_E_NOCONV raises unless
+        allow_noconv."""
         import torch
         nrhs = 1 if b.dim() == 1 else b.shape[0]
         if b.dtype != torch.complex128 or not b.is_cuda:
