@@ -165,8 +165,8 @@ int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, v
                 void* stream);
 
 /* Solve Z x = b for nrhs right-hand sides (device, [nrhs][N] complex128).
- * GMRES64: restarted GMRES (Sec. III-A), zero initial guess, FP64 classical Gram-Schmidt repeated
- * when the first pass loses more than 1 - 1/sqrt(2) of the norm.
+ * GMRES64: restarted GMRES (Sec. III-A), zero initial guess, FP64 classical Gram-Schmidt with a
+ * second pass when the first leaves less than opts->reorth of the new vector's norm.
  * IR_MIXED: FP64 flexible GMRES (20 steps per cycle) on the FP64 operator whose preconditioner is
  * one cycle (at most `restart` iterations, stopping early at inner_tol) of complex64 GMRES on
  * Z z = v; with an exact inner solve each outer step is one refinement x += Z^{-1}(b - Zx).

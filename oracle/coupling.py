@@ -11,8 +11,11 @@ The integrals are point rules, as the paper states: 8 volume points (2x2x2 Gauss
 5 surface points (rule R5) for the near conductors; 1 volume point (voxel centre) and 1 surface
 point (triangle centroid) for the far conductors. The coil rows of eq. (8) are the transpose.
 
-Parity pins (tests): the dyad against finite differences of g, the near rule against a
-high-order rule for well-separated pairs, reciprocity of the assembled system.
+Parity pins (tests): the dyad against finite differences of g; both point rules against the
+converged mixed-potential form of the same entry (k0^2 times the vector potential integrated over
+the voxel plus the scalar potential of div f integrated over its faces, high-order rules; no dyad
+involved) at 3, 6 and 12 voxels from the RWG, where the near rule's error falls from 2e-3 to 3e-6
+and stays below a fifth of the far rule's; reciprocity of the assembled system.
 """
 import numpy as np
 

@@ -26,7 +26,9 @@ Because the outer rule is not exact, the two orderings of a near pair differ sli
 entry is their average, so Z_cc is exactly symmetric.
 
 Parity pins (tests): closed forms against high-order numerical quadrature (off the triangle and
-in-plane), exact reciprocity Z_cc = Z_cc^T, energy balance of a port-driven closed cavity.
+in-plane); self, adjacent and near entries recomputed from the RWG definitions with the inner
+static integrals in polar coordinates about the foot of the outer point (1e-10); exact
+reciprocity Z_cc = Z_cc^T; energy balance of a port-driven closed cavity.
 """
 import numpy as np
 

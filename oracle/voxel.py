@@ -35,7 +35,9 @@ Gauss-Legendre rule whose order follows from the Bernstein-ellipse bound for tha
 
 Parity pins (tests): the trace identity sum_a I_ff^{aa} = k0^2 I_vv + dv delta_{d0} (exact), the
 6D/4D brute-force definitions at separated offsets, an independent tanh-sinh evaluation of the
-singular self terms, and convergence in the quadrature order.
+singular self terms, the off-diagonal face terms at every touching offset d in {0, 1}^3 from the
+closed-form potential of a rectangle integrated by a double-exponential rule (1e-10), and
+convergence in the quadrature order.
 """
 import numpy as np
 

@@ -862,12 +862,14 @@ template <typename R> static void matvec_schur(Handle& H, const cx<R>* x, cx<R>*
 
 // Right preconditioner of the reduced system: the inverse of its near block (direct Galerkin
 // entries of the near coils minus the eliminated far block's ACA term) on the near currents, the
-// inverse diagonal on the body unknowns, zero on the far currents. Identity when not built.
-template <typename R> static void precond_apply(Handle& H, const cx<R>* v, cx<R>* w, hipStream_t st) {
+// inverse diagonal on the body unknowns, zero on the far currents. Identity (zero on the far
+// currents) when `use` is false or the preconditioner is not built.
+template <typename R>
+static void precond_apply(Handle& H, const cx<R>* v, cx<R>* w, hipStream_t st, bool use = true) {
   Handle::Schur& Sc = H.schur;
   Handle::SchurOp<R>& P = schurop(H, R());
   const int mf = H.mf, mn = H.mn;
-  if (!Sc.precond) {
+  if (!use || !Sc.precond) {
     VSIE_HIP(hipMemcpyAsync(w, v, sizeof(cx<R>) * H.N, hipMemcpyDeviceToDevice, st));
     if (mf) VSIE_HIP(hipMemsetAsync(w, 0, sizeof(cx<R>) * mf, st));
     return;
@@ -1296,6 +1298,7 @@ int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, bool mixed, con
   OpData<double>& D = H.d64;
   const int64_t N = H.N, Nc = H.n_active;
   const int mf = H.mf, mn = H.mn, K = Sc.K, ka = aca_rank(H);
+  const bool use_pc = so.precond != 0;
   TTDesc<double> td;
   int r3[3];
   tt_desc(H, D, td, r3);
@@ -1323,7 +1326,7 @@ int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, bool mixed, con
   const double tol = nbr[3] > 0 ? so.tol * nb[3] / nbr[3] : so.tol;
   auto AM = [&](const cxd* in, cxd* out) {
     launch_scatter_idx(st, in, H.d_active, Nc, fin);
-    precond_apply<double>(H, fin, tmp, st);
+    precond_apply<double>(H, fin, tmp, st, use_pc);
     matvec_schur<double>(H, tmp, fout, st);
     launch_gather_idx(st, fout, H.d_active, Nc, out);
   };
@@ -1335,7 +1338,7 @@ int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, bool mixed, con
     auto AM32 = [&](const cxd* in, cxd* out) {
       launch_scatter_idx(st, in, H.d_active, Nc, fin);
       launch_d2f(st, fin, ws.x32, N);
-      precond_apply<float>(H, ws.x32, ws.y32, st);
+      precond_apply<float>(H, ws.x32, ws.y32, st, use_pc);
       matvec_schur<float>(H, ws.y32, ws.x32, st);
       launch_f2d(st, ws.x32, fout, N);
       launch_gather_idx(st, fout, H.d_active, Nc, out);
@@ -1352,7 +1355,7 @@ int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, bool mixed, con
   }
   // x = M u on the coupled unknowns, b on the air voxels
   launch_scatter_idx(st, ws.xc, H.d_active, Nc, fin);
-  precond_apply<double>(H, fin, tmp, st);
+  precond_apply<double>(H, fin, tmp, st, use_pc);
   launch_gather_idx(st, tmp, H.d_active, Nc, ws.wc);
   VSIE_HIP(hipMemcpyAsync(x, b, sizeof(cxd) * N, hipMemcpyDeviceToDevice, st));
   launch_scatter_idx(st, ws.wc, H.d_active, Nc, x);

@@ -208,11 +208,22 @@ class Operator:
 
     def matvec(self, x, out=None, stream=None):
         import torch
-        if not x.is_cuda or not x.is_contiguous():
-            raise ValueError("x must be a contiguous device tensor")
+        if x.dim() not in (1, 2) or x.shape[-1] != self.N:
+            raise ValueError("x must be [N] or [nrhs][N] with N = %d, got %s" % (self.N, tuple(x.shape)))
+        if not x.is_contiguous():
+            raise ValueError("x must be contiguous")
+        self._dtype_code(x)
+        if out is not None:
+            if (out.dtype != x.dtype or out.shape != x.shape or out.device != x.device
+                    or not out.is_contiguous()):
+                raise ValueError("out must be a contiguous tensor of x's dtype, shape and device")
+            if out.data_ptr() == x.data_ptr():
+                raise ValueError("out must not alias x")
+        if not x.is_cuda:
+            raise ValueError("x must be a device tensor")
         nrhs = 1 if x.dim() == 1 else x.shape[0]
-        if x.shape[-1] != self.N:
-            raise ValueError("x has length %d, operator size is %d" % (x.shape[-1], self.N))
+        if nrhs < 1:
+            raise ValueError("x holds no column")
         y = torch.empty_like(x) if out is None else out
         _check(load().vsie_matvec(self._h, self._dtype_code(x), nrhs, C.c_void_p(x.data_ptr()),
                                   C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
@@ -233,9 +244,15 @@ class Operator:
         repeated. Returns x and one stats dict per right-hand side; VSIE_E_NOCONV raises unless
         allow_noconv."""
         import torch
+        if b.dim() not in (1, 2) or b.shape[-1] != self.N:
+            raise ValueError("b must be [N] or [nrhs][N] with N = %d, got %s" % (self.N, tuple(b.shape)))
+        if b.dtype != torch.complex128 or not b.is_contiguous():
+            raise ValueError("b must be a contiguous complex128 tensor")
+        if not b.is_cuda:
+            raise ValueError("b must be a device tensor")
         nrhs = 1 if b.dim() == 1 else b.shape[0]
-        if b.dtype != torch.complex128 or not b.is_cuda:
-            raise ValueError("b must be a complex128 device tensor")
+        if nrhs < 1:
+            raise ValueError("b holds no column")
         x = torch.empty_like(b)
         o = SolveOpts(tol, restart, max_iter, method, inner_tol, 1 if precond else 0, reorth)
         st = (SolveStats * nrhs)()

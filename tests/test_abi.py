@@ -130,3 +130,35 @@ def test_binding_structs_match_the_header(vs, tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for f in py._fields_:
             assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_binding_rejects_bad_vectors_before_any_call(vs):
+    """Operator.matvec and Operator.solve check shape, contiguity, dtype and device of every vector
+    (and of a caller-supplied output) before they reach the library, so that a short or strided
+    buffer is never handed to a kernel."""
+    import torch
+    op = vs.Operator.__new__(vs.Operator)
+    op._h = None
+    op.N = 10
+    good = torch.zeros(10, dtype=torch.complex128)
+    bad = [torch.zeros(9, dtype=torch.complex128),                  # short
+           torch.zeros(20, dtype=torch.complex128)[::2],            # strided
+           torch.zeros((2, 3, 10), dtype=torch.complex128),         # wrong rank
+           torch.zeros(10, dtype=torch.float64)]                    # real
+    for x in bad:
+        with pytest.raises((ValueError, TypeError)):
+            op.matvec(x)
+        with pytest.raises((ValueError, TypeError)):
+            op.solve(x)
+    with pytest.raises(ValueError):
+        op.solve(good.to(torch.complex64))
+    # a well-formed host tensor is refused for not being on the device
+    with pytest.raises(ValueError):
+        op.matvec(good)
+    with pytest.raises(ValueError):
+        op.solve(good)
+    # outputs: shape, dtype and contiguity must match x
+    for out in (torch.zeros(9, dtype=torch.complex128), torch.zeros(10, dtype=torch.complex64),
+                torch.zeros(20, dtype=torch.complex128)[::2]):
+        with pytest.raises(ValueError):
+            op.matvec(good, out=out)

@@ -82,6 +82,9 @@ def test_body_probe_sampled_rows(big):
         ref[a] = np.where(tis, ref[a] + diag, x[off + a * nv + rows])
     got = np.stack([y[off + a * nv + rows] for a in range(3)])
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
+    y32 = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    got32 = np.stack([y32[off + a * nv + rows] for a in range(3)])
+    e_bb32 = np.linalg.norm(got32 - ref) / np.linalg.norm(ref)
     # sampled near rows: y_n[m] = h^3 sum_v W_m(v) . sum_q T(q - v) x_q
     ms = rng.choice(rn.m, 40, replace=False)
     sub = subset(rn, ms)
@@ -100,6 +103,11 @@ def test_body_probe_sampled_rows(big):
                 refn[i] += g.h ** 3 * np.sum(Wm[a] * Tm[:, j, c]) * qv[j]
     gotn = y[op.m_far + ms]
     assert np.linalg.norm(gotn - refn) / np.linalg.norm(refn) < 1e-10
+    e_nb32 = np.linalg.norm(y32[op.m_far + ms] - refn) / np.linalg.norm(refn)
+    print("complex64 against the oracle, body probe: body rows %.2e, near rows %.2e" % (e_bb32, e_nb32))
+    # complex64 bars: the body rows carry FP32 rounding of the FFT convolution; the near rows read
+    # the grid field at the coil, whose own near field sets the FP32 grid's dynamic range
+    assert e_bb32 < 1e-5 and e_nb32 < 2e-4
 
 
 def test_near_probe_sampled_rows(big):
@@ -142,6 +150,66 @@ def test_near_probe_sampled_rows(big):
         ref[i] = g.h ** 3 * s
     got = y[op.m_far + ms]
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
+    y32 = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    e_nn32 = np.linalg.norm(y32[op.m_far + ms] - ref) / np.linalg.norm(ref)
+    # body rows of a near source: the FP64 product is the reference (checked against the oracle
+    # through the body probe and the bilinear identity); the FP32 error there is the near-to-body one
+    nb = slice(op.m_far + op.m_near, op.N)
+    e_bn32 = np.linalg.norm(y32[nb] - y[nb]) / np.linalg.norm(y[nb])
+    print("complex64, near probe: near rows vs oracle %.2e, body rows vs FP64 %.2e" % (e_nn32, e_bn32))
+    assert e_nn32 < 1e-5 and e_bn32 < 2e-4
+
+
+def _tt_apply(G, xf):
+    """Body field of far currents through TT cores [G1 (n1,r1), G2 (r1,n2,r2), G3 (r2,n3,r3),
+    G4 (r3,m)], G4 first (eqs. (16)-(17)); returned with i1 fastest."""
+    G1, G2, G3, G4 = G
+    t3 = np.einsum("bkc,c->bk", G3, G4 @ xf)
+    t2 = np.einsum("ajb,bk->ajk", G2, t3)
+    return np.einsum("ia,ajk->ijk", G1, t2).transpose(2, 1, 0).ravel()
+
+
+def _tt_apply_t(G, xb):
+    """Far rows of body currents through the same cores (eqs. (18)-(19)); xb with i1 fastest."""
+    G1, G2, G3, G4 = G
+    n1, n2, n3 = G1.shape[0], G2.shape[1], G3.shape[1]
+    X = xb.reshape(n3, n2, n1).transpose(2, 1, 0)
+    u2 = np.einsum("ajb,ajk->bk", G2, np.einsum("ia,ijk->ajk", G1, X))
+    return np.einsum("bkc,bk->c", G3, u2) @ G4
+
+
+def test_tt_forward_and_transpose_against_cores(big):
+    """The TT chains at the workload's shapes (split-K over n1 n2 = 10752 in 128-wide chunks, the
+    merged-core GEMM's output tiles, the k-sums) against the exported cores contracted on the CPU:
+    every body row of a random far current and the far rows of a random body current, FP64 at
+    1e-10 and complex64 stated."""
+    p, op, rf, rn, chi, k = big
+    nv = int(np.prod(p.grid.n))
+    mf, mn = op.m_far, op.m_near
+    off = mf + mn
+    tissue = chi != 0
+    cores = [op.export_tt(a) for a in range(3)]
+    xf = synth.complex_normal(mf, 31)
+    x = np.zeros(op.N, np.complex128)
+    x[:mf] = xf
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    y32 = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    for a in range(3):
+        ref = np.where(tissue, _tt_apply(cores[a], xf), 0)
+        e = np.linalg.norm(y[off + a * nv: off + (a + 1) * nv] - ref) / np.linalg.norm(ref)
+        e32 = np.linalg.norm(y32[off + a * nv: off + (a + 1) * nv] - ref) / np.linalg.norm(ref)
+        print("TT forward component %d: FP64 %.2e, complex64 %.2e" % (a, e, e32))
+        assert e < 1e-10 and e32 < 1e-5
+    xb = synth.complex_normal(3 * nv, 32)
+    x = np.zeros(op.N, np.complex128)
+    x[off:] = xb
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    y32 = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    ref = sum(_tt_apply_t(cores[a], np.where(tissue, xb[a * nv:(a + 1) * nv], 0)) for a in range(3))
+    e = np.linalg.norm(y[:mf] - ref) / np.linalg.norm(ref)
+    e32 = np.linalg.norm(y32[:mf] - ref) / np.linalg.norm(ref)
+    print("TT transpose: FP64 %.2e, complex64 %.2e" % (e, e32))
+    assert e < 1e-10 and e32 < 1e-5
 
 
 def test_far_probe_dense_column(big):
@@ -155,6 +223,10 @@ def test_far_probe_dense_column(big):
     ms = np.unique(np.concatenate([[j0], rng.choice(rf.m, 300, replace=False)]))
     ref = surface.zcc_block(subset(rf, ms), subset(rf, [j0]), k)[:, 0]
     assert np.linalg.norm(y[ms] - ref) / np.linalg.norm(ref) < 1e-10
+    y32 = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    e32 = np.linalg.norm(y32[ms] - ref) / np.linalg.norm(ref)
+    print("complex64, far probe: far rows vs oracle %.2e" % e32)
+    assert e32 < 1e-5
 
 
 def test_tt_and_aca_bilinear_identity(big):
@@ -206,7 +278,8 @@ def test_aca_sampled_rows(big):
     approx = U[rows] @ V[cols].conj().T
     err = np.linalg.norm(approx - Z) / np.linalg.norm(Z)
     print("ACA rank %d: sampled relative error %.2e" % (U.shape[1], err))
-    assert err < 1e-2
+    # the ACA tolerance is 1e-3 (Sec. IV-C); its stopping rule estimates the error, so a factor 3
+    assert err < 3e-3
 
 
 def test_far_elimination_solves_full_system(big):

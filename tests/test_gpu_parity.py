@@ -115,16 +115,20 @@ def test_batched_columns_match(small):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_batched_far_block_matches_single_columns(small, dtype):
-    """Six right-hand sides (groups of four and two in the batched far-block pass) give the
-    single-column products."""
+    """Eighteen right-hand sides: the batched far-block pass takes them as a full group of 16 and
+    a ragged group of 2 (so the second group's column offsets of x, y and the partial sums are
+    exercised); every column equals its single-column product, and in FP64 the oracle's."""
     p, op, d, _, S_same, _ = small
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
-    X = to_dev(np.stack([synth.complex_normal(op.N, 10 + s) for s in range(6)]), tdt)
+    Xh = np.stack([synth.complex_normal(op.N, 10 + s) for s in range(18)])
+    X = to_dev(Xh, tdt)
     Y = op.matvec(X)
-    for c in range(6):
+    for c in range(18):
         y1 = op.matvec(X[c].contiguous())
         e = float(torch.linalg.norm(Y[c] - y1) / torch.linalg.norm(y1))
-        assert e <= (1e-14 if dtype == "c128" else 1e-6)
+        assert e <= (1e-14 if dtype == "c128" else 1e-6), (c, e)
+        if dtype == "c128":
+            assert rel(Y[c].cpu().numpy(), S_same.matvec(Xh[c])) < 1e-10, c
 
 
 def test_complex64_matvec_error(small):
@@ -157,23 +161,27 @@ def test_gmres_solution_matches_oracle(small):
 
 
 def test_mixed_precision_refinement(small):
-    """complex64 inner GMRES + FP64 residual reaches the FP64 relative residual 1e-6. Two
-    solutions with residual <= 1e-6 may differ by up to cond(Z) * 2e-6; the bound below uses the
-    condition number of the densified operator."""
+    """complex64 inner GMRES + FP64 residual reaches the FP64 relative residual 1e-6, measured
+    with the oracle's own operator (not the library's). The solution's distance from the oracle's
+    LU solution and from the FP64 GMRES solution (itself only converged to 1e-6 on a system of
+    condition ~1e7) is bounded at a few times the measured values (1.2e-6 and 4.1e-4)."""
     p, op, d, _, S_same, _ = small
     b = system.port_rhs(d, 0)
     x64, s64 = op.solve(to_dev(b), tol=1e-6, restart=600, max_iter=12000)
     x, st = op.solve(to_dev(b), tol=1e-6, restart=600, max_iter=12000, method=1, inner_tol=1e-3)
     x = x.cpu().numpy()
     assert st[0]["converged"] and st[0]["rel_residual"] <= 1e-6
+    r_oracle = rel(S_same.matvec(x), b)
     e = rel(x, x64.cpu().numpy())
     xo = S_same.solve(b)
     e_oracle = rel(x, xo)
-    cond = np.linalg.cond(S_same.Z)
-    print("mixed-precision IR: %d refinements, %d inner iterations (FP64 GMRES: %d); error vs FP64 solve "
-          "%.2e, vs oracle LU %.2e, cond %.1e" % (st[0]["refinements"], st[0]["iterations"], s64[0]["iterations"],
-                                                  e, e_oracle, cond))
-    assert e <= cond * 2e-6 and e_oracle <= cond * 1e-6
+    e64_oracle = rel(x64.cpu().numpy(), xo)
+    print("mixed-precision IR: %d refinements, %d inner iterations (FP64 GMRES: %d); oracle residual %.2e; "
+          "error vs FP64 solve %.2e, vs oracle LU %.2e (FP64 GMRES vs oracle LU %.2e)"
+          % (st[0]["refinements"], st[0]["iterations"], s64[0]["iterations"], r_oracle, e, e_oracle, e64_oracle))
+    assert r_oracle <= 1.01e-6
+    assert e_oracle <= 1e-5
+    assert e <= 2e-3 and e <= 2 * e64_oracle + 1e-5
 
 
 def test_body_only_volume_operator():
@@ -213,6 +221,8 @@ def test_tt_cross_accuracy_against_brute_force():
         print("component %d: TT-cross ranks %s (TT-SVD at 1e-3: %s), error %.2e, estimate %.2e"
               % (a, info["tt_rank"][a], ref_ranks, err, info["tt_err_est"][a]))
         assert err < 3e-3
+        # the cross needs at most twice the ranks of the quasi-optimal TT-SVD at the same tolerance
+        assert all(rc <= 2 * rs for rc, rs in zip(info["tt_rank"][a], ref_ranks)), (info["tt_rank"][a], ref_ranks)
 
 
 def test_aca_accuracy_against_dense_block():

@@ -145,18 +145,21 @@ def test_schur_solve_all_ports(small):
 
 def test_schur_mixed_precision_solve(small):
     """Flexible FP64 GMRES with complex64 inner cycles on the reduced system reaches 1e-8 on every
-    port; two solutions at that residual differ by at most cond(A) x 2e-8."""
+    port, with the residual measured by the oracle's own operator; the solution matches the
+    oracle's dense solve to the FP64 eliminated solve's bar (1e-5)."""
     p, op, d, _, S_same = small
-    cond = np.linalg.cond(S_same.Z)
     for port in range(op.n_ports):
         b = system.port_rhs(d, port)
         x, st = op.solve(to_dev(b), tol=1e-8, restart=50, max_iter=400, method=3)
         s = st[0]
-        print("mixed port %d: %d inner iterations, %d FP64 steps, residual %.2e"
-              % (port, s["iterations"], s["refinements"], s["rel_residual"]))
+        x = x.cpu().numpy()
+        r_o = rel(S_same.matvec(x), b)
+        e_o = rel(x, S_same.solve(b))
+        print("mixed port %d: %d inner iterations, %d FP64 steps, residual %.2e (oracle %.2e), vs oracle solve %.2e"
+              % (port, s["iterations"], s["refinements"], s["rel_residual"], r_o, e_o))
         assert s["converged"] and s["rel_residual"] <= 1e-8
-        assert rel(S_same.matvec(x.cpu().numpy()), b) <= 2e-8
-        assert rel(x.cpu().numpy(), S_same.solve(b)) <= cond * 2e-8
+        assert r_o <= 2e-8
+        assert e_o <= 1e-5
 
 
 def test_schur_solve_with_far_excitation(small):
@@ -187,12 +190,42 @@ def test_gram_schmidt_reorth_threshold(small, lib):
         xs[kappa] = x.cpu().numpy()
         if kappa == 0.0:
             assert s["gs_second_passes"] == 0
-    for kappa in (0.0, 0.1):
-        assert rel(xs[kappa], xs[0.5 ** 0.5]) <= cond * 2e-8
+    ref = S_same.solve(b)
+    for kappa in (0.0, 0.1, 0.5 ** 0.5):
+        assert rel(S_same.matvec(xs[kappa]), b) <= 2e-8
+        assert rel(xs[kappa], ref) <= 1e-5
+    del cond
     for bad in (-0.1, 1.5, float("nan")):
         with pytest.raises(lib.VsieError) as e:
             op.solve(to_dev(b), tol=1e-8, method=2, reorth=bad)
         assert e.value.code == 1
+
+
+def test_schur_solve_without_preconditioner(lib):
+    """precond = 0 solves the unpreconditioned reduced system even when the preconditioner is
+    already built (it changes the iteration count, not the solution): body + far shield on a
+    ragged grid with a permittivity that varies from voxel to voxel (so that the body diagonal is
+    not a multiple of the identity), against the oracle's dense solve."""
+    p = _edge_problem("far")
+    g = p.grid
+    tissue = g.eps_r != 1.0
+    rng = np.random.default_rng(12)
+    g.eps_r[tissue] *= rng.uniform(0.3, 1.7, int(tissue.sum()))
+    g.sigma[tissue] *= rng.uniform(0.3, 1.7, int(tissue.sum()))
+    op = lib.Operator(p)
+    d, _, S_same, _ = oracle_same(p, op)
+    op.schur_setup(precond=True)
+    b = synth.complex_normal(op.N, 8)
+    ref = S_same.solve(b)
+    its = {}
+    for pc in (True, False):
+        x, st = op.solve(to_dev(b), tol=1e-10, restart=50, max_iter=3000, method=2, precond=pc)
+        assert st[0]["converged"]
+        its[pc] = st[0]["iterations"]
+        e = rel(x.cpu().numpy(), ref)
+        print("precond=%d: %d iterations, vs oracle solve %.2e" % (pc, its[pc], e))
+        assert e <= 1e-7
+    assert its[True] != its[False]
 
 
 def _edge_problem(kind):

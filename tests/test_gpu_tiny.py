@@ -47,7 +47,74 @@ def test_tiny_hybrid_against_fully_assembled(tiny):
     print("tiny: TT ranks %s, ACA rank %d, product vs fully assembled %.2e, port solution %.2e (%d iterations)"
           % (op.info()["tt_rank"], op.info()["aca_rank"], e_prod, e_sol, st[0]["iterations"]))
     assert st[0]["converged"]
-    assert e_prod <= 1e-2 and e_sol <= 1e-2
+    # product: within the TT-cross and ACA tolerance (1e-3, Sec. IV-C) with a factor 3 for the
+    # held-out estimate; solution: the paper's hybrid-vs-assembled differences for PWC are
+    # 0.08-0.52 % (Table II), this case measured 0.41 %
+    assert e_prod <= 3e-3 and e_sol <= 6e-3
+
+
+def _tt_apply(G, xf):
+    """Body field of far currents through TT cores [G1 (n1,r1), G2 (r1,n2,r2), G3 (r2,n3,r3),
+    G4 (r3,m)], contracted G4 first (eqs. (16)-(17)); returned with i1 fastest."""
+    G1, G2, G3, G4 = G
+    t3 = np.einsum("bkc,c->bk", G3, G4 @ xf)              # (r2, n3)
+    t2 = np.einsum("ajb,bk->ajk", G2, t3)                  # (r1, n2, n3)
+    y = np.einsum("ia,ajk->ijk", G1, t2)                   # (n1, n2, n3)
+    return y.transpose(2, 1, 0).ravel()
+
+
+def _tt_apply_t(G, xb):
+    """Far rows of body currents through the same cores (eqs. (18)-(19)); xb with i1 fastest."""
+    G1, G2, G3, G4 = G
+    n1, n2, n3 = G1.shape[0], G2.shape[1], G3.shape[1]
+    X = xb.reshape(n3, n2, n1).transpose(2, 1, 0)
+    u1 = np.einsum("ia,ijk->ajk", G1, X)
+    u2 = np.einsum("ajb,ajk->bk", G2, u1)
+    u3 = np.einsum("bkc,bk->c", G3, u2)
+    return u3 @ G4
+
+
+def test_tt_products_two_split_k_chunks(lib):
+    """TT forward (far currents to body rows) and transpose (body currents to far rows) on the
+    16^3 grid, whose n1 n2 = 256 spans two 128-wide split-K chunks of the merged-core GEMM: random
+    cores of the 2 mm workload's ranks (13, 42, 96) imported, results against the cores
+    contracted on the CPU, 1e-10. Air voxels carry identity rows and columns, so only tissue
+    voxels couple."""
+    p = synth.tiny_case()
+    op = lib.Operator(p, build_far=0)
+    d = system.discretize(p)
+    n1, n2, n3 = p.grid.n
+    nv = n1 * n2 * n3
+    mf, mn = op.m_far, op.m_near
+    rng = np.random.default_rng(17)
+    ranks = (13, 42, 96)
+    cores = []
+    for a in range(3):
+        c = lambda *s: (rng.standard_normal(s) + 1j * rng.standard_normal(s)) / np.sqrt(s[0])
+        G = [c(n1, ranks[0]), c(ranks[0], n2, ranks[1]), c(ranks[1], n3, ranks[2]), c(ranks[2], mf)]
+        op.import_tt(a, G)
+        cores.append(G)
+    tissue = (d.chi != 0).ravel()
+    xf = synth.complex_normal(mf, 3)
+    x = np.zeros(op.N, np.complex128)
+    x[:mf] = xf
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    off = mf + mn
+    for a in range(3):
+        ref = np.where(tissue, _tt_apply(cores[a], xf), 0)
+        got = y[off + a * nv: off + (a + 1) * nv]
+        e = rel(got, ref)
+        print("TT forward component %d: rel err %.2e" % (a, e))
+        assert e < 1e-10
+    x = np.zeros(op.N, np.complex128)
+    xb = synth.complex_normal(3 * nv, 4)
+    x[off:] = xb
+    y = op.matvec(to_dev(x)).cpu().numpy()
+    ref = sum(_tt_apply_t(cores[a], np.where(tissue, xb[a * nv:(a + 1) * nv], 0)) for a in range(3))
+    # the far rows also hold the dense far block's and the ACA's share, both zero for x_f = x_n = 0
+    e = rel(y[:mf], ref)
+    print("TT transpose: rel err %.2e" % e)
+    assert e < 1e-10
 
 
 def test_mie_variant_solve(lib):

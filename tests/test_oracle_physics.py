@@ -58,8 +58,10 @@ def test_vie_mie_high_contrast_converges_first_order():
     at first order (error roughly halves when h halves)."""
     e_coarse = _vie_mie_error(10, 5e-3, 20e-3)
     e_fine = _vie_mie_error(18, 2.5e-3, 20e-3)
-    assert e_coarse < 0.6
-    assert e_fine < 0.6 * e_coarse
+    # measured 47 % and 24 %: PWC currents on a staircased sphere of contrast 52 converge at first
+    # order from a large error, so the pin is the rate together with both levels
+    assert e_coarse < 0.5 and e_fine < 0.27
+    assert e_fine < 0.56 * e_coarse
 
 
 @pytest.fixture(scope="module")
