@@ -267,6 +267,21 @@ int vsie_schur_precond(struct vsie_handle* h, const void* x_dev, void* y_dev, vo
  * scratch; blocks. Errors: E_ARG, E_SINGULAR (exactly zero pivot column), E_NOMEM, E_HIP. */
 int vsie_dense_lu_solve(int n, void* A_dev, int64_t lda, void* B_dev, int64_t ldb, int nrhs, void* stream);
 
+/* vsie_dense_lu_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc). Same arguments, same kernels and
+ * the same result; the workspace (inverted diagonal blocks, panel work, the n x nrhs solve buffer,
+ * pivots, permutation, singularity flag) is a static device array of the library, about 16.8 MB,
+ * held on every GPU the library runs on until the process ends; its address on a device is looked
+ * up on the first call there. Sizes: n <= VSIE_LU_NOALLOC_MAX_N, nrhs <= VSIE_LU_NOALLOC_MAX_NRHS,
+ * else E_ARG. Calls no hipMalloc, hipFree or other allocating routine, on the device or the host
+ * (the row permutation is formed on the device; only the singularity flag is read back). Every
+ * call on one GPU shares that GPU's workspace, which keeps the last call's contents: calls that
+ * overlap on one GPU (several streams or host threads) race and must be serialised by the caller.
+ * Blocks. Errors: E_ARG, E_SINGULAR, E_HIP. */
+#define VSIE_LU_NOALLOC_MAX_N 4096
+#define VSIE_LU_NOALLOC_MAX_NRHS 64
+int vsie_dense_lu_solve_noalloc(int n, void* A_dev, int64_t lda, void* B_dev, int64_t ldb, int nrhs, void* stream);
+
 void vsie_destroy(struct vsie_handle* h);
 const char* vsie_last_error(void);
 

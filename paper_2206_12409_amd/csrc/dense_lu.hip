@@ -243,6 +243,29 @@ __global__ void k_gather_rows(const cxd* __restrict__ src, int64_t ls, const int
 
 static unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Row permutation of the factorisation: the interchanges ipiv[0..n) applied in order to the
+// identity, perm[i] = the row of A that ends in row i. The swaps are a sequential chain, so one
+// thread applies them in LDS (n <= LU_PERM_LDS) and the workgroup writes the result out.
+__global__ __launch_bounds__(256) void k_lu_perm(const int* __restrict__ ipiv, int n, int* __restrict__ perm) {
+  __shared__ int q[LU_PERM_LDS];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = i;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < n; ++j) {
+      const int p = ipiv[j];
+      const int t = q[j];
+      q[j] = q[p];
+      q[p] = t;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = q[i];
+}
+
 // C = (negate ? -1 : 1) A B (+ C when accumulate), all row-major with the given row strides
 static void gemm_rm(hipStream_t st, int M, int N, int K, const cxd* A, int64_t lda, const cxd* B, int64_t ldb, cxd* C,
                     int64_t ldc, int accumulate, int negate) {
@@ -281,11 +304,12 @@ static void lu_urows(hipStream_t st, cxd* A, int64_t lda, int r0, int nb, int c0
 
 constexpr int LU_GROUP = 4;
 
-void lu_factor(hipStream_t st, DenseLU& F, cxd* work) {
+void lu_factor(hipStream_t st, DenseLU& F, cxd* work, bool device_perm) {
   const int n = F.n;
   const int64_t lda = F.lda;
   cxd* A = F.A;
-  VSIE_HIP(hipMemsetAsync(F.d_info, 0, sizeof(int), st));
+  if (device_perm && n > LU_PERM_LDS) throw Error(VSIE_E_ARG, "dense LU: device permutation limited to n <= 8192");
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, F.d_info, 1, 0);
   // one panel of nb columns at k: pivots and rank-one updates inside it, its interchanges applied
   // to every other column, inverses of its diagonal triangles
   auto panel = [&](int k, int nb) {
@@ -342,8 +366,18 @@ void lu_factor(hipStream_t st, DenseLU& F, cxd* work) {
     }
   }
   VSIE_HIP(hipGetLastError());
-  std::vector<int> ipiv(n);
   int info = 0;
+  if (device_perm) {
+    // nothing held on the host: the permutation is formed on the device, only info comes back
+    if (n > 0) hipLaunchKernelGGL(k_lu_perm, dim3(1), dim3(256), 0, st, F.d_ipiv, n, F.d_perm);
+    VSIE_HIP(hipGetLastError());
+    VSIE_HIP(hipMemcpyAsync(&info, F.d_info, sizeof(int), hipMemcpyDeviceToHost, st));
+    VSIE_HIP(hipStreamSynchronize(st));
+    if (info != 0)
+      throw Error(VSIE_E_SINGULAR, "dense LU: exactly singular pivot in column " + std::to_string(info - 1));
+    return;
+  }
+  std::vector<int> ipiv(n);
   if (n > 0) VSIE_HIP(hipMemcpyAsync(ipiv.data(), F.d_ipiv, sizeof(int) * n, hipMemcpyDeviceToHost, st));
   VSIE_HIP(hipMemcpyAsync(&info, F.d_info, sizeof(int), hipMemcpyDeviceToHost, st));
   VSIE_HIP(hipStreamSynchronize(st));

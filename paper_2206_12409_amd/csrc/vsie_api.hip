@@ -3,7 +3,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
+#include <string>
 
 #include "dense_lu.h"
 #include "kernels.h"
@@ -1862,6 +1864,76 @@ int vsie_dense_lu_solve(int n, void* A_dev, int64_t lda, void* B_dev, int64_t ld
     if (nrhs > 0) {
       Scratch W(sizeof(cxd) * (size_t)n * nrhs);
       lu_solve(st, F, (cxd*)B_dev, ldb, nrhs, W.as<cxd>());
+      VSIE_HIP(hipStreamSynchronize(st));
+    }
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Workspace of vsie_dense_lu_solve_noalloc: one static device array per GPU, carved into the
+// inverted diagonal blocks, the factorisation's work panel, the solve's n x nrhs buffer, the pivots,
+// the permutation and the singularity flag. Host code never passes the array's name to a kernel
+// (on the host it only stands for the symbol): each device's address is looked up once with
+// hipGetSymbolAddress and kept in g_lu_scratch_ptr.
+namespace {
+constexpr int64_t LU_NA_ALIGN = 256;
+constexpr int64_t lu_na_round(int64_t b) { return (b + LU_NA_ALIGN - 1) / LU_NA_ALIGN * LU_NA_ALIGN; }
+constexpr int64_t LU_NA_BLK = lu_na_round((int64_t)((VSIE_LU_NOALLOC_MAX_N + LU_NB - 1) / LU_NB) * LU_NB * LU_NB * 16);
+constexpr int64_t LU_NA_WORK = lu_na_round((int64_t)LU_NB * VSIE_LU_NOALLOC_MAX_N * 16);
+constexpr int64_t LU_NA_W = lu_na_round((int64_t)VSIE_LU_NOALLOC_MAX_N * VSIE_LU_NOALLOC_MAX_NRHS * 16);
+constexpr int64_t LU_NA_INT = lu_na_round((int64_t)VSIE_LU_NOALLOC_MAX_N * 4);
+constexpr int64_t LU_NA_BYTES = 2 * LU_NA_BLK + LU_NA_WORK + LU_NA_W + 2 * LU_NA_INT + LU_NA_ALIGN;
+static_assert(VSIE_LU_NOALLOC_MAX_N <= LU_PERM_LDS, "permutation formed on the device");
+constexpr int LU_NA_MAX_DEVICES = 64;
+std::mutex g_lu_scratch_mutex;
+void* g_lu_scratch_ptr[LU_NA_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[LU_NA_BYTES];
+
+// device address of this GPU's copy of scratch (looked up on the first call on that device)
+static void* lu_scratch_address() {
+  int dev = 0;
+  VSIE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= LU_NA_MAX_DEVICES) throw Error(VSIE_E_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_lu_scratch_mutex);
+  if (!g_lu_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    VSIE_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Error(VSIE_E_HIP, "hipGetSymbolAddress returned no address");
+    g_lu_scratch_ptr[dev] = ptr;
+  }
+  return g_lu_scratch_ptr[dev];
+}
+
+extern "C" {
+
+int vsie_dense_lu_solve_noalloc(int n, void* A_dev, int64_t lda, void* B_dev, int64_t ldb, int nrhs, void* stream) {
+  if (n < 0 || nrhs < 0 || lda < n || ldb < nrhs || (n > 0 && (!A_dev || (nrhs > 0 && !B_dev))))
+    return fail(VSIE_E_ARG, "bad argument");
+  if (n > VSIE_LU_NOALLOC_MAX_N || nrhs > VSIE_LU_NOALLOC_MAX_NRHS)
+    return fail(VSIE_E_ARG, "dense LU without allocation: n <= " + std::to_string(VSIE_LU_NOALLOC_MAX_N) +
+                                " and nrhs <= " + std::to_string(VSIE_LU_NOALLOC_MAX_NRHS) + " only");
+  if (n == 0) return VSIE_OK;
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char* base = (unsigned char*)lu_scratch_address();
+    DenseLU F;
+    F.n = n;
+    F.lda = lda;
+    F.A = (cxd*)A_dev;
+    F.Linv = (cxd*)base;
+    F.Uinv = (cxd*)(base + LU_NA_BLK);
+    cxd* work = (cxd*)(base + 2 * LU_NA_BLK);
+    cxd* W = (cxd*)(base + 2 * LU_NA_BLK + LU_NA_WORK);
+    F.d_ipiv = (int*)(base + 2 * LU_NA_BLK + LU_NA_WORK + LU_NA_W);
+    F.d_perm = (int*)(base + 2 * LU_NA_BLK + LU_NA_WORK + LU_NA_W + LU_NA_INT);
+    F.d_info = (int*)(base + 2 * LU_NA_BLK + LU_NA_WORK + LU_NA_W + 2 * LU_NA_INT);
+    lu_factor(st, F, work, true);   // clears the flag, blocks to read it back
+    if (nrhs > 0) {
+      lu_solve(st, F, (cxd*)B_dev, ldb, nrhs, W);
       VSIE_HIP(hipStreamSynchronize(st));
     }
   });

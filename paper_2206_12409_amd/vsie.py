@@ -22,7 +22,8 @@ X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
 EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_sizes", "vsie_rhs",
             "vsie_matvec", "vsie_solve", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
             "vsie_profile", "vsie_profile_mask", "vsie_profile_read", "vsie_schur_setup", "vsie_schur_info",
-            "vsie_schur_matvec", "vsie_schur_precond", "vsie_dense_lu_solve", "vsie_destroy", "vsie_last_error"]
+            "vsie_schur_matvec", "vsie_schur_precond", "vsie_dense_lu_solve", "vsie_dense_lu_solve_noalloc",
+            "vsie_destroy", "vsie_last_error"]
 
 
 STAGES = ["build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "body_out", "pfft_gather",
@@ -97,6 +98,7 @@ def load(path=LIB_PATH):
     lib.vsie_schur_matvec.argtypes = [vp, vp, vp, vp]
     lib.vsie_schur_precond.argtypes = [vp, vp, vp, vp]
     lib.vsie_dense_lu_solve.argtypes = [C.c_int, vp, C.c_int64, vp, C.c_int64, C.c_int, vp]
+    lib.vsie_dense_lu_solve_noalloc.argtypes = [C.c_int, vp, C.c_int64, vp, C.c_int64, C.c_int, vp]
     lib.vsie_destroy.argtypes = [vp]
     lib.vsie_destroy.restype = None
     lib.vsie_last_error.restype = C.c_char_p
@@ -388,9 +390,13 @@ class Operator:
         _check(load().vsie_import(self._h, X_ACA, 0, buf, len(blob)))
 
 
-def dense_lu_solve(A, B, stream=None):
+LU_NOALLOC_MAX_N, LU_NOALLOC_MAX_NRHS = 4096, 64
+
+
+def dense_lu_solve(A, B, stream=None, noalloc=False):
     """Solve A X = B on the device (complex128, row-major). A is overwritten by its LU factors and
-    B by X; both are returned."""
+    B by X; both are returned. noalloc selects vsie_dense_lu_solve_noalloc (static workspace,
+    n <= LU_NOALLOC_MAX_N, nrhs <= LU_NOALLOC_MAX_NRHS)."""
     import torch
     if A.dtype != torch.complex128 or B.dtype != torch.complex128 or not (A.is_cuda and B.is_cuda):
         raise ValueError("complex128 device tensors only")
@@ -399,6 +405,7 @@ def dense_lu_solve(A, B, stream=None):
     Bm = B if B.dim() == 2 else B.view(-1, 1)
     if Bm.shape[0] != A.shape[0] or Bm.stride(1) != 1:
         raise ValueError("B must have n rows and unit column stride")
-    _check(load().vsie_dense_lu_solve(A.shape[0], C.c_void_p(A.data_ptr()), A.stride(0), C.c_void_p(Bm.data_ptr()),
-                                      Bm.stride(0), Bm.shape[1], _stream_ptr(stream)))
+    fn = load().vsie_dense_lu_solve_noalloc if noalloc else load().vsie_dense_lu_solve
+    _check(fn(A.shape[0], C.c_void_p(A.data_ptr()), A.stride(0), C.c_void_p(Bm.data_ptr()), Bm.stride(0), Bm.shape[1],
+              _stream_ptr(stream)))
     return A, B

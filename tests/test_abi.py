@@ -97,6 +97,11 @@ def test_new_entry_points_reject_bad_arguments(vs):
     assert lib.vsie_dense_lu_solve(4, dummy, 4, dummy, 1, 2, None) == 1     # ldb < nrhs
     assert lib.vsie_dense_lu_solve(4, None, 4, dummy, 1, 1, None) == 1
     assert lib.vsie_dense_lu_solve(0, None, 0, None, 0, 0, None) == 0       # empty system: nothing to do
+    nmax, rmax = vs.LU_NOALLOC_MAX_N, vs.LU_NOALLOC_MAX_NRHS
+    assert lib.vsie_dense_lu_solve_noalloc(nmax + 1, dummy, nmax + 1, dummy, 1, 1, None) == 1
+    assert lib.vsie_dense_lu_solve_noalloc(8, dummy, 8, dummy, rmax + 1, rmax + 1, None) == 1
+    assert lib.vsie_dense_lu_solve_noalloc(4, dummy, 3, dummy, 1, 1, None) == 1
+    assert lib.vsie_dense_lu_solve_noalloc(0, None, 0, None, 0, 0, None) == 0
     o = vs.SolveOpts()
     lib.vsie_default_solve_opts(C.byref(o))
     assert o.precond == 1 and o.method == vs.VSIE_GMRES64 and o.restart == 50 and o.tol == 1e-6
@@ -130,6 +135,13 @@ def test_binding_structs_match_the_header(vs, tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for f in py._fields_:
             assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_noalloc_limits_match_the_header(vs):
+    import re as _re
+    src = open(os.path.join(ROOT, "include", "vsie.h")).read()
+    assert int(_re.search(r"#define VSIE_LU_NOALLOC_MAX_N (\d+)", src).group(1)) == vs.LU_NOALLOC_MAX_N
+    assert int(_re.search(r"#define VSIE_LU_NOALLOC_MAX_NRHS (\d+)", src).group(1)) == vs.LU_NOALLOC_MAX_NRHS
 
 
 def test_binding_rejects_bad_vectors_before_any_call(vs):
