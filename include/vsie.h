@@ -59,6 +59,12 @@ enum vsie_status {
 
 enum vsie_domain { VSIE_NEAR = 0, VSIE_FAR = 1 };
 enum vsie_dtype { VSIE_C128 = 0, VSIE_C64 = 1 };
+/* basis of the body currents (Sec. II-B): piecewise constant (3 unknowns per voxel) or piecewise
+ * linear (12 per voxel; not built, vsie_create returns E_UNSUPPORTED) */
+enum vsie_basis { VSIE_BASIS_PWC = 0, VSIE_BASIS_PWL = 1 };
+/* operator data held by the handle: complex128 only, or complex128 plus complex64 copies for the
+ * complex64 product and the mixed-precision solvers */
+enum vsie_precision { VSIE_PREC_FP64 = 0, VSIE_PREC_MIXED = 1 };
 
 /* A triangle mesh of a perfectly conducting surface (Sec. II-B, RWG basis). */
 typedef struct {
@@ -84,15 +90,23 @@ typedef struct {
   const vsie_mesh* meshes;
 } vsie_problem;
 
+/* Setup options. The discretisation fields fix the operator the paper defines (Sec. II-B, Sec. IV-B,
+ * Sec. IV-C); values other than the listed ones give E_UNSUPPORTED. */
 typedef struct {
   double tt_tol;              /* TT-cross relative accuracy, Sec. IV-C: 1e-3 */
   int32_t tt_rank_max;        /* rank cap per TT unfolding, 1..128 */
   double aca_tol;             /* ACA relative accuracy, Sec. IV-C: 1e-3 */
   int32_t aca_rank_max;       /* 1..256 */
   int32_t precorrect_dist;    /* Chebyshev distance (voxels) of precorrected pairs, default 2 */
-  int32_t build_c64;          /* also prepare complex64 operator data (mixed precision) */
+  int32_t precision;          /* VSIE_PREC_FP64 or VSIE_PREC_MIXED (default) */
   int32_t build_far;          /* compute TT-cross and ACA (0: zero far coupling until imported) */
-  uint64_t seed;              /* TT-cross initial index sets */
+  uint64_t seed;              /* TT-cross initial index sets, ACA held-out rows */
+  int32_t basis;              /* VSIE_BASIS_PWC (default); VSIE_BASIS_PWL: E_UNSUPPORTED */
+  int32_t stencil;            /* pFFT expansion block edge in voxels, Sec. IV-B: 5 */
+  int32_t quad_near_vol;      /* near coupling, volume points per voxel, Sec. IV-C: 8 (2x2x2 Gauss) */
+  int32_t quad_near_surf;     /* near coupling, points per triangle: 5 */
+  int32_t quad_far_vol;       /* far coupling (TT-cross entries): 1 (voxel centre) */
+  int32_t quad_far_surf;      /* far coupling: 1 (triangle centroid) */
 } vsie_options;
 
 typedef struct {
@@ -115,7 +129,7 @@ typedef struct {
   double tol;                 /* relative residual ||b - Ax|| / ||b||, default 1e-6 */
   int32_t restart;            /* GMRES restart length, default 50 (Sec. IV-C) */
   int32_t max_iter;           /* GMRES64: iterations; IR_MIXED: total inner complex64 iterations */
-  int32_t method;             /* VSIE_GMRES64, VSIE_IR_MIXED, VSIE_SCHUR or VSIE_SCHUR_MIXED */
+  int32_t method;             /* a vsie_method */
   double inner_tol;           /* IR_MIXED: inner complex64 solve tolerance, default 1e-3 */
   int32_t precond;            /* SCHUR: 1 (default) right-preconditions the reduced system, 0 none */
   double reorth;              /* Gram-Schmidt: a second classical pass follows a first that leaves less
@@ -125,7 +139,13 @@ typedef struct {
                                  ten roundings; 0 = always one pass; must lie in [0, 1] (else E_ARG) */
 } vsie_solve_opts;
 
-enum vsie_method { VSIE_GMRES64 = 0, VSIE_IR_MIXED = 1, VSIE_SCHUR = 2, VSIE_SCHUR_MIXED = 3 };
+enum vsie_method {
+  VSIE_GMRES64 = 0,
+  VSIE_IR_MIXED = 1,
+  VSIE_SCHUR = 2,
+  VSIE_SCHUR_MIXED = 3,
+  VSIE_SCHUR_LEARNED = 4   /* reduced system, flexible GMRES with the attached network (vsie_net_attach) */
+};
 
 typedef struct {
   int32_t iterations;         /* Krylov iterations (IR_MIXED: inner complex64 iterations) */
@@ -138,7 +158,8 @@ typedef struct {
 } vsie_solve_stats;
 
 /* Fill defaults: tt_tol 1e-3, tt_rank_max 96, aca_tol 1e-3, aca_rank_max 128,
- * precorrect_dist 2, build_c64 1, build_far 1, seed 1. */
+ * precorrect_dist 2, precision VSIE_PREC_MIXED, build_far 1, seed 1, basis VSIE_BASIS_PWC,
+ * stencil 5, quadrature 8 / 5 near and 1 / 1 far. */
 int vsie_default_options(vsie_options* opts);
 int vsie_default_solve_opts(vsie_solve_opts* opts);
 
@@ -150,15 +171,22 @@ int vsie_default_solve_opts(vsie_solve_opts* opts);
 int vsie_create(const vsie_problem* problem, const vsie_options* opts, void* stream,
                 struct vsie_handle** out);
 
+/* Sizes of the discrete system of eq. (15) (unknown counts of Sec. III: far and near RWG functions,
+ * three PWC components per voxel), the extended pFFT grid and its circulant FFT sizes (Sec. II-B),
+ * the compression ranks (eqs. (12), (14)), device bytes and setup time. Host only. Errors: E_ARG. */
 int vsie_sizes(const struct vsie_handle* h, vsie_sizes_t* out);
 
 /* Delta-gap right-hand side of one port (Sec. II-A after eq. (2)): b_m = s_m i w eps0 V0 l_m,
- * V0 = 1 V, into the caller-owned device buffer b_dev of N complex values of type dtype.
- * Asynchronous on stream. Errors: E_ARG (port out of range). */
+ * V0 = 1 V, into the caller-owned device buffer b_dev of N complex values of type dtype. The port
+ * tables live on the device from vsie_create on: this call only launches a fill and a scatter on
+ * the stream (asynchronous, no allocation, no synchronisation). Errors: E_ARG (port out of range,
+ * bad dtype, null pointer). */
 int vsie_rhs(const struct vsie_handle* h, int port, int dtype, void* b_dev, void* stream);
 
-/* y = Z x for nrhs columns, layout [nrhs][N] complex interleaved (complex128 or complex64 as
- * dtype says), device memory owned by the caller, 256-byte aligned, x and y must not alias.
+/* y = Z x, the hybrid operator of eq. (15) (far block eq. (6), ACA block eq. (12), pFFT block
+ * eq. (13) with the block-Toeplitz volume convolution of Sec. II-B, TT coupling eqs. (16)-(19)), for
+ * nrhs columns, layout [nrhs][N] complex interleaved (complex128 or complex64 as dtype says),
+ * device memory owned by the caller, 256-byte aligned, x and y must not alias.
  * Asynchronous on stream. The handle's work buffers serialise calls on one handle.
  * Errors: E_ARG, E_STATE (complex64 data not built), E_HIP. */
 int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, void* y_dev,
@@ -177,6 +205,10 @@ int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, v
  * SCHUR_MIXED: the same reduced, preconditioned system solved as IR_MIXED does: FP64 flexible
  * GMRES (20 steps per cycle) whose preconditioner is one complex64 GMRES cycle on the complex64
  * reduced operator (iterations count the inner ones, refinements the FP64 steps).
+ * SCHUR_LEARNED: FP64 flexible GMRES (restart `restart`) on the reduced system with the variable
+ * right preconditioner P(v) = M v + (learned body correction of the attached network, see
+ * vsie_net_attach); iterations count the preconditioner applications, refinements the flexible
+ * steps. Needs an attached network (else E_STATE); builds the SCHUR preconditioner M.
  * x_dev receives complex128. Blocks.
  * The Krylov basis and work vectors hold only the unknowns that couple (far and near currents,
  * tissue voxels): air voxels carry identity rows and columns, so their solution is b there.
@@ -185,10 +217,23 @@ int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, v
 int vsie_solve(struct vsie_handle* h, const vsie_solve_opts* opts, int nrhs, const void* b_dev,
                void* x_dev, vsie_solve_stats* stats, void* stream);
 
-/* Port current I = sum_m s_m l_m x_m of a solution held in host memory (complex128, length N). */
+/* The coil-port solves of the paper (one GMRES solve per channel, Sec. IV-C; Table I averages the
+ * channels): for each of the nports port numbers in ports (host array) the delta-gap right-hand
+ * side of vsie_rhs is formed on the device and Z x = b is solved as vsie_solve does with the same
+ * options; x_dev ([nports][N] complex128, caller-owned device memory) receives the solutions and
+ * stats (may be NULL) one entry per port. Blocks. Allocates the right-hand sides besides
+ * vsie_solve's work vectors. Errors: E_ARG (null pointer, nports < 1, port out of range), and
+ * those of vsie_solve. */
+int vsie_solve_ports(struct vsie_handle* h, const vsie_solve_opts* opts, int nports, const int32_t* ports,
+                     void* x_dev, vsie_solve_stats* stats, void* stream);
+
+/* Port current I = sum_m s_m l_m x_m of a solution held in host memory (complex128, length N):
+ * the current through the delta-gap edge of Sec. II-A; the input admittance is I / V0, V0 = 1 V. */
 int vsie_port_current(const struct vsie_handle* h, int port, const double* x_host, double* I_re_im);
 
-/* Setup artefacts (host copies), for checkpointing and for tests. `index` selects the TT
+/* Setup artefacts (host copies): the compressed blocks that Sec. VI proposes to store and recycle
+ * (TT cores of eq. (14), ACA factors of eq. (12)), the pFFT stencils of eq. (13) and the Toeplitz
+ * generator of Sec. II-B, for checkpointing and for tests. `index` selects the TT
  * component (0..2) where relevant. Call with host == NULL to query the byte count.
  *   VSIE_X_TT_CORES    int32 r1,r2,r3 then complex128 G1[n1][r1], G2[r1][n2][r2],
  *                      G3[r2][n3][r3], G4[r3][m_f]
@@ -282,7 +327,72 @@ int vsie_dense_lu_solve(int n, void* A_dev, int64_t lda, void* B_dev, int64_t ld
 #define VSIE_LU_NOALLOC_MAX_NRHS 64
 int vsie_dense_lu_solve_noalloc(int n, void* A_dev, int64_t lda, void* B_dev, int64_t ldb, int nrhs, void* stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Learned preconditioner (an addition to the paper's method, whose conclusion, Sec. VI, names a
+ * Calderon preconditioner as future work). A 3D convolutional U-Net on the voxel grid (4 levels,
+ * 16 to 64 channels, 3x3x3 convolutions, average pooling, nearest upsampling, ReLU; bfloat16
+ * matrix-core convolutions with float32 accumulation, float32 master weights, Adam) maps the body
+ * part of a residual (Re, Im of three components, scaled to unit RMS, plus two channels of the
+ * body diagonal's inverse) to a correction of the body currents. Parameter layout (float32, the
+ * order of the network's twelve layers e1a e1b e2a e2b e3a e3b e4a e4b d3 d2 d1 out): per layer
+ * the weights [Cout][3][3][3][Cin] (taps z, y, x), then the biases [Cout].
+ * The network object is independent of any handle: it collects training pairs from the solves of
+ * one or several handles (phantoms) whose body grids agree, trains on them, and is attached to the
+ * handle whose solves it preconditions. The network grid is the body grid rounded up to multiples
+ * of 8 per axis. */
+struct vsie_net;
+/* New network: He-normal weights from a seeded generator, zero biases; room for pair_capacity
+ * training pairs (bfloat16, 32 bytes per grid voxel each, allocated at the first collected pair).
+ * Errors: E_ARG, E_NOMEM. */
+int vsie_net_create(uint64_t seed, int64_t pair_capacity, struct vsie_net** out);
+void vsie_net_destroy(struct vsie_net* net);
+/* Parameter count, collected pairs and Adam steps taken (each pointer may be NULL). */
+int vsie_net_info(const struct vsie_net* net, int64_t* nparam, int64_t* n_pairs, int64_t* adam_steps);
+/* Copy the float32 parameters (layout above) to or from host memory; count must equal nparam.
+ * Blocks. Errors: E_ARG. */
+int vsie_net_get_params(const struct vsie_net* net, float* host, int64_t count);
+int vsie_net_set_params(struct vsie_net* net, const float* host, int64_t count);
+/* Training pairs from the preconditioned SCHUR solves of the given ports of h (opts->method must be
+ * VSIE_SCHUR with precond 1): every Arnoldi step applies the reduced operator A_S to z = M v and
+ * stores (input: body part of w = A_S z scaled to unit RMS with the material channels; target:
+ * body part of z - D^-1 w over the same scale times the largest |D^-1|), until the capacity is
+ * reached. *n_pairs receives the total held. Blocks. Errors: those of vsie_solve_ports except
+ * E_NOCONV, E_ARG (grid differs from the pairs already held). */
+int vsie_net_collect(struct vsie_net* net, struct vsie_handle* h, int nports, const int32_t* ports,
+                     const vsie_solve_opts* opts, int64_t* n_pairs, void* stream);
+/* epochs passes of Adam (learning rate lr, betas 0.9 / 0.999, eps 1e-8) over the stored pairs,
+ * one pair per step in a seeded shuffled order, each pair under a random common complex phase;
+ * loss = sum (y - t)^2 / (2 n); *last_loss = mean loss of the last epoch. Blocks.
+ * Errors: E_ARG, E_STATE (no pairs). */
+int vsie_net_train(struct vsie_net* net, int epochs, float lr, uint64_t seed, double* last_loss, void* stream);
+/* Attach net (NULL detaches) to h for VSIE_SCHUR_LEARNED; net must outlive its use. */
+int vsie_net_attach(struct vsie_handle* h, struct vsie_net* net);
+/* Network passes on explicit device tensors (float32, [D][H][W][C], D, H, W multiples of 8):
+ * forward of x (C = 8) into y (C = 6); loss and all parameter gradients for x and target t
+ * (C = 6) with the gradients copied to grads_host (nparam floats, may be NULL); one Adam step with
+ * the gradients held. Errors: E_ARG, E_NOMEM, E_HIP. */
+int vsie_net_forward(struct vsie_net* net, int D, int H, int W, const float* x_dev, float* y_dev, void* stream);
+int vsie_net_gradients(struct vsie_net* net, int D, int H, int W, const float* x_dev, const float* t_dev,
+                       double* loss, float* grads_host, void* stream);
+int vsie_net_adam(struct vsie_net* net, float lr, void* stream);
+/* One layer on explicit device buffers, in the kernels' storage layout ([D][H][W][C] float32, C
+ * padded to a multiple of 16 with zeros; D, H, W the layer's own grid). mode 0: forward with
+ * bias and ReLU, in0 the (first) input and, for the decoder layers d3, d2, d1, in0 at half
+ * resolution (upsampled in place) and in1 the skip input; out has the padded Cout channels.
+ * mode 1: gradient with respect to the layer input from the output gradient in0 (masked by
+ * mask > 0, mask = the layer output, for ReLU layers); out has the padded Cin channels.
+ * Errors: E_ARG. */
+int vsie_net_layer(struct vsie_net* net, int layer, int mode, int D, int H, int W, const float* in0,
+                   const float* in1, const float* mask, float* out, void* stream);
+/* Weight and bias gradients of one layer from its input(s) and output gradient g (masked by
+ * mask > 0 for ReLU layers), copied to host: gw [Cout][27][Cin], gb [Cout]. Blocks. */
+int vsie_net_layer_wgrad(struct vsie_net* net, int layer, int D, int H, int W, const float* in0, const float* in1,
+                         const float* g, const float* mask, float* gw_host, float* gb_host, void* stream);
+
+/* Release the handle and every device allocation it owns (operator data of eq. (15), solver and
+ * elimination work space). NULL is ignored. Not thread-safe against calls on the same handle. */
 void vsie_destroy(struct vsie_handle* h);
+/* Message of the last failed call on this thread (empty if none); valid until the next call. */
 const char* vsie_last_error(void);
 
 #ifdef __cplusplus

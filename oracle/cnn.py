@@ -114,13 +114,20 @@ def up2_backward(g):
     return g.reshape(D // 2, 2, H // 2, 2, W // 2, 2, C).sum((1, 3, 5))
 
 
-def forward(p, x, keep=False):
+def _identity(a):
+    return a
+
+
+def forward(p, x, keep=False, quant=False):
     """Network output for input x [D][H][W][8]; with keep, also the activations the backward
-    pass needs (pre-activation values of every convolution and its inputs)."""
+    pass needs (pre-activation values of every convolution and its inputs). quant rounds every
+    convolution's input and weights to bfloat16 (the matrix-core operands) and keeps the rest in
+    float64."""
     acts = {}
+    q = bf16 if quant else _identity
 
     def layer(name, inp, relu):
-        z = conv3(inp, p[name + ".w"], p[name + ".b"])
+        z = conv3(q(inp), q(p[name + ".w"]), p[name + ".b"])
         acts[name] = (inp, z)
         return np.maximum(z, 0.0) if relu else z
 
@@ -140,19 +147,23 @@ def loss(p, x, t):
     return 0.5 * np.sum((y - t) ** 2) / t.size
 
 
-def backward(p, x, t):
-    """Loss and its gradients with respect to every parameter and to the input x."""
-    y, acts = forward(p, x, keep=True)
+def backward(p, x, t, quant=False):
+    """Loss and its gradients with respect to every parameter and to the input x. quant: the
+    convolutions' operands rounded to bfloat16 as in forward, and in the backward products the
+    layer input, the weights and the masked output gradient rounded likewise (the bias gradient
+    sums the unrounded output gradient)."""
+    y, acts = forward(p, x, keep=True, quant=quant)
     g = {}
     gy = (y - t) / t.size
+    q = bf16 if quant else _identity
 
     def back(name, gout, relu):
         inp, z = acts[name]
         if relu:
             gout = gout * (z > 0)
-        gx, gw, gb = conv3_backward(inp, p[name + ".w"], gout)
+        gx, gw, _ = conv3_backward(q(inp), q(p[name + ".w"]), q(gout))
         g[name + ".w"] = gw
-        g[name + ".b"] = gb
+        g[name + ".b"] = gout.sum((0, 1, 2))
         return gx
 
     gd1 = back("out", gy, False)

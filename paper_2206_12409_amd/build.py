@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvsie.so")
 BUILD = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["kernels.hip", "vsie_api.hip", "dense_lu.hip"]
+HIP_SOURCES = ["kernels.hip", "vsie_api.hip", "dense_lu.hip", "cnn.hip", "learned.hip"]
 HOST_SOURCES = ["setup_host.cpp", "setup_compress.cpp"]
 ARCH = os.environ.get("VSIE_OFFLOAD_ARCH", "gfx950")
 

@@ -780,8 +780,13 @@ __global__ __launch_bounds__(NP * L / V) ZCONV_ATTR void k_zconv3(cx<R>* __restr
 // so the FFT exchanges only synchronise the wavefront. The block's NP pencils (adjacent k1) are
 // loaded and stored through an LDS staging area [NP][3][L + 1] with neighbouring threads on
 // neighbouring pencils (coalesced), the only two block-wide barriers.
+#ifdef ZCONV4_WAVES
+#define ZCONV4_ATTR __attribute__((amdgpu_waves_per_eu(ZCONV4_WAVES, 8)))
+#else
+#define ZCONV4_ATTR
+#endif
 template <typename R, int L, int V, int NP>
-__global__ __launch_bounds__(NP * L / V) void k_zconv4(cx<R>* __restrict__ buf, int n3, int P1, int P2,
+__global__ __launch_bounds__(NP * L / V) ZCONV4_ATTR void k_zconv4(cx<R>* __restrict__ buf, int n3, int P1, int P2,
                                                        const cx<R>* __restrict__ spec, const cx<R>* __restrict__ tw,
                                                        const int* __restrict__ order) {
   constexpr int T = L / V;

@@ -5,8 +5,10 @@
 #include <cstring>
 #include <mutex>
 #include <numeric>
+#include <random>
 #include <string>
 
+#include "cnn.h"
 #include "dense_lu.h"
 #include "kernels.h"
 
@@ -14,6 +16,10 @@ using namespace vsie;
 
 struct vsie_handle {
   Handle H;
+};
+
+struct vsie_net {
+  NetState S;
 };
 
 namespace {
@@ -146,7 +152,7 @@ void setup_volume(Handle& H) {
   const double scale = H.h * H.h * H.h / ((double)P1 * P2 * P3);
   H.d64.spec = H.dalloc<cxd>(6 * SO);
   launch_extract_octant<double>(st, full2, H.P, scale, H.d64.spec);
-  if (H.opts.build_c64) {
+  if (H.opts.precision) {
     H.d32.spec = H.dalloc<cxf>(6 * SO);
     launch_extract_octant<float>(st, full2, H.P, scale, H.d32.spec);
   }
@@ -155,7 +161,7 @@ void setup_volume(Handle& H) {
   (void)hipFree(full2);
   for (int a = 0; a < 3; ++a) {
     H.d64.tw[a] = tw[a];
-    if (H.opts.build_c64) H.d32.tw[a] = twiddles<float>(H, H.P[a]);
+    if (H.opts.precision) H.d32.tw[a] = twiddles<float>(H, H.P[a]);
   }
   // body diagonal and mask
   std::vector<cxd> dv(H.nv, cxd{0, 0});
@@ -168,7 +174,7 @@ void setup_volume(Handle& H) {
     }
   H.d_mask = upload(H, mask);
   H.d64.dv_chi = upload_cx<double>(H, dv);
-  if (H.opts.build_c64) H.d32.dv_chi = upload_cx<float>(H, dv);
+  if (H.opts.precision) H.d32.dv_chi = upload_cx<float>(H, dv);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -181,7 +187,7 @@ void setup_pfft(Handle& H) {
     for (int a = 0; a < 3; ++a) base_ext[3 * i + a] = H.base[3 * i + a] + H.ob[a];
   H.d_base = upload(H, base_ext);
   H.d64.W = upload(H, H.Wh);
-  if (H.opts.build_c64) {
+  if (H.opts.precision) {
     std::vector<float> wf(H.Wh.begin(), H.Wh.end());
     H.d32.W = upload(H, wf);
   }
@@ -217,7 +223,7 @@ void setup_pfft(Handle& H) {
   H.d_rowptr = upload(H, rowptr);
   H.d_rowrwg = upload(H, rowrwg);
   H.d64.roww = upload(H, roww);
-  if (H.opts.build_c64) {
+  if (H.opts.precision) {
     std::vector<float> rf(roww.begin(), roww.end());
     H.d32.roww = upload(H, rf);
   }
@@ -324,7 +330,7 @@ void setup_pfft(Handle& H) {
   H.d_pc_rowptr = upload(H, rp);
   H.d_pc_col = upload(H, col);
   H.d64.pc_val = upload_cx<double>(H, val);
-  if (H.opts.build_c64) H.d32.pc_val = upload_cx<float>(H, val);
+  if (H.opts.precision) H.d32.pc_val = upload_cx<float>(H, val);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -361,7 +367,10 @@ void copy_zff_c64(Handle& H) {
 }
 
 void setup_aca(Handle& H) {
-  // partially pivoted ACA of Z_nf (m_n x m_f) ~ sum_l u_l v_l^T; stored as U V^* (V = conj(v))
+  // partially pivoted ACA of Z_nf (m_n x m_f) ~ sum_l u_l v_l^T; stored as U V^* (V = conj(v)).
+  // The stopping estimate ||u_k|| ||v_k|| <= tol ||S_k||_F only sees the rows the pivots visited;
+  // once it holds, the error is measured on held-out rows (exact rows of the block against U V^*)
+  // and, while that exceeds tol, the approximation continues from the worst held-out row.
   const int mn = H.mn, mf = H.mf;
   cxd* d_row = H.dalloc<cxd>(mf);
   cxd* d_col = H.dalloc<cxd>(mn);
@@ -370,6 +379,40 @@ void setup_aca(Handle& H) {
   int i = 0;
   double norm2 = 0;
   const int kmax = std::min({H.opts.aca_rank_max, mn, mf, 256});
+  // held-out rows: a seeded sample of the near RWGs, at most 32
+  std::vector<int> hold;
+  {
+    std::mt19937_64 rng(H.opts.seed * 7919 + 17);
+    std::vector<int> all(mn);
+    std::iota(all.begin(), all.end(), 0);
+    std::shuffle(all.begin(), all.end(), rng);
+    all.resize(std::min(mn, 32));
+    std::sort(all.begin(), all.end());
+    hold = all;
+  }
+  std::vector<std::vector<cxd>> hold_rows;
+  double hold_norm2 = 0;
+  for (int q : hold) {
+    launch_zcc_dense(H.stream, H.dnear, H.dfar, H.k0, q, 1, d_row);
+    hold_rows.push_back(download(d_row, mf));
+    for (const cxd& z : hold_rows.back()) hold_norm2 += z.re * z.re + z.im * z.im;
+  }
+  // relative error of the current U V^T on the held-out rows, and the worst row
+  auto held_out = [&](int* worst) {
+    double e2 = 0, wbest = -1;
+    *worst = -1;
+    for (size_t h = 0; h < hold.size(); ++h) {
+      double r2 = 0;
+      for (int j = 0; j < mf; ++j) {
+        cxd d = hold_rows[h][j];
+        for (size_t l = 0; l < us.size(); ++l) d -= us[l][hold[h]] * vs[l][j];
+        r2 += d.re * d.re + d.im * d.im;
+      }
+      e2 += r2;
+      if (r2 > wbest && !used_row[hold[h]]) { wbest = r2; *worst = hold[h]; }
+    }
+    return hold_norm2 > 0 ? std::sqrt(e2 / hold_norm2) : 0.0;
+  };
   for (int it = 0; it < 4 * kmax && (int)us.size() < kmax; ++it) {
     used_row[i] = 1;
     launch_zcc_dense(H.stream, H.dnear, H.dfar, H.k0, i, 1, d_row);
@@ -412,7 +455,12 @@ void setup_aca(Handle& H) {
     norm2 += 2.0 * cross.re + nu * nvv;
     us.push_back(u);
     vs.push_back(v);
-    if (sqrt(nu * nvv) <= H.opts.aca_tol * sqrt(std::max(norm2, 0.0))) break;
+    if (sqrt(nu * nvv) <= H.opts.aca_tol * sqrt(std::max(norm2, 0.0))) {
+      int worst = -1;
+      if (held_out(&worst) <= H.opts.aca_tol || worst < 0) break;
+      i = worst;   // the estimate was optimistic: continue from the worst held-out row
+      continue;
+    }
     int nxt = -1;
     best = -1;
     for (int q = 0; q < mn; ++q) {
@@ -447,7 +495,7 @@ void upload_aca(Handle& H) {
   const std::vector<cxd> Ut = rank_major(H.aca_U), Vt = rank_major(H.aca_V);
   H.d64.U = upload_cx<double>(H, Ut);
   H.d64.V = upload_cx<double>(H, Vt);
-  if (H.opts.build_c64) {
+  if (H.opts.precision) {
     H.d32.U = upload_cx<float>(H, Ut);
     H.d32.V = upload_cx<float>(H, Vt);
   }
@@ -530,10 +578,10 @@ void upload_tt(Handle& H, int chi) {
     }
   });
   H.d64.G12[chi] = upload_cx<double>(H, M);
-  if (H.opts.build_c64) H.d32.G12[chi] = upload_cx<float>(H, M);
+  if (H.opts.precision) H.d32.G12[chi] = upload_cx<float>(H, M);
   for (int k = 2; k < 4; ++k) {
     H.d64.G[chi][k] = upload_cx<double>(H, H.tt_host[chi][k]);
-    if (H.opts.build_c64) H.d32.G[chi][k] = upload_cx<float>(H, H.tt_host[chi][k]);
+    if (H.opts.precision) H.d32.G[chi][k] = upload_cx<float>(H, H.tt_host[chi][k]);
   }
 }
 
@@ -994,6 +1042,7 @@ static void setup_schur(Handle& H, bool precond) {
       if (H.chi[p].re != 0 || H.chi[p].im != 0)
         for (int a = 0; a < 3; ++a) inv[(size_t)a * H.nv + p] = cinv(h3 * cinv(H.chi[p]) + h3 * T0[a]);
     Sc.d64.invdiag = upload_cx<double>(H, inv);
+    build_material(H, inv);
     Sc.precond = true;
   }
   // complex64 copies for the mixed-precision solve
@@ -1330,10 +1379,31 @@ int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, bool mixed, con
     launch_scatter_idx(st, in, H.d_active, Nc, fin);
     precond_apply<double>(H, fin, tmp, st, use_pc);
     matvec_schur<double>(H, tmp, fout, st);
+    // training pairs of the learned preconditioner: z = M v with its exact image A_S z
+    if (H.collect && use_pc && Sc.precond) net_collect_pair(H, *H.collect, tmp, fout, Sc.vec[2], st);
     launch_gather_idx(st, fout, H.d_active, Nc, out);
   };
   int it = 0;
-  if (!mixed) {
+  const bool learned = so.method == VSIE_SCHUR_LEARNED;
+  if (learned) {
+    // flexible GMRES on A_S x = b_r with the preconditioner P(v) = M v + learned body correction
+    auto AS = [&](const cxd* in, cxd* out) {
+      launch_scatter_idx(st, in, H.d_active, Nc, fin);
+      matvec_schur<double>(H, fin, fout, st);
+      launch_gather_idx(st, fout, H.d_active, Nc, out);
+    };
+    auto PL = [&](const cxd* v, cxd* z) {
+      launch_scatter_idx(st, v, H.d_active, Nc, fin);
+      precond_apply<double>(H, fin, tmp, st, true);
+      net_apply(H, *H.net, fin, tmp, st);
+      launch_gather_idx(st, tmp, H.d_active, Nc, z);
+      ++it;
+      return it < so.max_iter;
+    };
+    int steps = 0;
+    S.fgmres(AS, PL, ws.bc, ws.xc, tol, so.restart, &steps, rel, ws.Vout, ws.Zout, ws.wc, ws.hv);
+    *outer = steps;
+  } else if (!mixed) {
     it = S.gmres(AM, ws.bc, ws.xc, tol, so.restart, so.max_iter, restarts, rel, H.d_krylov, ws.wc, ws.hv);
   } else {
     // complex64 product of the preconditioned reduced operator on compact FP64 vectors
@@ -1355,10 +1425,14 @@ int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, bool mixed, con
     };
     S.fgmres(AM, P32, ws.bc, ws.xc, tol, IR_OUTER_M, outer, rel, ws.Vout, ws.Zout, ws.wc, ws.hv);
   }
-  // x = M u on the coupled unknowns, b on the air voxels
-  launch_scatter_idx(st, ws.xc, H.d_active, Nc, fin);
-  precond_apply<double>(H, fin, tmp, st, use_pc);
-  launch_gather_idx(st, tmp, H.d_active, Nc, ws.wc);
+  // x = M u on the coupled unknowns (the flexible method's iterate is x itself), b on the air voxels
+  if (learned) {
+    VSIE_HIP(hipMemcpyAsync(ws.wc, ws.xc, sizeof(cxd) * Nc, hipMemcpyDeviceToDevice, st));
+  } else {
+    launch_scatter_idx(st, ws.xc, H.d_active, Nc, fin);
+    precond_apply<double>(H, fin, tmp, st, use_pc);
+    launch_gather_idx(st, tmp, H.d_active, Nc, ws.wc);
+  }
   VSIE_HIP(hipMemcpyAsync(x, b, sizeof(cxd) * N, hipMemcpyDeviceToDevice, st));
   launch_scatter_idx(st, ws.wc, H.d_active, Nc, x);
   if (mf) {
@@ -1373,6 +1447,23 @@ int solve_schur(Handle& H, Solver& S, const vsie_solve_opts& so, bool mixed, con
   return it;
 }
 
+__global__ void k_zero_words(uint64_t* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// delta-gap right-hand side of one port from the device tables: zero fill, then the port's edges
+void port_rhs(const Handle& H, int port, int dtype, void* b, hipStream_t st) {
+  const int64_t words = (dtype == VSIE_C128 ? 2 : 1) * H.N;   // 8-byte words of N complex values
+  const unsigned blocks = (unsigned)std::min<int64_t>((words + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_zero_words, dim3(blocks), dim3(256), 0, st, (uint64_t*)b, words);
+  const int e0 = H.port_off[port], ne = H.port_off[port + 1] - e0;
+  if (dtype == VSIE_C128)
+    launch_scatter_rhs<double>(st, H.d_port_idx + e0, H.d_port_re + e0, H.d_port_im + e0, ne, (cxd*)b);
+  else
+    launch_scatter_rhs<float>(st, H.d_port_idx + e0, H.d_port_re + e0, H.d_port_im + e0, ne, (cxf*)b);
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -1385,9 +1476,15 @@ int vsie_default_options(vsie_options* o) {
   o->aca_tol = 1e-3;
   o->aca_rank_max = 128;
   o->precorrect_dist = 2;
-  o->build_c64 = 1;
+  o->precision = VSIE_PREC_MIXED;
   o->build_far = 1;
   o->seed = 1;
+  o->basis = VSIE_BASIS_PWC;
+  o->stencil = 5;
+  o->quad_near_vol = 8;
+  o->quad_near_surf = 5;
+  o->quad_far_vol = 1;
+  o->quad_far_surf = 1;
   return VSIE_OK;
 }
 
@@ -1431,8 +1528,16 @@ int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, v
     if (!(p->freq_hz > 0) || !std::isfinite(p->freq_hz)) throw Error(VSIE_E_ARG, "frequency must be positive");
     if (!p->eps_r || !p->sigma) throw Error(VSIE_E_ARG, "null material arrays");
     if (H.opts.precorrect_dist < 0 || H.opts.tt_rank_max < 1 || H.opts.tt_rank_max > 128 ||
-        H.opts.aca_rank_max < 1 || H.opts.aca_rank_max > 256)
+        H.opts.aca_rank_max < 1 || H.opts.aca_rank_max > 256 || !(H.opts.tt_tol > 0) || !(H.opts.aca_tol > 0) ||
+        (H.opts.precision != VSIE_PREC_FP64 && H.opts.precision != VSIE_PREC_MIXED))
       throw Error(VSIE_E_ARG, "invalid options");
+    if (H.opts.basis == VSIE_BASIS_PWL)
+      throw Error(VSIE_E_UNSUPPORTED, "piecewise-linear body basis is not built (PWC only)");
+    if (H.opts.basis != VSIE_BASIS_PWC) throw Error(VSIE_E_ARG, "unknown basis");
+    if (H.opts.stencil != 5) throw Error(VSIE_E_UNSUPPORTED, "pFFT stencil: 5x5x5 blocks only");
+    if (H.opts.quad_near_vol != 8 || H.opts.quad_near_surf != 5 || H.opts.quad_far_vol != 1 ||
+        H.opts.quad_far_surf != 1)
+      throw Error(VSIE_E_UNSUPPORTED, "coupling quadrature: 8 x 5 points near and 1 x 1 far only");
     if (p->n_meshes < 0 || (p->n_meshes > 0 && !p->meshes)) throw Error(VSIE_E_ARG, "bad mesh list");
     H.h = p->h;
     H.freq = p->freq_hz;
@@ -1471,8 +1576,27 @@ int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, v
       }
       H.Ne = (int64_t)H.ne[0] * H.ne[1] * H.ne[2];
     }
-    H.have32 = H.opts.build_c64 != 0;
+    H.have32 = H.opts.precision != 0;
     progress("geometry and stencils", t0);
+    {
+      // delta-gap tables (Sec. II-A): b_m = s_m i w eps0 V0 l_m, V0 = 1 V
+      const double ws = H.omega * EPS0;
+      std::vector<int> idx;
+      std::vector<double> vre, vim;
+      H.port_off.assign(1, 0);
+      for (const auto& pe : H.ports) {
+        for (const PortEdge& e : pe) {
+          const Rwg& R = e.domain == VSIE_FAR ? H.far : H.near;
+          idx.push_back((e.domain == VSIE_FAR ? 0 : H.mf) + e.idx);
+          vre.push_back(0.0);
+          vim.push_back(ws * R.len[e.idx] * e.sign);
+        }
+        H.port_off.push_back((int)idx.size());
+      }
+      H.d_port_idx = upload(H, idx);
+      H.d_port_re = upload(H, vre);
+      H.d_port_im = upload(H, vim);
+    }
     H.dfar = make_rwg_dev(H, H.far);
     H.dnear = make_rwg_dev(H, H.near);
     setup_volume(H);
@@ -1481,7 +1605,7 @@ int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, v
     progress("pFFT projection and precorrection", t0);
     if (H.mf > 0) {
       setup_dense_far(H);
-      if (H.opts.build_c64) copy_zff_c64(H);
+      if (H.opts.precision) copy_zff_c64(H);
       progress("dense far block", t0);
       if (H.opts.build_far) {
         if (H.mn > 0) setup_aca(H);
@@ -1493,7 +1617,7 @@ int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, v
       }
     }
     alloc_work<double>(H, H.d64);
-    if (H.opts.build_c64) alloc_work<float>(H, H.d32);
+    if (H.opts.precision) alloc_work<float>(H, H.d32);
     VSIE_HIP(hipStreamSynchronize(H.stream));
     H.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   });
@@ -1534,34 +1658,8 @@ int vsie_rhs(const vsie_handle* hd, int port, int dtype, void* b_dev, void* stre
   if (port < 0 || port >= (int)H.ports.size()) return fail(VSIE_E_ARG, "port out of range");
   if (dtype != VSIE_C128 && dtype != VSIE_C64) return fail(VSIE_E_ARG, "bad dtype");
   return guarded([&]() {
-    hipStream_t st = (hipStream_t)stream;
-    const double ws = H.omega * EPS0;   // i w eps0 V0 l s -> (0, ws * l * s)
-    std::vector<int> idx;
-    std::vector<double> vre, vim;
-    for (const PortEdge& e : H.ports[port]) {
-      const Rwg& R = e.domain == VSIE_FAR ? H.far : H.near;
-      int off = e.domain == VSIE_FAR ? 0 : H.mf;
-      idx.push_back(off + e.idx);
-      vre.push_back(0.0);
-      vim.push_back(ws * R.len[e.idx] * e.sign);
-    }
-    const size_t esz = dtype == VSIE_C128 ? sizeof(cxd) : sizeof(cxf);
-    VSIE_HIP(hipMemsetAsync(b_dev, 0, esz * H.N, st));
-    int* d_idx = nullptr;
-    double *d_re = nullptr, *d_im = nullptr;
-    int ne = (int)idx.size();
-    VSIE_HIP(hipMalloc(&d_idx, sizeof(int) * std::max(ne, 1)));
-    VSIE_HIP(hipMalloc(&d_re, sizeof(double) * std::max(ne, 1)));
-    VSIE_HIP(hipMalloc(&d_im, sizeof(double) * std::max(ne, 1)));
-    VSIE_HIP(hipMemcpyAsync(d_idx, idx.data(), sizeof(int) * ne, hipMemcpyHostToDevice, st));
-    VSIE_HIP(hipMemcpyAsync(d_re, vre.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
-    VSIE_HIP(hipMemcpyAsync(d_im, vim.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st));
-    if (dtype == VSIE_C128) launch_scatter_rhs<double>(st, d_idx, d_re, d_im, ne, (cxd*)b_dev);
-    else launch_scatter_rhs<float>(st, d_idx, d_re, d_im, ne, (cxf*)b_dev);
-    VSIE_HIP(hipStreamSynchronize(st));
-    (void)hipFree(d_idx);
-    (void)hipFree(d_re);
-    (void)hipFree(d_im);
+    port_rhs(H, port, dtype, b_dev, (hipStream_t)stream);
+    VSIE_HIP(hipGetLastError());
   });
 }
 
@@ -1583,17 +1681,58 @@ int vsie_matvec(vsie_handle* hd, int dtype, int nrhs, const void* x_dev, void* y
   });
 }
 
+static int check_solve_opts(const vsie_handle* hd, const vsie_solve_opts* o, vsie_solve_opts& so) {
+  if (o) so = *o;
+  else vsie_default_solve_opts(&so);
+  if (so.restart < 1 || so.restart > 1000 || so.max_iter < 1 || !(so.tol > 0)) return fail(VSIE_E_ARG, "bad solve options");
+  if (so.method < VSIE_GMRES64 || so.method > VSIE_SCHUR_LEARNED) return fail(VSIE_E_ARG, "unknown solve method");
+  if (so.method == VSIE_SCHUR_LEARNED && !hd->H.net) return fail(VSIE_E_STATE, "no network attached (vsie_net_attach)");
+  if (!(so.reorth >= 0 && so.reorth <= 1)) return fail(VSIE_E_ARG, "reorth must lie in [0, 1]");
+  if ((so.method == VSIE_IR_MIXED || so.method == VSIE_SCHUR_MIXED) && !hd->H.have32)
+    return fail(VSIE_E_STATE, "complex64 operator data not built");
+  return VSIE_OK;
+}
+
+static int solve_impl(vsie_handle* hd, const vsie_solve_opts& so, int nrhs, const void* b_dev, void* x_dev,
+                      vsie_solve_stats* stats, void* stream);
+
 int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* b_dev, void* x_dev,
                vsie_solve_stats* stats, void* stream) {
   if (!hd || !b_dev || !x_dev || nrhs < 1) return fail(VSIE_E_ARG, "bad argument");
   vsie_solve_opts so;
-  if (o) so = *o;
-  else vsie_default_solve_opts(&so);
-  if (so.restart < 1 || so.restart > 1000 || so.max_iter < 1 || !(so.tol > 0)) return fail(VSIE_E_ARG, "bad solve options");
-  if (so.method < VSIE_GMRES64 || so.method > VSIE_SCHUR_MIXED) return fail(VSIE_E_ARG, "unknown solve method");
-  if (!(so.reorth >= 0 && so.reorth <= 1)) return fail(VSIE_E_ARG, "reorth must lie in [0, 1]");
-  if ((so.method == VSIE_IR_MIXED || so.method == VSIE_SCHUR_MIXED) && !hd->H.have32)
-    return fail(VSIE_E_STATE, "complex64 operator data not built");
+  const int rc = check_solve_opts(hd, o, so);
+  if (rc != VSIE_OK) return rc;
+  return solve_impl(hd, so, nrhs, b_dev, x_dev, stats, stream);
+}
+
+int vsie_solve_ports(vsie_handle* hd, const vsie_solve_opts* o, int nports, const int32_t* ports, void* x_dev,
+                     vsie_solve_stats* stats, void* stream) {
+  if (!hd || !ports || !x_dev || nports < 1) return fail(VSIE_E_ARG, "bad argument");
+  for (int i = 0; i < nports; ++i)
+    if (ports[i] < 0 || ports[i] >= (int)hd->H.ports.size()) return fail(VSIE_E_ARG, "port out of range");
+  vsie_solve_opts so;
+  int rc = check_solve_opts(hd, o, so);
+  if (rc != VSIE_OK) return rc;
+  void* b = nullptr;
+  rc = guarded([&]() {
+    const size_t bytes = sizeof(cxd) * (size_t)hd->H.N * nports;
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+      b = nullptr;
+      throw Error(VSIE_E_NOMEM, "hipMalloc of the port right-hand sides failed");
+    }
+    for (int i = 0; i < nports; ++i) port_rhs(hd->H, ports[i], VSIE_C128, (cxd*)b + (size_t)i * hd->H.N, (hipStream_t)stream);
+    VSIE_HIP(hipGetLastError());
+  });
+  if (rc == VSIE_OK) rc = solve_impl(hd, so, nports, b, x_dev, stats, stream);
+  if (b) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    (void)hipFree(b);
+  }
+  return rc;
+}
+
+static int solve_impl(vsie_handle* hd, const vsie_solve_opts& so, int nrhs, const void* b_dev, void* x_dev,
+                      vsie_solve_stats* stats, void* stream) {
   Handle& H = hd->H;
   int status = VSIE_OK;
   int rc = guarded([&]() {
@@ -1640,7 +1779,12 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       launch_f2d(st, y32, fout, N);
       launch_gather_idx(st, fout, H.d_active, Nc, out);
     };
-    if (so.method == VSIE_SCHUR || so.method == VSIE_SCHUR_MIXED) setup_schur(H, so.precond != 0);
+    const bool schur = so.method == VSIE_SCHUR || so.method == VSIE_SCHUR_MIXED || so.method == VSIE_SCHUR_LEARNED;
+    if (schur) setup_schur(H, so.precond != 0 || so.method == VSIE_SCHUR_LEARNED);
+    if (so.method == VSIE_SCHUR_LEARNED) {
+      ws.Vout = (cxd*)vec(Nc * (so.restart + 1), sizeof(cxd));
+      ws.Zout = (cxd*)vec(Nc * so.restart, sizeof(cxd));
+    }
     for (int c = 0; c < nrhs; ++c) {
       auto t0 = std::chrono::steady_clock::now();
       const cxd* b = (const cxd*)b_dev + c * N;
@@ -1649,7 +1793,7 @@ int vsie_solve(vsie_handle* hd, const vsie_solve_opts* o, int nrhs, const void* 
       std::memset(&s, 0, sizeof(s));
       const int64_t passes0 = S.second_passes;
       double rel = 0;
-      if (so.method == VSIE_SCHUR || so.method == VSIE_SCHUR_MIXED) {
+      if (schur) {
         s.iterations = solve_schur(H, S, so, so.method == VSIE_SCHUR_MIXED, b, x, ws, &s.restarts, &s.refinements, &rel,
                                    st);
       } else {
@@ -1936,6 +2080,186 @@ int vsie_dense_lu_solve_noalloc(int n, void* A_dev, int64_t lda, void* B_dev, in
       lu_solve(st, F, (cxd*)B_dev, ldb, nrhs, W);
       VSIE_HIP(hipStreamSynchronize(st));
     }
+  });
+}
+
+// ---------------------------------------------------------------------------------------------
+// learned preconditioner
+
+int vsie_net_create(uint64_t seed, int64_t pair_capacity, vsie_net** out) {
+  if (!out || pair_capacity < 0) return fail(VSIE_E_ARG, "bad argument");
+  *out = nullptr;
+  vsie_net* n = new (std::nothrow) vsie_net();
+  if (!n) return fail(VSIE_E_NOMEM, "network allocation");
+  int rc = guarded([&]() {
+    cnn_init(n->S.N, seed);
+    n->S.cap = pair_capacity;
+  });
+  if (rc != VSIE_OK) {
+    delete n;
+    return rc;
+  }
+  *out = n;
+  return VSIE_OK;
+}
+
+void vsie_net_destroy(vsie_net* n) { delete n; }
+
+int vsie_net_info(const vsie_net* n, int64_t* nparam, int64_t* n_pairs, int64_t* adam_steps) {
+  if (!n) return fail(VSIE_E_ARG, "null network");
+  if (nparam) *nparam = n->S.N.nparam;
+  if (n_pairs) *n_pairs = n->S.count;
+  if (adam_steps) *adam_steps = n->S.N.step;
+  return VSIE_OK;
+}
+
+int vsie_net_get_params(const vsie_net* n, float* host, int64_t count) {
+  if (!n || !host || count != n->S.N.nparam) return fail(VSIE_E_ARG, "bad argument");
+  return guarded([&]() {
+    VSIE_HIP(hipDeviceSynchronize());
+    VSIE_HIP(hipMemcpy(host, n->S.N.params, sizeof(float) * count, hipMemcpyDeviceToHost));
+  });
+}
+
+int vsie_net_set_params(vsie_net* n, const float* host, int64_t count) {
+  if (!n || !host || count != n->S.N.nparam) return fail(VSIE_E_ARG, "bad argument");
+  return guarded([&]() {
+    VSIE_HIP(hipDeviceSynchronize());
+    VSIE_HIP(hipMemcpy(n->S.N.params, host, sizeof(float) * count, hipMemcpyHostToDevice));
+    cnn_refresh_weights(n->S.N, nullptr);
+    VSIE_HIP(hipDeviceSynchronize());
+  });
+}
+
+int vsie_net_attach(vsie_handle* hd, vsie_net* n) {
+  if (!hd) return fail(VSIE_E_ARG, "null handle");
+  hd->H.net = n ? &n->S : nullptr;
+  if (n) return guarded([&]() { cnn_refresh_weights(n->S.N, hd->H.stream); VSIE_HIP(hipStreamSynchronize(hd->H.stream)); });
+  return VSIE_OK;
+}
+
+int vsie_net_collect(vsie_net* n, vsie_handle* hd, int nports, const int32_t* ports, const vsie_solve_opts* o,
+                     int64_t* n_pairs, void* stream) {
+  if (!n || !hd || !ports || nports < 1) return fail(VSIE_E_ARG, "bad argument");
+  vsie_solve_opts so;
+  int rc = check_solve_opts(hd, o, so);
+  if (rc != VSIE_OK) return rc;
+  if (so.method != VSIE_SCHUR || !so.precond) return fail(VSIE_E_ARG, "pairs come from the preconditioned SCHUR solve");
+  void* x = nullptr;
+  rc = guarded([&]() {
+    if (hipMalloc(&x, sizeof(cxd) * (size_t)hd->H.N * nports) != hipSuccess) {
+      x = nullptr;
+      throw Error(VSIE_E_NOMEM, "hipMalloc of the solutions failed");
+    }
+  });
+  if (rc != VSIE_OK) return rc;
+  hd->H.collect = &n->S;
+  rc = vsie_solve_ports(hd, &so, nports, ports, x, nullptr, stream);
+  hd->H.collect = nullptr;
+  (void)hipStreamSynchronize((hipStream_t)stream);
+  (void)hipFree(x);
+  if (n_pairs) *n_pairs = n->S.count;
+  return rc == VSIE_E_NOCONV ? VSIE_OK : rc;
+}
+
+int vsie_net_train(vsie_net* n, int epochs, float lr, uint64_t seed, double* last_loss, void* stream) {
+  if (!n || epochs < 1 || !(lr > 0)) return fail(VSIE_E_ARG, "bad argument");
+  return guarded([&]() {
+    const double l = net_train(n->S, epochs, lr, seed, (hipStream_t)stream);
+    if (last_loss) *last_loss = l;
+  });
+}
+
+__global__ void k_copy_channels(const float* __restrict__ src, int cs, float* __restrict__ dst, int cd, int ncopy,
+                                int64_t nvox) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nvox * cd; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % cd);
+    dst[e] = c < ncopy ? src[(e / cd) * cs + c] : 0.f;
+  }
+}
+
+int vsie_net_forward(vsie_net* n, int D, int H, int W, const float* x_dev, float* y_dev, void* stream) {
+  if (!n || !x_dev || !y_dev) return fail(VSIE_E_ARG, "null argument");
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    Cnn& N = n->S.N;
+    cnn_size(N, D, H, W);
+    cnn_refresh_weights(N, st);
+    const int64_t nvox = (int64_t)D * H * W;
+    const unsigned nb = (unsigned)std::min<int64_t>((nvox * 16 + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_copy_channels, dim3(nb), dim3(256), 0, st, x_dev, CNN_IN, N.x_in, 16, CNN_IN, nvox);
+    cnn_forward(N, st);
+    hipLaunchKernelGGL(k_copy_channels, dim3(nb), dim3(256), 0, st, N.act[CNN_NLAYER - 1], 16, y_dev, CNN_OUT, CNN_OUT,
+                       nvox);
+    VSIE_HIP(hipGetLastError());
+  });
+}
+
+int vsie_net_gradients(vsie_net* n, int D, int H, int W, const float* x_dev, const float* t_dev, double* loss,
+                       float* grads_host, void* stream) {
+  if (!n || !x_dev || !t_dev) return fail(VSIE_E_ARG, "null argument");
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    Cnn& N = n->S.N;
+    cnn_size(N, D, H, W);
+    cnn_refresh_weights(N, st);
+    const int64_t nvox = (int64_t)D * H * W;
+    const unsigned nb = (unsigned)std::min<int64_t>((nvox * 16 + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_copy_channels, dim3(nb), dim3(256), 0, st, x_dev, CNN_IN, N.x_in, 16, CNN_IN, nvox);
+    hipLaunchKernelGGL(k_copy_channels, dim3(nb), dim3(256), 0, st, t_dev, CNN_OUT, N.target, 16, CNN_OUT, nvox);
+    cnn_forward(N, st);
+    cnn_backward(N, st);
+    VSIE_HIP(hipGetLastError());
+    if (loss) VSIE_HIP(hipMemcpyAsync(loss, N.red, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (grads_host) VSIE_HIP(hipMemcpyAsync(grads_host, N.grads, sizeof(float) * N.nparam, hipMemcpyDeviceToHost, st));
+    VSIE_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int vsie_net_adam(vsie_net* n, float lr, void* stream) {
+  if (!n || !(lr > 0)) return fail(VSIE_E_ARG, "bad argument");
+  return guarded([&]() {
+    cnn_adam(n->S.N, lr, (hipStream_t)stream);
+    VSIE_HIP(hipGetLastError());
+  });
+}
+
+int vsie_net_layer(vsie_net* n, int layer, int mode, int D, int H, int W, const float* in0, const float* in1,
+                   const float* mask, float* out, void* stream) {
+  if (!n || layer < 0 || layer >= CNN_NLAYER || (mode != 0 && mode != 1) || !in0 || !out)
+    return fail(VSIE_E_ARG, "bad argument");
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    Cnn& N = n->S.N;
+    cnn_refresh_weights(N, st);
+    const CnnLayerDesc& d = N.L[layer];
+    const bool dec = layer >= 8 && layer <= 10;   // input [up2(a), b], b = the skip
+    const int cb = dec ? (layer == 8 ? 48 : layer == 9 ? 32 : 16) : 0;
+    if (mode == 0) {
+      cnn_conv_forward(st, in0, d.cin_p - cb, dec, dec ? in1 : nullptr, cb, nullptr, N.wf + d.wf_off,
+                       N.params + d.b_off, d.relu, out, d.cout_p, d.cout, D, H, W);
+    } else {
+      cnn_conv_forward(st, in0, d.cout_p, false, nullptr, 0, d.relu ? mask : nullptr, N.wb + d.wb_off, nullptr, false,
+                       out, d.cin_p, d.cin_p, D, H, W);
+    }
+    VSIE_HIP(hipGetLastError());
+  });
+}
+
+int vsie_net_layer_wgrad(vsie_net* n, int layer, int D, int H, int W, const float* in0, const float* in1,
+                         const float* g, const float* mask, float* gw_host, float* gb_host, void* stream) {
+  if (!n || layer < 0 || layer >= CNN_NLAYER || !in0 || !g || !gw_host || !gb_host) return fail(VSIE_E_ARG, "bad argument");
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    Cnn& N = n->S.N;
+    const CnnLayerDesc& d = N.L[layer];
+    const bool dec = layer >= 8 && layer <= 10;
+    const int cb = dec ? (layer == 8 ? 48 : layer == 9 ? 32 : 16) : 0;
+    cnn_conv_wgrad(N, st, layer, in0, d.cin_p - cb, dec, dec ? in1 : nullptr, cb, g, d.relu ? mask : nullptr, d.cout_p,
+                   N.grads + d.w_off, N.grads + d.b_off, D, H, W);
+    VSIE_HIP(hipMemcpyAsync(gw_host, N.grads + d.w_off, sizeof(float) * 27 * d.cout * d.cin, hipMemcpyDeviceToHost, st));
+    VSIE_HIP(hipMemcpyAsync(gb_host, N.grads + d.b_off, sizeof(float) * d.cout, hipMemcpyDeviceToHost, st));
+    VSIE_HIP(hipStreamSynchronize(st));
   });
 }
 

@@ -101,6 +101,8 @@ struct DenseLU {
   std::vector<int> perm;   // row i of L U is row perm[i] of A
 };
 
+struct NetState;
+
 struct Handle {
   // problem
   int n[3];
@@ -113,6 +115,12 @@ struct Handle {
   int mf = 0, mn = 0;
   int64_t N = 0;
   std::vector<std::vector<PortEdge>> ports;
+  // delta-gap tables on the device: the edges of port p are entries [port_off[p], port_off[p + 1])
+  // of d_port_idx (global unknown) and d_port_re / d_port_im (value i w eps0 V0 l_m s_m)
+  std::vector<int> port_off;
+  int* d_port_idx = nullptr;
+  double* d_port_re = nullptr;
+  double* d_port_im = nullptr;
   vsie_options opts;
   // extended grid
   int ne[3], ob[3], P[3];
@@ -165,6 +173,12 @@ struct Handle {
   static constexpr int HOST_PINNED_ELEMS = 2048;
   int64_t device_bytes = 0;
   double setup_seconds = 0;
+  // learned preconditioner: material channels of the network, the attached network (applied by
+  // the learned solve method) and the network that collects training pairs during solves
+  float* d_material = nullptr;   // [n_v][2]
+  double mat_scale = 0;
+  NetState* net = nullptr;
+  NetState* collect = nullptr;
   hipStream_t stream = nullptr;
   std::vector<void*> allocations;
   // per-stage timing of the matrix-vector product (HIP events on the caller's stream)
@@ -253,5 +267,7 @@ struct EntryFn {
 };
 void tt_cross(EntryFn& f, const int n[4], double tol, int rmax, uint64_t seed, std::vector<cxd> cores[4],
               int ranks[3], double* err_est);
+// TT rounding of a 4-core train to relative Frobenius accuracy delta (ranks updated in place)
+void tt_round(const int n[4], std::vector<cxd> cores[4], int ranks[3], double delta);
 
 }  // namespace vsie

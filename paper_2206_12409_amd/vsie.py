@@ -15,15 +15,20 @@ LIB_PATH = os.path.join(HERE, "libvsie.so")
 VSIE_OK, VSIE_E_NOCONV = 0, 7
 VSIE_NEAR, VSIE_FAR = 0, 1
 VSIE_C128, VSIE_C64 = 0, 1
-VSIE_GMRES64, VSIE_IR_MIXED, VSIE_SCHUR, VSIE_SCHUR_MIXED = 0, 1, 2, 3
+VSIE_GMRES64, VSIE_IR_MIXED, VSIE_SCHUR, VSIE_SCHUR_MIXED, VSIE_SCHUR_LEARNED = 0, 1, 2, 3, 4
 VSIE_E_SINGULAR = 11
+VSIE_E_UNSUPPORTED = 9
+VSIE_BASIS_PWC, VSIE_BASIS_PWL = 0, 1
+VSIE_PREC_FP64, VSIE_PREC_MIXED = 0, 1
 X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
 
 EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_sizes", "vsie_rhs",
-            "vsie_matvec", "vsie_solve", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
+            "vsie_matvec", "vsie_solve", "vsie_solve_ports", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
             "vsie_profile", "vsie_profile_mask", "vsie_profile_read", "vsie_schur_setup", "vsie_schur_info",
             "vsie_schur_matvec", "vsie_schur_precond", "vsie_dense_lu_solve", "vsie_dense_lu_solve_noalloc",
-            "vsie_destroy", "vsie_last_error"]
+            "vsie_net_create", "vsie_net_destroy", "vsie_net_info", "vsie_net_get_params", "vsie_net_set_params",
+            "vsie_net_collect", "vsie_net_train", "vsie_net_attach", "vsie_net_forward", "vsie_net_gradients",
+            "vsie_net_adam", "vsie_net_layer", "vsie_net_layer_wgrad", "vsie_destroy", "vsie_last_error"]
 
 
 STAGES = ["build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "body_out", "pfft_gather",
@@ -44,8 +49,10 @@ class ProblemC(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("tt_tol", C.c_double), ("tt_rank_max", C.c_int32), ("aca_tol", C.c_double),
-                ("aca_rank_max", C.c_int32), ("precorrect_dist", C.c_int32), ("build_c64", C.c_int32),
-                ("build_far", C.c_int32), ("seed", C.c_uint64)]
+                ("aca_rank_max", C.c_int32), ("precorrect_dist", C.c_int32), ("precision", C.c_int32),
+                ("build_far", C.c_int32), ("seed", C.c_uint64), ("basis", C.c_int32), ("stencil", C.c_int32),
+                ("quad_near_vol", C.c_int32), ("quad_near_surf", C.c_int32), ("quad_far_vol", C.c_int32),
+                ("quad_far_surf", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -85,6 +92,8 @@ def load(path=LIB_PATH):
     lib.vsie_rhs.argtypes = [vp, C.c_int, C.c_int, vp, vp]
     lib.vsie_matvec.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
     lib.vsie_solve.argtypes = [vp, C.POINTER(SolveOpts), C.c_int, vp, vp, C.POINTER(SolveStats), vp]
+    lib.vsie_solve_ports.argtypes = [vp, C.POINTER(SolveOpts), C.c_int, C.POINTER(C.c_int32), vp,
+                                     C.POINTER(SolveStats), vp]
     lib.vsie_port_current.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.vsie_export.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(C.c_size_t)]
     lib.vsie_import.argtypes = [vp, C.c_int, C.c_int, vp, C.c_size_t]
@@ -99,6 +108,22 @@ def load(path=LIB_PATH):
     lib.vsie_schur_precond.argtypes = [vp, vp, vp, vp]
     lib.vsie_dense_lu_solve.argtypes = [C.c_int, vp, C.c_int64, vp, C.c_int64, C.c_int, vp]
     lib.vsie_dense_lu_solve_noalloc.argtypes = [C.c_int, vp, C.c_int64, vp, C.c_int64, C.c_int, vp]
+    fp = C.POINTER(C.c_float)
+    lib.vsie_net_create.argtypes = [C.c_uint64, C.c_int64, C.POINTER(vp)]
+    lib.vsie_net_destroy.argtypes = [vp]
+    lib.vsie_net_destroy.restype = None
+    lib.vsie_net_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.vsie_net_get_params.argtypes = [vp, fp, C.c_int64]
+    lib.vsie_net_set_params.argtypes = [vp, fp, C.c_int64]
+    lib.vsie_net_collect.argtypes = [vp, vp, C.c_int, C.POINTER(C.c_int32), C.POINTER(SolveOpts),
+                                     C.POINTER(C.c_int64), vp]
+    lib.vsie_net_train.argtypes = [vp, C.c_int, C.c_float, C.c_uint64, C.POINTER(C.c_double), vp]
+    lib.vsie_net_attach.argtypes = [vp, vp]
+    lib.vsie_net_forward.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
+    lib.vsie_net_gradients.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, C.POINTER(C.c_double), fp, vp]
+    lib.vsie_net_adam.argtypes = [vp, C.c_float, vp]
+    lib.vsie_net_layer.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp]
+    lib.vsie_net_layer_wgrad.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, fp, fp, vp]
     lib.vsie_destroy.argtypes = [vp]
     lib.vsie_destroy.restype = None
     lib.vsie_last_error.restype = C.c_char_p
@@ -231,10 +256,16 @@ class Operator:
                                   C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
         return y
 
-    def rhs(self, port, dtype=None, stream=None):
+    def rhs(self, port, dtype=None, stream=None, out=None):
+        """Delta-gap right-hand side of `port` (vsie_rhs), into `out` when given."""
         import torch
         dt = torch.complex128 if dtype is None else dtype
-        b = torch.empty(self.N, dtype=dt, device="cuda")
+        if out is None:
+            b = torch.empty(self.N, dtype=dt, device="cuda")
+        else:
+            if out.shape != (self.N,) or not out.is_contiguous() or not out.is_cuda:
+                raise ValueError("out must be a contiguous device vector of length N")
+            b = out
         _check(load().vsie_rhs(self._h, int(port), self._dtype_code(b), C.c_void_p(b.data_ptr()), _stream_ptr(stream)))
         return b
 
@@ -262,11 +293,30 @@ class Operator:
                                _stream_ptr(stream))
         if rc != VSIE_OK and not (allow_noconv and rc == VSIE_E_NOCONV):
             _check(rc)
-        stats = [dict(iterations=s.iterations, restarts=s.restarts, refinements=s.refinements,
-                      rel_residual=s.rel_residual, block_residual=list(s.block_residual), seconds=s.seconds,
-                      gs_second_passes=s.gs_second_passes,
-                      converged=rc == VSIE_OK) for s in st]
-        return x, stats
+        return x, self._stats(st, rc)
+
+    def solve_ports(self, ports, tol=1e-6, restart=50, max_iter=5000, method=VSIE_GMRES64, inner_tol=1e-3,
+                    stream=None, allow_noconv=False, precond=True, reorth=0.1):
+        """Solve for the delta-gap excitation of each port in `ports` (vsie_solve_ports); returns
+        x [nports][N] complex128 on the device and one stats dict per port."""
+        import torch
+        pl = np.ascontiguousarray([int(p) for p in ports], np.int32)
+        if pl.size < 1:
+            raise ValueError("no port given")
+        x = torch.empty((pl.size, self.N), dtype=torch.complex128, device="cuda")
+        o = SolveOpts(tol, restart, max_iter, method, inner_tol, 1 if precond else 0, reorth)
+        st = (SolveStats * pl.size)()
+        rc = load().vsie_solve_ports(self._h, C.byref(o), int(pl.size), pl.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     C.c_void_p(x.data_ptr()), st, _stream_ptr(stream))
+        if rc != VSIE_OK and not (allow_noconv and rc == VSIE_E_NOCONV):
+            _check(rc)
+        return x, self._stats(st, rc)
+
+    @staticmethod
+    def _stats(st, rc):
+        return [dict(iterations=s.iterations, restarts=s.restarts, refinements=s.refinements,
+                     rel_residual=s.rel_residual, block_residual=list(s.block_residual), seconds=s.seconds,
+                     gs_second_passes=s.gs_second_passes, converged=rc == VSIE_OK) for s in st]
 
     def schur_setup(self, precond=True):
         """Eliminate the far-conductor currents (and build the reduced system's preconditioner)."""
@@ -388,6 +438,125 @@ class Operator:
         blob = k.tobytes() + U.tobytes() + V.tobytes()
         buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
         _check(load().vsie_import(self._h, X_ACA, 0, buf, len(blob)))
+
+
+# layers of the learned preconditioner's network: (name, Cin, Cout, ReLU); parameters per layer are
+# the weights [Cout][3][3][3][Cin] then the biases [Cout], in this order
+NET_LAYERS = (("e1a", 8, 16, True), ("e1b", 16, 16, True), ("e2a", 16, 32, True), ("e2b", 32, 32, True),
+              ("e3a", 32, 48, True), ("e3b", 48, 48, True), ("e4a", 48, 64, True), ("e4b", 64, 64, True),
+              ("d3", 112, 48, True), ("d2", 80, 32, True), ("d1", 48, 16, True), ("out", 16, 6, False))
+
+
+def _dev_ptr(t, dtype_name="float32"):
+    import torch
+    if t is None:
+        return C.c_void_p(None)
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != getattr(torch, dtype_name):
+        raise ValueError("contiguous %s device tensors only" % dtype_name)
+    return C.c_void_p(t.data_ptr())
+
+
+class Net:
+    """The learned preconditioner's network (vsie_net_*): parameters, training pairs, training."""
+
+    def __init__(self, seed=1, pair_capacity=0):
+        h = C.c_void_p()
+        _check(load().vsie_net_create(int(seed), int(pair_capacity), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().vsie_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load().vsie_net_info(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(nparam=a.value, n_pairs=b.value, adam_steps=c.value)
+
+    def get_params(self):
+        n = self.info()["nparam"]
+        out = np.zeros(n, np.float32)
+        _check(load().vsie_net_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float)), n))
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, np.float32)
+        _check(load().vsie_net_set_params(self._h, flat.ctypes.data_as(C.POINTER(C.c_float)), flat.size))
+
+    @staticmethod
+    def unflatten(flat):
+        """{name.w: [Cout][3][3][3][Cin], name.b: [Cout]} views of a flat parameter vector."""
+        out, off = {}, 0
+        for name, ci, co, _ in NET_LAYERS:
+            nw = co * 27 * ci
+            out[name + ".w"] = flat[off:off + nw].reshape(co, 3, 3, 3, ci)
+            off += nw
+            out[name + ".b"] = flat[off:off + co]
+            off += co
+        return out
+
+    @staticmethod
+    def flatten(p):
+        return np.concatenate([np.concatenate([np.asarray(p[n + ".w"]).ravel(), np.asarray(p[n + ".b"]).ravel()])
+                               for n, _, _, _ in NET_LAYERS]).astype(np.float32)
+
+    def collect(self, op, ports, restart=50, max_iter=1000, tol=1e-6, stream=None):
+        pl = np.ascontiguousarray([int(p) for p in ports], np.int32)
+        o = SolveOpts(tol, restart, max_iter, VSIE_SCHUR, 1e-3, 1, 0.1)
+        n = C.c_int64()
+        _check(load().vsie_net_collect(self._h, op._h, int(pl.size), pl.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       C.byref(o), C.byref(n), _stream_ptr(stream)))
+        return n.value
+
+    def train(self, epochs, lr=1e-3, seed=0, stream=None):
+        loss = C.c_double()
+        _check(load().vsie_net_train(self._h, int(epochs), float(lr), int(seed), C.byref(loss), _stream_ptr(stream)))
+        return loss.value
+
+    def attach(self, op):
+        _check(load().vsie_net_attach(op._h, self._h))
+
+    def forward(self, x, stream=None):
+        """x: [D][H][W][8] float32 device tensor -> y [D][H][W][6]."""
+        import torch
+        D, H, W, _ = x.shape
+        y = torch.empty((D, H, W, 6), dtype=torch.float32, device="cuda")
+        _check(load().vsie_net_forward(self._h, D, H, W, _dev_ptr(x), _dev_ptr(y), _stream_ptr(stream)))
+        return y
+
+    def gradients(self, x, t, stream=None):
+        D, H, W, _ = x.shape
+        loss = C.c_double()
+        g = np.zeros(self.info()["nparam"], np.float32)
+        _check(load().vsie_net_gradients(self._h, D, H, W, _dev_ptr(x), _dev_ptr(t), C.byref(loss),
+                                         g.ctypes.data_as(C.POINTER(C.c_float)), _stream_ptr(stream)))
+        return loss.value, g
+
+    def adam(self, lr, stream=None):
+        _check(load().vsie_net_adam(self._h, float(lr), _stream_ptr(stream)))
+
+    def layer(self, layer, mode, dims, in0, in1=None, mask=None, out=None, stream=None):
+        D, H, W = dims
+        _check(load().vsie_net_layer(self._h, int(layer), int(mode), D, H, W, _dev_ptr(in0), _dev_ptr(in1),
+                                     _dev_ptr(mask), _dev_ptr(out), _stream_ptr(stream)))
+        return out
+
+    def layer_wgrad(self, layer, dims, in0, g, in1=None, mask=None, stream=None):
+        D, H, W = dims
+        _, ci, co, _ = NET_LAYERS[layer]
+        gw = np.zeros((co, 27, ci), np.float32)
+        gb = np.zeros(co, np.float32)
+        _check(load().vsie_net_layer_wgrad(self._h, int(layer), D, H, W, _dev_ptr(in0), _dev_ptr(in1), _dev_ptr(g),
+                                           _dev_ptr(mask), gw.ctypes.data_as(C.POINTER(C.c_float)),
+                                           gb.ctypes.data_as(C.POINTER(C.c_float)), _stream_ptr(stream)))
+        return gw.reshape(co, 3, 3, 3, ci), gb
 
 
 LU_NOALLOC_MAX_N, LU_NOALLOC_MAX_NRHS = 4096, 64

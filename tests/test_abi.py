@@ -37,6 +37,24 @@ def test_every_declared_symbol_is_exported(vs):
 def test_default_options(vs):
     o = vs.default_options()
     assert o.tt_tol == 1e-3 and o.aca_tol == 1e-3 and o.tt_rank_max == 96 and o.precorrect_dist == 2
+    assert o.precision == vs.VSIE_PREC_MIXED and o.basis == vs.VSIE_BASIS_PWC and o.stencil == 5
+    assert (o.quad_near_vol, o.quad_near_surf, o.quad_far_vol, o.quad_far_surf) == (8, 5, 1, 1)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("basis", 1, 9),            # piecewise-linear basis (Sec. II-B): not built
+    ("basis", 7, 1),
+    ("stencil", 4, 9),          # pFFT block other than 5x5x5 (Sec. IV-B)
+    ("quad_near_vol", 27, 9),   # coupling rules other than 8 x 5 / 1 x 1 (Sec. IV-C)
+    ("quad_far_surf", 3, 9),
+    ("precision", 2, 1),
+    ("tt_tol", 0.0, 1),
+])
+def test_rejects_unsupported_options(vs, field, value, code):
+    """Options outside the built discretisation are refused before any device work."""
+    with pytest.raises(vs.VsieError) as e:
+        vs.Operator(synth.small_case(), stream=0, **{field: value})
+    assert e.value.code == code, str(e.value)
 
 
 def _expect(vs, problem, code):
@@ -107,6 +125,9 @@ def test_new_entry_points_reject_bad_arguments(vs):
     assert o.precond == 1 and o.method == vs.VSIE_GMRES64 and o.restart == 50 and o.tol == 1e-6
     assert o.reorth == 0.1
     assert lib.vsie_solve(None, C.byref(o), 1, dummy, dummy, None, None) == 1
+    ports = (C.c_int32 * 1)(0)
+    assert lib.vsie_solve_ports(None, C.byref(o), 1, ports, dummy, None, None) == 1
+    assert lib.vsie_rhs(None, 0, 0, dummy, None) == 1
 
 
 def test_binding_structs_match_the_header(vs, tmp_path):

@@ -142,10 +142,29 @@ def test_complex64_matvec_error(small):
 
 
 def test_port_rhs_matches_oracle(small):
+    """vsie_rhs (device tables, fill and scatter on the stream) in both precisions, into buffers
+    that held other values before."""
     p, op, d, *_ = small
     for port in range(op.n_ports):
-        b = op.rhs(port).cpu().numpy()
-        assert rel(b, system.port_rhs(d, port)) < 1e-15
+        ref = system.port_rhs(d, port)
+        b = torch.full((op.N,), 3.0 + 1j, dtype=torch.complex128, device="cuda")
+        assert rel(op.rhs(port, out=b).cpu().numpy(), ref) < 1e-15
+        b32 = op.rhs(port, dtype=torch.complex64).cpu().numpy().astype(np.complex128)
+        assert rel(b32, ref) < 1e-7
+
+
+def test_solve_ports_matches_solve(small):
+    """vsie_solve_ports forms each port's right-hand side itself and gives the solve of vsie_solve
+    bit for bit."""
+    p, op, d, *_ = small
+    ports = list(range(op.n_ports))
+    B = torch.stack([op.rhs(pt) for pt in ports])
+    X1, s1 = op.solve(B, tol=1e-8, restart=50, max_iter=400, method=2)
+    X2, s2 = op.solve_ports(ports, tol=1e-8, restart=50, max_iter=400, method=2)
+    assert torch.equal(X1, X2)
+    assert [s["iterations"] for s in s1] == [s["iterations"] for s in s2]
+    with pytest.raises(Exception):
+        op.solve_ports([op.n_ports])
 
 
 def test_gmres_solution_matches_oracle(small):

@@ -1,0 +1,59 @@
+"""The learned preconditioner end to end on a small configuration (16^3 voxels at 5 mm, a seeded
+head-like phantom, the 60 mm strip loop with one port): training pairs from the preconditioned
+plain solves of four other seeded phantoms, training on the GPU, then the eliminated system of a
+held-out phantom solved by flexible GMRES with the trained network against the plain
+preconditioned GMRES, which stays the judge of its result."""
+import numpy as np
+import pytest
+
+import vsie_synth as synth
+from vsie_synth.meshes import strip_loop_flat
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _problem(seed):
+    g = synth.head_phantom(seed, (16, 16, 16), 5e-3)
+    loop = strip_loop_flat((45.5e-3, 0.37e-3, -0.41e-3), side=60e-3, width=5e-3, step=5e-3)
+    return synth.Problem(g, [loop], synth.problems.LARMOR_7T_HZ, "learned-%d" % seed)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    import paper_2206_12409_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    net = pkg.Net(seed=11, pair_capacity=400)
+    for seed in (101, 102, 103, 104):
+        op = pkg.Operator(_problem(seed))
+        n = net.collect(op, [0], restart=50, max_iter=400, tol=1e-8)
+        print("phantom %d: %d pairs held" % (seed, n), flush=True)
+        op.close()
+    losses = [net.train(1, lr=1e-3, seed=e) for e in range(30)]
+    print("training loss by epoch: first %.3e, last %.3e" % (losses[0], losses[-1]))
+    return pkg, net, losses
+
+
+def test_training_reduces_the_loss(trained):
+    _, net, losses = trained
+    assert net.info()["n_pairs"] > 50
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_learned_preconditioner_gain(trained):
+    pkg, net, _ = trained
+    op = pkg.Operator(_problem(0))
+    b = op.rhs(0)
+    x0, s0 = op.solve(b, tol=1e-8, restart=50, max_iter=1000, method=pkg.vsie.VSIE_SCHUR)
+    net.attach(op)
+    x1, s1 = op.solve(b, tol=1e-8, restart=50, max_iter=1000, method=pkg.vsie.VSIE_SCHUR_LEARNED)
+    r1 = float(torch.linalg.norm(b - op.matvec(x1)) / torch.linalg.norm(b))
+    d = float(torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0))
+    print("held-out phantom: plain preconditioned GMRES %d iterations (%.3f s), learned flexible GMRES %d "
+          "iterations (%.3f s); learned residual %.2e, difference from the plain solution %.2e"
+          % (s0[0]["iterations"], s0[0]["seconds"], s1[0]["iterations"], s1[0]["seconds"], r1, d))
+    assert s0[0]["converged"] and s1[0]["converged"]
+    assert r1 <= 1.5e-8
+    assert d <= 1e-5
+    assert s1[0]["iterations"] < s0[0]["iterations"]

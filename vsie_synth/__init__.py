@@ -17,10 +17,10 @@ Conventions shared by every consumer:
 from .phantoms import Grid, sphere_phantom, head_phantom
 from .meshes import Mesh, strip_loop_flat, strip_loop_on_cylinder, loop_array, cylinder_shield
 from .vectors import complex_normal
-from .problems import Problem, tiny_case, two_mm_case, small_case, mie_case
+from .problems import Problem, tiny_case, two_mm_case, one_mm_case, small_case, mie_case
 
 __all__ = [
     "Grid", "sphere_phantom", "head_phantom", "Mesh", "strip_loop_flat", "strip_loop_on_cylinder",
     "loop_array", "cylinder_shield", "complex_normal", "Problem", "tiny_case", "two_mm_case",
-    "small_case", "mie_case",
+    "small_case", "mie_case", "one_mm_case",
 ]

@@ -7,6 +7,8 @@
   * ``two_mm_case``: 96x112x128 voxels at 2 mm, head-like phantom (seed 0), eight conformal
                      loops on a 120 mm cylinder (near, eight ports), open tube shield
                      r = 340 mm, L = 1.2 m, about 20k triangles (far).
+  * ``one_mm_case``: 192x224x256 voxels at 1 mm, head-like phantom (seed 7), 32 loops in two rings
+                     of 16 (near, 32 ports), the same shield meshed with about 40k triangles (far).
   * ``mie_case``   : the sphere alone (plane-wave excitation is built by the consumer).
 """
 from dataclasses import dataclass, field
@@ -54,9 +56,28 @@ def two_mm_case(seed=0, n=(96, 112, 128), h=2e-3, n_loops=8, shield_around=128, 
     return Problem(g, [shield, coil], LARMOR_7T_HZ, "2mm")
 
 
+def one_mm_case(seed=7, n=(192, 224, 256), h=1e-3, loops_per_ring=16, shield_around=180, shield_along=111):
+    """192x224x256 voxels at 1 mm, head-like phantom (seed 7), 32 conformal loops in two rings of 16
+    on the 120 mm cylinder (4 mm strips meshed at 1 mm along and 2 mm across, so that every RWG pair
+    fits its 5x5x5 pFFT block at h = 1 mm), open tube shield r = 340 mm, L = 1.2 m, about 40k
+    triangles."""
+    from .meshes import Mesh
+    g = head_phantom(seed, n, h)
+    rings = [loop_array(loops_per_ring, radius=0.12, length=0.1, gap=10e-3, width=4e-3, step=1e-3,
+                        z_centre=zc, phi_offset=0.0013 + 0.5 * ring * 2 * np.pi / loops_per_ring)
+             for ring, zc in enumerate((-55.37e-3, 55.37e-3))]
+    nv0 = len(rings[0].verts)
+    coil = Mesh(np.concatenate([r.verts for r in rings]),
+                np.concatenate([rings[0].tris, rings[1].tris + nv0]).astype(np.int32), NEAR,
+                np.concatenate([rings[0].port_edges, rings[1].port_edges + nv0]).astype(np.int32),
+                np.concatenate([rings[0].port_id, rings[1].port_id + rings[0].n_ports]).astype(np.int32))
+    shield = cylinder_shield(0.340, 1.2, shield_around, shield_along, closed=False)
+    return Problem(g, [shield, coil], LARMOR_7T_HZ, "1mm")
+
+
 def mie_case(n=16, h=5e-3, radius=35e-3):
     return Problem(sphere_phantom((n, n, n), h, radius, 52.0, 0.55), [], LARMOR_7T_HZ, "mie")
 
 
-__all__ = ["Problem", "tiny_case", "small_case", "two_mm_case", "mie_case", "NEAR", "FAR",
+__all__ = ["Problem", "tiny_case", "small_case", "two_mm_case", "one_mm_case", "mie_case", "NEAR", "FAR",
            "LARMOR_7T_HZ"]
