@@ -303,6 +303,112 @@ def other_precisions(op, x, y, args):
     return value32, err32, value_conc, same
 
 
+def learned_solve(pkg, synth, op, X_plain, args):
+    """The learned preconditioner at 2 mm: training pairs from the preconditioned plain solves of
+    every port of other seeded phantoms (same grid), training on the GPU, then flexible GMRES on
+    the workload's eliminated system with the network, against the plain preconditioned solve."""
+    import torch
+    t0 = time.perf_counter()
+    net = pkg.Net(seed=1, pair_capacity=args.learn_pairs)
+    for seed in range(100, 100 + args.learn_phantoms):
+        opt = pkg.Operator(synth.two_mm_case(seed))
+        n = net.collect(opt, range(opt.n_ports), restart=args.restart, max_iter=args.max_iter, tol=1e-6)
+        opt.close()
+        del opt
+        torch.cuda.synchronize()
+        print("learned: phantom %d, %d pairs held" % (seed, n), file=sys.stderr, flush=True)
+    collect_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = [net.train(1, lr=args.learn_lr, seed=e) for e in range(args.learn_epochs)]
+    train_s = time.perf_counter() - t0
+    net.attach(op)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, st = op.solve_ports(range(op.n_ports), tol=1e-6, restart=args.restart, max_iter=args.max_iter,
+                           method=pkg.vsie.VSIE_SCHUR_LEARNED, allow_noconv=True)
+    wall = time.perf_counter() - t0
+    conv = [s_["rel_residual"] <= 1e-6 for s_ in st]
+    # the plain method judges the result: distance from its solution, and the residual under the
+    # full operator of eq. (15) applied by vsie_matvec
+    diff = float(torch.linalg.norm(X - X_plain) / torch.linalg.norm(X_plain))
+    B = torch.stack([op.rhs(pt) for pt in range(op.n_ports)])
+    res = float(max(torch.linalg.norm(B[i] - op.matvec(X[i].contiguous())) / torch.linalg.norm(B[i])
+                    for i in range(op.n_ports)))
+    its = [s_["iterations"] for s_ in st]
+    return dict(method="far currents eliminated, flexible GMRES with the base preconditioner plus the trained "
+                       "network's body correction (bf16 MFMA convolutions)",
+                train_phantoms=list(range(100, 100 + args.learn_phantoms)), pairs=net.info()["n_pairs"],
+                epochs=args.learn_epochs, lr=args.learn_lr, loss_first_epoch=losses[0], loss_last_epoch=losses[-1],
+                collect_seconds=round(collect_s, 2), train_seconds=round(train_s, 2),
+                seconds_total=round(wall, 3), converged_ports=int(sum(conv)), mean_iterations=float(np.mean(its)),
+                max_rel_residual=float(max(s_["rel_residual"] for s_ in st)), full_operator_residual=res,
+                rel_diff_vs_plain=diff,
+                ms_per_iteration=round(1e3 * sum(s_["seconds"] for s_ in st) / max(1, sum(its)), 3),
+                time_to_1e6_mean_s=(round(float(np.mean([s_["seconds"] for s_ in st])), 4) if all(conv) else None))
+
+
+def one_mm(args):
+    """The 1 mm configuration (192x224x256 voxels, 32 channels, 40k-triangle shield): setup, the
+    FP64 and complex64 products with their stage times, the elimination, and the preconditioned
+    eliminated solve of the first ports. Prints one JSON line (an extra workload, not the 2 mm
+    headline)."""
+    import torch
+
+    import paper_2206_12409_amd as pkg
+    import vsie_synth as synth
+    torch.cuda.set_device(0)
+    problem = synth.one_mm_case()
+    t0 = time.perf_counter()
+    op = pkg.Operator(problem)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = op.info()
+    info["n"] = tuple(int(v) for v in problem.grid.n)
+    print("1 mm setup %.1f s: %s" % (setup_s, json.dumps(info)), file=sys.stderr, flush=True)
+    x = torch.from_numpy(synth.complex_normal(op.N, 1234)).cuda()
+    y = torch.empty_like(x)
+    out = {"workload": "hybrid VSIE 1 mm: 192x224x256 head-like phantom (seed 7), 32-loop array %d near RWG, "
+                       "open shield %d far RWG, 297.2 MHz" % (op.m_near, op.m_far),
+           "n_unknowns": op.N, "setup_seconds": round(setup_s, 1), "info": info}
+    for name, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        xx = x.to(dt)
+        yy = torch.empty_like(xx)
+        for _ in range(args.warmup):
+            op.matvec(xx, out=yy)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            op.matvec(xx, out=yy)
+        torch.cuda.synchronize()
+        rate = args.steps / (time.perf_counter() - t0)
+        op.profile(True)
+        for _ in range(5):
+            op.matvec(xx, out=yy)
+        st = {k: round(v[0] / v[1], 4) for k, v in op.profile_read().items()}
+        op.profile(False)
+        out[name] = {"matvec_per_s": round(rate, 2), "ms": round(1e3 / rate, 3), "stages_ms": st}
+        print("1 mm %s: %.2f matvec/s %s" % (name, rate, json.dumps(st)), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    sinfo = op.schur_setup(precond=True)
+    torch.cuda.synchronize()
+    schur_s = time.perf_counter() - t0
+    ports = list(range(min(args.one_mm_ports, op.n_ports)))
+    t0 = time.perf_counter()
+    X, sts = op.solve_ports(ports, tol=1e-6, restart=args.restart, max_iter=args.max_iter, method=2,
+                            allow_noconv=True)
+    wall = time.perf_counter() - t0
+    its = [s_["iterations"] for s_ in sts]
+    res = float(max(torch.linalg.norm(op.rhs(pt) - op.matvec(X[i].contiguous())) / torch.linalg.norm(op.rhs(pt))
+                    for i, pt in enumerate(ports)))
+    out["solve"] = dict(method="far currents eliminated, right-preconditioned GMRES", ports=ports,
+                        schur_setup_seconds=round(schur_s, 1), n_proxy=sinfo["n_proxy"],
+                        seconds_total=round(wall, 2), mean_iterations=float(np.mean(its)),
+                        converged_ports=int(sum(s_["rel_residual"] <= 1e-6 for s_ in sts)),
+                        max_rel_residual=float(max(s_["rel_residual"] for s_ in sts)), full_operator_residual=res,
+                        time_to_1e6_mean_s=round(float(np.mean([s_["seconds"] for s_ in sts])), 3))
+    print(json.dumps({"one_mm": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +417,13 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-solve", action="store_true", help="also time the oracle's dense LU solve (small case)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner training and solve")
+    ap.add_argument("--one-mm", action="store_true", help="run the 1 mm configuration instead (extra workload)")
+    ap.add_argument("--one-mm-ports", type=int, default=4, help="ports solved at 1 mm")
+    ap.add_argument("--learn-phantoms", type=int, default=2, help="seeded training phantoms (seeds 100, 101, ...)")
+    ap.add_argument("--learn-pairs", type=int, default=2048)
+    ap.add_argument("--learn-epochs", type=int, default=3)
+    ap.add_argument("--learn-lr", type=float, default=3e-4)
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--max-iter", type=int, default=1000, help="iterations of the preconditioned solve")
     ap.add_argument("--plain-max-iter", type=int, default=500, help="iterations of plain GMRES and mixed IR")
@@ -339,6 +452,9 @@ def main():
         print("bench.py runs on one GPU only (the path has no multi-GPU mode); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.one_mm:
+        one_mm(args)
+        return
     import torch
 
     import paper_2206_12409_amd as pkg
@@ -475,6 +591,9 @@ def main():
             rel_diff_vs_fp64=float(torch.linalg.norm(Xm - Xs) / torch.linalg.norm(Xs)),
             time_to_1e6_mean_s=(round(float(np.mean([s_["seconds"] for s_ in stm])), 4) if all(convm) else None))
         print("schur_precond_mixed: %s" % solve["schur_precond_mixed"], file=sys.stderr, flush=True)
+        if not args.no_learned:
+            solve["learned"] = learned_solve(pkg, synth, op, Xs, args)
+            print("learned: %s" % solve["learned"], file=sys.stderr, flush=True)
         # plain FP64 GMRES(restart) on the full system (Sec. IV-C uses restart 50)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

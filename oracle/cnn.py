@@ -12,7 +12,8 @@ Every convolution is 3 x 3 x 3 with unit stride and zero padding of one voxel ("
 
     out[z, y, x, o] = b[o] + sum_{dz, dy, dx, i} w[o, dz, dy, dx, i] in[z + dz - 1, y + dy - 1, x + dx - 1, i].
 
-Architecture (level l at 1 / 2^(l-1) of the grid; ReLU after every convolution but the last):
+Architecture (level l at 1 / 2^(l-1) of the grid; a leaky ReLU, act(z) = z for z > 0 and
+LEAK z otherwise, after every convolution but the last, so that no unit stops learning):
 
     e1 = conv(conv(x, 8 -> 16), 16 -> 16)              p1 = avgpool2(e1)
     e2 = conv(conv(p1, 16 -> 32), 32 -> 32)            p2 = avgpool2(e2)
@@ -38,6 +39,8 @@ every parameter group and the input, pooling and upsampling adjoint to each othe
 factor 8.
 """
 import numpy as np
+
+LEAK = 0.1
 
 LAYERS = (  # (name, Cin, Cout, relu)
     ("e1a", 8, 16, True), ("e1b", 16, 16, True),
@@ -118,6 +121,14 @@ def _identity(a):
     return a
 
 
+def act(z):
+    return np.where(z > 0, z, LEAK * z)
+
+
+def act_slope(z):
+    return np.where(z > 0, 1.0, LEAK)
+
+
 def forward(p, x, keep=False, quant=False):
     """Network output for input x [D][H][W][8]; with keep, also the activations the backward
     pass needs (pre-activation values of every convolution and its inputs). quant rounds every
@@ -129,7 +140,7 @@ def forward(p, x, keep=False, quant=False):
     def layer(name, inp, relu):
         z = conv3(q(inp), q(p[name + ".w"]), p[name + ".b"])
         acts[name] = (inp, z)
-        return np.maximum(z, 0.0) if relu else z
+        return act(z) if relu else z
 
     e1 = layer("e1b", layer("e1a", x, True), True)
     e2 = layer("e2b", layer("e2a", avgpool2(e1), True), True)
@@ -160,7 +171,7 @@ def backward(p, x, t, quant=False):
     def back(name, gout, relu):
         inp, z = acts[name]
         if relu:
-            gout = gout * (z > 0)
+            gout = gout * act_slope(z)
         gx, gw, _ = conv3_backward(q(inp), q(p[name + ".w"]), q(gout))
         g[name + ".w"] = gw
         g[name + ".b"] = gout.sum((0, 1, 2))

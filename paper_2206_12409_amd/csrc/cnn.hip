@@ -9,7 +9,8 @@
 // 27 taps are converted to bfloat16 and staged in LDS, then each wavefront runs 27 x (Cout / 16)
 // MFMA 16x16x16 steps (A = 16 voxels x 16 input channels, B = 16 input x 16 output channels).
 // The decoder inputs [up2(a), b] are read in place (half-resolution reads of a), and the
-// backward-data pass multiplies its input gradient by the ReLU mask while staging.
+// backward-data pass multiplies its input gradient by the activation's slope (1 where the layer
+// output is positive, LEAK elsewhere) while staging.
 //
 // Weight gradients: per (output tile, input tile) and z plane, a workgroup accumulates all 27 taps
 // over the plane's voxel tiles with MFMA steps whose reduction dimension is the voxels
@@ -32,6 +33,9 @@ __device__ inline uint16_t to_bf16(float f) {
 }
 
 static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+constexpr float LEAK = 0.1f;   // slope of the activation for negative inputs (leaky ReLU)
+__device__ inline float leak_mask(float g, float y) { return y > 0.f ? g : LEAK * g; }
 
 // ---------------------------------------------------------------------------------------------
 // convolution forward (also the backward-data pass with reversed, transposed weights)
@@ -81,10 +85,10 @@ __global__ __launch_bounds__(256) void k_conv3_fwd(ConvArgs a) {
           v = *reinterpret_cast<const float4*>(a.in0 + vox * a.c0 + kc + 4 * q);
           if (a.mask) {
             const float4 m = *reinterpret_cast<const float4*>(a.mask + vox * a.c0 + kc + 4 * q);
-            v.x = m.x > 0.f ? v.x : 0.f;
-            v.y = m.y > 0.f ? v.y : 0.f;
-            v.z = m.z > 0.f ? v.z : 0.f;
-            v.w = m.w > 0.f ? v.w : 0.f;
+            v.x = leak_mask(v.x, m.x);
+            v.y = leak_mask(v.y, m.y);
+            v.z = leak_mask(v.z, m.z);
+            v.w = leak_mask(v.w, m.w);
           }
         } else {
           const int64_t vox = ((int64_t)gz * a.H + gy) * a.W + gx;
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(256) void k_conv3_fwd(ConvArgs a) {
       float v = 0.f;
       if (o < a.cout) {
         v = acc[n][j] + (a.bias ? a.bias[o] : 0.f);
-        if (a.relu) v = fmaxf(v, 0.f);
+        if (a.relu && !(v > 0.f)) v *= LEAK;
       }
       a.out[(((int64_t)z * a.H + y) * a.W + x) * a.cout_p + o] = v;
     }
@@ -214,10 +218,10 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(WgradArgs a) {
         gv = *reinterpret_cast<const float4*>(a.g + vox * a.cout_p + oc + 4 * q);
         if (a.mask) {
           const float4 m = *reinterpret_cast<const float4*>(a.mask + vox * a.cout_p + oc + 4 * q);
-          gv.x = m.x > 0.f ? gv.x : 0.f;
-          gv.y = m.y > 0.f ? gv.y : 0.f;
-          gv.z = m.z > 0.f ? gv.z : 0.f;
-          gv.w = m.w > 0.f ? gv.w : 0.f;
+          gv.x = leak_mask(gv.x, m.x);
+          gv.y = leak_mask(gv.y, m.y);
+          gv.z = leak_mask(gv.z, m.z);
+          gv.w = leak_mask(gv.w, m.w);
         }
       }
       uint16_t* d = gt + v * 16 + 4 * q;
@@ -247,7 +251,7 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(WgradArgs a) {
         for (int xx = x0; xx < min(x0 + CT_X, a.W); ++xx) {
           const int64_t vox = ((int64_t)z * a.H + yy) * a.W + xx;
           float gv = a.g[vox * a.cout_p + oc + o];
-          if (a.mask && !(a.mask[vox * a.cout_p + oc + o] > 0.f)) gv = 0.f;
+          if (a.mask) gv = leak_mask(gv, a.mask[vox * a.cout_p + oc + o]);
           bsum += gv;
         }
     }

@@ -98,12 +98,19 @@ __global__ void k_net_output_add(const float* __restrict__ y, const float2* __re
 }
 
 // training pair p: [D][H][W][16] bfloat16, channels 0..7 input, 8..13 target
+// A pair whose body part carries less than PAIR_MIN_BODY of the coupled vector's norm is stored
+// as zeros (it teaches nothing the body network can see: its correction comes from the near
+// currents, e.g. the product of a restart, whose body part is only the residual).
+constexpr double PAIR_MIN_BODY = 0.3;
+
 __global__ void k_pack_pair(const cxd* __restrict__ wb, const cxd* __restrict__ zb, const cxd* __restrict__ dw,
-                            const float2* __restrict__ mat, const double* __restrict__ scale, double c, int n1, int n2,
-                            int n3, int D, int H, int W, uint16_t* __restrict__ pair) {
+                            const float2* __restrict__ mat, const double* __restrict__ scale,
+                            const double* __restrict__ wnorm, double nbody, double c, int n1, int n2, int n3, int D,
+                            int H, int W, uint16_t* __restrict__ pair) {
   const int64_t nvox = (int64_t)D * H * W, nv = (int64_t)n1 * n2 * n3;
   const double s = *scale;
-  const double inv = s > 0 ? 1.0 / s : 0.0, invt = s > 0 ? 1.0 / (s * c) : 0.0;
+  const bool keep = s > 0 && s * sqrt(nbody) >= PAIR_MIN_BODY * *wnorm;
+  const double inv = keep ? 1.0 / s : 0.0, invt = keep ? 1.0 / (s * c) : 0.0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nvox; e += (int64_t)gridDim.x * blockDim.x) {
     const int xx = (int)(e % W), yy = (int)((e / W) % H), zz = (int)(e / ((int64_t)W * H));
     float v[16];
@@ -111,7 +118,7 @@ __global__ void k_pack_pair(const cxd* __restrict__ wb, const cxd* __restrict__ 
     if (xx < n1 && yy < n2 && zz < n3) {
       const int64_t p = xx + (int64_t)n1 * (yy + (int64_t)n2 * zz);
       const float2 m = mat[p];
-      if (m.x != 0.f || m.y != 0.f) {
+      if (keep && (m.x != 0.f || m.y != 0.f)) {
         for (int comp = 0; comp < 3; ++comp) {
           const cxd a = wb[comp * nv + p];
           v[2 * comp] = (float)(a.re * inv);
@@ -221,10 +228,13 @@ void net_collect_pair(Handle& H, NetState& S, const cxd* z_full, const cxd* w_fu
   launch_mul_diag<double>(st, w_full + off, H.schur.d64.invdiag, dw_tmp, nb);
   hipLaunchKernelGGL(k_body_sumsq, dim3(blocks), dim3(256), 0, st, w_full + off, nb, S.N.red + 2560);
   hipLaunchKernelGGL(k_rms, dim3(1), dim3(64), 0, st, S.N.red + 2560, (int)blocks, 3.0 * H.tissue.size(), S.N.red + 2);
+  // norm of the coupled part of w (near currents and body)
+  hipLaunchKernelGGL(k_body_sumsq, dim3(blocks), dim3(256), 0, st, w_full + H.mf, (int64_t)H.mn + nb, S.N.red + 2560);
+  hipLaunchKernelGGL(k_rms, dim3(1), dim3(64), 0, st, S.N.red + 2560, (int)blocks, 1.0, S.N.red + 4);
   uint16_t* dst = S.pairs + (size_t)S.count * 16 * D * Hg * W;
   hipLaunchKernelGGL(k_pack_pair, dim3(nb256((int64_t)D * Hg * W)), dim3(256), 0, st, w_full + off, z_full + off,
-                     dw_tmp, (const float2*)H.d_material, S.N.red + 2, H.mat_scale, H.n[0], H.n[1], H.n[2], D, Hg, W,
-                     dst);
+                     dw_tmp, (const float2*)H.d_material, S.N.red + 2, S.N.red + 4, 3.0 * H.tissue.size(),
+                     H.mat_scale, H.n[0], H.n[1], H.n[2], D, Hg, W, dst);
   VSIE_HIP(hipGetLastError());
   S.count += 1;
 }

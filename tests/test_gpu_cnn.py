@@ -4,9 +4,10 @@ single layers forward, backward-data and weight gradient on a ragged grid (tiles
 cut at the edges), the whole network's forward and gradients, and the Adam step.
 
 Bars: a single layer 2e-5 relative to its largest output (float32 accumulation of up to 3024
-products); the whole network 2e-3 (activations between layers are float32 on the device and
-float64 in the oracle, so the next layer's bfloat16 rounding can differ by one unit in a few
-values); Adam 1e-6 relative."""
+products); the whole network's output 2e-3 and its gradients 8e-3 per parameter group, four
+bfloat16 unit roundoffs (2^-9 each): activations between layers are float32 on the device and
+float64 in the oracle, so the next layer's bfloat16 rounding of a value can differ by one unit,
+and the gradients pass through twelve such roundings twice; Adam 1e-6 relative."""
 import numpy as np
 import pytest
 
@@ -74,7 +75,7 @@ def test_layer_forward_and_backward_data(net, lib, layer):
     out = torch.empty((D, H, W, _cp(co)), dtype=torch.float32, device="cuda")
     n.layer(layer, 0, DIMS, in0, in1, None, out)
     z = cnn.conv3(cnn.bf16(x), cnn.bf16(w), b)
-    ref = np.maximum(z, 0) if relu else z
+    ref = cnn.act(z) if relu else z
     got = out.cpu().numpy()
     e = _relerr(got[..., :co], ref)
     print("layer %s forward: %.2e" % (name, e))
@@ -82,7 +83,7 @@ def test_layer_forward_and_backward_data(net, lib, layer):
     assert np.all(got[..., co:] == 0)
     # backward-data: gradient of the layer input from a random output gradient, ReLU-masked
     g = rng.standard_normal((D, H, W, co)).astype(np.float32).astype(np.float64)
-    gm = g * (ref > 0) if relu else g
+    gm = g * cnn.act_slope(ref) if relu else g
     gx_ref, _, _ = cnn.conv3_backward(cnn.bf16(x), cnn.bf16(w), cnn.bf16(gm))
     gout = torch.empty((D, H, W, _cp(ci) if not dec else ci), dtype=torch.float32, device="cuda")
     n.layer(layer, 1, DIMS, _pad(g, _cp(co)), None, out if relu else None, gout)
@@ -110,7 +111,7 @@ def test_layer_weight_gradient(net, lib, layer):
         in0, in1 = _pad(x, _cp(ci)), None
     g = rng.standard_normal((D, H, W, co)).astype(np.float32).astype(np.float64)
     mask = rng.standard_normal((D, H, W, co)).astype(np.float32) if relu else None
-    gm = g * (mask > 0) if relu else g
+    gm = g * cnn.act_slope(mask) if relu else g
     _, gw_ref, _ = cnn.conv3_backward(cnn.bf16(x), cnn.bf16(p[name + ".w"]), cnn.bf16(gm))
     gb_ref = gm.sum((0, 1, 2))
     gw, gb = n.layer_wgrad(layer, DIMS, in0, _pad(g, _cp(co)), in1, _pad(mask, _cp(co)) if relu else None)
@@ -138,7 +139,7 @@ def test_network_forward_and_gradients(net, lib):
     g = lib.Net.unflatten(gflat)
     worst = max(float(np.linalg.norm(g[k] - g_ref[k]) / np.linalg.norm(g_ref[k])) for k in g_ref)
     print("network gradients: worst parameter group %.2e" % worst)
-    assert worst < 2e-3
+    assert worst < 8e-3
 
 
 def test_adam_step_matches_oracle(lib):
