@@ -157,7 +157,7 @@ typedef struct {
   int32_t gs_second_passes;   /* Arnoldi steps that took the second Gram-Schmidt pass */
 } vsie_solve_stats;
 
-/* Fill defaults: tt_tol 1e-3, tt_rank_max 96, aca_tol 1e-3, aca_rank_max 128,
+/* Fill defaults: tt_tol 1e-3, tt_rank_max 96, aca_tol 1e-3, aca_rank_max 256,
  * precorrect_dist 2, precision VSIE_PREC_MIXED, build_far 1, seed 1, basis VSIE_BASIS_PWC,
  * stencil 5, quadrature 8 / 5 near and 1 / 1 far. */
 int vsie_default_options(vsie_options* opts);

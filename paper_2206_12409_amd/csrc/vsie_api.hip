@@ -1474,7 +1474,7 @@ int vsie_default_options(vsie_options* o) {
   o->tt_tol = 1e-3;
   o->tt_rank_max = 96;
   o->aca_tol = 1e-3;
-  o->aca_rank_max = 128;
+  o->aca_rank_max = 256;
   o->precorrect_dist = 2;
   o->precision = VSIE_PREC_MIXED;
   o->build_far = 1;

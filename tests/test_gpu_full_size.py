@@ -1,6 +1,7 @@
-"""Full-size parity on the 2 mm workload (96x112x128 voxels, 8-loop array, 20k-triangle shield):
-k-sparse probes through the C ABI, sampled outputs evaluated one by one by the oracle
-(paper eq. (15); the same operator bench.py times)."""
+"""Full-size parity on the 2 mm workload (96x112x128 voxels, 8-loop array, 20k-triangle shield;
+the operator bench.py times) and on the 1 mm configuration (192x224x256 voxels, 32-loop array,
+40k-triangle shield): k-sparse probes through the C ABI, sampled outputs evaluated one by one by
+the oracle (paper eq. (15))."""
 import numpy as np
 import pytest
 
@@ -20,12 +21,13 @@ def subset(r, idx):
     return RWG(r.edge[idx], r.tri[idx], r.free[idx], r.free_local[idx], r.length[idx], r.verts, r.tris, r.area)
 
 
-@pytest.fixture(scope="module")
-def big():
+@pytest.fixture(scope="module", params=["2mm", "1mm"])
+def big(request):
     import paper_2206_12409_amd as pkg
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
-    p = synth.two_mm_case()
+    p = synth.two_mm_case() if request.param == "2mm" else synth.one_mm_case()
+    print("full-size workload %s" % request.param, flush=True)
     op = pkg.Operator(p)
     g = p.grid
     far = merge(p.meshes, 1)
@@ -34,7 +36,8 @@ def big():
     rn = build_rwg(near[0], near[1])
     chi = chi_of(g.eps_r, g.sigma, p.freq_hz).ravel()
     k = k0_of(p.freq_hz)
-    return p, op, rf, rn, chi, k
+    yield p, op, rf, rn, chi, k
+    op.close()
 
 
 def _idx3(flat, n):
