@@ -73,14 +73,17 @@ __global__ void k_extract_octant(const cxd* __restrict__ full, int P1, int P2, i
   const int64_t SO = (int64_t)S1 * S2 * S3;
   int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= SO) return;
-  // output layout [f2][f1][f3][6]: the six components of one frequency are one contiguous record
-  // and a z pencil (fixed f1, f2) reads consecutive records
-  const int f3 = (int)(id % S3), f1 = (int)((id / S3) % S1), f2 = (int)(id / ((int64_t)S3 * S1));
+  // output layout [f2][f1][6][f3]: for a z pencil (fixed f1, f2) each of the six components is a
+  // contiguous run over f3, so the lanes of a wavefront (consecutive frequencies) read whole cache
+  // lines
+  const int f3 = (int)(id % S3);
+  const int64_t pen = id / S3;
+  const int f1 = (int)(pen % S1), f2 = (int)(pen / S1);
   const int64_t PT = (int64_t)P1 * P2 * P3;
   int64_t src = f1 + (int64_t)P1 * (f2 + (int64_t)P2 * f3);
   for (int c = 0; c < 6; ++c) {
     cxd v = full[c * PT + src];
-    spec[6 * id + c] = cx<R>{(R)(v.re * scale), (R)(v.im * scale)};
+    spec[(pen * 6 + c) * S3 + f3] = cx<R>{(R)(v.re * scale), (R)(v.im * scale)};
   }
 }
 
@@ -426,11 +429,11 @@ __global__ __launch_bounds__(256) void k_fft_z_conv(cx<R>* __restrict__ buf, int
     int f3 = k3 <= L / 2 ? k3 : L - k3;
     R s1 = k1 <= P1 / 2 ? (R)1 : (R)-1;
     R s3 = k3 <= L / 2 ? (R)1 : (R)-1;
-    const cx<R>* rec = spec + 6 * (((int64_t)f2 * S1 + f1) * S3 + f3);
-    cx<R> Txx = rec[0], Tyy = rec[1], Tzz = rec[2];
-    cx<R> Txy = (s1 * s2) * rec[3];
-    cx<R> Txz = (s1 * s3) * rec[4];
-    cx<R> Tyz = (s2 * s3) * rec[5];
+    const cx<R>* rec = spec + 6 * ((int64_t)f2 * S1 + f1) * S3 + f3;
+    cx<R> Txx = rec[0], Tyy = rec[S3], Tzz = rec[2 * S3];
+    cx<R> Txy = (s1 * s2) * rec[3 * S3];
+    cx<R> Txz = (s1 * s3) * rec[4 * S3];
+    cx<R> Tyz = (s2 * s3) * rec[5 * S3];
     cx<R> x = X[0][u], y = X[1][u], z = X[2][u];
     X[0][u] = Txx * x + Txy * y + Txz * z;
     X[1][u] = Txy * x + Tyy * y + Tyz * z;
@@ -569,9 +572,108 @@ template <int L, int V> struct ZRad {   // radix of stage s of the forward trans
   }
 };
 
+// exchange barrier: the whole block, or only the wavefront when each pencil lives in one
+// wavefront (LDS accesses of one wavefront complete in order; the fence keeps the compiler from
+// moving them across)
+template <bool WAVE> __device__ inline void zsync() {
+  if (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The same Stockham transform for pencils held by one thread group, with its LDS traffic laid out
+// for the banks. Exchange slot a of a pencil row is stored at a ^ ((a >> log2 V) & 15): with
+// 16-byte elements the stores of the early stages (sub-length 1 and V, lanes V or V^2 slots
+// apart) otherwise fall on a few banks, while the swizzle keeps every load and store of every
+// stage conflict-free and the row in place. A stage's twiddles w_L^(q kk tstep), q < RAD, come
+// from one table entry w = w_L^(kk tstep) per butterfly (per-stage tables in LDS, consecutive
+// lanes on consecutive entries) and its powers w^q by multiplication; the twiddles inside the
+// small DFTs are exact constants (multiples of an eighth turn, or of a sixteenth for radix 16).
+template <int L, int V> struct ZTw {
+  using Z = ZRad<L, V>;
+  // sub-length of forward stage s and of inverse stage u (the inverse runs the stages backwards)
+  static constexpr int ls_fwd(int s) {
+    int r = 1;
+    for (int i = 0; i < s; ++i) r *= Z::rad(i);
+    return r;
+  }
+  static constexpr int ls_inv(int u) {
+    int r = 1;
+    for (int i = 0; i < u; ++i) r *= Z::rad(Z::nst - 1 - i);
+    return r;
+  }
+  // table offsets: forward stages 1.., then inverse stages 1.. (stage 0 has no twiddles)
+  static constexpr int off_fwd(int s) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += ls_fwd(i);
+    return o;
+  }
+  static constexpr int n_fwd() { return off_fwd(Z::nst); }
+  static constexpr int off_inv(int u) {
+    int o = n_fwd();
+    for (int i = 1; i < u; ++i) o += ls_inv(i);
+    return o;
+  }
+  static constexpr int size() { return off_inv(Z::nst); }
+};
+
+static_assert(ZTw<256, 4>::size() == 168 && ZTw<128, 4>::size() == 126 && ZTw<1024, 16>::size() == 340,
+              "per-stage twiddle table sizes");
+
+template <int L, int V> __device__ inline int zswz(int a) {
+  constexpr int S = ZRad<V, 2>::lg(V);
+  return a ^ ((a >> S) & 15);
+}
+
+// fill the per-stage twiddle tables (all threads of the block, stride nthr) from w_L^m = tw[m]
+template <typename R, int L, int V>
+__device__ inline void ztw_fill(cx<R>* tws, const cx<R>* __restrict__ tw, int t, int nthr) {
+  using Z = ZRad<L, V>;
+  using W = ZTw<L, V>;
+  for (int e = t; e < W::size(); e += nthr) {
+    int ls = 1, rad = 1, k = 0;
+#pragma unroll
+    for (int s = 1; s < Z::nst; ++s)
+      if (e >= W::off_fwd(s) && e < W::off_fwd(s) + W::ls_fwd(s)) {
+        ls = W::ls_fwd(s);
+        rad = Z::rad(s);
+        k = e - W::off_fwd(s);
+      }
+#pragma unroll
+    for (int u = 1; u < Z::nst; ++u)
+      if (e >= W::off_inv(u) && e < W::off_inv(u) + W::ls_inv(u)) {
+        ls = W::ls_inv(u);
+        rad = Z::rad(Z::nst - 1 - u);
+        k = e - W::off_inv(u);
+      }
+    tws[e] = tw[(k * (L / (rad * ls))) & (L - 1)];
+  }
+}
+
+// w_RAD^m (forward sign), exact for RAD <= 16: multiples of 2 pi / 16 from three constants
+template <typename R> __device__ inline cx<R> unit16(int m16) {
+  constexpr R C1 = (R)0.92387953251128675613L;   // cos(pi / 8)
+  constexpr R S1 = (R)0.38268343236508977173L;   // sin(pi / 8)
+  constexpr R H = (R)0.70710678118654752440L;    // sqrt(1 / 2)
+  const int m = m16 & 15;
+  // first quadrant values of cos for m = 0..4
+  const R cq[5] = {(R)1, C1, H, S1, (R)0};
+  const int q = m >> 2, r = m & 3;
+  R c = cq[r], s = cq[4 - r];   // cos and sin of 2 pi r / 16
+  // rotate by q quarter turns: angle 2 pi m / 16 = q pi / 2 + 2 pi r / 16
+  R cr = c, sr = s;
+  if (q == 1) { cr = -s; sr = c; }
+  else if (q == 2) { cr = -c; sr = -s; }
+  else if (q == 3) { cr = s; sr = -c; }
+  return cx<R>{cr, -sr};
+}
+
 template <typename R, int RAD, bool FWD>
-__device__ inline void small_dft(cx<R>* a, const cx<R>* __restrict__ tw, int tw_stride) {
-  // in-place DFT of length RAD on a[0..RAD) (natural order in and out); w_RAD^k = tw[k tw_stride]
+__device__ inline void small_dft_c(cx<R>* a) {
   cx<R> v[RAD];
 #pragma unroll
   for (int q = 0; q < RAD; ++q) v[bitrev_of(q, RAD)] = a[q];
@@ -582,8 +684,11 @@ __device__ inline void small_dft(cx<R>* a, const cx<R>* __restrict__ tw, int tw_
 #pragma unroll
       for (int j = 0; j < ln / 2; ++j) {
         cx<R> t = v[i + j + ln / 2];
-        if (j != 0) {
-          cx<R> w = tw[(j * (RAD / ln)) * tw_stride];
+        const int m16 = j * (16 / ln);   // w_ln^j = w_16^(16 j / ln)
+        if (m16 == 4) {
+          t = FWD ? cx<R>{t.im, -t.re} : cx<R>{-t.im, t.re};   // times -i (forward) or i
+        } else if (m16 != 0) {
+          cx<R> w = unit16<R>(m16);
           if (!FWD) w.im = -w.im;
           t = w * t;
         }
@@ -597,30 +702,30 @@ __device__ inline void small_dft(cx<R>* a, const cx<R>* __restrict__ tw, int tw_
   for (int q = 0; q < RAD; ++q) a[q] = v[q];
 }
 
-// radix-RAD stage on the thread's V / RAD butterflies b = j + T i held in v[i * RAD + q]
 template <typename R, int L, int V, int RAD, bool FWD>
-__device__ inline void zstage(cx<R>* v, int j, int Ls, const cx<R>* __restrict__ tw) {
+__device__ inline void zstage_c(cx<R>* v, int j, int Ls, const cx<R>* tw1) {
   constexpr int T = L / V;
   constexpr int NB = V / RAD;
-  const int tstep = L / (RAD * Ls);
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int b = j + T * i;
     const int kk = b & (Ls - 1);
     cx<R>* a = v + i * RAD;
     if (Ls > 1) {
+      cx<R> w1 = tw1[kk];
+      if (!FWD) w1.im = -w1.im;
+      cx<R> wq = w1;
 #pragma unroll
       for (int q = 1; q < RAD; ++q) {
-        cx<R> w = tw[(q * kk * tstep) & (L - 1)];
-        if (!FWD) w.im = -w.im;
-        a[q] = a[q] * w;
+        a[q] = a[q] * wq;
+        if (q + 1 < RAD) wq = wq * w1;
       }
     }
-    small_dft<R, RAD, FWD>(a, tw, L / RAD);
+    small_dft_c<R, RAD, FWD>(a);
   }
 }
 template <typename R, int L, int V, int RAD>
-__device__ inline void zstore(cx<R>* Sp, const cx<R>* v, int j, int Ls) {
+__device__ inline void zstore_c(cx<R>* Sp, const cx<R>* v, int j, int Ls) {
   constexpr int T = L / V;
   constexpr int NB = V / RAD;
 #pragma unroll
@@ -629,164 +734,110 @@ __device__ inline void zstore(cx<R>* Sp, const cx<R>* v, int j, int Ls) {
     const int kk = b & (Ls - 1);
     const int base = (b - kk) * RAD + kk;
 #pragma unroll
-    for (int q = 0; q < RAD; ++q) Sp[base + q * Ls] = v[i * RAD + q];
+    for (int q = 0; q < RAD; ++q) Sp[zswz<L, V>(base + q * Ls)] = v[i * RAD + q];
   }
 }
 template <typename R, int L, int V, int RAD>
-__device__ inline void zload(const cx<R>* Sp, cx<R>* v, int j) {
+__device__ inline void zload_c(const cx<R>* Sp, cx<R>* v, int j) {
   constexpr int T = L / V;
   constexpr int NB = V / RAD;
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int q = 0; q < RAD; ++q) v[i * RAD + q] = Sp[j + T * i + (L / RAD) * q];
+    for (int q = 0; q < RAD; ++q) v[i * RAD + q] = Sp[zswz<L, V>(j + T * i + (L / RAD) * q)];
 }
-
-// exchange barrier: the whole block, or only the wavefront when each pencil lives in one
-// wavefront (LDS accesses of one wavefront complete in order; the fence keeps the compiler from
-// moving them across)
-template <bool WAVE> __device__ inline void zsync() {
-  if (WAVE) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  } else {
-    __syncthreads();
-  }
-}
-
-template <typename R, int L, int V, bool FWD, int RAD, bool WAVE>
-__device__ inline void zstep(cx<R>* Sp, cx<R>* v, int j, int Ls, bool load, bool store,
-                             const cx<R>* __restrict__ tw) {
+template <typename R, int L, int V, bool FWD, int RAD>
+__device__ inline void zstep_c(cx<R>* Sp, cx<R>* v, int j, int Ls, bool load, bool store, const cx<R>* tw1) {
   if (load) {
-    zsync<WAVE>();
-    zload<R, L, V, RAD>(Sp, v, j);
+    zsync<true>();
+    zload_c<R, L, V, RAD>(Sp, v, j);
   }
-  zstage<R, L, V, RAD, FWD>(v, j, Ls, tw);
+  zstage_c<R, L, V, RAD, FWD>(v, j, Ls, tw1);
   if (store) {
-    if (load) zsync<WAVE>();
-    zstore<R, L, V, RAD>(Sp, v, j, Ls);
+    if (load) zsync<true>();
+    zstore_c<R, L, V, RAD>(Sp, v, j, Ls);
   }
 }
-template <typename R, int L, int V, bool FWD, bool WAVE>
-__device__ inline void zstep_any(int rad, cx<R>* Sp, cx<R>* v, int j, int Ls, bool load, bool store,
-                                 const cx<R>* __restrict__ tw) {
-  if (rad == V) zstep<R, L, V, FWD, V, WAVE>(Sp, v, j, Ls, load, store, tw);
-  else if (rad == V / 2 && V >= 4) zstep<R, L, V, FWD, (V >= 4 ? V / 2 : 2), WAVE>(Sp, v, j, Ls, load, store, tw);
-  else if (rad == V / 4 && V >= 8) zstep<R, L, V, FWD, (V >= 8 ? V / 4 : 2), WAVE>(Sp, v, j, Ls, load, store, tw);
+template <typename R, int L, int V, bool FWD>
+__device__ inline void zstep_any_c(int rad, cx<R>* Sp, cx<R>* v, int j, int Ls, bool load, bool store,
+                                   const cx<R>* tw1) {
+  if (rad == V) zstep_c<R, L, V, FWD, V>(Sp, v, j, Ls, load, store, tw1);
+  else if (rad == V / 2 && V >= 4) zstep_c<R, L, V, FWD, (V >= 4 ? V / 2 : 2)>(Sp, v, j, Ls, load, store, tw1);
+  else if (rad == V / 4 && V >= 8) zstep_c<R, L, V, FWD, (V >= 8 ? V / 4 : 2)>(Sp, v, j, Ls, load, store, tw1);
 }
-
-// all stages of one transform; the first forward (last inverse) stage works on registers only
-template <typename R, int L, int V, bool FWD, bool WAVE = false>
-__device__ inline void zfft(cx<R>* Sp, cx<R>* v, int j, const cx<R>* __restrict__ tw) {
+// all stages of one transform on a pencil row held by one wavefront (or part of one); tws: the
+// per-stage twiddle tables (ZTw layout)
+template <typename R, int L, int V, bool FWD>
+__device__ inline void zfft_c(cx<R>* Sp, cx<R>* v, int j, const cx<R>* tws) {
   using Z = ZRad<L, V>;
+  using W = ZTw<L, V>;
   int Ls = 1;
   if (FWD) {
 #pragma unroll
     for (int s = 0; s < Z::nst; ++s) {
-      zstep_any<R, L, V, true, WAVE>(Z::rad(s), Sp, v, j, Ls, s > 0, s + 1 < Z::nst, tw);
+      zstep_any_c<R, L, V, true>(Z::rad(s), Sp, v, j, Ls, s > 0, s + 1 < Z::nst, tws + W::off_fwd(s));
       Ls *= Z::rad(s);
     }
   } else {
 #pragma unroll
     for (int s = Z::nst - 1; s >= 0; --s) {
-      zstep_any<R, L, V, false, WAVE>(Z::rad(s), Sp, v, j, Ls, s < Z::nst - 1, s > 0, tw);
+      const int u = Z::nst - 1 - s;
+      zstep_any_c<R, L, V, false>(Z::rad(s), Sp, v, j, Ls, s < Z::nst - 1, s > 0, tws + W::off_inv(u));
       Ls *= Z::rad(s);
     }
   }
 }
 
-#ifdef ZCONV_WAVES
-#define ZCONV_ATTR __attribute__((amdgpu_waves_per_eu(ZCONV_WAVES, 8)))
-#else
-#define ZCONV_ATTR
-#endif
-template <typename R, int L, int V, int NP>
-__global__ __launch_bounds__(NP * L / V) ZCONV_ATTR void k_zconv3(cx<R>* __restrict__ buf, int n3, int P1, int P2,
-                                                       const cx<R>* __restrict__ spec, const cx<R>* __restrict__ tw,
-                                                       const int* __restrict__ order) {
-  constexpr int T = L / V;
-  constexpr int RAD_LAST = ZRad<L, V>::rad(ZRad<L, V>::nst - 1);
-  constexpr int NB_LAST = V / RAD_LAST;
-  __shared__ cx<R> S[NP * (L + 1)];
-  __shared__ cx<R> twl[L];   // twiddles w_L^k staged once per block (LDS latency in every stage)
-  const int t = threadIdx.x;
-  for (int k = t; k < L; k += NP * L / V) twl[k] = tw[k];
-  const int p = t % NP, j = t / NP;
-  // the block order puts the (up to four) blocks that read the same folded spectra next to
-  // each other: k2 with P2 - k2 and each k1 tile with its mirror tile
-  const int k2 = order[2 * blockIdx.x];
-  const int k1 = order[2 * blockIdx.x + 1] * NP + p;
-  const bool valid = k1 < P1;
-  const int64_t plane = (int64_t)P1 * P2, comp = plane * n3;
-  cx<R>* col = buf + (int64_t)k2 * P1 + (valid ? k1 : 0);
-  cx<R>* Sp = S + p * (L + 1);
-  cx<R> H[3][V];
+// Staging of a block's NP adjacent pencils (all three components, planes n < n3 <= L / 2) between
+// buf (pencil k1 at base + k1, plane n at + n plane, component c at + c comp) and the LDS rows
+// S[(p 3 + c) (L + 1) + n]. Thread t takes pencil t % NP and the planes t / NP + m NT / NP, with
+// neighbouring threads on neighbouring pencils (coalesced); every load is issued before the first
+// LDS store. np_here: pencils of the block that exist.
+template <typename R, int L, int NP, int NT>
+__device__ inline void zstage_in(cx<R>* S, const cx<R>* __restrict__ base, int t, int n3, int64_t plane,
+                                 int64_t comp, int np_here) {
+  constexpr int NSTEP = NT / NP;
+  constexpr int MAXIT = (L / 2 + NSTEP - 1) / NSTEP;
+  const int p = t % NP, n0 = t / NP;
+  const bool ok = p < np_here;
+  cx<R> v[3][MAXIT];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    // first stage input x[j + T q]; planes at or beyond L / 2 >= n3 are zero
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int q = 0; q < V; ++q) {
-      const int n = j + T * q;
-      H[c][q] = (2 * q < V && valid && n < n3) ? col[c * comp + (int64_t)n * plane] : cx<R>{0, 0};
+    for (int m = 0; m < MAXIT; ++m) {
+      const int n = n0 + m * NSTEP;
+      v[c][m] = (ok && n < n3) ? base[c * comp + (int64_t)n * plane + p] : cx<R>{0, 0};
     }
-    __syncthreads();   // twiddle table ready; the previous component's last exchange has been read
-    zfft<R, L, V, true>(Sp, H[c], j, twl);
-  }
-  // spectral 3 x 3 multiply: H[c][i RAD_LAST + q] is X[k3], k3 = j + T i + (L / RAD_LAST) q
-  {
-    const int S1 = P1 / 2 + 1, S3 = L / 2 + 1;
-    const int f1 = k1 <= P1 / 2 ? k1 : P1 - k1;
-    const int f2 = k2 <= P2 / 2 ? k2 : P2 - k2;
-    const R s1 = k1 <= P1 / 2 ? (R)1 : (R)-1;
-    const R s2 = k2 <= P2 / 2 ? (R)1 : (R)-1;
-    const cx<R>* sp = spec + (valid ? 6 * ((int64_t)f2 * S1 + f1) * S3 : 0);
 #pragma unroll
-    for (int i = 0; i < NB_LAST; ++i)
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int q = 0; q < RAD_LAST; ++q) {
-        const int k3 = j + T * i + (L / RAD_LAST) * q;
-        const int f3 = k3 <= L / 2 ? k3 : L - k3;
-        const R s3 = k3 <= L / 2 ? (R)1 : (R)-1;
-        const cx<R>* rec = sp + 6 * f3;
-        const cx<R> Txx = rec[0], Tyy = rec[1], Tzz = rec[2];
-        const cx<R> Txy = (s1 * s2) * rec[3];
-        const cx<R> Txz = (s1 * s3) * rec[4];
-        const cx<R> Tyz = (s2 * s3) * rec[5];
-        const int e = i * RAD_LAST + q;
-        const cx<R> x = H[0][e], y = H[1][e], z = H[2][e];
-        H[0][e] = Txx * x + Txy * y + Txz * z;
-        H[1][e] = Txy * x + Tyy * y + Tyz * z;
-        H[2][e] = Txz * x + Tyz * y + Tzz * z;
-#ifndef ZCONV_NO_SB
-        // FP64: keep the spectral loads of one frequency at a time (fewer live registers)
-        if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
-#endif
-      }
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    __syncthreads();   // LDS free for this component's exchanges
-    zfft<R, L, V, false>(Sp, H[c], j, twl);
-    // last inverse stage output: thread holds x[j + T q]
-#pragma unroll
-    for (int q = 0; q < V / 2; ++q) {
-      const int n = j + T * q;
-      if (valid && n < n3) col[c * comp + (int64_t)n * plane] = H[c][q];
+    for (int m = 0; m < MAXIT; ++m) {
+      const int n = n0 + m * NSTEP;
+      if (n < n3) S[(p * 3 + c) * (L + 1) + n] = v[c][m];
     }
-  }
+}
+template <typename R, int L, int NP, int NT>
+__device__ inline void zstage_out(const cx<R>* S, cx<R>* __restrict__ base, int t, int n3, int64_t plane,
+                                  int64_t comp, int np_here) {
+  constexpr int NSTEP = NT / NP;
+  constexpr int MAXIT = (L / 2 + NSTEP - 1) / NSTEP;
+  const int p = t % NP, n0 = t / NP;
+  if (p >= np_here) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int m = 0; m < MAXIT; ++m) {
+      const int n = n0 + m * NSTEP;
+      if (n < n3) base[c * comp + (int64_t)n * plane + p] = S[(p * 3 + c) * (L + 1) + n];
+    }
 }
 
 // Fused z pass, one wavefront (or part of one) per pencil: T = L / V <= 64 threads own a pencil,
 // so the FFT exchanges only synchronise the wavefront. The block's NP pencils (adjacent k1) are
 // loaded and stored through an LDS staging area [NP][3][L + 1] with neighbouring threads on
 // neighbouring pencils (coalesced), the only two block-wide barriers.
-#ifdef ZCONV4_WAVES
-#define ZCONV4_ATTR __attribute__((amdgpu_waves_per_eu(ZCONV4_WAVES, 8)))
-#else
-#define ZCONV4_ATTR
-#endif
 template <typename R, int L, int V, int NP>
-__global__ __launch_bounds__(NP * L / V) ZCONV4_ATTR void k_zconv4(cx<R>* __restrict__ buf, int n3, int P1, int P2,
+__global__ __launch_bounds__(NP * L / V) void k_zconv4(cx<R>* __restrict__ buf, int n3, int P1, int P2,
                                                        const cx<R>* __restrict__ spec, const cx<R>* __restrict__ tw,
                                                        const int* __restrict__ order) {
   constexpr int T = L / V;
@@ -796,18 +847,15 @@ __global__ __launch_bounds__(NP * L / V) ZCONV4_ATTR void k_zconv4(cx<R>* __rest
   constexpr int NB_LAST = V / RAD_LAST;
   static_assert(T <= 64, "a pencil must fit one wavefront");
   __shared__ cx<R> S[NP * 3 * LP];
-  __shared__ cx<R> twl[L];   // twiddles w_L^k staged once per block
+  __shared__ cx<R> tws[ZTw<L, V>::size()];   // per-stage twiddle tables
   const int t = threadIdx.x;
-  for (int k = t; k < L; k += NT) twl[k] = tw[k];
+  ztw_fill<R, L, V>(tws, tw, t, NT);
   const int k2 = order[2 * blockIdx.x];
   const int k10 = order[2 * blockIdx.x + 1] * NP;
   const int64_t plane = (int64_t)P1 * P2, comp = plane * n3;
   cx<R>* base = buf + (int64_t)k2 * P1 + k10;
   // staging load: element (c, n, p), pencils fastest
-  for (int e = t; e < 3 * n3 * NP; e += NT) {
-    const int p = e % NP, n = (e / NP) % n3, c = e / (NP * n3);
-    S[(p * 3 + c) * LP + n] = (k10 + p < P1) ? base[c * comp + (int64_t)n * plane + p] : cx<R>{0, 0};
-  }
+  zstage_in<R, L, NP, NT>(S, base, t, n3, plane, comp, P1 - k10);
   __syncthreads();
   const int p = t / T, j = t % T;
   const int k1 = k10 + p;
@@ -823,7 +871,7 @@ __global__ __launch_bounds__(NP * L / V) ZCONV4_ATTR void k_zconv4(cx<R>* __rest
     }
   zsync<true>();   // the staged inputs of this pencil are in registers; its LDS rows are free
 #pragma unroll
-  for (int c = 0; c < 3; ++c) zfft<R, L, V, true, true>(Sp + c * LP, H[c], j, twl);
+  for (int c = 0; c < 3; ++c) zfft_c<R, L, V, true>(Sp + c * LP, H[c], j, tws);
   {
     const int S1 = P1 / 2 + 1, S3 = L / 2 + 1;
     const int f1 = k1 <= P1 / 2 ? k1 : P1 - k1;
@@ -838,25 +886,24 @@ __global__ __launch_bounds__(NP * L / V) ZCONV4_ATTR void k_zconv4(cx<R>* __rest
         const int k3 = j + T * i + (L / RAD_LAST) * q;
         const int f3 = k3 <= L / 2 ? k3 : L - k3;
         const R s3 = k3 <= L / 2 ? (R)1 : (R)-1;
-        const cx<R>* rec = sp + 6 * f3;
-        const cx<R> Txx = rec[0], Tyy = rec[1], Tzz = rec[2];
-        const cx<R> Txy = (s1 * s2) * rec[3];
-        const cx<R> Txz = (s1 * s3) * rec[4];
-        const cx<R> Tyz = (s2 * s3) * rec[5];
+        const cx<R>* rec = sp + f3;
+        const cx<R> Txx = rec[0], Tyy = rec[S3], Tzz = rec[2 * S3];
+        const cx<R> Txy = (s1 * s2) * rec[3 * S3];
+        const cx<R> Txz = (s1 * s3) * rec[4 * S3];
+        const cx<R> Tyz = (s2 * s3) * rec[5 * S3];
         const int e = i * RAD_LAST + q;
         const cx<R> x = H[0][e], y = H[1][e], z = H[2][e];
         H[0][e] = Txx * x + Txy * y + Txz * z;
         H[1][e] = Txy * x + Tyy * y + Tyz * z;
         H[2][e] = Txz * x + Tyz * y + Tzz * z;
-#ifndef ZCONV_NO_SB
+        // FP64: keep the spectral loads of one frequency at a time (fewer live registers)
         if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
-#endif
       }
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     zsync<true>();
-    zfft<R, L, V, false, true>(Sp + c * LP, H[c], j, twl);
+    zfft_c<R, L, V, false>(Sp + c * LP, H[c], j, tws);
   }
   zsync<true>();   // every exchange of this pencil is read before the outputs overwrite the rows
 #pragma unroll
@@ -867,18 +914,62 @@ __global__ __launch_bounds__(NP * L / V) ZCONV4_ATTR void k_zconv4(cx<R>* __rest
       if (n < n3) Sp[c * LP + n] = H[c][q];
     }
   __syncthreads();
-  for (int e = t; e < 3 * n3 * NP; e += NT) {
-    const int pp = e % NP, n = (e / NP) % n3, c = e / (NP * n3);
-    if (k10 + pp < P1) base[c * comp + (int64_t)n * plane + pp] = S[(pp * 3 + c) * LP + n];
-  }
+  zstage_out<R, L, NP, NT>(S, base, t, n3, plane, comp, P1 - k10);
 }
 
-#ifndef ZCONV_V64
-#define ZCONV_V64 4
+// z-pass configuration per precision (k_zconv4): the smallest number V of values per thread (a
+// pencil must also fit one wavefront, T = L / V <= 64), the threads per block, and the LDS per block
+// (staging and twiddles). Measured at 2 mm (L = 256) and 1 mm (L = 512): FP64 with four values
+// per thread, complex64 with eight; at L = 512 four pencils per block (98 KB of LDS) beat two.
+#ifndef ZCONV_VMIN64
+#define ZCONV_VMIN64 4
 #endif
-#ifndef ZCONV_FORCE3
-#define ZCONV_FORCE3 0
+#ifndef ZCONV_VMIN32
+#define ZCONV_VMIN32 8
 #endif
+#ifndef ZCONV_THREADS
+#define ZCONV_THREADS 256
+#endif
+#ifndef ZCONV_LDS_CAP
+#define ZCONV_LDS_CAP 110000
+#endif
+constexpr int zconv_v(int L, bool fp64) {
+  const int vmin = fp64 ? ZCONV_VMIN64 : ZCONV_VMIN32;
+  return L / vmin > 64 ? L / 64 : vmin;
+}
+// entries of the per-stage twiddle tables of a length-L transform with radix V stages (ZTw)
+constexpr int ztw_size(int L, int V) {
+  int lgL = 0, lgV = 0;
+  for (int x = L; x > 1; x >>= 1) ++lgL;
+  for (int x = V; x > 1; x >>= 1) ++lgV;
+  const int nst = (lgL + lgV - 1) / lgV;
+  int rads[16] = {};
+  int r = 1;
+  for (int i = 0; i + 1 < nst; ++i) {
+    rads[i] = V;
+    r *= V;
+  }
+  rads[nst - 1] = L / r;
+  int tot = 0, ls = 1;
+  for (int s = 0; s + 1 < nst; ++s) tot += (ls *= rads[s]);
+  ls = 1;
+  for (int u = 0; u + 1 < nst; ++u) tot += (ls *= rads[nst - 1 - u]);
+  return tot;
+}
+static_assert(ztw_size(64, 4) == ZTw<64, 4>::size() && ztw_size(128, 4) == ZTw<128, 4>::size() &&
+                  ztw_size(256, 4) == ZTw<256, 4>::size() && ztw_size(512, 8) == ZTw<512, 8>::size() &&
+                  ztw_size(1024, 16) == ZTw<1024, 16>::size() && ztw_size(128, 8) == ZTw<128, 8>::size(),
+              "twiddle table sizes");
+constexpr int zconv_np(int L, bool fp64) {
+  const int T = L / zconv_v(L, fp64);
+  int np = ZCONV_THREADS / T;
+  if (np < 1) np = 1;
+  const int elem = fp64 ? 16 : 8;
+  const int tws = ztw_size(L, zconv_v(L, fp64));
+  while (np > 1 && (np * 3 * (L + 1) + tws) * elem > ZCONV_LDS_CAP) np /= 2;
+  return np;
+}
+
 template <int L> struct Split;
 template <> struct Split<8> { static constexpr int A = 4, B = 2; };
 template <> struct Split<16> { static constexpr int A = 4, B = 4; };
@@ -949,7 +1040,7 @@ void fft_strided(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, i
 
 int zconv_pencils(int L, bool fp64) {
   if (L < 64 || L > 1024) return 0;
-  return 256 * (fp64 ? ZCONV_V64 : 8) / L;
+  return zconv_np(L, fp64);
 }
 
 std::vector<int> zconv_order(int L, int P1, int P2, bool fp64) {
@@ -1005,22 +1096,17 @@ std::vector<int> zconv_order(int L, int P1, int P2, bool fp64) {
 template <typename R>
 void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const cx<R>* spec, const cx<R>* tw,
                 const int* order) {
-  // register-staged Stockham variant: V values per thread and component, 256 threads per block
+  // register-staged Stockham transform: V values per thread and component, one pencil per group
   if (L >= 64 && L <= 1024) {
     if (!order) throw Error(VSIE_E_STATE, "z-pass block order missing");
     VSIE_FFT_SWITCH(L, {
       if constexpr (LL >= 64) {
-        constexpr int V = sizeof(R) == 8 ? ZCONV_V64 : 8;
-        constexpr int NP = 256 * V / LL;
+        constexpr bool F64 = sizeof(R) == 8;
+        constexpr int V = zconv_v(LL, F64);
+        constexpr int NP = zconv_np(LL, F64);
         dim3 grid((unsigned)(P2 * ((P1 + NP - 1) / NP)));
-        // FP64: one pencil per wavefront (measured faster at 2 mm); complex64: pencils across the
-        // block's wavefronts
-        if constexpr (LL / V <= 64 && sizeof(R) == 8 && !ZCONV_FORCE3)
-          hipLaunchKernelGGL((k_zconv4<R, LL, V, NP>), grid, dim3(NP * LL / V), 0, st, buf, n3, P1, P2, spec, tw,
-                             order);
-        else
-          hipLaunchKernelGGL((k_zconv3<R, LL, V, NP>), grid, dim3(NP * LL / V), 0, st, buf, n3, P1, P2, spec, tw,
-                             order);
+        hipLaunchKernelGGL((k_zconv4<R, LL, V, NP>), grid, dim3(NP * LL / V), 0, st, buf, n3, P1, P2, spec, tw,
+                           order);
       }
     });
     return;

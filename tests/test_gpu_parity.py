@@ -223,6 +223,28 @@ def test_body_only_volume_operator():
     assert rel(xs.cpu().numpy(), S.solve(b)) < 1e-8
 
 
+@pytest.mark.parametrize("n", [(4, 5, 20), (6, 5, 33), (3, 3, 65), (2, 2, 129), (1, 1, 257)])
+def test_z_pass_lengths(lib, n):
+    """Body-only product on boxes whose z extent selects each fused z-pass length P3 = 64, 128,
+    256, 512, 1024 (P1 = 8 is below the pencils per block at the two shortest lengths, so the
+    pencil tiles are ragged): FP64 at 1e-10 and complex64 at 1e-5 against the dense Galerkin
+    matrix."""
+    g = synth.random_block(n, 5e-3, seed=sum(n))
+    p = synth.Problem(g, [], synth.problems.LARMOR_7T_HZ, "block")
+    op = lib.Operator(p)
+    d = system.discretize(p)
+    S, _ = system.assemble_direct(d)
+    x = synth.complex_normal(op.N, 11)
+    ref = S.matvec(x)
+    e64 = rel(op.matvec(to_dev(x)).cpu().numpy(), ref)
+    y32 = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+    e32 = rel(y32, ref)
+    print("z-pass box %s: FP64 %.2e, complex64 %.2e" % (n, e64, e32))
+    op.close()
+    assert e64 < 1e-10
+    assert e32 < 1e-5
+
+
 def test_tt_cross_accuracy_against_brute_force():
     """Product TT-cross cores (eq. (14)) against the oracle's brute-force far coupling tensor."""
     import paper_2206_12409_amd as pkg

@@ -14,13 +14,13 @@ Conventions shared by every consumer:
     orientation; ports are directed vertex pairs ``(a, b)`` of interior edges plus a port id;
     positive port current flows out of the triangle that lists ``a`` then ``b`` in cyclic order.
 """
-from .phantoms import Grid, sphere_phantom, head_phantom
+from .phantoms import Grid, sphere_phantom, head_phantom, random_block
 from .meshes import Mesh, strip_loop_flat, strip_loop_on_cylinder, loop_array, cylinder_shield
 from .vectors import complex_normal
 from .problems import Problem, tiny_case, two_mm_case, one_mm_case, small_case, mie_case
 
 __all__ = [
-    "Grid", "sphere_phantom", "head_phantom", "Mesh", "strip_loop_flat", "strip_loop_on_cylinder",
+    "Grid", "sphere_phantom", "head_phantom", "random_block", "Mesh", "strip_loop_flat", "strip_loop_on_cylinder",
     "loop_array", "cylinder_shield", "complex_normal", "Problem", "tiny_case", "two_mm_case",
     "small_case", "mie_case", "one_mm_case",
 ]

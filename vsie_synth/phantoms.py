@@ -48,6 +48,17 @@ def sphere_phantom(n=(16, 16, 16), h=5e-3, radius=35e-3, eps_r=52.0, sigma=0.55)
     return g
 
 
+def random_block(n, h=5e-3, seed=0):
+    """Every voxel of an n-voxel box is tissue with eps_r ~ U[1.5, 80] and sigma ~ U[0, 0.9] S/m
+    (seeded): a body with no air, for grids of any shape."""
+    n = tuple(int(v) for v in n)
+    rng = np.random.default_rng(seed)
+    origin = -0.5 * h * np.array(n, dtype=np.float64)
+    eps = 1.5 + 78.5 * rng.random(n[::-1])
+    sig = 0.9 * rng.random(n[::-1])
+    return Grid(n, float(h), origin, eps, sig, np.ones(n[::-1], np.int32))
+
+
 def head_phantom(seed, n=(96, 112, 128), h=2e-3):
     """Five nested seeded ellipsoids, labels 1..5 from outside in, air outside.
 
