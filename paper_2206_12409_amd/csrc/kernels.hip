@@ -460,8 +460,8 @@ __global__ __launch_bounds__(256) void k_fft_z_conv(cx<R>* __restrict__ buf, int
 // Two-level register FFT of length L = A * B (A >= B): thread j < B loads x[j + B m], m < A, and
 // transforms over m in registers; after the twiddle w_L^(j k1) one LDS transpose hands thread
 // k1 < A the values over j, which it transforms in registers to X[k1 + A k2]. Global loads and
-// stores go straight from/to registers; the transpose is the only LDS traffic (conflict-free with
-// the A+1 row padding).
+// stores go straight from/to registers; the transpose is the only LDS traffic (its padding is
+// chosen per lane layout to keep the banks apart).
 __host__ __device__ constexpr int bitrev_of(int m, int n) {
   int r = 0;
   for (int b = 1, hi = n >> 1; b < n; b <<= 1, hi >>= 1)
@@ -497,7 +497,12 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
                                                  int64_t in_hi, int64_t out_hi, int64_t nrows,
                                                  const cx<R>* __restrict__ tw) {
   constexpr int L = A * B;
-  __shared__ cx<R> S[NP * B * (A + 1)];
+  // transpose rows of RS and pencils PS apart (16-byte slots). Row-major pencils (lanes along a
+  // pencil) need only the row padding; the strided form's lanes run across pencils, so their
+  // offset is skewed too, which keeps its transpose stores and loads off shared banks
+  constexpr int RS = A + (STRIDED ? (NP >= 16 ? 0 : (NP == 8 ? 8 : 4)) : 1);
+  constexpr int PS = B * RS + (STRIDED ? (NP >= 8 ? 1 : 3) : 0);
+  __shared__ cx<R> S[(NP - 1) * PS + B * RS];
   __shared__ cx<R> twl[L];   // twiddles staged once per block
   const int t = threadIdx.x;
   for (int k = t; k < L; k += NP * A) twl[k] = tw[k];
@@ -523,7 +528,7 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
     ib = in + row * in_hi;
     ob = out + row * out_hi;
   }
-  cx<R>* Sp = S + p * B * (A + 1);
+  cx<R>* Sp = S + p * PS;
   if (u < B) {
     const int j = u;
     cx<R> v[A];
@@ -537,7 +542,7 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
     for (int k1 = 0; k1 < A; ++k1) {
       cx<R> w = twl[(j * k1) & (L - 1)];
       if (!FWD) w.im = -w.im;
-      Sp[j * (A + 1) + k1] = (k1 == 0) ? v[k1] : v[k1] * w;
+      Sp[j * RS + k1] = (k1 == 0) ? v[k1] : v[k1] * w;
     }
   }
   __syncthreads();
@@ -545,7 +550,7 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
     const int k1 = u;
     cx<R> v[B];
 #pragma unroll
-    for (int j = 0; j < B; ++j) v[bitrev_of(j, B)] = Sp[j * (A + 1) + k1];
+    for (int j = 0; j < B; ++j) v[bitrev_of(j, B)] = Sp[j * RS + k1];
     reg_dft<R, B, L, FWD>(v, twl);
 #pragma unroll
     for (int k2 = 0; k2 < B; ++k2) {
