@@ -50,10 +50,12 @@ def stage_bytes(info, s):
         "aca": 2 * c * (mf + mn) * info["aca_rank"],
     }
     r = info["tt_rank"]
-    # per component: x-only part reads G4 (with x_f), the merged first-two-core block and x_b;
-    # the accumulation part reads G4 and the merged block again and updates y_b
-    b["tt_pre"] = sum(c * (r[a][2] * mf + r[a][1] * n1 * n2 + nv) for a in range(3))
-    b["tt_post"] = sum(c * (r[a][2] * mf + r[a][1] * n1 * n2 + 2 * nv) for a in range(3))
+    # tt_pre, per component: x_b and each of the four cores once (G4 serves the forward and the
+    # transpose products in one pass), plus x_f read and y_f updated once; tt_post, per component:
+    # the first two cores and the read-modify-write of y_b
+    b["tt_pre"] = sum(c * (nv + n1 * r[a][0] + r[a][0] * n2 * r[a][1] + r[a][1] * n3 * r[a][2] + r[a][2] * mf)
+                      for a in range(3)) + c * 3 * mf
+    b["tt_post"] = sum(c * (2 * nv + n1 * r[a][0] + r[a][0] * n2 * r[a][1]) for a in range(3))
     return b.get(s)
 
 

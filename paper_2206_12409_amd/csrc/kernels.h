@@ -57,6 +57,10 @@ template <typename R> void launch_lr_t(hipStream_t st, bool conj, const cx<R>* A
                                        cx<R>* part, int max_chunks, cx<R>* out);
 template <typename R> void launch_lr_n_add(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* t, int64_t M,
                                            int K, cx<R>* y);
+// one pass over V (K x M): out = V^H x and y += conj(V)^T s; part holds lr_dual_part_elems(M)
+template <typename R> void launch_lr_dual(hipStream_t st, const cx<R>* V, int K, int64_t M, const cx<R>* x,
+                                          const cx<R>* s, cx<R>* y, cx<R>* part, cx<R>* out);
+int64_t lr_dual_part_elems(int64_t M);
 template <typename R> void launch_gemv_rows(hipStream_t st, const cx<R>* A, const cx<R>* x, int64_t nrow, int64_t ncol,
                                             cx<R>* out, int accumulate);
 // Batched strided complex GEMM, C(i,j) = sum_k A(i,k) B(k,j), with element (i,j) of batch b at
@@ -87,19 +91,22 @@ template <typename R> struct GemmSet {
 template <typename R> void launch_zgemm(hipStream_t st, const GemmSet<R>& S);
 
 constexpr int TT_RMAX = 128;
-constexpr int TT_KCHUNK = 128;  // split-K chunk of the transpose contraction over n1 n2
+constexpr int TT_KBATCH = 64;   // most split-K batches of the transpose contraction over (j1, i2)
 template <typename R> struct TTDesc {
-  const cx<R>* M[3];    // merged first two cores, [r2][n1 n2]
+  const cx<R>* G1[3];   // [n1][r1]
+  const cx<R>* G2[3];   // [r1][n2][r2]
   const cx<R>* G3[3];   // [r2][n3][r3]
   const cx<R>* G4[3];   // [r3][m_f]
-  int r2[3], r3[3];
+  int r1[3], r2[3], r3[3];
 };
-// forward and transpose far coupling of all three components: y_b += mask Zt x_f,
-// y_f += sum_c Zt_c^T (mask x_b)
+// forward and transpose far coupling of all three components, y_b += mask Zt x_f and
+// y_f += sum_c Zt_c^T (mask x_b): launch_tt_pre reads x, adds the transpose into y_f (which must
+// already hold the rest of its product) and leaves the forward intermediates in the work buffer;
+// launch_tt_post adds the forward part into y_b
 template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
-                                         const cx<R>* xb, const uint8_t* mask, cx<R>* work);
+                                         const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* work);
 template <typename R> void launch_tt_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
-                                          const uint8_t* mask, cx<R>* yf, cx<R>* yb, const cx<R>* work);
+                                          const uint8_t* mask, cx<R>* yb, cx<R>* work);
 // the halves used by the reduced (far-eliminated) operator: the transpose chain alone (s3 at the
 // start of the work buffer), the forward chain from given rank vectors u3[c][TT_RMAX] instead of
 // G4 x_f, and the forward accumulation into y_b alone
@@ -108,7 +115,7 @@ template <typename R> void launch_tt_transpose_pre(hipStream_t st, const TTDesc<
 template <typename R> void launch_tt_forward_from(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
                                                   const cx<R>* u3, cx<R>* work);
 template <typename R> void launch_tt_forward_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
-                                                  const uint8_t* mask, cx<R>* yb, const cx<R>* work);
+                                                  const uint8_t* mask, cx<R>* yb, cx<R>* work);
 int64_t tt_work_elems(const int n[3], int mf);
 // y = Z x for the symmetric far block stored as upper-triangle tiles (part: 2 SYM_TB per tile)
 template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,

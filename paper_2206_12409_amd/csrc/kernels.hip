@@ -1277,6 +1277,104 @@ __global__ __launch_bounds__(256) void k_lr_n_add(const cx<R>* __restrict__ A, c
                   (ri[0][row] + ri[1][row]) + (ri[2][row] + ri[3][row])};
 }
 
+// Both products with a row-major block of rows in one pass over it: for every row l (flattened
+// over up to three blocks A_b [nrows_b][m], row r of block b at l = off_b + r) the partial sums
+// part[blk][l] = sum over the workgroup's columns i of op(A[l][i]) x[i], and the column sums
+// ypart[g][i] = sum over row group g of op(A[l][i]) s[l] (op = conj if CONJ; y += sum_g ypart[g]
+// afterwards). Each element is read once. A workgroup of 16 wavefronts covers DUAL_COLS columns
+// (DUAL_CPL per lane, 64 apart, so that a row's lane sums cover several columns before they are
+// combined across the wavefront) and one of DUAL_RG row groups: wavefront w of group g takes rows
+// 16 g + w + 16 DUAL_RG k. s holds at most DUAL_MAXROWS entries.
+constexpr int DUAL_CPL = 4;
+constexpr int DUAL_COLS = 64 * DUAL_CPL;
+constexpr int DUAL_RG = 2;
+constexpr int DUAL_MAXROWS = 384;
+template <typename R> struct DualRows {
+  const cx<R>* A[3];
+  int nrows[3];
+  int off[3];
+  int nblock;
+};
+template <typename R, bool CONJ>
+__global__ __launch_bounds__(1024) void k_dual_rows(DualRows<R> D, const cx<R>* __restrict__ x,
+                                                    const cx<R>* __restrict__ s, int64_t m,
+                                                    cx<R>* __restrict__ ypart, cx<R>* __restrict__ part, int pstride) {
+  __shared__ cx<R> sv[DUAL_MAXROWS];
+  __shared__ R yr[16][DUAL_COLS], yi[16][DUAL_COLS];
+  const int t = threadIdx.x;
+  for (int l = t; l < pstride; l += 1024) sv[l] = s[l];
+  __syncthreads();
+  const int lane = t % 64, w = t / 64, g = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * DUAL_COLS + lane;
+  cx<R> xv[DUAL_CPL], ya[DUAL_CPL];
+#pragma unroll
+  for (int q = 0; q < DUAL_CPL; ++q) {
+    const int64_t i = i0 + 64 * q;
+    xv[q] = i < m ? x[i] : cx<R>{0, 0};
+    ya[q] = cx<R>{0, 0};
+  }
+  int nr = 0;
+  for (int b = 0; b < D.nblock; ++b) nr += D.nrows[b];
+  for (int r = 16 * g + w; r < nr; r += 16 * DUAL_RG) {
+    int b = 0, rr = r;
+    while (b + 1 < D.nblock && rr >= D.nrows[b]) rr -= D.nrows[b++];
+    const int l = D.off[b] + rr;
+    const cx<R>* a = D.A[b] + (int64_t)rr * m;
+    const cx<R> sl = sv[l];
+    cx<R> av[DUAL_CPL];
+#pragma unroll
+    for (int q = 0; q < DUAL_CPL; ++q) {
+      const int64_t i = i0 + 64 * q;
+      av[q] = i < m ? a[i] : cx<R>{0, 0};
+    }
+    cx<R> pr = {0, 0};
+#pragma unroll
+    for (int q = 0; q < DUAL_CPL; ++q) {
+      if (CONJ) {
+        pr += mul_conj_a(av[q], xv[q]);
+        ya[q] += mul_conj_a(av[q], sl);
+      } else {
+        pr += av[q] * xv[q];
+        ya[q] += av[q] * sl;
+      }
+    }
+    R re = pr.re, im = pr.im;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      re += __shfl_xor(re, o, 64);
+      im += __shfl_xor(im, o, 64);
+    }
+    if (lane == 0) part[(int64_t)blockIdx.x * pstride + l] = cx<R>{re, im};
+  }
+#pragma unroll
+  for (int q = 0; q < DUAL_CPL; ++q) {
+    yr[w][lane + 64 * q] = ya[q].re;
+    yi[w][lane + 64 * q] = ya[q].im;
+  }
+  __syncthreads();
+  if (t < DUAL_COLS) {
+    const int64_t i = (int64_t)blockIdx.x * DUAL_COLS + t;
+    if (i < m) {
+      cx<R> acc = {0, 0};
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc += cx<R>{yr[q][t], yi[q][t]};
+      ypart[(int64_t)g * m + i] = acc;
+    }
+  }
+}
+
+// y[i] += sum_g ypart[g][i], g < DUAL_RG
+template <typename R>
+__global__ __launch_bounds__(256) void k_dual_finish(const cx<R>* __restrict__ ypart, int64_t m, cx<R>* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  cx<R> acc = y[i];
+#pragma unroll
+  for (int g = 0; g < DUAL_RG; ++g) acc += ypart[(int64_t)g * m + i];
+  y[i] = acc;
+}
+
+
 // out[l] = sum_b part[b][l]: one block per column, tree reduction
 template <typename R>
 __global__ __launch_bounds__(256) void k_sum_partials(const cx<R>* __restrict__ part, int nblk, int K,
@@ -1297,6 +1395,17 @@ __global__ __launch_bounds__(256) void k_sum_partials(const cx<R>* __restrict__ 
   }
   if (threadIdx.x == 0) out[l] = cx<R>{rr[0], ri[0]};
 }
+
+// the launches of one pass: partial sums of part (nblk x pstride) into out, y += column sums
+template <typename R, bool CONJ>
+static void launch_dual(hipStream_t st, const DualRows<R>& D, const cx<R>* x, const cx<R>* s, int64_t m, cx<R>* y,
+                        cx<R>* ypart, cx<R>* part, int pstride, cx<R>* out) {
+  const unsigned nb = (unsigned)((m + DUAL_COLS - 1) / DUAL_COLS);
+  hipLaunchKernelGGL((k_dual_rows<R, CONJ>), dim3(nb, DUAL_RG), dim3(1024), 0, st, D, x, s, m, ypart, part, pstride);
+  hipLaunchKernelGGL(k_dual_finish<R>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, ypart, m, y);
+  hipLaunchKernelGGL(k_sum_partials<R>, dim3(pstride), dim3(256), 0, st, part, (int)nb, pstride, out);
+}
+int64_t dual_work_elems(int64_t m) { return ((m + DUAL_COLS - 1) / DUAL_COLS) * DUAL_MAXROWS + DUAL_RG * m; }
 
 // one block per row: out[row] = sum_j A[row][j] x[j]  (dense GEMV, row-major, write)
 template <typename R>
@@ -1655,20 +1764,21 @@ __global__ __launch_bounds__(256) void k_symv_multi(const cx<R>* __restrict__ Zp
   }
 }
 
-// s2[c][j2][i3] = sum_b part[c][b][j2][i3]  (split-K reduction of the transpose contraction);
-// a block covers 32 outputs with 8 slices over b
+// s2[c][j2][i3] = sum_b part[c][b][j2][i3], b < nb_c = ceil(r1_c n2 / kc) (split-K reduction of
+// the transpose contraction over (j1, i2)); a block covers 32 outputs with 8 slices over b
 template <typename R>
-__global__ __launch_bounds__(256) void k_tt_ksum(TTDesc<R> T, const cx<R>* __restrict__ part, int nkc, int n3,
+__global__ __launch_bounds__(256) void k_tt_ksum(TTDesc<R> T, const cx<R>* __restrict__ part, int kc, int n2, int n3,
                                                  cx<R>* __restrict__ s2) {
   __shared__ R rr[8][32], ri[8][32];
   const int c = blockIdx.y;
   const int o = threadIdx.x % 32, sl = threadIdx.x / 32;
   const int id = blockIdx.x * 32 + o;
   const bool live = id < T.r2[c] * n3;
+  const int nb = (T.r1[c] * n2 + kc - 1) / kc;
   cx<R> acc = {0, 0};
   if (live) {
-    const cx<R>* p = part + (int64_t)c * nkc * TT_RMAX * n3 + id;
-    for (int b = sl; b < nkc; b += 8) acc += p[(int64_t)b * TT_RMAX * n3];
+    const cx<R>* p = part + (int64_t)c * TT_KBATCH * TT_RMAX * n3 + id;
+    for (int b = sl; b < nb; b += 8) acc += p[(int64_t)b * TT_RMAX * n3];
   }
   rr[sl][o] = acc.re;
   ri[sl][o] = acc.im;
@@ -1682,68 +1792,100 @@ __global__ __launch_bounds__(256) void k_tt_ksum(TTDesc<R> T, const cx<R>* __res
 }
 
 // ---------------------------------------------------------------------------------------------
-// Tensor-train far coupling (eqs. (16)-(19)). Cores row-major: G3[j2][i3][j3], G4[j3][i4]; the
-// first two cores are held contracted, M[j2][p] = sum_j1 G1[i1][j1] G2[j1][i2][j2] with
-// p = i1 + n1 i2 (n1 n2 r2 entries, a few MB). Intermediates per component:
-//   forward   t4[j3] -> t3[j2][i3] -> y_b[p + n1 n2 i3] += mask * sum_j2 M[j2][p] t3[j2][i3]
-//   transpose S2[j2][i3] = sum_p M[j2][p] mask x_b[p + n1 n2 i3] -> s3[j3] -> y_f[i4]
+// Tensor-train far coupling (eqs. (16)-(19)). Cores row-major: G1[i1][j1], G2[j1][i2][j2],
+// G3[j2][i3][j3], G4[j3][i4]. The body index is i1 + n1 i2 + n1 n2 i3 = i1 + n1 row with
+// row = i2 + n2 i3. Intermediates per component, contracted one core at a time so that the work
+// on the body-sized vectors costs r1 products per voxel (the smallest rank):
+//   forward   t4[j3] -> t3[j2][i3] -> U[i3][j1][i2] = sum_j2 G2[j1][i2][j2] t3[j2][i3]
+//             -> y_b[i1 + n1 row] += mask * sum_j1 G1[i1][j1] U[i3][j1][i2]
+//   transpose T1[i3][j1][i2] = sum_i1 G1[i1][j1] mask x_b[i1 + n1 row]
+//             -> S2[j2][i3] = sum_(j1, i2) G2[j1][i2][j2] T1[i3][j1][i2] -> s3[j3] -> y_f[i4]
 
-// forward, G4 first: part[c][j3][chunk] = sum_{i4 in chunk} G4[j3][i4] x_f[i4]
-constexpr int TT_F4_RB = 4;        // ranks per block of the G4 x_f partial sums
-constexpr int TT_F4_CHUNK = 2048;  // far currents per block
+// T1 on the matrix cores: a wavefront owns 16 rows (the MFMA's columns) and a 16-wide tile of j1
+// (its rows), K = i1 in steps of 4; operands straight from memory (x_b is read once, G1 is a few
+// KB and stays in cache). t1 points at component 0; components are t1_cs apart.
 template <typename R>
-__global__ __launch_bounds__(256) void k_tt_f4(TTDesc<R> T, const cx<R>* __restrict__ xf, int mf, int chunk,
-                                               cx<R>* __restrict__ part, int nchunk) {
-  // partial sums of G4[c][j3] . x_f over one chunk of the far currents, TT_F4_RB ranks per block
-  // (each x_f value loaded once for all of them)
-  constexpr int RB = TT_F4_RB;
-  __shared__ R rr[RB][4], ri[RB][4];
-  const int c = blockIdx.z, j0 = blockIdx.y * RB, ch = blockIdx.x;
-  const int r3 = T.r3[c];
-  cx<R> acc[RB];
+__global__ __launch_bounds__(256) void k_tt_t1(TTDesc<R> T, const cx<R>* __restrict__ xb,
+                                               const uint8_t* __restrict__ mask, int n1, int n2, int rows, int64_t nv,
+                                               cx<R>* __restrict__ t1, int64_t t1_cs) {
+  using MM = Mfma16<R>;
+  using V = typename MM::V;
+  const int c = blockIdx.y;
+  const int r1 = T.r1[c];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int row0 = (blockIdx.x * 4 + wave) * 16;
+  if (row0 >= rows) return;   // the whole wavefront leaves
+  const int li = lane % 16, lk = lane / 16;
+  const int row = row0 + li;
+  const bool rv = row < rows;
+  const cx<R>* xr = xb + (int64_t)c * nv + (int64_t)(rv ? row : 0) * n1;
+  const uint8_t* mr = mask + (int64_t)(rv ? row : 0) * n1;
+  const cx<R>* g1 = T.G1[c];
+  const int i3 = row / n2, i2 = row - (row / n2) * n2;
+  cx<R>* out = t1 + (int64_t)c * t1_cs + (int64_t)i3 * r1 * n2 + i2;
+  constexpr int KB = 8;   // K-steps whose operands are loaded together (loads in flight)
+  for (int jt = 0; jt < r1; jt += 16) {
+    const int ja = jt + li;   // the A row this lane supplies
+    V dr = V{0, 0, 0, 0}, di = V{0, 0, 0, 0};
+    for (int kb = 0; kb < n1; kb += 4 * KB) {
+      cx<R> a[KB], b[KB];
+      uint8_t mk[KB];
 #pragma unroll
-  for (int q = 0; q < RB; ++q) acc[q] = cx<R>{0, 0};
-  const int i0 = ch * chunk, i1 = min(mf, i0 + chunk);
-  for (int i = i0 + threadIdx.x; i < i1; i += 256) {
-    const cx<R> xv = xf[i];
+      for (int q = 0; q < KB; ++q) {
+        const int i1 = kb + 4 * q + lk;
+        const bool in = i1 < n1;
+        a[q] = (ja < r1 && in) ? g1[(int64_t)i1 * r1 + ja] : cx<R>{0, 0};
+        b[q] = (rv && in) ? xr[i1] : cx<R>{0, 0};
+        mk[q] = (rv && in) ? mr[i1] : 0;
+      }
 #pragma unroll
-    for (int q = 0; q < RB; ++q)
-      if (j0 + q < r3) acc[q] += T.G4[c][(int64_t)(j0 + q) * mf + i] * xv;
-  }
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-#pragma unroll
-  for (int q = 0; q < RB; ++q) {
-    R re = acc[q].re, im = acc[q].im;
-    for (int off = 32; off > 0; off >>= 1) {
-      re += __shfl_down(re, off, 64);
-      im += __shfl_down(im, off, 64);
+      for (int q = 0; q < KB; ++q) {
+        const cx<R> bb = mk[q] ? b[q] : cx<R>{0, 0};
+        dr = MM::mma(a[q].re, bb.re, dr);
+        dr = MM::mma(-a[q].im, bb.im, dr);
+        di = MM::mma(a[q].re, bb.im, di);
+        di = MM::mma(a[q].im, bb.re, di);
+      }
     }
-    if (lane == 0) {
-      rr[q][wave] = re;
-      ri[q][wave] = im;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < RB && j0 + (int)threadIdx.x < r3) {
-    const int q = threadIdx.x;
-    part[((int64_t)c * TT_RMAX + j0 + q) * nchunk + ch] =
-        cx<R>{(rr[q][0] + rr[q][1]) + (rr[q][2] + rr[q][3]), (ri[q][0] + ri[q][1]) + (ri[q][2] + ri[q][3])};
+    if (rv)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j1 = jt + MM::row(lane, v);
+        if (j1 < r1) out[(int64_t)j1 * n2] = cx<R>{dr[v], di[v]};
+      }
   }
 }
 
-// t3[c][row] = sum_j3 G3[row][j3] t4[j3] over rows (j2, i3) of G3; t4 summed from the partials
-// into LDS first; 16 lanes per row read it contiguously, 16 rows per block
+// y_b[c][i1 + n1 row] += mask * sum_j1 G1[c][i1][j1] U[c][i3][j1][i2], one voxel per thread
+// (consecutive threads on consecutive voxels: coalesced read-modify-write of y_b)
 template <typename R>
-__global__ __launch_bounds__(256) void k_tt_f3(TTDesc<R> T, const cx<R>* __restrict__ part, int nchunk, int n3,
+__global__ __launch_bounds__(256) void k_tt_yb(TTDesc<R> T, const cx<R>* __restrict__ u, int64_t u_cs,
+                                               const uint8_t* __restrict__ mask, int n1, int n2, int nv,
+                                               cx<R>* __restrict__ yb) {
+  const int c = blockIdx.y;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nv || !mask[e]) return;
+  const unsigned row = (unsigned)e / (unsigned)n1;
+  const int i1 = e - (int)row * n1;
+  const unsigned i3 = row / (unsigned)n2;
+  const int i2 = (int)row - (int)i3 * n2;
+  const int r1 = T.r1[c];
+  const cx<R>* g = T.G1[c] + (int64_t)i1 * r1;
+  const cx<R>* uc = u + (int64_t)c * u_cs + (int64_t)i3 * r1 * n2 + i2;
+  cx<R> acc = {0, 0};
+  for (int j1 = 0; j1 < r1; ++j1) acc += g[j1] * uc[(int64_t)j1 * n2];
+  yb[(int64_t)c * nv + e] += acc;
+}
+
+// t3[c][row] = sum_j3 G3[row][j3] t4v[c][j3] over rows (j2, i3) of G3; t4 staged in LDS; 16 lanes
+// per row read it contiguously, 16 rows per block
+template <typename R>
+__global__ __launch_bounds__(256) void k_tt_f3(TTDesc<R> T, const cx<R>* __restrict__ t4v, int n3,
                                                cx<R>* __restrict__ t3) {
   __shared__ cx<R> t4[TT_RMAX];
   const int c = blockIdx.y;
   const int r2 = T.r2[c], r3 = T.r3[c];
-  for (int j3 = threadIdx.x; j3 < r3; j3 += 256) {
-    cx<R> acc = {0, 0};
-    for (int ch = 0; ch < nchunk; ++ch) acc += part[((int64_t)c * TT_RMAX + j3) * nchunk + ch];
-    t4[j3] = acc;
-  }
+  for (int j3 = threadIdx.x; j3 < r3; j3 += 256) t4[j3] = t4v[c * TT_RMAX + j3];
   __syncthreads();
   const int row = blockIdx.x * 16 + threadIdx.x / 16;
   const int lane = threadIdx.x % 16;
@@ -1761,7 +1903,7 @@ __global__ __launch_bounds__(256) void k_tt_f3(TTDesc<R> T, const cx<R>* __restr
 
 // partial sums of s3[c][j3] = sum_k G3[k][j3] S2[c][k] over rows k = (j2, i3) of G3, TT_KROWS rows
 // per block: part[blk][c TT_RMAX + j3] (zero for j3 >= r3)
-constexpr int TT_KROWS = 64;
+constexpr int TT_KROWS = 16;
 template <typename R>
 __global__ __launch_bounds__(256) void k_ttT_3(TTDesc<R> T, const cx<R>* __restrict__ s2, int n3,
                                                cx<R>* __restrict__ part) {
@@ -1775,7 +1917,11 @@ __global__ __launch_bounds__(256) void k_ttT_3(TTDesc<R> T, const cx<R>* __restr
   for (int j3 = lane; j3 < TT_RMAX; j3 += 64) {
     cx<R> acc = {0, 0};
     if (j3 < r3)
-      for (int k = k0 + sl; k < k0 + TT_KROWS && k < K; k += 4) acc += T.G3[c][(int64_t)k * r3 + j3] * sv[k];
+#pragma unroll
+      for (int q = 0; q < TT_KROWS / 4; ++q) {
+        const int k = k0 + sl + 4 * q;
+        if (k < K) acc += T.G3[c][(int64_t)k * r3 + j3] * sv[k];
+      }
     rr[sl][j3] = acc.re;
     ri[sl][j3] = acc.im;
   }
@@ -1783,33 +1929,6 @@ __global__ __launch_bounds__(256) void k_ttT_3(TTDesc<R> T, const cx<R>* __restr
   for (int j3 = threadIdx.x; j3 < TT_RMAX; j3 += 256)
     part[(int64_t)blockIdx.x * 3 * TT_RMAX + c * TT_RMAX + j3] =
         cx<R>{(rr[0][j3] + rr[1][j3]) + (rr[2][j3] + rr[3][j3]), (ri[0][j3] + ri[1][j3]) + (ri[2][j3] + ri[3][j3])};
-}
-
-// y_f[i4] += sum_c sum_j3 G4[c][j3][i4] s3[c][j3]; 64 rows per block, four wavefronts split j3
-template <typename R>
-__global__ __launch_bounds__(1024) void k_ttT_4(TTDesc<R> T, const cx<R>* __restrict__ s3, int mf,
-                                                cx<R>* __restrict__ yf) {
-  // y_f[i] += sum_c sum_j3 G4[c][j3][i] s3[c][j3]: 64 far currents per block, sixteen wavefronts
-  // taking every sixteenth rank
-  __shared__ cx<R> sv[3 * TT_RMAX];
-  __shared__ R rr[16][64], ri[16][64];
-  for (int l = threadIdx.x; l < 3 * TT_RMAX; l += 1024) sv[l] = s3[l];
-  __syncthreads();
-  const int row = threadIdx.x % 64, sl = threadIdx.x / 64;
-  const int64_t i = (int64_t)blockIdx.x * 64 + row;
-  cx<R> acc = {0, 0};
-  if (i < mf)
-    for (int c = 0; c < 3; ++c)
-      for (int j3 = sl; j3 < T.r3[c]; j3 += 16) acc += T.G4[c][(int64_t)j3 * mf + i] * sv[c * TT_RMAX + j3];
-  rr[sl][row] = acc.re;
-  ri[sl][row] = acc.im;
-  __syncthreads();
-  if (sl == 0 && i < mf) {
-    cx<R> s = {0, 0};
-#pragma unroll
-    for (int q = 0; q < 16; ++q) s += cx<R>{rr[q][row], ri[q][row]};
-    yf[i] += s;
-  }
 }
 
 // =============================================================================================
@@ -1994,6 +2113,19 @@ template <typename R> void launch_lr_t(hipStream_t st, bool conj, const cx<R>* A
     hipLaunchKernelGGL((k_lr_t_partial<R, false>), dim3(nch, K), dim3(256), 0, st, A, x, M, K, chunk, part);
   hipLaunchKernelGGL(k_sum_partials<R>, dim3(K), dim3(256), 0, st, part, nch, K, out);
 }
+template <typename R> void launch_lr_dual(hipStream_t st, const cx<R>* V, int K, int64_t M, const cx<R>* x,
+                                          const cx<R>* s, cx<R>* y, cx<R>* work, cx<R>* out) {
+  if (K <= 0 || M <= 0) return;
+  if (K > 256) throw Error(VSIE_E_ARG, "low-rank factor wider than 256 columns");
+  DualRows<R> D{};
+  D.nblock = 1;
+  D.A[0] = V;
+  D.nrows[0] = K;
+  cx<R>* ypart = work;
+  cx<R>* part = work + DUAL_RG * M;
+  launch_dual<R, true>(st, D, x, s, M, y, ypart, part, K, out);
+}
+int64_t lr_dual_part_elems(int64_t M) { return dual_work_elems(M); }
 template <typename R> void launch_lr_n_add(hipStream_t st, bool conj, const cx<R>* A, const cx<R>* t, int64_t M,
                                            int K, cx<R>* y) {
   if (M <= 0 || K <= 0) return;
@@ -2007,68 +2139,97 @@ template <typename R> void launch_gemv_rows(hipStream_t st, const cx<R>* A, cons
                                             cx<R>* out, int accumulate) {
   if (nrow > 0) hipLaunchKernelGGL(k_gemv_rows<R>, dim3((unsigned)nrow), dim3(256), 0, st, A, x, ncol, out, accumulate);
 }
-// TT work layout: part (3 RMAX nchunk; later s3) | t3 (3 RMAX n3) | s2 (3 RMAX n3) |
-// split-K partials (3 nkc RMAX n3) | s3 partials (nk3 3 RMAX)
+// TT work layout (element offsets fixed by n and m_f): s3 (3 RMAX) | t3 (3 RMAX n3) | s2 (3 RMAX
+// n3) | split-K partials (3 KBATCH RMAX n3) | s3 partials (nk3 3 RMAX) | T1 or U (3 components of
+// n3 RMAX n2) | G4 pass partial sums and column sums (dual_work_elems) | t4 (3 RMAX)
 struct TTWork {
-  int n1, n2, n3, n12, mf, nchunk, nkc, nk3, rmax2, rmax3;
-  int64_t nv;
+  int n1, n2, n3, mf, nk3, rmax1, rmax2, rmax3, kc2;
+  int64_t nv, o_t3, o_s2, o_kpart, o_s3part, o_t1, o_t4part, o_t4, t1_cs, total;
 };
-template <typename R> static TTWork tt_layout(const TTDesc<R>& T, const int n[3], int mf) {
-  TTWork w;
+static TTWork tt_offsets(const int n[3], int mf) {
+  TTWork w{};
   w.n1 = n[0];
   w.n2 = n[1];
   w.n3 = n[2];
-  w.n12 = n[0] * n[1];
-  w.nv = (int64_t)w.n12 * w.n3;
+  w.nv = (int64_t)n[0] * n[1] * n[2];
   w.mf = mf;
-  w.rmax2 = 1;
-  w.rmax3 = 1;
+  const int nk3max = (TT_RMAX * w.n3 + TT_KROWS - 1) / TT_KROWS;
+  w.o_t3 = 3LL * TT_RMAX;
+  w.o_s2 = w.o_t3 + 3LL * TT_RMAX * w.n3;
+  w.o_kpart = w.o_s2 + 3LL * TT_RMAX * w.n3;
+  w.o_s3part = w.o_kpart + 3LL * TT_KBATCH * TT_RMAX * w.n3;
+  w.o_t1 = w.o_s3part + 3LL * TT_RMAX * nk3max;
+  w.t1_cs = (int64_t)TT_RMAX * w.n2 * w.n3;
+  w.o_t4part = w.o_t1 + 3 * w.t1_cs;
+  w.o_t4 = w.o_t4part + dual_work_elems(std::max(mf, 1));
+  w.total = w.o_t4 + 3LL * TT_RMAX;
+  return w;
+}
+template <typename R> static TTWork tt_layout(const TTDesc<R>& T, const int n[3], int mf) {
+  TTWork w = tt_offsets(n, mf);
+  w.rmax1 = w.rmax2 = w.rmax3 = 1;
   for (int c = 0; c < 3; ++c) {
+    w.rmax1 = std::max(w.rmax1, T.r1[c]);
     w.rmax2 = std::max(w.rmax2, T.r2[c]);
     w.rmax3 = std::max(w.rmax3, T.r3[c]);
   }
-  w.nchunk = (mf + TT_F4_CHUNK - 1) / TT_F4_CHUNK;
-  w.nkc = (w.n12 + TT_KCHUNK - 1) / TT_KCHUNK;
   w.nk3 = (w.rmax2 * w.n3 + TT_KROWS - 1) / TT_KROWS;
+  // split-K chunk of the (j1, i2) contraction: a multiple of 16 giving at most KBATCH batches
+  const int k2 = w.rmax1 * w.n2;
+  w.kc2 = 16 * (((k2 + TT_KBATCH - 1) / TT_KBATCH + 15) / 16);
+  if (w.nv >= ((int64_t)1 << 31)) throw Error(VSIE_E_GRID, "TT coupling of a body of 2^31 or more voxels");
   return w;
 }
 
-// Everything of the TT coupling that reads only x: forward G4 x_f then G3 (eqs. (16)-(17)) into
-// t3, and the transpose (eqs. (18)-(19)) S2 = M (mask x_b) over the merged first two cores, then
-// G3 into s3. Writes the work buffer only.
+// The TT coupling up to its accumulation into y_b: the transpose chain from x_b to s3
+// (eqs. (18)-(19)), then one pass over G4 for y_f += sum_c G4^T s3 and the forward G4 x_f
+// (eq. (16)), then G3 into t3 (eq. (17)). y_f must already hold the rest of its product.
 template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
-                                         const cx<R>* xb, const uint8_t* mask, cx<R>* work) {
+                                         const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* work) {
   const TTWork w = tt_layout(T, n, mf);
-  cx<R>* part = work;
-  cx<R>* t3 = part + 3LL * TT_RMAX * w.nchunk;
-  hipLaunchKernelGGL(k_tt_f4<R>, dim3(w.nchunk, (w.rmax3 + TT_F4_RB - 1) / TT_F4_RB, 3), dim3(256), 0, st, T, xf, mf,
-                     TT_F4_CHUNK, part, w.nchunk);
-  hipLaunchKernelGGL(k_tt_f3<R>, dim3((w.rmax2 * w.n3 + 15) / 16, 3), dim3(256), 0, st, T, part, w.nchunk, w.n3, t3);
   launch_tt_transpose_pre<R>(st, T, n, mf, xb, mask, work);
+  const cx<R>* s3 = work;
+  cx<R>* t4part = work + w.o_t4part;
+  cx<R>* t4 = work + w.o_t4;
+  DualRows<R> G{};
+  G.nblock = 3;
+  for (int c = 0; c < 3; ++c) {
+    G.A[c] = T.G4[c];
+    G.nrows[c] = T.r3[c];
+    G.off[c] = c * TT_RMAX;
+  }
+  launch_dual<R, false>(st, G, xf, s3, (int64_t)mf, yf, t4part + dual_work_elems(mf) - DUAL_RG * (int64_t)mf,
+                        t4part, 3 * TT_RMAX, t4);
+  hipLaunchKernelGGL(k_tt_f3<R>, dim3((w.rmax2 * w.n3 + 15) / 16, 3), dim3(256), 0, st, T, t4, w.n3,
+                     work + w.o_t3);
 }
 
 // The transpose half of launch_tt_pre: s3[c][j3] (at the start of the work buffer) from x_b.
 template <typename R> void launch_tt_transpose_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
                                                    const cx<R>* xb, const uint8_t* mask, cx<R>* work) {
   const TTWork w = tt_layout(T, n, mf);
-  const int kc = TT_KCHUNK;
-  cx<R>* part = work;
-  cx<R>* t3 = part + 3LL * TT_RMAX * w.nchunk;
-  cx<R>* s2 = t3 + 3LL * TT_RMAX * w.n3;
-  cx<R>* kpart = s2 + 3LL * TT_RMAX * w.n3;
-  cx<R>* s3part = kpart + 3LL * w.nkc * TT_RMAX * w.n3;
-  cx<R>* s3 = part;
-  // S2(j2, i3) = sum_p M[j2][p] mask x_b[c][p + n12 i3], split over p in chunks of kc
+  cx<R>* s2 = work + w.o_s2;
+  cx<R>* kpart = work + w.o_kpart;
+  cx<R>* s3part = work + w.o_s3part;
+  cx<R>* t1 = work + w.o_t1;
+  cx<R>* s3 = work;
+  const int rows = w.n2 * w.n3;
+  // T1[c][i3][j1][i2] over the first core (x_b read once)
+  hipLaunchKernelGGL(k_tt_t1<R>, dim3((rows + 63) / 64, 3), dim3(256), 0, st, T, xb, mask, w.n1, w.n2, rows, w.nv, t1,
+                     w.t1_cs);
+  // S2(j2, i3) = sum_k G2[k][j2] T1[i3][k], k = (j1, i2), split over k in chunks of kc2
   GemmSet<R> B{};
   B.nprob = 3;
   for (int c = 0; c < 3; ++c) {
-    B.g[c] = GemmArgs<R>{T.M[c], w.n12, 1, kc, xb + (int64_t)c * w.nv, 1, w.n12, kc,
-                         kpart + (int64_t)c * w.nkc * TT_RMAX * w.n3, w.n3, 1, (int64_t)TT_RMAX * w.n3,
-                         T.r2[c], w.n3, kc, w.n12, mask, nullptr, 0};
-    B.nbatch[c] = w.nkc;
+    const int ktot = T.r1[c] * w.n2;
+    B.g[c] = GemmArgs<R>{T.G2[c], 1, T.r2[c], (int64_t)w.kc2 * T.r2[c], t1 + c * w.t1_cs, 1, ktot, w.kc2,
+                         kpart + (int64_t)c * TT_KBATCH * TT_RMAX * w.n3, w.n3, 1, (int64_t)TT_RMAX * w.n3,
+                         T.r2[c], w.n3, w.kc2, ktot, nullptr, nullptr, 0, 0};
+    B.nbatch[c] = (ktot + w.kc2 - 1) / w.kc2;
   }
   launch_zgemm<R>(st, B);
-  hipLaunchKernelGGL(k_tt_ksum<R>, dim3((w.rmax2 * w.n3 + 31) / 32, 3), dim3(256), 0, st, T, kpart, w.nkc, w.n3, s2);
+  hipLaunchKernelGGL(k_tt_ksum<R>, dim3((w.rmax2 * w.n3 + 31) / 32, 3), dim3(256), 0, st, T, kpart, w.kc2, w.n2, w.n3,
+                     s2);
   hipLaunchKernelGGL(k_ttT_3<R>, dim3(w.nk3, 3), dim3(256), 0, st, T, s2, w.n3, s3part);
   hipLaunchKernelGGL(k_sum_partials<R>, dim3(3 * TT_RMAX), dim3(256), 0, st, s3part, w.nk3, 3 * TT_RMAX, s3);
 }
@@ -2077,42 +2238,36 @@ template <typename R> void launch_tt_transpose_pre(hipStream_t st, const TTDesc<
 template <typename R> void launch_tt_forward_from(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
                                                   const cx<R>* u3, cx<R>* work) {
   const TTWork w = tt_layout(T, n, mf);
-  cx<R>* t3 = work + 3LL * TT_RMAX * w.nchunk;
-  hipLaunchKernelGGL(k_tt_f3<R>, dim3((w.rmax2 * w.n3 + 15) / 16, 3), dim3(256), 0, st, T, u3, 1, w.n3, t3);
+  cx<R>* t3 = work + w.o_t3;
+  hipLaunchKernelGGL(k_tt_f3<R>, dim3((w.rmax2 * w.n3 + 15) / 16, 3), dim3(256), 0, st, T, u3, w.n3, t3);
 }
 
-// The accumulations: y_b[c] += mask * (merged core) t3 (forward) and y_f += sum_c G4^T s3
-// (transpose), from the work buffer filled by launch_tt_pre.
+// The accumulation into y_b from the work buffer filled by launch_tt_pre.
 template <typename R> void launch_tt_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
-                                          const uint8_t* mask, cx<R>* yf, cx<R>* yb, const cx<R>* work) {
-  const TTWork w = tt_layout(T, n, mf);
-  const cx<R>* s3 = work;
+                                          const uint8_t* mask, cx<R>* yb, cx<R>* work) {
   launch_tt_forward_post<R>(st, T, n, mf, mask, yb, work);
-  hipLaunchKernelGGL(k_ttT_4<R>, dim3((mf + 63) / 64), dim3(1024), 0, st, T, s3, mf, yf);
 }
 
-// The forward half of launch_tt_post: y_b[c] += mask * (merged core) t3.
+// The forward half of launch_tt_post: U = G2 t3, then y_b[c] += mask * G1 U.
 template <typename R> void launch_tt_forward_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
-                                                  const uint8_t* mask, cx<R>* yb, const cx<R>* work) {
+                                                  const uint8_t* mask, cx<R>* yb, cx<R>* work) {
   const TTWork w = tt_layout(T, n, mf);
-  const cx<R>* t3 = work + 3LL * TT_RMAX * w.nchunk;
+  const cx<R>* t3 = work + w.o_t3;
+  cx<R>* u = work + w.o_t1;
   GemmSet<R> F{};
   F.nprob = 3;
   for (int c = 0; c < 3; ++c) {
-    // C(i3, p) = y_b[c][p + n12 i3] += mask * sum_j2 t3[j2][i3] M[j2][p]  (p along the columns)
-    F.g[c] = GemmArgs<R>{t3 + (int64_t)c * TT_RMAX * w.n3, 1, w.n3, 0, T.M[c], w.n12, 1, 0, yb + (int64_t)c * w.nv,
-                         w.n12, 1, 0, w.n3, w.n12, T.r2[c], 0, nullptr, mask, 1};
+    // U(k, i3) = U[c][i3][k], k = (j1, i2): sum_j2 G2[k][j2] t3[j2][i3]
+    const int K2 = T.r1[c] * w.n2;
+    F.g[c] = GemmArgs<R>{T.G2[c], T.r2[c], 1, 0, t3 + (int64_t)c * TT_RMAX * w.n3, w.n3, 1, 0, u + c * w.t1_cs, 1, K2,
+                         0, K2, w.n3, T.r2[c], 0, nullptr, nullptr, 0, 0};
     F.nbatch[c] = 1;
   }
   launch_zgemm<R>(st, F);
+  hipLaunchKernelGGL(k_tt_yb<R>, dim3((unsigned)((w.nv + 255) / 256), 3), dim3(256), 0, st, T, u, w.t1_cs, mask, w.n1,
+                     w.n2, (int)w.nv, yb);
 }
-int64_t tt_work_elems(const int n[3], int mf) {
-  const int nchunk = (mf + TT_F4_CHUNK - 1) / TT_F4_CHUNK;
-  const int nkc = (n[0] * n[1] + TT_KCHUNK - 1) / TT_KCHUNK;
-  const int nk3 = (TT_RMAX * n[2] + TT_KROWS - 1) / TT_KROWS;
-  return 3LL * TT_RMAX * std::max(nchunk, 1) + 6LL * TT_RMAX * n[2] + 3LL * nkc * TT_RMAX * n[2] +
-         3LL * TT_RMAX * nk3;
-}
+int64_t tt_work_elems(const int n[3], int mf) { return tt_offsets(n, mf).total; }
 template <typename R> void launch_symv_tiles(hipStream_t st, const cx<R>* Zp, const int* tiles, int T, const cx<R>* x,
                                              int m, cx<R>* part) {
   const int64_t nt = (int64_t)T * (T + 1) / 2;
@@ -2346,16 +2501,18 @@ template void launch_mul_diag<float>(hipStream_t, const cxf*, const cxf*, cxf*, 
                                   cx<R>*, int);                                                                      \
   template void launch_lr_t<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*, int, cx<R>*);      \
   template void launch_lr_n_add<R>(hipStream_t, bool, const cx<R>*, const cx<R>*, int64_t, int, cx<R>*);              \
+  template void launch_lr_dual<R>(hipStream_t, const cx<R>*, int, int64_t, const cx<R>*, const cx<R>*, cx<R>*, cx<R>*, \
+                                  cx<R>*);                                                                            \
   template void launch_gemv_rows<R>(hipStream_t, const cx<R>*, const cx<R>*, int64_t, int64_t, cx<R>*, int);          \
   template void launch_tt_pre<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*, const cx<R>*,       \
-                                 const uint8_t*, cx<R>*);                                                             \
-  template void launch_tt_post<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const uint8_t*, cx<R>*, cx<R>*,   \
-                                  const cx<R>*);                                                                      \
+                                 const uint8_t*, cx<R>*, cx<R>*);                                                     \
+  template void launch_tt_post<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const uint8_t*, cx<R>*,           \
+                                  cx<R>*);                                                                            \
   template void launch_tt_transpose_pre<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*,          \
                                            const uint8_t*, cx<R>*);                                             \
   template void launch_tt_forward_from<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*, cx<R>*); \
   template void launch_tt_forward_post<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const uint8_t*,        \
-                                          cx<R>*, const cx<R>*);                                                \
+                                          cx<R>*, cx<R>*);                                                \
   template void launch_scatter_rhs<R>(hipStream_t, const int*, const double*, const double*, int, cx<R>*);         \
   template void launch_symv_tiles<R>(hipStream_t, const cx<R>*, const int*, int, const cx<R>*, int, cx<R>*);      \
   template void launch_symv_reduce<R>(hipStream_t, const cx<R>*, int, int, cx<R>*);                                            \

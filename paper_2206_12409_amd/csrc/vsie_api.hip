@@ -556,30 +556,9 @@ void setup_tt(Handle& H) {
   }
 }
 
-// Device copies of G3, G4 and of the contraction of the first two cores over j1,
-// M[j2][i1 + n1 i2] = sum_j1 G1[i1][j1] G2[j1][i2][j2] (eq. (14) with cores 1 and 2 merged).
+// Device copies of the four cores of one component (eq. (14)).
 void upload_tt(Handle& H, int chi) {
-  const int n1 = H.n[0], n2 = H.n[1];
-  const int r1 = H.tt_r[chi][0], r2 = H.tt_r[chi][1];
-  const std::vector<cxd>& G1 = H.tt_host[chi][0];
-  const std::vector<cxd>& G2 = H.tt_host[chi][1];
-  const int64_t n12 = (int64_t)n1 * n2;
-  std::vector<cxd> M((size_t)r2 * n12);
-  parallel_for((int64_t)r2 * n2, host_threads(), [&](int64_t b, int64_t e) {
-    for (int64_t q = b; q < e; ++q) {
-      const int64_t j2 = q / n2;
-      const int i2 = (int)(q % n2);
-      for (int i1 = 0; i1 < n1; ++i1) {
-          cxd acc{0, 0};
-          for (int j1 = 0; j1 < r1; ++j1)
-            acc += G1[(size_t)i1 * r1 + j1] * G2[((size_t)j1 * n2 + i2) * r2 + j2];
-        M[(size_t)j2 * n12 + (size_t)i2 * n1 + i1] = acc;
-      }
-    }
-  });
-  H.d64.G12[chi] = upload_cx<double>(H, M);
-  if (H.opts.precision) H.d32.G12[chi] = upload_cx<float>(H, M);
-  for (int k = 2; k < 4; ++k) {
+  for (int k = 0; k < 4; ++k) {
     H.d64.G[chi][k] = upload_cx<double>(H, H.tt_host[chi][k]);
     if (H.opts.precision) H.d32.G[chi][k] = upload_cx<float>(H, H.tt_host[chi][k]);
   }
@@ -590,7 +569,8 @@ template <typename R> void alloc_work(Handle& H, OpData<R>& D) {
   D.bufB = H.dalloc<cx<R>>(3LL * H.ne[2] * H.ne[1] * H.P[0]);
   D.bufC = H.dalloc<cx<R>>(3LL * H.ne[2] * H.P[1] * H.P[0]);
   D.tt_work = H.dalloc<cx<R>>(tt_work_elems(H.n, std::max(H.mf, 1)));
-  D.small_work = H.dalloc<cx<R>>(512 * 256 + 256);
+  D.small_work = H.dalloc<cx<R>>(512 * 256 + 512);
+  if (H.mf > 0) D.dual_part = H.dalloc<cx<R>>(lr_dual_part_elems(H.mf));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -688,6 +668,23 @@ static void volume_chain(Handle& H, OpData<R>& D, const cx<R>* xn, const cx<R>* 
   }
 }
 
+template <typename R> static bool tt_desc(const Handle& H, const OpData<R>& D, TTDesc<R>& td, int r3[3]) {
+  bool have = H.mf > 0;
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < 4; ++k) have = have && D.G[c][k] != nullptr;
+  for (int c = 0; c < 3; ++c) {
+    td.G1[c] = D.G[c][0];
+    td.G2[c] = D.G[c][1];
+    td.G3[c] = D.G[c][2];
+    td.G4[c] = D.G[c][3];
+    td.r1[c] = have ? H.tt_r[c][0] : 0;
+    td.r2[c] = have ? H.tt_r[c][1] : 0;
+    td.r3[c] = have ? H.tt_r[c][2] : 0;
+    r3[c] = td.r3[c];
+  }
+  return have;
+}
+
 // far_done: y_f already holds Z_ff x_f (the batched tile pass of vsie_matvec)
 template <typename R>
 void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t st, bool far_done = false) {
@@ -704,17 +701,10 @@ void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t s
   cx<R>* yf = y;
   cx<R>* yn = y + mf;
   cx<R>* yb = y + mf + mn;
-  const bool have_tt = mf && D.G12[0] && D.G12[1] && D.G12[2];
   TTDesc<R> td;
-  if (have_tt)
-    for (int c = 0; c < 3; ++c) {
-      td.M[c] = D.G12[c];
-      td.G3[c] = D.G[c][2];
-      td.G4[c] = D.G[c][3];
-      td.r2[c] = H.tt_r[c][1];
-      td.r3[c] = H.tt_r[c][2];
-    }
-  // dense far block (writes y_f), then the parts of the TT coupling that read only x
+  int r3[3];
+  const bool have_tt = tt_desc(H, D, td, r3);
+  // dense far block (writes y_f), then the TT coupling's x-side work and its y_f part
   auto far_chain = [&]() {
     if (!far_done) {
       T.begin(8, fs);
@@ -726,7 +716,7 @@ void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t s
     }
     if (have_tt) {
       T.begin(11, fs);
-      launch_tt_pre<R>(fs, td, H.n, mf, xf, xb, H.d_mask, D.tt_work);
+      launch_tt_pre<R>(fs, td, H.n, mf, xf, xb, H.d_mask, yf, D.tt_work);
       T.end(11, fs);
     }
   };
@@ -745,21 +735,21 @@ void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t s
   T.begin(9);
   launch_csr_add<R>(st, H.d_pc_rowid, H.d_pc_rowptr, H.d_pc_col, D.pc_val, x, y, H.n_pcrows);
   T.end(9);
-  // ACA: y_n += U (V^* x_f), y_f += conj(V) (U^T x_n)
+  // ACA: y_n += U (V^* x_f), y_f += conj(V) (U^T x_n); V is read once for both
   if (mf && mn && H.aca_k > 0) {
     T.begin(10);
     cx<R>* part = D.small_work;
-    cx<R>* t = D.small_work + 512 * 256;
-    launch_lr_t<R>(st, true, D.V, xf, mf, H.aca_k, part, 512, t);
-    launch_lr_n_add<R>(st, false, D.U, t, mn, H.aca_k, yn);
-    launch_lr_t<R>(st, false, D.U, xn, mn, H.aca_k, part, 512, t);
-    launch_lr_n_add<R>(st, true, D.V, t, mf, H.aca_k, yf);
+    cx<R>* tn = D.small_work + 512 * 256;
+    cx<R>* tf = tn + 256;
+    launch_lr_t<R>(st, false, D.U, xn, mn, H.aca_k, part, 512, tn);
+    launch_lr_dual<R>(st, D.V, H.aca_k, mf, xf, tn, yf, D.dual_part, tf);
+    launch_lr_n_add<R>(st, false, D.U, tf, mn, H.aca_k, yn);
     T.end(10);
   }
-  // TT far coupling (eqs. (16)-(19)): the accumulations into y_b and y_f
+  // TT far coupling (eqs. (16)-(17)): the accumulation into y_b
   if (have_tt) {
     T.begin(13);
-    launch_tt_post<R>(st, td, H.n, mf, H.d_mask, yf, yb, D.tt_work);
+    launch_tt_post<R>(st, td, H.n, mf, H.d_mask, yb, D.tt_work);
     T.end(13);
   }
   T.collect();
@@ -811,18 +801,6 @@ struct Scratch {
   template <typename T> T* as() const { return (T*)p; }
 };
 
-template <typename R> static bool tt_desc(const Handle& H, const OpData<R>& D, TTDesc<R>& td, int r3[3]) {
-  const bool have = H.mf && D.G12[0] && D.G12[1] && D.G12[2];
-  for (int c = 0; c < 3; ++c) {
-    td.M[c] = D.G12[c];
-    td.G3[c] = D.G[c][2];
-    td.G4[c] = D.G[c][3];
-    td.r2[c] = have ? H.tt_r[c][1] : 0;
-    td.r3[c] = have ? H.tt_r[c][2] : 0;
-    r3[c] = td.r3[c];
-  }
-  return have;
-}
 static int aca_rank(const Handle& H) { return (H.mf > 0 && H.mn > 0 && H.aca_k > 0) ? H.aca_k : 0; }
 static OpData<double>& opdata(Handle& H, double) { return H.d64; }
 static OpData<float>& opdata(Handle& H, float) { return H.d32; }

@@ -69,9 +69,8 @@ template <typename R> struct OpData {
   // ACA
   cx<R>* U = nullptr;          // [m_n][k]
   cx<R>* V = nullptr;          // [m_f][k]
-  // TT cores per component (G3, G4) and the first two cores contracted, [r2][n1 n2]
+  // TT cores per component: G1 [n1][r1], G2 [r1][n2][r2], G3 [r2][n3][r3], G4 [r3][m_f]
   cx<R>* G[3][4] = {};
-  cx<R>* G12[3] = {};
   // dense far block
   cx<R>* Zff = nullptr;        // upper-triangle tiles of the symmetric far block
   cx<R>* sym_part = nullptr;   // per-tile partial sums
@@ -82,6 +81,7 @@ template <typename R> struct OpData {
   cx<R>* bufC = nullptr;       // [3][ne3][P2][P1]
   cx<R>* tt_work = nullptr;    // TT intermediates
   cx<R>* small_work = nullptr; // ACA / reductions
+  cx<R>* dual_part = nullptr;  // partial sums of the one-pass product with V
 };
 
 constexpr int LU_NB = 64;   // panel width of the dense LU
