@@ -34,8 +34,10 @@ def stage_bytes(info, s):
     SO = (P1 // 2 + 1) * (P2 // 2 + 1) * (P3 // 2 + 1)
     mf, mn = info["m_far"], info["m_near"]
     b = {
-        "build_grid": c * (3 * nv + 3 * Ne) + mn * 0,
-        "fft_x_fwd": c * (3 * Ne + 3 * ne3 * ne2 * P1),
+        # the grid build is fused into the first pass: it reads the masked body currents (and, per
+        # grid voxel, one 4-byte projection-row index; per body voxel one mask byte) and writes the
+        # x-transformed rows
+        "fft_x_fwd": c * (3 * nv + 3 * ne3 * ne2 * P1) + 4 * Ne + nv,
         "fft_y_fwd": c * (3 * ne3 * ne2 * P1 + 3 * ne3 * P2 * P1),
         "fft_z_conv": c * (2 * 3 * ne3 * P2 * P1 + 6 * SO),
         "fft_y_inv": c * (3 * ne3 * P2 * P1 + 3 * ne3 * ne2 * P1),
@@ -60,7 +62,7 @@ def stage_bytes(info, s):
 
 
 KERNEL_OF_STAGE = {   # stages that are a single kernel launch, and that kernel's name
-    "build_grid": "k_build_grid", "fft_x_fwd": "k_fft2", "fft_y_fwd": "k_fft2", "fft_z_conv": "k_zconv4",
+    "fft_x_fwd": "k_fft2", "fft_y_fwd": "k_fft2", "fft_z_conv": "k_zconv4",
     "fft_y_inv": "k_fft2", "fft_x_inv": "k_fft2", "body_out": "k_body_out", "pfft_gather": "k_pfft_gather",
     "gemv_far": "k_symv_tiles", "gemv_far_reduce": "k_symv_reduce", "precorrect": "k_csr_add",
 }
@@ -542,7 +544,7 @@ def main():
     achieved = db / (dom_ms * 1e-3) / 1e9
     conv_ms = sum(per_stage.get(k, 0) for k in ("build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv",
                                                    "fft_y_inv", "fft_x_inv", "body_out"))
-    conv_b = sum(stage_bytes(info, k) for k in ("build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv",
+    conv_b = sum(stage_bytes(info, k) or 0 for k in ("build_grid", "fft_x_fwd", "fft_y_fwd", "fft_z_conv",
                                                   "fft_y_inv", "fft_x_inv", "body_out"))
     print("stages: %s" % json.dumps(rl), file=sys.stderr, flush=True)
 

@@ -43,9 +43,13 @@ void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const
 std::vector<int> zconv_order(int L, int P1, int P2, bool fp64);
 
 // matvec
-template <typename R> void launch_build_grid(hipStream_t st, const cx<R>* xb, const cx<R>* xn, const uint8_t* mask,
-                                             const int* vox2row, const int* rowptr, const int* rowrwg, const R* roww,
-                                             cx<R>* grid, const GridDims& g);
+// the first forward pass along x with the grid sources (masked x_b and the pFFT projection of x_n,
+// eq. (13), gathered per projection row into projv [nprojrows][3] first) formed on the fly: out
+// rows [3][ne3][ne2][L]
+template <typename R>
+void fft_rows_grid(hipStream_t st, int L, const cx<R>* xb, const cx<R>* xn, const uint8_t* mask, const int* vox2row,
+                   const uint8_t* rowhas, const int* rowptr, const int* rowrwg, const R* roww, int nprojrows,
+                   cx<R>* projv, const GridDims& g, cx<R>* out, const cx<R>* tw);
 template <typename R> void launch_body_out(hipStream_t st, const cx<R>* xb, const cx<R>* E, const cx<R>* dvchi,
                                            const uint8_t* mask, cx<R>* yb, const GridDims& g);
 template <typename R> void launch_pfft_gather(hipStream_t st, const R* W, const int* base, const cx<R>* E, cx<R>* yn,

@@ -491,11 +491,54 @@ __device__ inline void reg_dft(cx<R>* v, const cx<R>* __restrict__ tw) {
   }
 }
 
-template <typename R, int A, int B, int NP, bool FWD, bool STRIDED>
+// Sources of the extended grid (eq. (13)): masked body currents plus the pFFT projection of the
+// near currents, which a voxel-keyed CSR (one row of weights per grid voxel that any stencil
+// touches) gathers into projv[row][3] first. Read in place of a stored grid by the first forward
+// pass.
+template <typename R> struct GridSrc {
+  const cx<R>* xb;
+  const uint8_t* mask;
+  const int* vox2row;
+  const uint8_t* rowhas;   // per x row (i2 + ne2 i3): any projection voxel in it
+  const cx<R>* projv;
+  GridDims g;
+};
+
+// projv[r][c] = sum_e roww[e][c] x_n[rwg(e)] over CSR row r: four lanes per projection row, each
+// summing every fourth entry, combined by two lane exchanges (fixed order)
+template <typename R>
+__global__ __launch_bounds__(256) void k_proj_rows(const int* __restrict__ rowptr, const int* __restrict__ rowrwg,
+                                                   const R* __restrict__ roww, const cx<R>* __restrict__ xn,
+                                                   int nrows, cx<R>* __restrict__ projv) {
+  const int r = blockIdx.x * 64 + threadIdx.x / 4, sub = threadIdx.x % 4;
+  const bool live = r < nrows;
+  R a[6] = {0, 0, 0, 0, 0, 0};
+  if (live)
+    for (int e = rowptr[r] + sub; e < rowptr[r + 1]; e += 4) {
+      const cx<R> j = xn[rowrwg[e]];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const R w = roww[3 * (int64_t)e + q];
+        a[2 * q] += w * j.re;
+        a[2 * q + 1] += w * j.im;
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    a[q] += __shfl_xor(a[q], 1, 4);
+    a[q] += __shfl_xor(a[q], 2, 4);
+  }
+  if (live && sub < 3) projv[3 * (int64_t)r + sub] = cx<R>{a[2 * sub], a[2 * sub + 1]};
+}
+
+// SRC: row-major forward pass over x whose input rows (c, i3, i2) are formed from the grid
+// sources instead of read (the grid build fused into the first FFT pass).
+template <typename R, int A, int B, int NP, bool FWD, bool STRIDED, bool SRC = false>
 __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, cx<R>* __restrict__ out, int n_in,
                                                  int n_out, int64_t in_stride, int64_t out_stride, int n_lo,
                                                  int64_t in_hi, int64_t out_hi, int64_t nrows,
-                                                 const cx<R>* __restrict__ tw) {
+                                                 const cx<R>* __restrict__ tw, GridSrc<R> gs) {
+  static_assert(!SRC || (FWD && !STRIDED), "grid sources feed the forward row pass only");
   constexpr int L = A * B;
   // transpose rows of RS and pencils PS apart (16-byte slots). Row-major pencils (lanes along a
   // pencil) need only the row padding; the strided form's lanes run across pencils, so their
@@ -532,10 +575,42 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
   if (u < B) {
     const int j = u;
     cx<R> v[A];
+    if constexpr (SRC) {
+      // row = (c ne3 + i3) ne2 + i2; body voxel (n - ob1, i2 - ob2, i3 - ob3) when inside
+      const GridDims& g = gs.g;
+      const int64_t row = (int64_t)blockIdx.x * NP + p;
+      const int plane = g.ne3 * g.ne2;
+      const int c = valid ? (int)(row / plane) : 0;
+      const int rem = valid ? (int)(row - (int64_t)c * plane) : 0;
+      const int i3 = rem / g.ne2, i2 = rem - (rem / g.ne2) * g.ne2;
+      const int b2 = i2 - g.ob2, b3 = i3 - g.ob3;
+      const bool rin = valid && gs.xb && b2 >= 0 && b2 < g.n2 && b3 >= 0 && b3 < g.n3;
+      const int64_t pb = (int64_t)g.n1 * (b2 + (int64_t)g.n2 * b3) - g.ob1;
+      const int64_t vrow = (int64_t)g.ne1 * (i2 + (int64_t)g.ne2 * i3);
+      const bool rproj = valid && gs.vox2row && gs.rowhas[i2 + (int64_t)g.ne2 * i3];
+      const cx<R>* xbc = gs.xb + (int64_t)c * g.nv;
+      // every load of the row issued before any is tested; the projection rows (voxels next to
+      // the near conductors only) are walked afterwards
+      int pr[A];
 #pragma unroll
-    for (int m = 0; m < A; ++m) {
-      const int n = j + B * m;
-      v[bitrev_of(m, A)] = (valid && n < n_in) ? ib[(int64_t)n * in_stride] : cx<R>{0, 0};
+      for (int m = 0; m < A; ++m) {
+        const int n = j + B * m;
+        const int b1 = n - g.ob1;
+        const bool inb = rin && n < n_in && b1 >= 0 && b1 < g.n1;
+        const cx<R> xv = inb ? xbc[pb + n] : cx<R>{0, 0};
+        const uint8_t mk = inb ? gs.mask[pb + n] : 0;
+        v[bitrev_of(m, A)] = mk ? xv : cx<R>{0, 0};
+        pr[m] = (rproj && n < n_in) ? gs.vox2row[vrow + n] : -1;
+      }
+#pragma unroll
+      for (int m = 0; m < A; ++m)
+        if (pr[m] >= 0) v[bitrev_of(m, A)] += gs.projv[3 * (int64_t)pr[m] + c];
+    } else {
+#pragma unroll
+      for (int m = 0; m < A; ++m) {
+        const int n = j + B * m;
+        v[bitrev_of(m, A)] = (valid && n < n_in) ? ib[(int64_t)n * in_stride] : cx<R>{0, 0};
+      }
     }
     reg_dft<R, A, L, FWD>(v, twl);
 #pragma unroll
@@ -1019,10 +1094,31 @@ void fft_rows(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, int 
     dim3 grid((unsigned)((nrows + NP - 1) / NP));
     if (fwd)
       hipLaunchKernelGGL((k_fft2<R, A, B, NP, true, false>), grid, dim3(NP * A), 0, st, in, out, n_in, n_out, 1, 1, 0,
-                         in_row, out_row, nrows, tw);
+                         in_row, out_row, nrows, tw, GridSrc<R>{});
     else
       hipLaunchKernelGGL((k_fft2<R, A, B, NP, false, false>), grid, dim3(NP * A), 0, st, in, out, n_in, n_out, 1, 1, 0,
-                         in_row, out_row, nrows, tw);
+                         in_row, out_row, nrows, tw, GridSrc<R>{});
+  });
+}
+
+template <typename R>
+void fft_rows_grid(hipStream_t st, int L, const cx<R>* xb, const cx<R>* xn, const uint8_t* mask, const int* vox2row,
+                   const uint8_t* rowhas, const int* rowptr, const int* rowrwg, const R* roww, int nprojrows,
+                   cx<R>* projv, const GridDims& g, cx<R>* out, const cx<R>* tw) {
+  if (g.Ne >= ((int64_t)1 << 31)) throw Error(VSIE_E_GRID, "extended grid of 2^31 or more voxels");
+  const bool proj = xn && vox2row && rowhas && nprojrows > 0;
+  if (proj)
+    hipLaunchKernelGGL(k_proj_rows<R>, dim3((nprojrows + 63) / 64), dim3(256), 0, st, rowptr, rowrwg, roww, xn,
+                       nprojrows, projv);
+  const GridSrc<R> gs{xb, mask, proj ? vox2row : nullptr, rowhas, projv, g};
+  const int64_t nrows = 3LL * g.ne3 * g.ne2;
+  VSIE_FFT_SWITCH(L, {
+    constexpr int A = Split<LL>::A;
+    constexpr int B = Split<LL>::B;
+    constexpr int NP = (sizeof(R) == 8 ? 128 : 256) / A;
+    dim3 grid((unsigned)((nrows + NP - 1) / NP));
+    hipLaunchKernelGGL((k_fft2<R, A, B, NP, true, false, true>), grid, dim3(NP * A), 0, st, nullptr, out, g.ne1, L,
+                       1, 1, 0, 0, (int64_t)L, nrows, tw, gs);
   });
 }
 
@@ -1036,10 +1132,10 @@ void fft_strided(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, i
     dim3 grid((unsigned)(n_hi * ((n_lo + NP - 1) / NP)));
     if (fwd)
       hipLaunchKernelGGL((k_fft2<R, A, B, NP, true, true>), grid, dim3(NP * A), 0, st, in, out, n_in, n_out, in_stride,
-                         out_stride, n_lo, in_hi, out_hi, 0, tw);
+                         out_stride, n_lo, in_hi, out_hi, 0, tw, GridSrc<R>{});
     else
       hipLaunchKernelGGL((k_fft2<R, A, B, NP, false, true>), grid, dim3(NP * A), 0, st, in, out, n_in, n_out, in_stride,
-                         out_stride, n_lo, in_hi, out_hi, 0, tw);
+                         out_stride, n_lo, in_hi, out_hi, 0, tw, GridSrc<R>{});
   });
 }
 
@@ -1125,6 +1221,12 @@ void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const
 
 template void fft_rows<double>(hipStream_t, int, bool, const cxd*, cxd*, int, int, int64_t, int64_t, int64_t, const cxd*);
 template void fft_rows<float>(hipStream_t, int, bool, const cxf*, cxf*, int, int, int64_t, int64_t, int64_t, const cxf*);
+template void fft_rows_grid<double>(hipStream_t, int, const cxd*, const cxd*, const uint8_t*, const int*,
+                                    const uint8_t*, const int*, const int*, const double*, int, cxd*, const GridDims&,
+                                    cxd*, const cxd*);
+template void fft_rows_grid<float>(hipStream_t, int, const cxf*, const cxf*, const uint8_t*, const int*,
+                                   const uint8_t*, const int*, const int*, const float*, int, cxf*, const GridDims&,
+                                   cxf*, const cxf*);
 template void fft_strided<double>(hipStream_t, int, bool, const cxd*, cxd*, int, int, int64_t, int64_t, int, int64_t,
                                   int64_t, int64_t, const cxd*);
 template void fft_strided<float>(hipStream_t, int, bool, const cxf*, cxf*, int, int, int64_t, int64_t, int, int64_t,
@@ -1135,44 +1237,6 @@ template void fft_z_conv<float>(hipStream_t, int, cxf*, int, int, int, const cxf
 // =============================================================================================
 // Matvec kernels
 // =============================================================================================
-
-// extended-grid sources: masked body currents + pFFT projection of the near RWG currents
-template <typename R>
-__global__ void k_build_grid(const cx<R>* __restrict__ xb, const cx<R>* __restrict__ xn,
-                             const uint8_t* __restrict__ mask, const int* __restrict__ vox2row,
-                             const int* __restrict__ rowptr, const int* __restrict__ rowrwg,
-                             const R* __restrict__ roww, cx<R>* __restrict__ grid, GridDims g) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= g.Ne) return;
-  // 32-bit index arithmetic (the launcher checks Ne < 2^31): 64-bit division is a long software
-  // sequence on the GPU and held this kernel well below the HBM rate
-  const int vi = (int)v, t12 = vi / g.ne1;
-  const int i1 = vi - t12 * g.ne1, i3 = t12 / g.ne2, i2 = t12 - i3 * g.ne2;
-  int b1 = i1 - g.ob1, b2 = i2 - g.ob2, b3 = i3 - g.ob3;
-  cx<R> a[3] = {{0, 0}, {0, 0}, {0, 0}};
-  if (xb && b1 >= 0 && b1 < g.n1 && b2 >= 0 && b2 < g.n2 && b3 >= 0 && b3 < g.n3) {
-    int64_t p = b1 + (int64_t)g.n1 * (b2 + (int64_t)g.n2 * b3);
-    if (mask[p]) {
-      a[0] = xb[p];
-      a[1] = xb[g.nv + p];
-      a[2] = xb[2 * g.nv + p];
-    }
-  }
-  if (vox2row && xn) {
-    int r = vox2row[v];
-    if (r >= 0) {
-      for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        cx<R> j = xn[rowrwg[e]];
-        a[0] += roww[3 * (int64_t)e] * j;
-        a[1] += roww[3 * (int64_t)e + 1] * j;
-        a[2] += roww[3 * (int64_t)e + 2] * j;
-      }
-    }
-  }
-  grid[v] = a[0];
-  grid[g.Ne + v] = a[1];
-  grid[2 * g.Ne + v] = a[2];
-}
 
 // body rows: tissue y = h^3/chi x + (T * x) ; air y = x
 template <typename R>
@@ -2080,13 +2144,6 @@ __global__ void k_scatter_rhs(const int* __restrict__ idx, const double* __restr
 
 // ---------------------------------------------------------------------------------------------
 // explicit instantiations and host launchers
-template <typename R> void launch_build_grid(hipStream_t st, const cx<R>* xb, const cx<R>* xn, const uint8_t* mask,
-                                             const int* vox2row, const int* rowptr, const int* rowrwg, const R* roww,
-                                             cx<R>* grid, const GridDims& g) {
-  if (g.Ne >= ((int64_t)1 << 31)) throw Error(VSIE_E_GRID, "extended grid of 2^31 or more voxels");
-  hipLaunchKernelGGL(k_build_grid<R>, dim3((unsigned)((g.Ne + 255) / 256)), dim3(256), 0, st, xb, xn, mask, vox2row,
-                     rowptr, rowrwg, roww, grid, g);
-}
 template <typename R> void launch_body_out(hipStream_t st, const cx<R>* xb, const cx<R>* E, const cx<R>* dvchi,
                                            const uint8_t* mask, cx<R>* yb, const GridDims& g) {
   hipLaunchKernelGGL(k_body_out<R>, dim3((unsigned)((g.nv + 255) / 256)), dim3(256), 0, st, xb, E, dvchi, mask, yb, g);
@@ -2492,8 +2549,6 @@ template void launch_mul_diag<double>(hipStream_t, const cxd*, const cxd*, cxd*,
 template void launch_mul_diag<float>(hipStream_t, const cxf*, const cxf*, cxf*, int64_t);
 
 #define VSIE_INST(R)                                                                                                  \
-  template void launch_build_grid<R>(hipStream_t, const cx<R>*, const cx<R>*, const uint8_t*, const int*, const int*, \
-                                     const int*, const R*, cx<R>*, const GridDims&);                                  \
   template void launch_body_out<R>(hipStream_t, const cx<R>*, const cx<R>*, const cx<R>*, const uint8_t*, cx<R>*,     \
                                    const GridDims&);                                                                 \
   template void launch_pfft_gather<R>(hipStream_t, const R*, const int*, const cx<R>*, cx<R>*, int, const GridDims&); \

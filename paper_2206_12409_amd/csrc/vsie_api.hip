@@ -219,6 +219,10 @@ void setup_pfft(Handle& H) {
   rowptr.push_back((int)ents.size());
   H.n_gridrows = (int)rowptr.size() - 1;
   H.nnz_grid = (int64_t)ents.size();
+  // per x row (i2, i3) of the extended grid: does any of its voxels carry a projection row
+  std::vector<uint8_t> rowhas((size_t)H.ne[1] * H.ne[2], 0);
+  for (size_t e = 0; e < ents.size(); ++e) rowhas[(size_t)(ents[e].v / H.ne[0])] = 1;
+  H.d_rowhasproj = upload(H, rowhas);
   H.d_vox2row = upload(H, vox2row);
   H.d_rowptr = upload(H, rowptr);
   H.d_rowrwg = upload(H, rowrwg);
@@ -570,6 +574,7 @@ template <typename R> void alloc_work(Handle& H, OpData<R>& D) {
   D.bufC = H.dalloc<cx<R>>(3LL * H.ne[2] * H.P[1] * H.P[0]);
   D.tt_work = H.dalloc<cx<R>>(tt_work_elems(H.n, std::max(H.mf, 1)));
   D.small_work = H.dalloc<cx<R>>(512 * 256 + 512);
+  if (H.n_gridrows > 0) D.projv = H.dalloc<cx<R>>(3LL * H.n_gridrows);
   if (H.mf > 0) D.dual_part = H.dalloc<cx<R>>(lr_dual_part_elems(H.mf));
 }
 
@@ -639,12 +644,10 @@ static void volume_chain(Handle& H, OpData<R>& D, const cx<R>* xn, const cx<R>* 
   const int mn = H.mn;
   const int P1 = H.P[0], P2 = H.P[1], P3 = H.P[2];
   const int ne1 = H.ne[0], ne2 = H.ne[1], ne3 = H.ne[2];
-  T.begin(0, st);
-  launch_build_grid<R>(st, xb, mn ? xn : nullptr, H.d_mask, mn ? H.d_vox2row : nullptr, H.d_rowptr, H.d_rowrwg, D.roww,
-                       D.gridA, g);
-  T.end(0, st);
+  // the grid build (stage 0) is fused into the first FFT pass (stage 1)
   T.begin(1, st);
-  fft_rows<R>(st, P1, true, D.gridA, D.bufB, ne1, P1, ne1, P1, 3LL * ne3 * ne2, D.tw[0]);
+  fft_rows_grid<R>(st, P1, xb, mn ? xn : nullptr, H.d_mask, mn ? H.d_vox2row : nullptr, H.d_rowhasproj, H.d_rowptr,
+                   H.d_rowrwg, D.roww, H.n_gridrows, D.projv, g, D.bufB, D.tw[0]);
   T.end(1, st);
   T.begin(2, st);
   fft_strided<R>(st, P2, true, D.bufB, D.bufC, ne2, P2, P1, P1, P1, 3LL * ne3, (int64_t)ne2 * P1, (int64_t)P2 * P1, D.tw[1]);

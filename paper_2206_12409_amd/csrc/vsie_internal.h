@@ -65,6 +65,7 @@ template <typename R> struct OpData {
   // pFFT
   R* W = nullptr;              // [m_n][3][125]
   R* roww = nullptr;           // [nnz_grid][3]
+  cx<R>* projv = nullptr;      // [n_gridrows][3]: projected near currents per projection voxel
   cx<R>* pc_val = nullptr;     // precorrection values
   // ACA
   cx<R>* U = nullptr;          // [m_n][k]
@@ -130,6 +131,7 @@ struct Handle {
   std::vector<double> Wh;         // [m_n][3][125]
   // grid CSR (by extended-grid voxel)
   int* d_vox2row = nullptr;
+  uint8_t* d_rowhasproj = nullptr;   // [ne3][ne2]: x row holds projection voxels
   int* d_rowptr = nullptr;
   int* d_rowrwg = nullptr;
   int n_gridrows = 0;
