@@ -192,6 +192,15 @@ int vsie_rhs(const struct vsie_handle* h, int port, int dtype, void* b_dev, void
 int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, void* y_dev,
                 void* stream);
 
+/* The same product as vsie_matvec, with the same result bit for bit, replayed from a HIP graph:
+ * the first call with a given (dtype, nrhs, x_dev, y_dev) waits for stream, captures the
+ * product's launches on the handle's capture stream and instantiates them; every call then launches
+ * the graph on stream (one submission instead of one per kernel). The graph holds the buffer
+ * addresses: they must stay allocated, with nrhs N elements each, while the handle may replay it.
+ * Up to 16 graphs are kept per handle (the oldest is dropped). Errors: as vsie_matvec. */
+int vsie_matvec_graph(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, void* y_dev,
+                      void* stream);
+
 /* Solve Z x = b for nrhs right-hand sides (device, [nrhs][N] complex128).
  * GMRES64: restarted GMRES (Sec. III-A), zero initial guess, FP64 classical Gram-Schmidt with a
  * second pass when the first leaves less than opts->reorth of the new vector's norm.

@@ -1662,6 +1662,70 @@ int vsie_matvec(vsie_handle* hd, int dtype, int nrhs, const void* x_dev, void* y
   });
 }
 
+// Graph-replayed product: the launches of one vsie_matvec on fixed buffers, captured once on a
+// capture stream (far-block chain on the same stream, no stage events) and replayed on the
+// caller's stream. The product path makes no allocation, copy, fill or synchronisation; the only
+// lazily allocated buffer (multi-column partial sums) is allocated before the capture.
+static constexpr size_t GRAPH_CACHE = 16;
+int vsie_matvec_graph(vsie_handle* hd, int dtype, int nrhs, const void* x_dev, void* y_dev, void* stream) {
+  if (!hd || !x_dev || !y_dev || nrhs < 1) return fail(VSIE_E_ARG, "bad argument");
+  if (x_dev == y_dev) return fail(VSIE_E_ARG, "x and y must not alias");
+  if (dtype != VSIE_C128 && dtype != VSIE_C64) return fail(VSIE_E_ARG, "bad dtype");
+  Handle& H = hd->H;
+  if (dtype == VSIE_C64 && !H.have32) return fail(VSIE_E_STATE, "complex64 operator data not built");
+  return guarded([&]() {
+    hipStream_t st = (hipStream_t)stream;
+    Handle::GraphEntry* ge = nullptr;
+    for (auto& g : H.graphs)
+      if (g.dtype == dtype && g.nrhs == nrhs && g.x == x_dev && g.y == y_dev) ge = &g;
+    if (!ge) {
+      if (!H.gstream) VSIE_HIP(hipStreamCreateWithFlags(&H.gstream, hipStreamNonBlocking));
+      auto prepare = [&](auto& D, auto zero) {
+        using R = decltype(zero);
+        if (nrhs > 1 && H.mf > 0 && !D.multi_part) {
+          const int64_t nt = (int64_t)H.sym_T * (H.sym_T + 1) / 2;
+          D.multi_part = H.dalloc<cx<R>>(16 * nt * 2 * SYM_TB);
+        }
+      };
+      if (dtype == VSIE_C128) prepare(H.d64, 0.0);
+      else prepare(H.d32, 0.0f);
+      VSIE_HIP(hipStreamSynchronize(st));   // the capture stream must not overtake earlier work
+      const bool conc = H.concurrent, prof = H.prof;
+      H.concurrent = false;
+      H.prof = false;
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(H.gstream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        try {
+          if (dtype == VSIE_C128) matvec_batch<double>(H, H.d64, (const cxd*)x_dev, (cxd*)y_dev, nrhs, H.gstream);
+          else matvec_batch<float>(H, H.d32, (const cxf*)x_dev, (cxf*)y_dev, nrhs, H.gstream);
+        } catch (...) {
+          (void)hipStreamEndCapture(H.gstream, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          H.concurrent = conc;
+          H.prof = prof;
+          throw;
+        }
+        e = hipStreamEndCapture(H.gstream, &graph);
+      }
+      H.concurrent = conc;
+      H.prof = prof;
+      if (e != hipSuccess) throw Error(VSIE_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) throw Error(VSIE_E_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+      if (H.graphs.size() == GRAPH_CACHE) {
+        (void)hipGraphExecDestroy(H.graphs.front().exec);
+        H.graphs.erase(H.graphs.begin());
+      }
+      H.graphs.push_back(Handle::GraphEntry{dtype, nrhs, x_dev, y_dev, exec});
+      ge = &H.graphs.back();
+    }
+    VSIE_HIP(hipGraphLaunch(ge->exec, st));
+  });
+}
+
 static int check_solve_opts(const vsie_handle* hd, const vsie_solve_opts* o, vsie_solve_opts& so) {
   if (o) so = *o;
   else vsie_default_solve_opts(&so);
@@ -1891,6 +1955,10 @@ int vsie_import(vsie_handle* hd, int what, int index, const void* host, size_t n
   Handle& H = hd->H;
   if (H.schur.ready) return fail(VSIE_E_STATE, "the far elimination was built from the current factors");
   return guarded([&]() {
+    // captured products hold the factors' device addresses: drop them
+    VSIE_HIP(hipDeviceSynchronize());
+    for (auto& g : H.graphs) (void)hipGraphExecDestroy(g.exec);
+    H.graphs.clear();
     const unsigned char* c = (const unsigned char*)host;
     if (what == VSIE_X_TT_CORES) {
       if (index < 0 || index > 2) throw Error(VSIE_E_ARG, "TT component out of range");

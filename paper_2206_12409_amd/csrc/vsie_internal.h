@@ -190,6 +190,15 @@ struct Handle {
   bool prof = false;
   uint32_t prof_stages = 0;      // stages timed while profiling
   bool concurrent = false;       // far-block chain on the second stream
+  // products captured as HIP graphs (vsie_matvec_graph), keyed by precision, columns and buffers
+  struct GraphEntry {
+    int dtype, nrhs;
+    const void* x;
+    void* y;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t gstream = nullptr; // capture stream
   // stage events of the last PROF_RING products, read back only by vsie_profile_read (or when the
   // ring wraps), so profiling adds no synchronisation to the products themselves
   static constexpr int PROF_RING = 256;
@@ -237,6 +246,8 @@ struct Handle {
   }
   ~Handle() {
     if (side) (void)hipStreamSynchronize(side);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (gstream) (void)hipStreamDestroy(gstream);
     for (void* p : allocations) (void)hipFree(p);
     if (h_pinned) (void)hipHostFree(h_pinned);
     for (auto& slot : ev)

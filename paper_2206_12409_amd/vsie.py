@@ -23,7 +23,7 @@ VSIE_PREC_FP64, VSIE_PREC_MIXED = 0, 1
 X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
 
 EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_sizes", "vsie_rhs",
-            "vsie_matvec", "vsie_solve", "vsie_solve_ports", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
+            "vsie_matvec", "vsie_matvec_graph", "vsie_solve", "vsie_solve_ports", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
             "vsie_profile", "vsie_profile_mask", "vsie_profile_read", "vsie_schur_setup", "vsie_schur_info",
             "vsie_schur_matvec", "vsie_schur_precond", "vsie_dense_lu_solve", "vsie_dense_lu_solve_noalloc",
             "vsie_net_create", "vsie_net_destroy", "vsie_net_info", "vsie_net_get_params", "vsie_net_set_params",
@@ -91,6 +91,7 @@ def load(path=LIB_PATH):
     lib.vsie_sizes.argtypes = [vp, C.POINTER(Sizes)]
     lib.vsie_rhs.argtypes = [vp, C.c_int, C.c_int, vp, vp]
     lib.vsie_matvec.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
+    lib.vsie_matvec_graph.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
     lib.vsie_solve.argtypes = [vp, C.POINTER(SolveOpts), C.c_int, vp, vp, C.POINTER(SolveStats), vp]
     lib.vsie_solve_ports.argtypes = [vp, C.POINTER(SolveOpts), C.c_int, C.POINTER(C.c_int32), vp,
                                      C.POINTER(SolveStats), vp]
@@ -255,6 +256,21 @@ class Operator:
         _check(load().vsie_matvec(self._h, self._dtype_code(x), nrhs, C.c_void_p(x.data_ptr()),
                                   C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
         return y
+
+    def matvec_graph(self, x, out, stream=None):
+        """vsie_matvec_graph: the product replayed from a HIP graph captured for these two buffers
+        (keep both tensors alive while the operator may replay it)."""
+        if out is None:
+            raise ValueError("the graph product needs a fixed output tensor")
+        if x.dim() not in (1, 2) or x.shape[-1] != self.N or not x.is_contiguous() or not x.is_cuda:
+            raise ValueError("x must be a contiguous device tensor [N] or [nrhs][N] with N = %d" % self.N)
+        if (out.dtype != x.dtype or out.shape != x.shape or out.device != x.device or not out.is_contiguous()
+                or out.data_ptr() == x.data_ptr()):
+            raise ValueError("out must be a contiguous tensor of x's dtype, shape and device, not aliasing x")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        _check(load().vsie_matvec_graph(self._h, self._dtype_code(x), nrhs, C.c_void_p(x.data_ptr()),
+                                        C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
 
     def rhs(self, port, dtype=None, stream=None, out=None):
         """Delta-gap right-hand side of `port` (vsie_rhs), into `out` when given."""
