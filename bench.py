@@ -695,6 +695,7 @@ def main():
         "concurrent_far_block": {"value": round(value_conc, 3) if value_conc else None, "unit": "matvec/s",
                                  "identical_result": same},
         "graph_product": graph,
+        "zpass_autotune": {k: op.zpass_tuning(complex64=(k == "c64")) for k in ("c128", "c64")},
         "batched_rhs": batched,
         "solve": solve,
         "setup_seconds": round(setup_s, 2),

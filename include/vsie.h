@@ -201,6 +201,19 @@ int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, v
 int vsie_matvec_graph(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, void* y_dev,
                       void* stream);
 
+/* The z pass of the block-Toeplitz convolution (Sec. II-B: the FFT along the third axis with the
+ * 3 x 3 spectral product) is compiled in up to three radix/tile candidates per FFT length:
+ * 0 the default, 1 half the pencils per workgroup, 2 twice the values per thread. vsie_create
+ * times each candidate on the operator's own buffers (three launches after a warm-up) and keeps the
+ * fastest, per precision. vsie_zpass_tuning reports, for dtype (VSIE_C128 / VSIE_C64): the chosen
+ * candidate, and per candidate c < 3 its values per thread v[c], pencils per workgroup np[c] and
+ * measured milliseconds per launch ms[c] (v[c] = np[c] = 0 and ms[c] = 0 where a candidate does not
+ * exist for this length; all zero for FFT lengths outside 64..1024). vsie_zpass_select makes
+ * candidate cand the one in use (for tests and experiments; cached graphs are dropped).
+ * Errors: E_ARG, E_STATE (complex64 data not built; no candidates for this grid). */
+int vsie_zpass_tuning(struct vsie_handle* h, int dtype, int* chosen, int* v, int* np, double* ms);
+int vsie_zpass_select(struct vsie_handle* h, int dtype, int cand);
+
 /* Solve Z x = b for nrhs right-hand sides (device, [nrhs][N] complex128).
  * GMRES64: restarted GMRES (Sec. III-A), zero initial guess, FP64 classical Gram-Schmidt with a
  * second pass when the first leaves less than opts->reorth of the new vector's norm.

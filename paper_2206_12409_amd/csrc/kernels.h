@@ -36,11 +36,14 @@ void fft_rows(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, int 
 template <typename R>
 void fft_strided(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, int n_in, int n_out, int64_t in_stride,
                  int64_t out_stride, int n_lo, int64_t n_hi, int64_t in_hi, int64_t out_hi, const cx<R>* tw);
+// fused z pass; lengths 64..1024 run candidate `cand` (0..2) of the z-pass tunings with its block
+// order (pairs k2, k1 tile from zconv_order for the same candidate)
 template <typename R>
 void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const cx<R>* spec, const cx<R>* tw,
-                const int* order);
-// block order of the z pass (pairs k2, k1 tile; empty when the LDS-staged variant is used)
-std::vector<int> zconv_order(int L, int P1, int P2, bool fp64);
+                const int* order, int cand);
+std::vector<int> zconv_order(int L, int P1, int P2, bool fp64, int cand);
+bool zconv_candidate(int L, bool fp64, int cand);                 // candidate exists for this length
+void zconv_shape(int L, bool fp64, int cand, int* v, int* np);   // its values per thread, pencils per block
 
 // matvec
 // the first forward pass along x with the grid sources (masked x_b and the pFFT projection of x_n,

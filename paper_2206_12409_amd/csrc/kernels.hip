@@ -844,6 +844,14 @@ __device__ inline void zstep_any_c(int rad, cx<R>* Sp, cx<R>* v, int j, int Ls, 
   if (rad == V) zstep_c<R, L, V, FWD, V>(Sp, v, j, Ls, load, store, tw1);
   else if (rad == V / 2 && V >= 4) zstep_c<R, L, V, FWD, (V >= 4 ? V / 2 : 2)>(Sp, v, j, Ls, load, store, tw1);
   else if (rad == V / 4 && V >= 8) zstep_c<R, L, V, FWD, (V >= 8 ? V / 4 : 2)>(Sp, v, j, Ls, load, store, tw1);
+  else if (rad == V / 8 && V >= 16) zstep_c<R, L, V, FWD, (V >= 16 ? V / 8 : 2)>(Sp, v, j, Ls, load, store, tw1);
+}
+// the stage radices a length-L transform with V values per thread uses: V, then the remainder,
+// which zstep_any_c covers down to V / 8
+template <int L, int V> constexpr bool zradices_supported() {
+  using Z = ZRad<L, V>;
+  const int r = Z::rad(Z::nst - 1);
+  return r == V || (r == V / 2 && V >= 4) || (r == V / 4 && V >= 8) || (r == V / 8 && V >= 16);
 }
 // all stages of one transform on a pencil row held by one wavefront (or part of one); tws: the
 // per-stage twiddle tables (ZTw layout)
@@ -926,6 +934,7 @@ __global__ __launch_bounds__(NP * L / V) void k_zconv4(cx<R>* __restrict__ buf, 
   constexpr int RAD_LAST = ZRad<L, V>::rad(ZRad<L, V>::nst - 1);
   constexpr int NB_LAST = V / RAD_LAST;
   static_assert(T <= 64, "a pencil must fit one wavefront");
+  static_assert(zradices_supported<L, V>(), "last stage radix not handled by the exchange steps");
   __shared__ cx<R> S[NP * 3 * LP];
   __shared__ cx<R> tws[ZTw<L, V>::size()];   // per-stage twiddle tables
   const int t = threadIdx.x;
@@ -1040,14 +1049,34 @@ static_assert(ztw_size(64, 4) == ZTw<64, 4>::size() && ztw_size(128, 4) == ZTw<1
                   ztw_size(256, 4) == ZTw<256, 4>::size() && ztw_size(512, 8) == ZTw<512, 8>::size() &&
                   ztw_size(1024, 16) == ZTw<1024, 16>::size() && ztw_size(128, 8) == ZTw<128, 8>::size(),
               "twiddle table sizes");
-constexpr int zconv_np(int L, bool fp64) {
-  const int T = L / zconv_v(L, fp64);
-  int np = ZCONV_THREADS / T;
+// pencils per block for V values per thread: the thread target, then halved until the staging
+// and twiddles fit the LDS budget
+constexpr int zconv_np_for(int L, int V, bool fp64) {
+  int np = ZCONV_THREADS / (L / V);
   if (np < 1) np = 1;
   const int elem = fp64 ? 16 : 8;
-  const int tws = ztw_size(L, zconv_v(L, fp64));
+  const int tws = ztw_size(L, V);
   while (np > 1 && (np * 3 * (L + 1) + tws) * elem > ZCONV_LDS_CAP) np /= 2;
   return np;
+}
+// The z-pass candidates the autotuner times at setup (ZCONV_NCAND per length and precision):
+// 0 the measured default; 1 half the pencils per block (smaller blocks, more of them); 2 twice the
+// values per thread (one fewer exchange for some lengths, more registers), when that keeps at
+// least eight threads per pencil.
+constexpr int ZCONV_NCAND = 3;
+constexpr int zconv_cand_v(int L, bool fp64, int c) {
+  const int v0 = zconv_v(L, fp64);
+  return (c == 2 && 2 * v0 <= 16 && L / (2 * v0) >= 8) ? 2 * v0 : v0;
+}
+constexpr int zconv_cand_np(int L, bool fp64, int c) {
+  const int v = zconv_cand_v(L, fp64, c);
+  const int np = zconv_np_for(L, v, fp64);
+  return (c == 1 && np > 1) ? np / 2 : np;
+}
+constexpr bool zconv_cand_ok(int L, bool fp64, int c) {
+  if (c == 0) return true;
+  if (c == 1) return zconv_np_for(L, zconv_v(L, fp64), fp64) > 1;
+  return zconv_cand_v(L, fp64, 2) != zconv_v(L, fp64);
 }
 
 template <int L> struct Split;
@@ -1139,17 +1168,50 @@ void fft_strided(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, i
   });
 }
 
-int zconv_pencils(int L, bool fp64) {
-  if (L < 64 || L > 1024) return 0;
-  return zconv_np(L, fp64);
+int zconv_pencils(int L, bool fp64, int cand) {
+  if (L < 64 || L > 1024 || cand < 0 || cand >= ZCONV_NCAND) return 0;
+  int np = 0;
+  VSIE_FFT_SWITCH(L, {
+    if (fp64) {
+      if (cand == 0) np = zconv_cand_np(LL, true, 0);
+      else if (cand == 1) np = zconv_cand_np(LL, true, 1);
+      else np = zconv_cand_np(LL, true, 2);
+    } else {
+      if (cand == 0) np = zconv_cand_np(LL, false, 0);
+      else if (cand == 1) np = zconv_cand_np(LL, false, 1);
+      else np = zconv_cand_np(LL, false, 2);
+    }
+  });
+  return np;
+}
+bool zconv_candidate(int L, bool fp64, int cand) {
+  if (L < 64 || L > 1024 || cand < 0 || cand >= ZCONV_NCAND) return false;
+  bool ok = false;
+  VSIE_FFT_SWITCH(L, {
+    if (cand == 0) ok = true;
+    else if (cand == 1) ok = zconv_cand_ok(LL, fp64, 1);
+    else ok = zconv_cand_ok(LL, fp64, 2);
+  });
+  return ok;
+}
+void zconv_shape(int L, bool fp64, int cand, int* v, int* np) {
+  *v = 0;
+  *np = 0;
+  if (!zconv_candidate(L, fp64, cand)) return;
+  VSIE_FFT_SWITCH(L, {
+    if (cand == 0) *v = zconv_cand_v(LL, fp64, 0);
+    else if (cand == 1) *v = zconv_cand_v(LL, fp64, 1);
+    else *v = zconv_cand_v(LL, fp64, 2);
+  });
+  *np = zconv_pencils(L, fp64, cand);
 }
 
-std::vector<int> zconv_order(int L, int P1, int P2, bool fp64) {
+std::vector<int> zconv_order(int L, int P1, int P2, bool fp64, int cand) {
   // Blocks that share spectral records (k2 and P2 - k2; k1 tiles t and TL - 1 - t) and input
   // cache lines (neighbouring tiles t, t + 1) form groups of up to eight. Workgroups are handed
   // to the eight XCDs round-robin, so the members of a full group are placed eight positions
   // apart: they run on one XCD, one after another, and share its L2.
-  const int NP = zconv_pencils(L, fp64);
+  const int NP = zconv_pencils(L, fp64, cand);
   std::vector<int> ord;
   if (NP == 0) return ord;
   const int TL = (P1 + NP - 1) / NP;
@@ -1194,20 +1256,32 @@ std::vector<int> zconv_order(int L, int P1, int P2, bool fp64) {
   return ord;
 }
 
+template <typename R, int LL, int C>
+static void zconv_launch(hipStream_t st, cx<R>* buf, int n3, int P1, int P2, const cx<R>* spec, const cx<R>* tw,
+                         const int* order) {
+  constexpr bool F64 = sizeof(R) == 8;
+  if constexpr (zconv_cand_ok(LL, F64, C)) {
+    constexpr int V = zconv_cand_v(LL, F64, C);
+    constexpr int NP = zconv_cand_np(LL, F64, C);
+    dim3 grid((unsigned)(P2 * ((P1 + NP - 1) / NP)));
+    hipLaunchKernelGGL((k_zconv4<R, LL, V, NP>), grid, dim3(NP * LL / V), 0, st, buf, n3, P1, P2, spec, tw, order);
+  } else {
+    throw Error(VSIE_E_ARG, "z-pass candidate not available for this length");
+  }
+}
+
 template <typename R>
 void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const cx<R>* spec, const cx<R>* tw,
-                const int* order) {
+                const int* order, int cand) {
   // register-staged Stockham transform: V values per thread and component, one pencil per group
   if (L >= 64 && L <= 1024) {
     if (!order) throw Error(VSIE_E_STATE, "z-pass block order missing");
     VSIE_FFT_SWITCH(L, {
       if constexpr (LL >= 64) {
-        constexpr bool F64 = sizeof(R) == 8;
-        constexpr int V = zconv_v(LL, F64);
-        constexpr int NP = zconv_np(LL, F64);
-        dim3 grid((unsigned)(P2 * ((P1 + NP - 1) / NP)));
-        hipLaunchKernelGGL((k_zconv4<R, LL, V, NP>), grid, dim3(NP * LL / V), 0, st, buf, n3, P1, P2, spec, tw,
-                           order);
+        if (cand == 0) (zconv_launch<R, LL, 0>)(st, buf, n3, P1, P2, spec, tw, order);
+        else if (cand == 1) (zconv_launch<R, LL, 1>)(st, buf, n3, P1, P2, spec, tw, order);
+        else if (cand == 2) (zconv_launch<R, LL, 2>)(st, buf, n3, P1, P2, spec, tw, order);
+        else throw Error(VSIE_E_ARG, "z-pass candidate out of range");
       }
     });
     return;
@@ -1231,8 +1305,8 @@ template void fft_strided<double>(hipStream_t, int, bool, const cxd*, cxd*, int,
                                   int64_t, int64_t, const cxd*);
 template void fft_strided<float>(hipStream_t, int, bool, const cxf*, cxf*, int, int, int64_t, int64_t, int, int64_t,
                                  int64_t, int64_t, const cxf*);
-template void fft_z_conv<double>(hipStream_t, int, cxd*, int, int, int, const cxd*, const cxd*, const int*);
-template void fft_z_conv<float>(hipStream_t, int, cxf*, int, int, int, const cxf*, const cxf*, const int*);
+template void fft_z_conv<double>(hipStream_t, int, cxd*, int, int, int, const cxd*, const cxd*, const int*, int);
+template void fft_z_conv<float>(hipStream_t, int, cxf*, int, int, int, const cxf*, const cxf*, const int*, int);
 
 // =============================================================================================
 // Matvec kernels

@@ -115,7 +115,7 @@ template <typename R> cx<R>* twiddles(Handle& H, int L) {
 void setup_volume(Handle& H) {
   hipStream_t st = H.stream;
   for (int v = 0; v < 2; ++v) {
-    const std::vector<int> ord = zconv_order(H.P[2], H.P[0], H.P[1], v == 0);
+    const std::vector<int> ord = zconv_order(H.P[2], H.P[0], H.P[1], v == 0, 0);
     if (!ord.empty()) H.d_zorder[v] = upload<int>(H, ord);
   }
   GaussTab gt_h;
@@ -568,6 +568,46 @@ void upload_tt(Handle& H, int chi) {
   }
 }
 
+// Autotuner of the z pass (radix and tile): every compiled candidate for this FFT length runs on
+// the operator's own work buffer and spectra (three timed launches after one warm-up), and the
+// fastest is kept with its block order.
+template <typename R> static void tune_zpass(Handle& H, OpData<R>& D) {
+  const int L = H.P[2];
+  const bool f64 = sizeof(R) == 8;
+  const int v = f64 ? 0 : 1;
+  if (L < 64 || L > 1024) return;
+  hipStream_t st = H.stream;
+  const int P1 = H.P[0], P2 = H.P[1], ne3 = H.ne[2];
+  VSIE_HIP(hipMemsetAsync(D.bufC, 0, sizeof(cx<R>) * 3 * (size_t)ne3 * P2 * P1, st));
+  hipEvent_t e0, e1;
+  VSIE_HIP(hipEventCreate(&e0));
+  VSIE_HIP(hipEventCreate(&e1));
+  double best = 1e300;
+  int bc = 0;
+  int* orders[3] = {};
+  for (int c = 0; c < 3; ++c) {
+    H.ztime[v][c] = 0;
+    if (!zconv_candidate(L, f64, c)) continue;
+    orders[c] = upload<int>(H, zconv_order(L, P1, P2, f64, c));
+    fft_z_conv<R>(st, L, D.bufC, ne3, P1, P2, D.spec, D.tw[2], orders[c], c);
+    VSIE_HIP(hipEventRecord(e0, st));
+    for (int k = 0; k < 3; ++k) fft_z_conv<R>(st, L, D.bufC, ne3, P1, P2, D.spec, D.tw[2], orders[c], c);
+    VSIE_HIP(hipEventRecord(e1, st));
+    VSIE_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    VSIE_HIP(hipEventElapsedTime(&ms, e0, e1));
+    H.ztime[v][c] = ms / 3.0;
+    if (ms / 3.0 < best) {
+      best = ms / 3.0;
+      bc = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  H.zcand[v] = bc;
+  H.d_zorder[v] = orders[bc];
+}
+
 template <typename R> void alloc_work(Handle& H, OpData<R>& D) {
   D.gridA = H.dalloc<cx<R>>(3 * H.Ne);
   D.bufB = H.dalloc<cx<R>>(3LL * H.ne[2] * H.ne[1] * H.P[0]);
@@ -653,7 +693,8 @@ static void volume_chain(Handle& H, OpData<R>& D, const cx<R>* xn, const cx<R>* 
   fft_strided<R>(st, P2, true, D.bufB, D.bufC, ne2, P2, P1, P1, P1, 3LL * ne3, (int64_t)ne2 * P1, (int64_t)P2 * P1, D.tw[1]);
   T.end(2, st);
   T.begin(3, st);
-  fft_z_conv<R>(st, P3, D.bufC, ne3, P1, P2, D.spec, D.tw[2], H.d_zorder[sizeof(R) == 8 ? 0 : 1]);
+  fft_z_conv<R>(st, P3, D.bufC, ne3, P1, P2, D.spec, D.tw[2], H.d_zorder[sizeof(R) == 8 ? 0 : 1],
+                H.zcand[sizeof(R) == 8 ? 0 : 1]);
   T.end(3, st);
   T.begin(4, st);
   fft_strided<R>(st, P2, false, D.bufC, D.bufB, P2, ne2, P1, P1, P1, 3LL * ne3, (int64_t)P2 * P1, (int64_t)ne2 * P1, D.tw[1]);
@@ -1599,6 +1640,8 @@ int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, v
     }
     alloc_work<double>(H, H.d64);
     if (H.opts.precision) alloc_work<float>(H, H.d32);
+    tune_zpass<double>(H, H.d64);
+    if (H.opts.precision) tune_zpass<float>(H, H.d32);
     VSIE_HIP(hipStreamSynchronize(H.stream));
     H.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   });
@@ -1723,6 +1766,38 @@ int vsie_matvec_graph(vsie_handle* hd, int dtype, int nrhs, const void* x_dev, v
       ge = &H.graphs.back();
     }
     VSIE_HIP(hipGraphLaunch(ge->exec, st));
+  });
+}
+
+int vsie_zpass_tuning(vsie_handle* hd, int dtype, int* chosen, int* v, int* np, double* ms) {
+  if (!hd || !chosen || !v || !np || !ms) return fail(VSIE_E_ARG, "null argument");
+  if (dtype != VSIE_C128 && dtype != VSIE_C64) return fail(VSIE_E_ARG, "bad dtype");
+  Handle& H = hd->H;
+  const int p = dtype == VSIE_C128 ? 0 : 1;
+  if (p == 1 && !H.have32) return fail(VSIE_E_STATE, "complex64 operator data not built");
+  return guarded([&]() {
+    *chosen = H.zcand[p];
+    for (int c = 0; c < 3; ++c) {
+      zconv_shape(H.P[2], p == 0, c, &v[c], &np[c]);
+      ms[c] = H.ztime[p][c];
+    }
+  });
+}
+
+int vsie_zpass_select(vsie_handle* hd, int dtype, int cand) {
+  if (!hd) return fail(VSIE_E_ARG, "null argument");
+  if (dtype != VSIE_C128 && dtype != VSIE_C64) return fail(VSIE_E_ARG, "bad dtype");
+  Handle& H = hd->H;
+  const int p = dtype == VSIE_C128 ? 0 : 1;
+  if (p == 1 && !H.have32) return fail(VSIE_E_STATE, "complex64 operator data not built");
+  if (H.P[2] < 64 || H.P[2] > 1024) return fail(VSIE_E_STATE, "this grid's z pass has no candidates");
+  if (!zconv_candidate(H.P[2], p == 0, cand)) return fail(VSIE_E_ARG, "no such z-pass candidate for this length");
+  return guarded([&]() {
+    VSIE_HIP(hipStreamSynchronize(H.stream));
+    H.d_zorder[p] = upload<int>(H, zconv_order(H.P[2], H.P[0], H.P[1], p == 0, cand));
+    H.zcand[p] = cand;
+    for (auto& g : H.graphs) (void)hipGraphExecDestroy(g.exec);
+    H.graphs.clear();
   });
 }
 

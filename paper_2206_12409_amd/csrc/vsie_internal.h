@@ -148,7 +148,9 @@ struct Handle {
   int* d_tiles = nullptr;         // [ntiles][2] (I, J), I <= J
   // body mask
   uint8_t* d_mask = nullptr;
-  int* d_zorder[2] = {};       // z-pass block order, FP64 / FP32 variants
+  int* d_zorder[2] = {};       // z-pass block order, FP64 / FP32, of the candidate in use
+  int zcand[2] = {0, 0};       // z-pass candidate chosen by the setup autotuner, FP64 / FP32
+  double ztime[2][3] = {};     // its measured time per launch (ms) of every candidate (0: absent)
   // TT
   int tt_r[3][3] = {};
   double tt_err[3] = {0, 0, 0};

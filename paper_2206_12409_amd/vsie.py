@@ -23,7 +23,7 @@ VSIE_PREC_FP64, VSIE_PREC_MIXED = 0, 1
 X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
 
 EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_sizes", "vsie_rhs",
-            "vsie_matvec", "vsie_matvec_graph", "vsie_solve", "vsie_solve_ports", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
+            "vsie_matvec", "vsie_matvec_graph", "vsie_zpass_tuning", "vsie_zpass_select", "vsie_solve", "vsie_solve_ports", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
             "vsie_profile", "vsie_profile_mask", "vsie_profile_read", "vsie_schur_setup", "vsie_schur_info",
             "vsie_schur_matvec", "vsie_schur_precond", "vsie_dense_lu_solve", "vsie_dense_lu_solve_noalloc",
             "vsie_net_create", "vsie_net_destroy", "vsie_net_info", "vsie_net_get_params", "vsie_net_set_params",
@@ -92,6 +92,9 @@ def load(path=LIB_PATH):
     lib.vsie_rhs.argtypes = [vp, C.c_int, C.c_int, vp, vp]
     lib.vsie_matvec.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
     lib.vsie_matvec_graph.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
+    lib.vsie_zpass_tuning.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_double)]
+    lib.vsie_zpass_select.argtypes = [vp, C.c_int, C.c_int]
     lib.vsie_solve.argtypes = [vp, C.POINTER(SolveOpts), C.c_int, vp, vp, C.POINTER(SolveStats), vp]
     lib.vsie_solve_ports.argtypes = [vp, C.POINTER(SolveOpts), C.c_int, C.POINTER(C.c_int32), vp,
                                      C.POINTER(SolveStats), vp]
@@ -271,6 +274,18 @@ class Operator:
         _check(load().vsie_matvec_graph(self._h, self._dtype_code(x), nrhs, C.c_void_p(x.data_ptr()),
                                         C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
+
+    def zpass_tuning(self, complex64=False):
+        """The setup autotuner's z-pass result: {"chosen": c, "candidates": [(v, np, ms), ...]}."""
+        ch = C.c_int(0)
+        v = (C.c_int * 3)()
+        npb = (C.c_int * 3)()
+        ms = (C.c_double * 3)()
+        _check(load().vsie_zpass_tuning(self._h, VSIE_C64 if complex64 else VSIE_C128, C.byref(ch), v, npb, ms))
+        return {"chosen": ch.value, "candidates": [(v[i], npb[i], ms[i]) for i in range(3)]}
+
+    def zpass_select(self, cand, complex64=False):
+        _check(load().vsie_zpass_select(self._h, VSIE_C64 if complex64 else VSIE_C128, int(cand)))
 
     def rhs(self, port, dtype=None, stream=None, out=None):
         """Delta-gap right-hand side of `port` (vsie_rhs), into `out` when given."""

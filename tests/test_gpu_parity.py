@@ -227,7 +227,8 @@ def test_body_only_volume_operator():
 def test_z_pass_lengths(lib, n):
     """Body-only product on boxes whose z extent selects each fused z-pass length P3 = 64, 128,
     256, 512, 1024 (P1 = 8 is below the pencils per block at the two shortest lengths, so the
-    pencil tiles are ragged): FP64 at 1e-10 and complex64 at 1e-5 against the dense Galerkin
+    pencil tiles are ragged), with every radix/tile candidate of the autotuner (the chosen one is
+    the fastest measured): FP64 at 1e-10 and complex64 at 1e-5 against the dense Galerkin
     matrix."""
     g = synth.random_block(n, 5e-3, seed=sum(n))
     p = synth.Problem(g, [], synth.problems.LARMOR_7T_HZ, "block")
@@ -236,13 +237,23 @@ def test_z_pass_lengths(lib, n):
     S, _ = system.assemble_direct(d)
     x = synth.complex_normal(op.N, 11)
     ref = S.matvec(x)
-    e64 = rel(op.matvec(to_dev(x)).cpu().numpy(), ref)
-    y32 = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
-    e32 = rel(y32, ref)
-    print("z-pass box %s: FP64 %.2e, complex64 %.2e" % (n, e64, e32))
+    # every radix/tile candidate of the setup autotuner, in both precisions
+    for c64 in (False, True):
+        tune = op.zpass_tuning(complex64=c64)
+        assert tune["candidates"][tune["chosen"]][2] == min(ms for v, npb, ms in tune["candidates"] if v > 0)
+        for cand, (v, npb, ms) in enumerate(tune["candidates"]):
+            if v == 0:
+                continue
+            op.zpass_select(cand, complex64=c64)
+            if c64:
+                y = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+            else:
+                y = op.matvec(to_dev(x)).cpu().numpy()
+            e = rel(y, ref)
+            print("z-pass box %s, %s candidate %d (V %d, %d pencils per block, %.3f ms): %.2e"
+                  % (n, "complex64" if c64 else "FP64", cand, v, npb, ms, e))
+            assert e < (1e-5 if c64 else 1e-10)
     op.close()
-    assert e64 < 1e-10
-    assert e32 < 1e-5
 
 
 def test_tt_cross_accuracy_against_brute_force():
