@@ -166,10 +166,20 @@ int vsie_default_solve_opts(vsie_solve_opts* opts);
 /* Set up the operator (Sec. III): RWG tables, extended grid, Green-tensor generator and its
  * circulant spectra (Sec. II-B), pFFT stencils and precorrection (eq. (13)), TT-cross of the far
  * coupling (eq. (14)), ACA of the near-far block (eq. (12)), dense Z_cc^ff (eq. (6)).
- * All inputs are copied; the handle owns every device allocation. Blocks until done.
+ * All inputs are copied; the handle owns every device allocation (the dense far block may be
+ * shared with handles made by vsie_create_shared). Blocks until done.
  * Errors: E_ARG, E_MESH, E_STENCIL, E_GRID, E_NOMEM, E_HIP, E_UNSUPPORTED. */
 int vsie_create(const vsie_problem* problem, const vsie_options* opts, void* stream,
                 struct vsie_handle** out);
+
+/* As vsie_create, but the dense far block Z_cc^ff (eq. (6)) and its tiling are taken from donor
+ * instead of assembled: for several phantoms inside the same far conductors (shield) at the same
+ * frequency. The far meshes (vertices, triangles and their order, hence the RWG numbering) and the
+ * frequency must equal the donor's, else E_ARG. The block is shared, not copied: it stays allocated
+ * while any handle built on it lives, in any destruction order; the complex64 copy is shared too.
+ * Errors: as vsie_create; E_STATE when the donor has no dense far block. */
+int vsie_create_shared(const vsie_problem* problem, const vsie_options* opts, struct vsie_handle* donor,
+                       void* stream, struct vsie_handle** out);
 
 /* Sizes of the discrete system of eq. (15) (unknown counts of Sec. III: far and near RWG functions,
  * three PWC components per voxel), the extended pFFT grid and its circulant FFT sizes (Sec. II-B),
@@ -200,6 +210,19 @@ int vsie_matvec(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, v
  * Up to 16 graphs are kept per handle (the oldest is dropped). Errors: as vsie_matvec. */
 int vsie_matvec_graph(struct vsie_handle* h, int dtype, int nrhs, const void* x_dev, void* y_dev,
                       void* stream);
+
+/* Products of several operators in one launch: one HIP graph holding, one operator after another,
+ * the launches of vsie_matvec(hs[i], dtype, nrhs[i], x[i], y[i]) for i < n (phantoms of different
+ * grids and ports in one batch, e.g. inside one shield); vsie_graph_launch replays all of them on
+ * stream, with the results of n separate vsie_matvec calls bit for bit. The operators and buffers
+ * must outlive the graph, and an operator may appear only once (its work buffers serve one product
+ * at a time); creation waits for stream. Errors: E_ARG, E_STATE (complex64 data not built), E_HIP,
+ * E_NOMEM. */
+typedef struct vsie_graph vsie_graph;
+int vsie_graph_create(int n, struct vsie_handle* const* hs, int dtype, const int* nrhs,
+                      const void* const* x_dev, void* const* y_dev, void* stream, vsie_graph** out);
+int vsie_graph_launch(vsie_graph* g, void* stream);
+int vsie_graph_destroy(vsie_graph* g);
 
 /* The z pass of the block-Toeplitz convolution (Sec. II-B: the FFT along the third axis with the
  * 3 x 3 spectral product) is compiled in up to three radix/tile candidates per FFT length:

@@ -18,6 +18,11 @@ struct vsie_handle {
   Handle H;
 };
 
+struct vsie_graph {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+};
+
 struct vsie_net {
   NetState S;
 };
@@ -340,34 +345,64 @@ void setup_pfft(Handle& H) {
 // ---------------------------------------------------------------------------------------------
 // far conductors: dense block, ACA of the near-far block, TT-cross of the far coupling
 // dense far block (eq. (6)), symmetric: only the upper-triangle tiles are assembled and stored
+template <typename T> static T* share_alloc(int64_t count) {
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(T) * (size_t)std::max<int64_t>(count, 1)) != hipSuccess)
+    throw Error(VSIE_E_NOMEM, "hipMalloc of the dense far block failed");
+  return (T*)p;
+}
+
+// assembled once per set of far conductors (H.far_share set beforehand: adopted from the operator
+// it was shared with)
 void setup_dense_far(Handle& H) {
   const int T = (H.mf + SYM_TB - 1) / SYM_TB;
   H.sym_T = T;
-  std::vector<int> tiles;
-  for (int I = 0; I < T; ++I)
-    for (int J = I; J < T; ++J) {
-      tiles.push_back(I);
-      tiles.push_back(J);
-    }
-  H.d_tiles = upload(H, tiles);
   const int64_t nt = (int64_t)T * (T + 1) / 2;
   const int64_t per = (int64_t)SYM_TB * SYM_TB;
-  H.d64.Zff = H.dalloc<cxd>(nt * per);
+  if (!H.far_share) {
+    auto sh = std::make_shared<FarShare>();
+    std::vector<int> tiles;
+    for (int I = 0; I < T; ++I)
+      for (int J = I; J < T; ++J) {
+        tiles.push_back(I);
+        tiles.push_back(J);
+      }
+    sh->T = T;
+    sh->k0 = H.k0;
+    sh->verts = H.far.verts;
+    sh->tris = H.far.tris;
+    sh->ea = H.far.ea;
+    sh->eb = H.far.eb;
+    sh->tp = H.far.tp;
+    sh->tm = H.far.tm;
+    sh->tiles = share_alloc<int>((int64_t)tiles.size());
+    VSIE_HIP(hipMemcpy(sh->tiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice));
+    sh->z64 = share_alloc<cxd>(nt * per);
+    const int64_t chunk = std::max<int64_t>(1, (1LL << 26) / per);
+    for (int64_t t0 = 0; t0 < nt; t0 += chunk)
+      launch_zcc_packed(H.stream, H.dfar, H.k0, sh->tiles, t0, std::min(chunk, nt - t0), sh->z64 + t0 * per);
+    VSIE_HIP(hipGetLastError());
+    VSIE_HIP(hipStreamSynchronize(H.stream));
+    H.device_bytes += sizeof(cxd) * nt * per;
+    H.far_share = sh;
+  }
+  H.d_tiles = H.far_share->tiles;
+  H.d64.Zff = H.far_share->z64;
   H.d64.sym_part = H.dalloc<cxd>(nt * 2 * SYM_TB);
-  const int64_t chunk = std::max<int64_t>(1, (1LL << 26) / per);
-  for (int64_t t0 = 0; t0 < nt; t0 += chunk)
-    launch_zcc_packed(H.stream, H.dfar, H.k0, H.d_tiles, t0, std::min(chunk, nt - t0), H.d64.Zff + t0 * per);
-  VSIE_HIP(hipGetLastError());
-  VSIE_HIP(hipStreamSynchronize(H.stream));
 }
 
 void copy_zff_c64(Handle& H) {
   const int64_t T = H.sym_T;
   const int64_t n = T * (T + 1) / 2 * SYM_TB * SYM_TB;
-  H.d32.Zff = H.dalloc<cxf>(n);
+  FarShare& sh = *H.far_share;
+  if (!sh.z32) {
+    sh.z32 = share_alloc<cxf>(n);
+    launch_d2f(H.stream, sh.z64, sh.z32, n);
+    VSIE_HIP(hipStreamSynchronize(H.stream));
+    H.device_bytes += sizeof(cxf) * n;
+  }
+  H.d32.Zff = sh.z32;
   H.d32.sym_part = H.dalloc<cxf>(T * (T + 1) / 2 * 2 * SYM_TB);
-  launch_d2f(H.stream, H.d64.Zff, H.d32.Zff, n);
-  VSIE_HIP(hipStreamSynchronize(H.stream));
 }
 
 void setup_aca(Handle& H) {
@@ -1529,7 +1564,22 @@ static void progress(const char* what, std::chrono::steady_clock::time_point t0)
   fflush(stderr);
 }
 
+static int create_impl(const vsie_problem* p, const vsie_options* opts, void* stream, vsie_handle* donor,
+                       vsie_handle** out);
+
 int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, vsie_handle** out) {
+  return create_impl(p, opts, stream, nullptr, out);
+}
+
+int vsie_create_shared(const vsie_problem* p, const vsie_options* opts, vsie_handle* donor, void* stream,
+                       vsie_handle** out) {
+  if (!donor) return fail(VSIE_E_ARG, "null donor");
+  if (!donor->H.far_share) return fail(VSIE_E_STATE, "the donor has no dense far block");
+  return create_impl(p, opts, stream, donor, out);
+}
+
+static int create_impl(const vsie_problem* p, const vsie_options* opts, void* stream, vsie_handle* donor,
+                       vsie_handle** out) {
   if (!p || !out) return fail(VSIE_E_ARG, "null argument");
   *out = nullptr;
   vsie_handle* hd = new (std::nothrow) vsie_handle();
@@ -1578,6 +1628,11 @@ int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, v
     build_rwg(p, VSIE_NEAR, H.near, pn);
     H.mf = H.far.m;
     H.mn = H.near.m;
+    if (donor) {
+      if (H.mf == 0 || !donor->H.far_share->same(H.far, H.k0))
+        throw Error(VSIE_E_ARG, "far conductors or frequency differ from the donor's");
+      H.far_share = donor->H.far_share;
+    }
     // ports in the order of the mesh list
     for (int mi = 0; mi < p->n_meshes; ++mi) {
       for (auto& q : pf)
@@ -1767,6 +1822,91 @@ int vsie_matvec_graph(vsie_handle* hd, int dtype, int nrhs, const void* x_dev, v
     }
     VSIE_HIP(hipGraphLaunch(ge->exec, st));
   });
+}
+
+// Products of several operators (phantoms of any grid sizes) captured one after another into one
+// HIP graph, replayed by one launch.
+int vsie_graph_create(int n, vsie_handle* const* hs, int dtype, const int* nrhs, const void* const* x,
+                      void* const* y, void* stream, vsie_graph** out) {
+  if (!out) return fail(VSIE_E_ARG, "null argument");
+  *out = nullptr;
+  if (n < 1 || !hs || !nrhs || !x || !y) return fail(VSIE_E_ARG, "bad argument");
+  if (dtype != VSIE_C128 && dtype != VSIE_C64) return fail(VSIE_E_ARG, "bad dtype");
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || !x[i] || !y[i] || nrhs[i] < 1 || x[i] == y[i]) return fail(VSIE_E_ARG, "bad operator or buffer");
+    if (dtype == VSIE_C64 && !hs[i]->H.have32) return fail(VSIE_E_STATE, "complex64 operator data not built");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(VSIE_E_ARG, "an operator appears twice (its work buffers are shared)");
+  }
+  vsie_graph* g = new (std::nothrow) vsie_graph();
+  if (!g) return fail(VSIE_E_NOMEM, "graph allocation");
+  const int rc = guarded([&]() {
+    VSIE_HIP(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+    for (int i = 0; i < n; ++i) {
+      Handle& H = hs[i]->H;
+      if (nrhs[i] > 1 && H.mf > 0) {
+        const int64_t nt = (int64_t)H.sym_T * (H.sym_T + 1) / 2;
+        if (dtype == VSIE_C128 && !H.d64.multi_part) H.d64.multi_part = H.dalloc<cxd>(16 * nt * 2 * SYM_TB);
+        if (dtype == VSIE_C64 && !H.d32.multi_part) H.d32.multi_part = H.dalloc<cxf>(16 * nt * 2 * SYM_TB);
+      }
+    }
+    VSIE_HIP(hipStreamSynchronize((hipStream_t)stream));
+    std::vector<std::pair<bool, bool>> saved;
+    for (int i = 0; i < n; ++i) {
+      saved.push_back({hs[i]->H.concurrent, hs[i]->H.prof});
+      hs[i]->H.concurrent = false;
+      hs[i]->H.prof = false;
+    }
+    auto restore = [&]() {
+      for (int i = 0; i < n; ++i) {
+        hs[i]->H.concurrent = saved[i].first;
+        hs[i]->H.prof = saved[i].second;
+      }
+    };
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        for (int i = 0; i < n; ++i) {
+          Handle& H = hs[i]->H;
+          if (dtype == VSIE_C128) matvec_batch<double>(H, H.d64, (const cxd*)x[i], (cxd*)y[i], nrhs[i], g->cap);
+          else matvec_batch<float>(H, H.d32, (const cxf*)x[i], (cxf*)y[i], nrhs[i], g->cap);
+        }
+      } catch (...) {
+        (void)hipStreamEndCapture(g->cap, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        restore();
+        throw;
+      }
+      e = hipStreamEndCapture(g->cap, &graph);
+    }
+    restore();
+    if (e != hipSuccess) throw Error(VSIE_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) throw Error(VSIE_E_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+  });
+  if (rc != VSIE_OK) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return VSIE_OK;
+}
+
+int vsie_graph_launch(vsie_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(VSIE_E_ARG, "null graph");
+  return guarded([&]() { VSIE_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream)); });
+}
+
+int vsie_graph_destroy(vsie_graph* g) {
+  if (!g) return VSIE_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  delete g;
+  return VSIE_OK;
 }
 
 int vsie_zpass_tuning(vsie_handle* hd, int dtype, int* chosen, int* v, int* np, double* ms) {

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <functional>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -104,6 +105,29 @@ struct DenseLU {
 
 struct NetState;
 
+// The dense far block (packed symmetric tiles, eq. (6)) and its tile table, shared by every
+// operator built over the same far conductors at the same frequency (several phantoms inside one
+// shield): the last operator that holds it frees it. `same` compares the far RWG set (geometry
+// and numbering) and the wavenumber.
+struct FarShare {
+  cxd* z64 = nullptr;
+  cxf* z32 = nullptr;
+  int* tiles = nullptr;
+  int T = 0;
+  double k0 = 0;
+  std::vector<double> verts;
+  std::vector<int> tris, ea, eb, tp, tm;
+  bool same(const Rwg& far, double k) const {
+    return k == k0 && far.verts == verts && far.tris == tris && far.ea == ea && far.eb == eb && far.tp == tp &&
+           far.tm == tm;
+  }
+  ~FarShare() {
+    if (z64) (void)hipFree(z64);
+    if (z32) (void)hipFree(z32);
+    if (tiles) (void)hipFree(tiles);
+  }
+};
+
 struct Handle {
   // problem
   int n[3];
@@ -146,6 +170,7 @@ struct Handle {
   // far block tiling
   int sym_T = 0;
   int* d_tiles = nullptr;         // [ntiles][2] (I, J), I <= J
+  std::shared_ptr<FarShare> far_share;   // owner of the dense far block and d_tiles
   // body mask
   uint8_t* d_mask = nullptr;
   int* d_zorder[2] = {};       // z-pass block order, FP64 / FP32, of the candidate in use

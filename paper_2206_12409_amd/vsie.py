@@ -22,7 +22,8 @@ VSIE_BASIS_PWC, VSIE_BASIS_PWL = 0, 1
 VSIE_PREC_FP64, VSIE_PREC_MIXED = 0, 1
 X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
 
-EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_sizes", "vsie_rhs",
+EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_create_shared", "vsie_sizes",
+            "vsie_rhs", "vsie_graph_create", "vsie_graph_launch", "vsie_graph_destroy",
             "vsie_matvec", "vsie_matvec_graph", "vsie_zpass_tuning", "vsie_zpass_select", "vsie_solve", "vsie_solve_ports", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
             "vsie_profile", "vsie_profile_mask", "vsie_profile_read", "vsie_schur_setup", "vsie_schur_info",
             "vsie_schur_matvec", "vsie_schur_precond", "vsie_dense_lu_solve", "vsie_dense_lu_solve_noalloc",
@@ -88,6 +89,11 @@ def load(path=LIB_PATH):
     lib.vsie_default_options.argtypes = [C.POINTER(Options)]
     lib.vsie_default_solve_opts.argtypes = [C.POINTER(SolveOpts)]
     lib.vsie_create.argtypes = [C.POINTER(ProblemC), C.POINTER(Options), vp, C.POINTER(vp)]
+    lib.vsie_create_shared.argtypes = [C.POINTER(ProblemC), C.POINTER(Options), vp, vp, C.POINTER(vp)]
+    lib.vsie_graph_create.argtypes = [C.c_int, C.POINTER(vp), C.c_int, C.POINTER(C.c_int), C.POINTER(vp),
+                                      C.POINTER(vp), vp, C.POINTER(vp)]
+    lib.vsie_graph_launch.argtypes = [vp, vp]
+    lib.vsie_graph_destroy.argtypes = [vp]
     lib.vsie_sizes.argtypes = [vp, C.POINTER(Sizes)]
     lib.vsie_rhs.argtypes = [vp, C.c_int, C.c_int, vp, vp]
     lib.vsie_matvec.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp]
@@ -166,7 +172,9 @@ def _stream_ptr(stream):
 class Operator:
     """Hybrid VSIE operator of one problem (vsie_synth.Problem-like: grid, meshes, freq_hz)."""
 
-    def __init__(self, problem, options=None, stream=None, **opt_kw):
+    def __init__(self, problem, options=None, stream=None, share_far_with=None, **opt_kw):
+        """share_far_with: an Operator over the same far conductors and frequency whose dense far
+        block this one uses instead of assembling its own (vsie_create_shared)."""
         lib = load()
         g = problem.grid
         self._keep = []
@@ -199,7 +207,11 @@ class Operator:
         p.meshes = meshes
         opts = options if options is not None else default_options(**opt_kw)
         h = C.c_void_p()
-        _check(lib.vsie_create(C.byref(p), C.byref(opts), _stream_ptr(stream), C.byref(h)))
+        if share_far_with is None:
+            _check(lib.vsie_create(C.byref(p), C.byref(opts), _stream_ptr(stream), C.byref(h)))
+        else:
+            _check(lib.vsie_create_shared(C.byref(p), C.byref(opts), share_far_with._h, _stream_ptr(stream),
+                                          C.byref(h)))
         self._h = h
         self._keep = None
         s = Sizes()
@@ -485,6 +497,49 @@ def _dev_ptr(t, dtype_name="float32"):
     if not t.is_cuda or not t.is_contiguous() or t.dtype != getattr(torch, dtype_name):
         raise ValueError("contiguous %s device tensors only" % dtype_name)
     return C.c_void_p(t.data_ptr())
+
+
+class ProductGraph:
+    """vsie_graph_create: the products of several operators (each with its own fixed x and out
+    tensors) captured into one HIP graph; launch() replays them all. Keep the operators and tensors
+    alive while the graph is used."""
+
+    def __init__(self, ops, xs, outs, stream=None):
+        if not (len(ops) == len(xs) == len(outs)) or not ops:
+            raise ValueError("one x and one out tensor per operator")
+        dt = None
+        for op, x, y in zip(ops, xs, outs):
+            if x.dim() not in (1, 2) or x.shape[-1] != op.N or not x.is_contiguous() or not x.is_cuda:
+                raise ValueError("x must be a contiguous device tensor [N] or [nrhs][N] of its operator")
+            if y.shape != x.shape or y.dtype != x.dtype or not y.is_contiguous() or y.data_ptr() == x.data_ptr():
+                raise ValueError("out must match x and not alias it")
+            code = op._dtype_code(x)
+            if dt is not None and code != dt:
+                raise ValueError("all products in one precision")
+            dt = code
+        n = len(ops)
+        hs = (C.c_void_p * n)(*[op._h.value for op in ops])
+        nr = (C.c_int * n)(*[1 if x.dim() == 1 else x.shape[0] for x in xs])
+        xp = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        yp = (C.c_void_p * n)(*[y.data_ptr() for y in outs])
+        g = C.c_void_p()
+        _check(load().vsie_graph_create(n, hs, dt, nr, xp, yp, _stream_ptr(stream), C.byref(g)))
+        self._g = g
+        self._keep = (ops, xs, outs)
+
+    def launch(self, stream=None):
+        _check(load().vsie_graph_launch(self._g, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_g", None):
+            load().vsie_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Net:

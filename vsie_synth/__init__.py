@@ -17,10 +17,10 @@ Conventions shared by every consumer:
 from .phantoms import Grid, sphere_phantom, head_phantom, random_block
 from .meshes import Mesh, strip_loop_flat, strip_loop_on_cylinder, loop_array, cylinder_shield
 from .vectors import complex_normal
-from .problems import Problem, tiny_case, two_mm_case, one_mm_case, small_case, mie_case
+from .problems import Problem, tiny_case, two_mm_case, one_mm_case, small_case, mie_case, uneven_phantom_set
 
 __all__ = [
     "Grid", "sphere_phantom", "head_phantom", "random_block", "Mesh", "strip_loop_flat", "strip_loop_on_cylinder",
     "loop_array", "cylinder_shield", "complex_normal", "Problem", "tiny_case", "two_mm_case",
-    "small_case", "mie_case", "one_mm_case",
+    "small_case", "mie_case", "one_mm_case", "uneven_phantom_set",
 ]

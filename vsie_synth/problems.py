@@ -75,9 +75,39 @@ def one_mm_case(seed=7, n=(192, 224, 256), h=1e-3, loops_per_ring=16, shield_aro
     return Problem(g, [shield, coil], LARMOR_7T_HZ, "1mm")
 
 
+def uneven_phantom_set(h=2e-3):
+    """Six head-like phantoms of uneven grids at 2 mm inside one shared open shield (r = 340 mm,
+    L = 1.2 m, about 20k triangles, the same mesh object for all): 48^3 (seed 10), 64x72x80 (11),
+    80x96x96 (12), 96x112x128 (13 and 14), 112x128x144 (15); loop arrays of 8, 8, 16, 16, 16 and 32
+    (two rings of 16) channels on a cylinder 20 mm outside the larger in-plane half-extent (at least
+    120 mm)."""
+    from .meshes import Mesh
+    shield = cylinder_shield(0.340, 1.2, 128, 78, closed=False)
+    spec = [((48, 48, 48), 10, 8), ((64, 72, 80), 11, 8), ((80, 96, 96), 12, 16), ((96, 112, 128), 13, 16),
+            ((96, 112, 128), 14, 16), ((112, 128, 144), 15, 32)]
+    out = []
+    for n, seed, nl in spec:
+        g = head_phantom(seed, n, h)
+        radius = max(0.12, 0.5 * max(n[0], n[1]) * h + 0.02)
+        if nl <= 16:
+            coil = loop_array(nl, radius=radius, length=0.1, gap=10e-3, width=5e-3, step=2e-3, z_centre=0.37e-3,
+                              phi_offset=0.0013)
+        else:
+            rings = [loop_array(16, radius=radius, length=0.1, gap=10e-3, width=5e-3, step=2e-3, z_centre=zc,
+                                phi_offset=0.0013 + 0.5 * ring * 2 * np.pi / 16)
+                     for ring, zc in enumerate((-55.37e-3, 55.37e-3))]
+            nv0 = len(rings[0].verts)
+            coil = Mesh(np.concatenate([r.verts for r in rings]),
+                        np.concatenate([rings[0].tris, rings[1].tris + nv0]).astype(np.int32), NEAR,
+                        np.concatenate([rings[0].port_edges, rings[1].port_edges + nv0]).astype(np.int32),
+                        np.concatenate([rings[0].port_id, rings[1].port_id + rings[0].n_ports]).astype(np.int32))
+        out.append(Problem(g, [shield, coil], LARMOR_7T_HZ, "%dx%dx%d" % n))
+    return out
+
+
 def mie_case(n=16, h=5e-3, radius=35e-3):
     return Problem(sphere_phantom((n, n, n), h, radius, 52.0, 0.55), [], LARMOR_7T_HZ, "mie")
 
 
-__all__ = ["Problem", "tiny_case", "small_case", "two_mm_case", "one_mm_case", "mie_case", "NEAR", "FAR",
-           "LARMOR_7T_HZ"]
+__all__ = ["Problem", "tiny_case", "small_case", "two_mm_case", "one_mm_case", "uneven_phantom_set", "mie_case",
+           "NEAR", "FAR", "LARMOR_7T_HZ"]
