@@ -302,6 +302,28 @@ int vsie_export(const struct vsie_handle* h, int what, int index, void* host, si
  * were formed from the factors in place). */
 int vsie_import(struct vsie_handle* h, int what, int index, const void* host, size_t nbytes);
 
+/* Persistent checkpoint of the setup products that cost the most to recompute: the TT cores of
+ * the three far-coupling components (eq. (14)) and the ACA factors of the near-far block
+ * (eq. (12)), the compressed coupling that Sec. VI proposes to store and reuse. Dense blocks,
+ * stencils and spectra are not stored: they are rebuilt by vsie_create in seconds.
+ *
+ * File layout (host byte order): char[8] "VSIECKPT", uint32 version (1), uint64 key, uint32
+ * record count, then per record uint32 kind (VSIE_X_TT_CORES or VSIE_X_ACA), uint32 index,
+ * uint64 byte count and that many bytes in the vsie_export layout. The key is a 64-bit FNV-1a
+ * hash of the inputs that fix the factors: grid sizes, spacing and origin, frequency, eps_r and
+ * sigma, every mesh with its ports, and the options tt_tol, tt_rank_max, aca_tol, aca_rank_max,
+ * seed, quad_far_vol and quad_far_surf.
+ *
+ * vsie_checkpoint_save writes path + ".part" and renames it to path, so a reader never sees a
+ * partial file. Errors: E_ARG (null argument, file not writable), E_STATE (no far conductors).
+ * vsie_checkpoint_load reads every record, then imports them as vsie_import does; intended for a
+ * handle created with build_far = 0 from the same inputs. Products afterwards are bitwise equal
+ * to those of the handle that saved the file. Errors: E_ARG (unreadable or damaged file, other
+ * version, key differs from this handle's inputs: nothing is changed then), E_STATE (after
+ * vsie_schur_setup). */
+int vsie_checkpoint_save(const struct vsie_handle* h, const char* path);
+int vsie_checkpoint_load(struct vsie_handle* h, const char* path);
+
 /* Concurrency of one product: enable != 0 runs the far-block chain (gemv_far, gemv_far_reduce,
  * tt_pre: the dense far block and the TT stages that read only x) on a second non-blocking stream
  * of default priority, forked from and joined back into the caller's stream with events, while the

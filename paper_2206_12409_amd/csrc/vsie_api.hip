@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -1567,6 +1568,46 @@ static void progress(const char* what, std::chrono::steady_clock::time_point t0)
 static int create_impl(const vsie_problem* p, const vsie_options* opts, void* stream, vsie_handle* donor,
                        vsie_handle** out);
 
+// 64-bit FNV-1a over the inputs that fix the TT and ACA factors: grid, materials, meshes (with
+// their ports), frequency, and the compression options (tolerances, rank caps, seed)
+static uint64_t input_hash(const vsie_problem* p, const vsie_options& o) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* data, size_t n) {
+    const unsigned char* c = (const unsigned char*)data;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(p->n, sizeof(p->n));
+  mix(&p->h, sizeof(double));
+  mix(p->origin, sizeof(p->origin));
+  mix(&p->freq_hz, sizeof(double));
+  const size_t nv = (size_t)p->n[0] * p->n[1] * p->n[2];
+  if (p->eps_r) mix(p->eps_r, sizeof(double) * nv);
+  if (p->sigma) mix(p->sigma, sizeof(double) * nv);
+  mix(&p->n_meshes, sizeof(int32_t));
+  for (int i = 0; i < p->n_meshes && p->meshes; ++i) {
+    const vsie_mesh& m = p->meshes[i];
+    mix(&m.n_verts, sizeof(int32_t));
+    mix(&m.n_tris, sizeof(int32_t));
+    mix(&m.domain, sizeof(int32_t));
+    mix(&m.n_port_edges, sizeof(int32_t));
+    if (m.verts && m.n_verts > 0) mix(m.verts, sizeof(double) * 3 * (size_t)m.n_verts);
+    if (m.tris && m.n_tris > 0) mix(m.tris, sizeof(int32_t) * 3 * (size_t)m.n_tris);
+    if (m.port_edges && m.n_port_edges > 0) mix(m.port_edges, sizeof(int32_t) * 2 * (size_t)m.n_port_edges);
+    if (m.port_id && m.n_port_edges > 0) mix(m.port_id, sizeof(int32_t) * (size_t)m.n_port_edges);
+  }
+  mix(&o.tt_tol, sizeof(double));
+  mix(&o.tt_rank_max, sizeof(int32_t));
+  mix(&o.aca_tol, sizeof(double));
+  mix(&o.aca_rank_max, sizeof(int32_t));
+  mix(&o.seed, sizeof(o.seed));
+  mix(&o.quad_far_vol, sizeof(int32_t));
+  mix(&o.quad_far_surf, sizeof(int32_t));
+  return h;
+}
+
 int vsie_create(const vsie_problem* p, const vsie_options* opts, void* stream, vsie_handle** out) {
   return create_impl(p, opts, stream, nullptr, out);
 }
@@ -1611,6 +1652,7 @@ static int create_impl(const vsie_problem* p, const vsie_options* opts, void* st
         H.opts.quad_far_surf != 1)
       throw Error(VSIE_E_UNSUPPORTED, "coupling quadrature: 8 x 5 points near and 1 x 1 far only");
     if (p->n_meshes < 0 || (p->n_meshes > 0 && !p->meshes)) throw Error(VSIE_E_ARG, "bad mesh list");
+    H.input_hash = input_hash(p, H.opts);
     H.h = p->h;
     H.freq = p->freq_hz;
     H.omega = 2.0 * PI * H.freq;
@@ -1907,6 +1949,87 @@ int vsie_graph_destroy(vsie_graph* g) {
   if (g->cap) (void)hipStreamDestroy(g->cap);
   delete g;
   return VSIE_OK;
+}
+
+// Checkpoint file: "VSIECKPT", uint32 version, uint64 input hash, uint32 records, then per record
+// uint32 kind, uint32 index, uint64 bytes and the vsie_export bytes of that record.
+static const char CKPT_MAGIC[8] = {'V', 'S', 'I', 'E', 'C', 'K', 'P', 'T'};
+static constexpr uint32_t CKPT_VERSION = 1;
+
+int vsie_checkpoint_save(const vsie_handle* hd, const char* path) {
+  if (!hd || !path) return fail(VSIE_E_ARG, "null argument");
+  const Handle& H = hd->H;
+  if (H.mf == 0) return fail(VSIE_E_STATE, "no far conductors: nothing to checkpoint");
+  return guarded([&]() {
+    std::vector<std::pair<std::pair<uint32_t, uint32_t>, std::vector<unsigned char>>> recs;
+    auto add = [&](int what, int index) {
+      size_t n = 0;
+      if (vsie_export(hd, what, index, nullptr, &n) != VSIE_OK) throw Error(VSIE_E_STATE, "export failed");
+      std::vector<unsigned char> b(n);
+      if (vsie_export(hd, what, index, b.data(), &n) != VSIE_OK) throw Error(VSIE_E_STATE, "export failed");
+      recs.push_back({{(uint32_t)what, (uint32_t)index}, std::move(b)});
+    };
+    for (int c = 0; c < 3; ++c)
+      if (!H.tt_host[c][0].empty()) add(VSIE_X_TT_CORES, c);
+    if (H.mn > 0 && H.aca_k > 0) add(VSIE_X_ACA, 0);
+    const std::string tmp = std::string(path) + ".part";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) throw Error(VSIE_E_ARG, std::string("cannot write ") + tmp);
+    bool ok = std::fwrite(CKPT_MAGIC, 1, 8, f) == 8;
+    const uint32_t ver = CKPT_VERSION, nrec = (uint32_t)recs.size();
+    ok = ok && std::fwrite(&ver, 4, 1, f) == 1 && std::fwrite(&H.input_hash, 8, 1, f) == 1 &&
+         std::fwrite(&nrec, 4, 1, f) == 1;
+    for (const auto& r : recs) {
+      const uint64_t nb = r.second.size();
+      ok = ok && std::fwrite(&r.first.first, 4, 1, f) == 1 && std::fwrite(&r.first.second, 4, 1, f) == 1 &&
+           std::fwrite(&nb, 8, 1, f) == 1 && std::fwrite(r.second.data(), 1, nb, f) == nb;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+      std::remove(tmp.c_str());
+      throw Error(VSIE_E_ARG, std::string("cannot write ") + path);
+    }
+  });
+}
+
+int vsie_checkpoint_load(vsie_handle* hd, const char* path) {
+  if (!hd || !path) return fail(VSIE_E_ARG, "null argument");
+  Handle& H = hd->H;
+  if (H.schur.ready) return fail(VSIE_E_STATE, "the far elimination was built from the current factors");
+  return guarded([&]() {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) throw Error(VSIE_E_ARG, std::string("cannot read ") + path);
+    struct Closer {
+      FILE* f;
+      ~Closer() { std::fclose(f); }
+    } closer{f};
+    char magic[8];
+    uint32_t ver = 0, nrec = 0;
+    uint64_t hash = 0;
+    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, CKPT_MAGIC, 8) != 0)
+      throw Error(VSIE_E_ARG, "not a checkpoint file");
+    if (std::fread(&ver, 4, 1, f) != 1 || ver != CKPT_VERSION) throw Error(VSIE_E_ARG, "checkpoint version differs");
+    if (std::fread(&hash, 8, 1, f) != 1 || hash != H.input_hash)
+      throw Error(VSIE_E_ARG, "checkpoint was written for other inputs or compression options");
+    if (std::fread(&nrec, 4, 1, f) != 1 || nrec > 16) throw Error(VSIE_E_ARG, "corrupt checkpoint");
+    // read every record before importing any, so that a damaged file changes nothing
+    std::vector<std::pair<std::pair<uint32_t, uint32_t>, std::vector<unsigned char>>> recs;
+    for (uint32_t i = 0; i < nrec; ++i) {
+      uint32_t what = 0, index = 0;
+      uint64_t nb = 0;
+      if (std::fread(&what, 4, 1, f) != 1 || std::fread(&index, 4, 1, f) != 1 || std::fread(&nb, 8, 1, f) != 1 ||
+          nb > ((uint64_t)1 << 36))
+        throw Error(VSIE_E_ARG, "corrupt checkpoint");
+      std::vector<unsigned char> b(nb);
+      if (std::fread(b.data(), 1, nb, f) != nb) throw Error(VSIE_E_ARG, "truncated checkpoint");
+      if (what != VSIE_X_TT_CORES && what != VSIE_X_ACA) throw Error(VSIE_E_ARG, "corrupt checkpoint");
+      recs.push_back({{what, index}, std::move(b)});
+    }
+    for (const auto& r : recs) {
+      const int rc = vsie_import(hd, (int)r.first.first, (int)r.first.second, r.second.data(), r.second.size());
+      if (rc != VSIE_OK) throw Error(rc, std::string("checkpoint record rejected: ") + vsie_last_error());
+    }
+  });
 }
 
 int vsie_zpass_tuning(vsie_handle* hd, int dtype, int* chosen, int* v, int* np, double* ms) {

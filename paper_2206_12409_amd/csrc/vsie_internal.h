@@ -171,6 +171,7 @@ struct Handle {
   int sym_T = 0;
   int* d_tiles = nullptr;         // [ntiles][2] (I, J), I <= J
   std::shared_ptr<FarShare> far_share;   // owner of the dense far block and d_tiles
+  uint64_t input_hash = 0;        // inputs that fix the compressed factors (checkpoint key)
   // body mask
   uint8_t* d_mask = nullptr;
   int* d_zorder[2] = {};       // z-pass block order, FP64 / FP32, of the candidate in use

@@ -24,7 +24,8 @@ X_TT_CORES, X_ACA, X_STENCIL, X_GENERATOR, X_EXT_GRID = 1, 2, 3, 4, 5
 
 EXPORTED = ["vsie_default_options", "vsie_default_solve_opts", "vsie_create", "vsie_create_shared", "vsie_sizes",
             "vsie_rhs", "vsie_graph_create", "vsie_graph_launch", "vsie_graph_destroy",
-            "vsie_matvec", "vsie_matvec_graph", "vsie_zpass_tuning", "vsie_zpass_select", "vsie_solve", "vsie_solve_ports", "vsie_port_current", "vsie_export", "vsie_import", "vsie_set_concurrency",
+            "vsie_matvec", "vsie_matvec_graph", "vsie_zpass_tuning", "vsie_zpass_select", "vsie_solve", "vsie_solve_ports", "vsie_port_current", "vsie_export", "vsie_import",
+            "vsie_checkpoint_save", "vsie_checkpoint_load", "vsie_set_concurrency",
             "vsie_profile", "vsie_profile_mask", "vsie_profile_read", "vsie_schur_setup", "vsie_schur_info",
             "vsie_schur_matvec", "vsie_schur_precond", "vsie_dense_lu_solve", "vsie_dense_lu_solve_noalloc",
             "vsie_net_create", "vsie_net_destroy", "vsie_net_info", "vsie_net_get_params", "vsie_net_set_params",
@@ -107,6 +108,8 @@ def load(path=LIB_PATH):
     lib.vsie_port_current.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.vsie_export.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(C.c_size_t)]
     lib.vsie_import.argtypes = [vp, C.c_int, C.c_int, vp, C.c_size_t]
+    lib.vsie_checkpoint_save.argtypes = [vp, C.c_char_p]
+    lib.vsie_checkpoint_load.argtypes = [vp, C.c_char_p]
     lib.vsie_profile.argtypes = [vp, C.c_int]
     lib.vsie_profile_mask.argtypes = [vp, C.c_uint32]
     lib.vsie_set_concurrency.argtypes = [vp, C.c_int]
@@ -481,6 +484,18 @@ class Operator:
         blob = k.tobytes() + U.tobytes() + V.tobytes()
         buf = (C.c_ubyte * len(blob)).from_buffer_copy(blob)
         _check(load().vsie_import(self._h, X_ACA, 0, buf, len(blob)))
+
+    def save_checkpoint(self, path):
+        """Store the TT cores and ACA factors of the far coupling (eqs. (12), (14)) in a file keyed
+        by the inputs that fix them."""
+        _check(load().vsie_checkpoint_save(self._h, os.fsencode(path)))
+
+    def load_checkpoint(self, path):
+        """Replace the far-coupling factors by those of a checkpoint written for the same inputs."""
+        _check(load().vsie_checkpoint_load(self._h, os.fsencode(path)))
+        s = Sizes()
+        _check(load().vsie_sizes(self._h, C.byref(s)))
+        self.sizes = s
 
 
 # layers of the learned preconditioner's network: (name, Cin, Cout, ReLU); parameters per layer are
