@@ -617,7 +617,7 @@ def main():
     batched = None
     if not args.only_fp64:
         value32, err32, value_conc, same, graph = other_precisions(op, x, y, args)
-        # eight right-hand sides per call: the far block is read once per four of them
+        # eight right-hand sides per call: the far block is read once for all of them (groups of up to 16)
         X8 = torch.stack([torch.from_numpy(synth.complex_normal(op.N, 2000 + s)) for s in range(8)]).cuda()
         Y8 = torch.empty_like(X8)
         for _ in range(2):
