@@ -33,11 +33,13 @@ def stage_bytes(info, s):
     Ne = ne1 * ne2 * ne3
     SO = (P1 // 2 + 1) * (P2 // 2 + 1) * (P3 // 2 + 1)
     mf, mn = info["m_far"], info["m_near"]
+    # body currents couple only at tissue voxels (chi != 0); the kernels that take them read x_b
+    # inside each x row's tissue run only, and the TT update of y_b touches tissue voxels only
+    nt = info["n_tissue"]
     b = {
-        # the grid build is fused into the first pass: it reads the masked body currents (and, per
-        # grid voxel, one 4-byte projection-row index; per body voxel one mask byte) and writes the
-        # x-transformed rows
-        "fft_x_fwd": c * (3 * nv + 3 * ne3 * ne2 * P1) + 4 * Ne + nv,
+        # the grid build is fused into the first pass: it reads the body currents at tissue voxels
+        # (and, per grid voxel, one 4-byte projection-row index) and writes the x-transformed rows
+        "fft_x_fwd": c * (3 * nt + 3 * ne3 * ne2 * P1) + 4 * Ne,
         "fft_y_fwd": c * (3 * ne3 * ne2 * P1 + 3 * ne3 * P2 * P1),
         "fft_z_conv": c * (2 * 3 * ne3 * P2 * P1 + 6 * SO),
         "fft_y_inv": c * (3 * ne3 * P2 * P1 + 3 * ne3 * ne2 * P1),
@@ -52,12 +54,12 @@ def stage_bytes(info, s):
         "aca": 2 * c * (mf + mn) * info["aca_rank"],
     }
     r = info["tt_rank"]
-    # tt_pre, per component: x_b and each of the four cores once (G4 serves the forward and the
-    # transpose products in one pass), plus x_f read and y_f updated once; tt_post, per component:
-    # the first two cores and the read-modify-write of y_b
-    b["tt_pre"] = sum(c * (nv + n1 * r[a][0] + r[a][0] * n2 * r[a][1] + r[a][1] * n3 * r[a][2] + r[a][2] * mf)
+    # tt_pre, per component: x_b at tissue voxels and each of the four cores once (G4 serves the
+    # forward and the transpose products in one pass), plus x_f read and y_f updated once;
+    # tt_post, per component: the first two cores and the read-modify-write of y_b at tissue voxels
+    b["tt_pre"] = sum(c * (nt + n1 * r[a][0] + r[a][0] * n2 * r[a][1] + r[a][1] * n3 * r[a][2] + r[a][2] * mf)
                       for a in range(3)) + c * 3 * mf
-    b["tt_post"] = sum(c * (2 * nv + n1 * r[a][0] + r[a][0] * n2 * r[a][1]) for a in range(3))
+    b["tt_post"] = sum(c * (2 * nt + n1 * r[a][0] + r[a][0] * n2 * r[a][1]) for a in range(3))
     return b.get(s)
 
 

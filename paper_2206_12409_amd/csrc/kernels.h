@@ -12,6 +12,15 @@ struct GridDims {
   int64_t nv, Ne;
 };
 
+// Tissue voxels of the body grid: one byte per voxel (1 = tissue) and, per x row r = i2 + n2 i3,
+// the run [lo, hi) of i1 outside which the row holds no tissue (lo = hi = 0 for a row of air). A
+// row with air inside its run stores ~lo (negative) in place of lo, and its bytes decide inside the
+// run. Kernels that read x_b only where it couples load nothing outside the runs.
+struct BodyMask {
+  const uint8_t* vox;
+  const int2* runs;   // [n3 n2]
+};
+
 // setup
 void launch_generator(hipStream_t st, const GaussTab* gt, const int ne[3], double kappa, const CellRule& cr, cxd* oct);
 void launch_embed_circulant(hipStream_t st, const cxd* oct, const int ne[3], const int P[3], cxd* full);
@@ -50,7 +59,7 @@ void zconv_shape(int L, bool fp64, int cand, int* v, int* np);   // its values p
 // eq. (13), gathered per projection row into projv [nprojrows][3] first) formed on the fly: out
 // rows [3][ne3][ne2][L]
 template <typename R>
-void fft_rows_grid(hipStream_t st, int L, const cx<R>* xb, const cx<R>* xn, const uint8_t* mask, const int* vox2row,
+void fft_rows_grid(hipStream_t st, int L, const cx<R>* xb, const cx<R>* xn, BodyMask mask, const int* vox2row,
                    const uint8_t* rowhas, const int* rowptr, const int* rowrwg, const R* roww, int nprojrows,
                    cx<R>* projv, const GridDims& g, cx<R>* out, const cx<R>* tw);
 template <typename R> void launch_body_out(hipStream_t st, const cx<R>* xb, const cx<R>* E, const cx<R>* dvchi,
@@ -111,14 +120,14 @@ template <typename R> struct TTDesc {
 // already hold the rest of its product) and leaves the forward intermediates in the work buffer;
 // launch_tt_post adds the forward part into y_b
 template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
-                                         const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* work);
+                                         const cx<R>* xb, BodyMask mask, cx<R>* yf, cx<R>* work);
 template <typename R> void launch_tt_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
                                           const uint8_t* mask, cx<R>* yb, cx<R>* work);
 // the halves used by the reduced (far-eliminated) operator: the transpose chain alone (s3 at the
 // start of the work buffer), the forward chain from given rank vectors u3[c][TT_RMAX] instead of
 // G4 x_f, and the forward accumulation into y_b alone
 template <typename R> void launch_tt_transpose_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
-                                                   const cx<R>* xb, const uint8_t* mask, cx<R>* work);
+                                                   const cx<R>* xb, BodyMask mask, cx<R>* work);
 template <typename R> void launch_tt_forward_from(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
                                                   const cx<R>* u3, cx<R>* work);
 template <typename R> void launch_tt_forward_post(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,

@@ -498,6 +498,7 @@ __device__ inline void reg_dft(cx<R>* v, const cx<R>* __restrict__ tw) {
 template <typename R> struct GridSrc {
   const cx<R>* xb;
   const uint8_t* mask;
+  const int2* runs;        // tissue run of each body x row (BodyMask)
   const int* vox2row;
   const uint8_t* rowhas;   // per x row (i2 + ne2 i3): any projection voxel in it
   const cx<R>* projv;
@@ -589,16 +590,20 @@ __global__ __launch_bounds__(NP * A) void k_fft2(const cx<R>* __restrict__ in, c
       const int64_t vrow = (int64_t)g.ne1 * (i2 + (int64_t)g.ne2 * i3);
       const bool rproj = valid && gs.vox2row && gs.rowhas[i2 + (int64_t)g.ne2 * i3];
       const cx<R>* xbc = gs.xb + (int64_t)c * g.nv;
-      // every load of the row issued before any is tested; the projection rows (voxels next to
-      // the near conductors only) are walked afterwards
+      // x_b is loaded only inside the row's tissue run (bytes tested only in a run with air
+      // inside); every load of the row is issued before any is tested; the projection rows (voxels
+      // next to the near conductors only) are walked afterwards
+      const int2 run = rin ? gs.runs[b2 + (int64_t)g.n2 * b3] : int2{0, 0};
+      const bool holes = run.x < 0;
+      const int lo = holes ? ~run.x : run.x, hi = run.y;
       int pr[A];
 #pragma unroll
       for (int m = 0; m < A; ++m) {
         const int n = j + B * m;
         const int b1 = n - g.ob1;
-        const bool inb = rin && n < n_in && b1 >= 0 && b1 < g.n1;
+        const bool inb = rin && n < n_in && b1 >= lo && b1 < hi && b1 >= 0 && b1 < g.n1;
         const cx<R> xv = inb ? xbc[pb + n] : cx<R>{0, 0};
-        const uint8_t mk = inb ? gs.mask[pb + n] : 0;
+        const uint8_t mk = (inb && holes) ? gs.mask[pb + n] : (uint8_t)inb;
         v[bitrev_of(m, A)] = mk ? xv : cx<R>{0, 0};
         pr[m] = (rproj && n < n_in) ? gs.vox2row[vrow + n] : -1;
       }
@@ -1131,7 +1136,7 @@ void fft_rows(hipStream_t st, int L, bool fwd, const cx<R>* in, cx<R>* out, int 
 }
 
 template <typename R>
-void fft_rows_grid(hipStream_t st, int L, const cx<R>* xb, const cx<R>* xn, const uint8_t* mask, const int* vox2row,
+void fft_rows_grid(hipStream_t st, int L, const cx<R>* xb, const cx<R>* xn, BodyMask mask, const int* vox2row,
                    const uint8_t* rowhas, const int* rowptr, const int* rowrwg, const R* roww, int nprojrows,
                    cx<R>* projv, const GridDims& g, cx<R>* out, const cx<R>* tw) {
   if (g.Ne >= ((int64_t)1 << 31)) throw Error(VSIE_E_GRID, "extended grid of 2^31 or more voxels");
@@ -1139,7 +1144,7 @@ void fft_rows_grid(hipStream_t st, int L, const cx<R>* xb, const cx<R>* xn, cons
   if (proj)
     hipLaunchKernelGGL(k_proj_rows<R>, dim3((nprojrows + 63) / 64), dim3(256), 0, st, rowptr, rowrwg, roww, xn,
                        nprojrows, projv);
-  const GridSrc<R> gs{xb, mask, proj ? vox2row : nullptr, rowhas, projv, g};
+  const GridSrc<R> gs{xb, mask.vox, mask.runs, proj ? vox2row : nullptr, rowhas, projv, g};
   const int64_t nrows = 3LL * g.ne3 * g.ne2;
   VSIE_FFT_SWITCH(L, {
     constexpr int A = Split<LL>::A;
@@ -1295,10 +1300,10 @@ void fft_z_conv(hipStream_t st, int L, cx<R>* buf, int n3, int P1, int P2, const
 
 template void fft_rows<double>(hipStream_t, int, bool, const cxd*, cxd*, int, int, int64_t, int64_t, int64_t, const cxd*);
 template void fft_rows<float>(hipStream_t, int, bool, const cxf*, cxf*, int, int, int64_t, int64_t, int64_t, const cxf*);
-template void fft_rows_grid<double>(hipStream_t, int, const cxd*, const cxd*, const uint8_t*, const int*,
+template void fft_rows_grid<double>(hipStream_t, int, const cxd*, const cxd*, BodyMask, const int*,
                                     const uint8_t*, const int*, const int*, const double*, int, cxd*, const GridDims&,
                                     cxd*, const cxd*);
-template void fft_rows_grid<float>(hipStream_t, int, const cxf*, const cxf*, const uint8_t*, const int*,
+template void fft_rows_grid<float>(hipStream_t, int, const cxf*, const cxf*, BodyMask, const int*,
                                    const uint8_t*, const int*, const int*, const float*, int, cxf*, const GridDims&,
                                    cxf*, const cxf*);
 template void fft_strided<double>(hipStream_t, int, bool, const cxd*, cxd*, int, int, int64_t, int64_t, int, int64_t,
@@ -1940,12 +1945,12 @@ __global__ __launch_bounds__(256) void k_tt_ksum(TTDesc<R> T, const cx<R>* __res
 //             -> S2[j2][i3] = sum_(j1, i2) G2[j1][i2][j2] T1[i3][j1][i2] -> s3[j3] -> y_f[i4]
 
 // T1 on the matrix cores: a wavefront owns 16 rows (the MFMA's columns) and a 16-wide tile of j1
-// (its rows), K = i1 in steps of 4; operands straight from memory (x_b is read once, G1 is a few
-// KB and stays in cache). t1 points at component 0; components are t1_cs apart.
+// (its rows), K = i1 in steps of 4 over the union of the 16 rows' tissue runs; operands straight
+// from memory (x_b is read only inside the runs, G1 is a few KB and stays in cache). t1 points at
+// component 0; components are t1_cs apart.
 template <typename R>
-__global__ __launch_bounds__(256) void k_tt_t1(TTDesc<R> T, const cx<R>* __restrict__ xb,
-                                               const uint8_t* __restrict__ mask, int n1, int n2, int rows, int64_t nv,
-                                               cx<R>* __restrict__ t1, int64_t t1_cs) {
+__global__ __launch_bounds__(256) void k_tt_t1(TTDesc<R> T, const cx<R>* __restrict__ xb, BodyMask mask, int n1,
+                                               int n2, int rows, int64_t nv, cx<R>* __restrict__ t1, int64_t t1_cs) {
   using MM = Mfma16<R>;
   using V = typename MM::V;
   const int c = blockIdx.y;
@@ -1957,7 +1962,17 @@ __global__ __launch_bounds__(256) void k_tt_t1(TTDesc<R> T, const cx<R>* __restr
   const int row = row0 + li;
   const bool rv = row < rows;
   const cx<R>* xr = xb + (int64_t)c * nv + (int64_t)(rv ? row : 0) * n1;
-  const uint8_t* mr = mask + (int64_t)(rv ? row : 0) * n1;
+  const uint8_t* mr = mask.vox + (int64_t)(rv ? row : 0) * n1;
+  const int2 run = rv ? mask.runs[row] : int2{0, 0};
+  const bool holes = run.x < 0;
+  const int lo = holes ? ~run.x : run.x, hi = run.y;
+  // K range of the wavefront: the union of its rows' runs
+  int klo = hi > lo ? lo : n1, khi = hi > lo ? hi : 0;
+  for (int o = 8; o > 0; o >>= 1) {
+    klo = min(klo, __shfl_xor(klo, o, 16));
+    khi = max(khi, __shfl_xor(khi, o, 16));
+  }
+  klo &= ~3;
   const cx<R>* g1 = T.G1[c];
   const int i3 = row / n2, i2 = row - (row / n2) * n2;
   cx<R>* out = t1 + (int64_t)c * t1_cs + (int64_t)i3 * r1 * n2 + i2;
@@ -1965,16 +1980,17 @@ __global__ __launch_bounds__(256) void k_tt_t1(TTDesc<R> T, const cx<R>* __restr
   for (int jt = 0; jt < r1; jt += 16) {
     const int ja = jt + li;   // the A row this lane supplies
     V dr = V{0, 0, 0, 0}, di = V{0, 0, 0, 0};
-    for (int kb = 0; kb < n1; kb += 4 * KB) {
+    for (int kb = klo; kb < khi; kb += 4 * KB) {
       cx<R> a[KB], b[KB];
       uint8_t mk[KB];
 #pragma unroll
       for (int q = 0; q < KB; ++q) {
         const int i1 = kb + 4 * q + lk;
-        const bool in = i1 < n1;
+        const bool in = i1 < khi;
+        const bool tin = rv && i1 >= lo && i1 < hi;   // inside this row's run (hence i1 < n1)
         a[q] = (ja < r1 && in) ? g1[(int64_t)i1 * r1 + ja] : cx<R>{0, 0};
-        b[q] = (rv && in) ? xr[i1] : cx<R>{0, 0};
-        mk[q] = (rv && in) ? mr[i1] : 0;
+        b[q] = tin ? xr[i1] : cx<R>{0, 0};
+        mk[q] = (tin && holes) ? mr[i1] : (uint8_t)tin;
       }
 #pragma unroll
       for (int q = 0; q < KB; ++q) {
@@ -2316,7 +2332,7 @@ template <typename R> static TTWork tt_layout(const TTDesc<R>& T, const int n[3]
 // (eqs. (18)-(19)), then one pass over G4 for y_f += sum_c G4^T s3 and the forward G4 x_f
 // (eq. (16)), then G3 into t3 (eq. (17)). y_f must already hold the rest of its product.
 template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf, const cx<R>* xf,
-                                         const cx<R>* xb, const uint8_t* mask, cx<R>* yf, cx<R>* work) {
+                                         const cx<R>* xb, BodyMask mask, cx<R>* yf, cx<R>* work) {
   const TTWork w = tt_layout(T, n, mf);
   launch_tt_transpose_pre<R>(st, T, n, mf, xb, mask, work);
   const cx<R>* s3 = work;
@@ -2337,7 +2353,7 @@ template <typename R> void launch_tt_pre(hipStream_t st, const TTDesc<R>& T, con
 
 // The transpose half of launch_tt_pre: s3[c][j3] (at the start of the work buffer) from x_b.
 template <typename R> void launch_tt_transpose_pre(hipStream_t st, const TTDesc<R>& T, const int n[3], int mf,
-                                                   const cx<R>* xb, const uint8_t* mask, cx<R>* work) {
+                                                   const cx<R>* xb, BodyMask mask, cx<R>* work) {
   const TTWork w = tt_layout(T, n, mf);
   cx<R>* s2 = work + w.o_s2;
   cx<R>* kpart = work + w.o_kpart;
@@ -2634,11 +2650,11 @@ template void launch_mul_diag<float>(hipStream_t, const cxf*, const cxf*, cxf*, 
                                   cx<R>*);                                                                            \
   template void launch_gemv_rows<R>(hipStream_t, const cx<R>*, const cx<R>*, int64_t, int64_t, cx<R>*, int);          \
   template void launch_tt_pre<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*, const cx<R>*,       \
-                                 const uint8_t*, cx<R>*, cx<R>*);                                                     \
+                                 BodyMask, cx<R>*, cx<R>*);                                                           \
   template void launch_tt_post<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const uint8_t*, cx<R>*,           \
                                   cx<R>*);                                                                            \
   template void launch_tt_transpose_pre<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*,          \
-                                           const uint8_t*, cx<R>*);                                             \
+                                           BodyMask, cx<R>*);                                                   \
   template void launch_tt_forward_from<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const cx<R>*, cx<R>*); \
   template void launch_tt_forward_post<R>(hipStream_t, const TTDesc<R>&, const int[3], int, const uint8_t*,        \
                                           cx<R>*, cx<R>*);                                                \

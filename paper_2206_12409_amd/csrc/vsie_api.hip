@@ -179,6 +179,20 @@ void setup_volume(Handle& H) {
       mask[p] = 1;
     }
   H.d_mask = upload(H, mask);
+  // tissue run [lo, hi) of each x row; ~lo marks a run with air inside it
+  std::vector<int2> runs((size_t)H.n[1] * H.n[2], int2{0, 0});
+  for (size_t r = 0; r < runs.size(); ++r) {
+    const uint8_t* m = mask.data() + r * H.n[0];
+    int lo = -1, hi = 0, cnt = 0;
+    for (int i = 0; i < H.n[0]; ++i)
+      if (m[i]) {
+        if (lo < 0) lo = i;
+        hi = i + 1;
+        ++cnt;
+      }
+    if (cnt > 0) runs[r] = int2{cnt == hi - lo ? lo : ~lo, hi};
+  }
+  H.d_runs = upload(H, runs);
   H.d64.dv_chi = upload_cx<double>(H, dv);
   if (H.opts.precision) H.d32.dv_chi = upload_cx<float>(H, dv);
 }
@@ -711,6 +725,8 @@ static void make_streams(Handle& H) {
   VSIE_HIP(hipEventCreateWithFlags(&H.join, hipEventDisableTiming));
 }
 
+static BodyMask body_mask(const Handle& H) { return BodyMask{H.d_mask, H.d_runs}; }
+
 // Volume convolution with the pFFT projection and interpolation of the near currents
 // (Sec. II-B, eq. (13)): y_b and y_n from x_b and x_n (x_n null when there are no near currents).
 template <typename R>
@@ -722,7 +738,7 @@ static void volume_chain(Handle& H, OpData<R>& D, const cx<R>* xn, const cx<R>* 
   const int ne1 = H.ne[0], ne2 = H.ne[1], ne3 = H.ne[2];
   // the grid build (stage 0) is fused into the first FFT pass (stage 1)
   T.begin(1, st);
-  fft_rows_grid<R>(st, P1, xb, mn ? xn : nullptr, H.d_mask, mn ? H.d_vox2row : nullptr, H.d_rowhasproj, H.d_rowptr,
+  fft_rows_grid<R>(st, P1, xb, mn ? xn : nullptr, body_mask(H), mn ? H.d_vox2row : nullptr, H.d_rowhasproj, H.d_rowptr,
                    H.d_rowrwg, D.roww, H.n_gridrows, D.projv, g, D.bufB, D.tw[0]);
   T.end(1, st);
   T.begin(2, st);
@@ -796,7 +812,7 @@ void matvec_one(Handle& H, OpData<R>& D, const cx<R>* x, cx<R>* y, hipStream_t s
     }
     if (have_tt) {
       T.begin(11, fs);
-      launch_tt_pre<R>(fs, td, H.n, mf, xf, xb, H.d_mask, yf, D.tt_work);
+      launch_tt_pre<R>(fs, td, H.n, mf, xf, xb, body_mask(H), yf, D.tt_work);
       T.end(11, fs);
     }
   };
@@ -921,7 +937,7 @@ template <typename R> static void far_proxies(Handle& H, const cx<R>* xn, const 
   const bool have_tt = tt_desc(H, D, td, r3);
   const int ka = aca_rank(H);
   if (ka) launch_lr_t<R>(st, false, D.U, xn, H.mn, ka, D.small_work, 512, schurop(H, R()).ta);
-  if (have_tt) launch_tt_transpose_pre<R>(st, td, H.n, H.mf, xb, H.d_mask, D.tt_work);
+  if (have_tt) launch_tt_transpose_pre<R>(st, td, H.n, H.mf, xb, body_mask(H), D.tt_work);
 }
 
 // Reduced product y_r = Z_rr x_r - R^T S t(x_r) on the near and body unknowns (x_f is not read,

@@ -174,6 +174,7 @@ struct Handle {
   uint64_t input_hash = 0;        // inputs that fix the compressed factors (checkpoint key)
   // body mask
   uint8_t* d_mask = nullptr;
+  int2* d_runs = nullptr;         // [n3 n2] tissue run of each body x row (see BodyMask)
   int* d_zorder[2] = {};       // z-pass block order, FP64 / FP32, of the candidate in use
   int zcand[2] = {0, 0};       // z-pass candidate chosen by the setup autotuner, FP64 / FP32
   double ztime[2][3] = {};     // its measured time per launch (ms) of every candidate (0: absent)

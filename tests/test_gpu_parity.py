@@ -290,3 +290,57 @@ def test_aca_accuracy_against_dense_block():
     err = np.linalg.norm(U @ V.conj().T - Z) / np.linalg.norm(Z)
     print("ACA rank %d, relative error %.2e" % (U.shape[1], err))
     assert err < 3e-3
+
+
+def test_body_rows_with_air_inside():
+    """The kernels that take body currents read x_b only inside each x row's tissue run and test
+    the voxel mask only in runs with air inside them. A sphere with air voxels cut out of some of
+    its x rows (rows of air, rows of one tissue run, rows with air inside their run), conductors
+    near and far: product against the oracle's operator with the same imported TT and low-rank
+    factors, FP64 at 1e-10 and complex64 at 1e-5, with large values of x at the air voxels (which
+    must reach only their identity rows)."""
+    import paper_2206_12409_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    p = synth.small_case()
+    g = p.grid
+    n1, n2, n3 = g.n
+    tissue = (g.eps_r != 1.0) | (g.sigma != 0)
+    rng = np.random.default_rng(5)
+    for i3 in range(n3):
+        for i2 in range(n2):
+            idx = np.flatnonzero(tissue[i3, i2])
+            if len(idx) >= 3 and rng.random() < 0.6:
+                k = int(rng.integers(idx[0] + 1, idx[-1]))
+                g.eps_r[i3, i2, k] = 1.0
+                g.sigma[i3, i2, k] = 0.0
+    tissue = (g.eps_r != 1.0) | (g.sigma != 0)
+    kinds = {"air": 0, "run": 0, "holes": 0}
+    for row in tissue.reshape(-1, n1):
+        idx = np.flatnonzero(row)
+        kinds["air" if len(idx) == 0 else ("run" if idx[-1] - idx[0] + 1 == len(idx) else "holes")] += 1
+    print("x rows:", kinds)
+    assert min(kinds.values()) > 0
+    op = pkg.Operator(p)
+    try:
+        d, S_direct, S_same, _ = oracle_same(p, op)
+        mf, mn = op.m_far, op.m_near
+        air = np.flatnonzero(~tissue.ravel())
+        # rows of air voxels are x itself; the coupled rows are compared on their own, since the
+        # large air values would dominate a norm over all rows
+        keep = np.ones(op.N, bool)
+        for c in range(3):
+            keep[mf + mn + c * n1 * n2 * n3 + air] = False
+        for seed in (61, 62):
+            x = synth.complex_normal(op.N, seed)
+            x[~keep] *= 1e6
+            ref = S_same.matvec(x)
+            y64 = op.matvec(to_dev(x)).cpu().numpy()
+            y32 = op.matvec(to_dev(x, torch.complex64)).cpu().numpy().astype(np.complex128)
+            e64, e32 = rel(y64[keep], ref[keep]), rel(y32[keep], ref[keep])
+            e_air = rel(y64[~keep], ref[~keep])
+            print("seed %d: coupled rows FP64 %.2e, complex64 %.2e; air rows %.2e" % (seed, e64, e32, e_air))
+            assert e64 < 1e-10 and e_air < 1e-12
+            assert e32 < 1e-5
+    finally:
+        op.close()
