@@ -44,7 +44,9 @@ def stage_bytes(info, s):
         "fft_z_conv": c * (2 * 3 * ne3 * P2 * P1 + 6 * SO),
         "fft_y_inv": c * (3 * ne3 * P2 * P1 + 3 * ne3 * ne2 * P1),
         "fft_x_inv": c * (3 * ne3 * ne2 * P1 + 3 * Ne),
-        "body_out": c * (2 * 3 * nv + 3 * nv + nv),
+        # x_b read and y_b written everywhere (identity rows in air); the x-pass output and dv/chi
+        # read at tissue voxels only; one mask byte per voxel
+        "body_out": c * (2 * 3 * nv + 3 * nt + nt) + nv,
         "pfft_gather": mn * 375 * (8 + c),
         # unique entries of the complex-symmetric far block plus x; the packed-tile partial sums
         # are charged to the reduction kernel
