@@ -128,6 +128,11 @@ def test_new_entry_points_reject_bad_arguments(vs):
     ports = (C.c_int32 * 1)(0)
     assert lib.vsie_solve_ports(None, C.byref(o), 1, ports, dummy, None, None) == 1
     assert lib.vsie_rhs(None, 0, 0, dummy, None) == 1
+    # checkpoint of the compressed far coupling: null handle or path
+    assert lib.vsie_checkpoint_save(None, b"/nonexistent/ckpt") == 1
+    assert lib.vsie_checkpoint_load(None, b"/nonexistent/ckpt") == 1
+    assert lib.vsie_checkpoint_save(dummy, None) == 1
+    assert lib.vsie_checkpoint_load(dummy, None) == 1
 
 
 def test_binding_structs_match_the_header(vs, tmp_path):
