@@ -881,54 +881,62 @@ __device__ inline void zfft_c(cx<R>* Sp, cx<R>* v, int j, const cx<R>* tws) {
   }
 }
 
-// Staging of a block's NP adjacent pencils (all three components, planes n < n3 <= L / 2) between
-// buf (pencil k1 at base + k1, plane n at + n plane, component c at + c comp) and the LDS rows
-// S[(p 3 + c) (L + 1) + n]. Thread t takes pencil t % NP and the planes t / NP + m NT / NP, with
-// neighbouring threads on neighbouring pencils (coalesced); every load is issued before the first
-// LDS store. np_here: pencils of the block that exist.
-template <typename R, int L, int NP, int NT>
-__device__ inline void zstage_in(cx<R>* S, const cx<R>* __restrict__ base, int t, int n3, int64_t plane,
-                                 int64_t comp, int np_here) {
-  constexpr int NSTEP = NT / NP;
-  constexpr int MAXIT = (L / 2 + NSTEP - 1) / NSTEP;
+// Staging of a block's NP adjacent pencils between buf (pencil k1 at base + k1, plane n at
+// + n plane, component c at + c comp) and the LDS rows S[p (L + 1) + n], one row per pencil that
+// the three components take in turn. Thread t takes pencil t % NP and the planes
+// t / NP + m NT / NP, with neighbouring threads on neighbouring pencils (coalesced). zstage_load
+// issues the loads of all three components at once into registers, zstage_put stores one
+// component into the rows, zstage_out writes one component's rows back. np_here: pencils of the
+// block that exist.
+template <int L, int NP, int NT> struct ZStage {
+  static constexpr int NSTEP = NT / NP;
+  static constexpr int MAXIT = (L / 2 + NSTEP - 1) / NSTEP;
+};
+template <typename R, int L, int NP, int NT, int M>
+__device__ inline void zstage_load(cx<R> (&v)[3][M], const cx<R>* __restrict__ base, int t, int n3, int64_t plane,
+                                   int64_t comp, int np_here) {
+  using Z = ZStage<L, NP, NT>;
+  static_assert(M == Z::MAXIT, "staging registers");
   const int p = t % NP, n0 = t / NP;
   const bool ok = p < np_here;
-  cx<R> v[3][MAXIT];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int m = 0; m < MAXIT; ++m) {
-      const int n = n0 + m * NSTEP;
+    for (int m = 0; m < Z::MAXIT; ++m) {
+      const int n = n0 + m * Z::NSTEP;
       v[c][m] = (ok && n < n3) ? base[c * comp + (int64_t)n * plane + p] : cx<R>{0, 0};
     }
+}
+template <typename R, int L, int NP, int NT, int M>
+__device__ inline void zstage_put(cx<R>* S, const cx<R> (&v)[M], int t, int n3) {
+  using Z = ZStage<L, NP, NT>;
+  static_assert(M == Z::MAXIT, "staging registers");
+  const int p = t % NP, n0 = t / NP;
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int m = 0; m < MAXIT; ++m) {
-      const int n = n0 + m * NSTEP;
-      if (n < n3) S[(p * 3 + c) * (L + 1) + n] = v[c][m];
-    }
+  for (int m = 0; m < Z::MAXIT; ++m) {
+    const int n = n0 + m * Z::NSTEP;
+    if (n < n3) S[p * (L + 1) + n] = v[m];
+  }
 }
 template <typename R, int L, int NP, int NT>
 __device__ inline void zstage_out(const cx<R>* S, cx<R>* __restrict__ base, int t, int n3, int64_t plane,
-                                  int64_t comp, int np_here) {
-  constexpr int NSTEP = NT / NP;
-  constexpr int MAXIT = (L / 2 + NSTEP - 1) / NSTEP;
+                                  int np_here) {
+  using Z = ZStage<L, NP, NT>;
   const int p = t % NP, n0 = t / NP;
-  if (p >= np_here) return;
+  if (p < np_here)
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int m = 0; m < MAXIT; ++m) {
-      const int n = n0 + m * NSTEP;
-      if (n < n3) base[c * comp + (int64_t)n * plane + p] = S[(p * 3 + c) * (L + 1) + n];
+    for (int m = 0; m < Z::MAXIT; ++m) {
+      const int n = n0 + m * Z::NSTEP;
+      if (n < n3) base[(int64_t)n * plane + p] = S[p * (L + 1) + n];
     }
 }
 
 // Fused z pass, one wavefront (or part of one) per pencil: T = L / V <= 64 threads own a pencil,
 // so the FFT exchanges only synchronise the wavefront. The block's NP pencils (adjacent k1) are
-// loaded and stored through an LDS staging area [NP][3][L + 1] with neighbouring threads on
-// neighbouring pencils (coalesced), the only two block-wide barriers.
+// loaded and stored through LDS with neighbouring threads on neighbouring pencils (coalesced). One
+// LDS row per pencil serves the staging and the exchanges of all three components in turn (a
+// third of the LDS of a row per component, so more blocks fit a CU); the staging of each component
+// is bracketed by block-wide barriers, the exchanges by wavefront barriers.
 template <typename R, int L, int V, int NP>
 __global__ __launch_bounds__(NP * L / V) void k_zconv4(cx<R>* __restrict__ buf, int n3, int P1, int P2,
                                                        const cx<R>* __restrict__ spec, const cx<R>* __restrict__ tw,
@@ -940,7 +948,7 @@ __global__ __launch_bounds__(NP * L / V) void k_zconv4(cx<R>* __restrict__ buf, 
   constexpr int NB_LAST = V / RAD_LAST;
   static_assert(T <= 64, "a pencil must fit one wavefront");
   static_assert(zradices_supported<L, V>(), "last stage radix not handled by the exchange steps");
-  __shared__ cx<R> S[NP * 3 * LP];
+  __shared__ cx<R> S[NP * LP];
   __shared__ cx<R> tws[ZTw<L, V>::size()];   // per-stage twiddle tables
   const int t = threadIdx.x;
   ztw_fill<R, L, V>(tws, tw, t, NT);
@@ -948,24 +956,31 @@ __global__ __launch_bounds__(NP * L / V) void k_zconv4(cx<R>* __restrict__ buf, 
   const int k10 = order[2 * blockIdx.x + 1] * NP;
   const int64_t plane = (int64_t)P1 * P2, comp = plane * n3;
   cx<R>* base = buf + (int64_t)k2 * P1 + k10;
-  // staging load: element (c, n, p), pencils fastest
-  zstage_in<R, L, NP, NT>(S, base, t, n3, plane, comp, P1 - k10);
-  __syncthreads();
+  const int np_here = P1 - k10;
+  // staging loads of all three components in flight together: element (c, n, p), pencils fastest
+  cx<R> sv[3][ZStage<L, NP, NT>::MAXIT];
+  zstage_load<R, L, NP, NT>(sv, base, t, n3, plane, comp, np_here);
   const int p = t / T, j = t % T;
   const int k1 = k10 + p;
   const bool valid = k1 < P1;
-  cx<R>* Sp = S + p * 3 * LP;
+  cx<R>* Sp = S + p * LP;
   cx<R> H[3][V];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < 3; ++c) {
+    if (c > 0) __syncthreads();   // every pencil has read the previous component from its row
+    zstage_put<R, L, NP, NT>(S, sv[c], t, n3);
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < V; ++q) {
       const int n = j + T * q;
-      H[c][q] = (2 * q < V && n < n3) ? Sp[c * LP + n] : cx<R>{0, 0};
+      H[c][q] = (2 * q < V && n < n3) ? Sp[n] : cx<R>{0, 0};
     }
-  zsync<true>();   // the staged inputs of this pencil are in registers; its LDS rows are free
+  }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) zfft_c<R, L, V, true>(Sp + c * LP, H[c], j, tws);
+  for (int c = 0; c < 3; ++c) {
+    zsync<true>();   // this pencil's row is free: its previous reads have completed
+    zfft_c<R, L, V, true>(Sp, H[c], j, tws);
+  }
   {
     const int S1 = P1 / 2 + 1, S3 = L / 2 + 1;
     const int f1 = k1 <= P1 / 2 ? k1 : P1 - k1;
@@ -997,24 +1012,30 @@ __global__ __launch_bounds__(NP * L / V) void k_zconv4(cx<R>* __restrict__ buf, 
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     zsync<true>();
-    zfft_c<R, L, V, false>(Sp + c * LP, H[c], j, tws);
+    zfft_c<R, L, V, false>(Sp, H[c], j, tws);
   }
-  zsync<true>();   // every exchange of this pencil is read before the outputs overwrite the rows
+  // outputs one component at a time: each pencil writes its row, the block writes the rows back
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < 3; ++c) {
+    if (c == 0)
+      zsync<true>();   // every exchange of this pencil is read before the outputs overwrite its row
+    else
+      __syncthreads();   // the previous component's rows are written back
 #pragma unroll
     for (int q = 0; q < V / 2; ++q) {
       const int n = j + T * q;
-      if (n < n3) Sp[c * LP + n] = H[c][q];
+      if (n < n3) Sp[n] = H[c][q];
     }
-  __syncthreads();
-  zstage_out<R, L, NP, NT>(S, base, t, n3, plane, comp, P1 - k10);
+    __syncthreads();
+    zstage_out<R, L, NP, NT>(S, base + c * comp, t, n3, plane, np_here);
+  }
 }
 
 // z-pass configuration per precision (k_zconv4): the smallest number V of values per thread (a
 // pencil must also fit one wavefront, T = L / V <= 64), the threads per block, and the LDS per block
-// (staging and twiddles). Measured at 2 mm (L = 256) and 1 mm (L = 512): FP64 with four values
-// per thread, complex64 with eight; at L = 512 four pencils per block (98 KB of LDS) beat two.
+// (one staging row per pencil, and the twiddles). Measured at 2 mm (L = 256) and 1 mm (L = 512):
+// FP64 with four values per thread, complex64 with eight; at L = 512 four pencils per block beat
+// two.
 #ifndef ZCONV_VMIN64
 #define ZCONV_VMIN64 4
 #endif
@@ -1061,7 +1082,7 @@ constexpr int zconv_np_for(int L, int V, bool fp64) {
   if (np < 1) np = 1;
   const int elem = fp64 ? 16 : 8;
   const int tws = ztw_size(L, V);
-  while (np > 1 && (np * 3 * (L + 1) + tws) * elem > ZCONV_LDS_CAP) np /= 2;
+  while (np > 1 && (np * (L + 1) + tws) * elem > ZCONV_LDS_CAP) np /= 2;
   return np;
 }
 // The z-pass candidates the autotuner times at setup (ZCONV_NCAND per length and precision):
