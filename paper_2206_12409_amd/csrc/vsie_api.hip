@@ -1972,6 +1972,27 @@ int vsie_graph_destroy(vsie_graph* g) {
 static const char CKPT_MAGIC[8] = {'V', 'S', 'I', 'E', 'C', 'K', 'P', 'T'};
 static constexpr uint32_t CKPT_VERSION = 1;
 
+// the checks vsie_import makes of a record's kind, index, ranks and size, made before any import
+static bool checkpoint_record_ok(const Handle& H, uint32_t what, uint32_t index, const std::vector<unsigned char>& b) {
+  if (what == VSIE_X_TT_CORES) {
+    if (index > 2 || H.mf == 0 || b.size() < 3 * sizeof(int)) return false;
+    int r[3];
+    std::memcpy(r, b.data(), sizeof(r));
+    for (int k = 0; k < 3; ++k)
+      if (r[k] < 1 || r[k] > 128) return false;
+    const size_t n = (size_t)H.n[0] * r[0] + (size_t)r[0] * H.n[1] * r[1] + (size_t)r[1] * H.n[2] * r[2] +
+                     (size_t)r[2] * H.mf;
+    return b.size() == 3 * sizeof(int) + sizeof(cxd) * n;
+  }
+  if (what == VSIE_X_ACA) {
+    if (index != 0 || H.mf == 0 || H.mn == 0 || b.size() < sizeof(int)) return false;
+    int k;
+    std::memcpy(&k, b.data(), sizeof(int));
+    return k >= 0 && k <= 256 && b.size() == sizeof(int) + sizeof(cxd) * ((size_t)H.mn * k + (size_t)H.mf * k);
+  }
+  return false;
+}
+
 int vsie_checkpoint_save(const vsie_handle* hd, const char* path) {
   if (!hd || !path) return fail(VSIE_E_ARG, "null argument");
   const Handle& H = hd->H;
@@ -2019,6 +2040,11 @@ int vsie_checkpoint_load(vsie_handle* hd, const char* path) {
       FILE* f;
       ~Closer() { std::fclose(f); }
     } closer{f};
+    // bytes in the file, so that a damaged record length is refused before anything is allocated
+    if (std::fseek(f, 0, SEEK_END) != 0) throw Error(VSIE_E_ARG, std::string("cannot read ") + path);
+    const long fsize = std::ftell(f);
+    if (fsize < 0 || std::fseek(f, 0, SEEK_SET) != 0) throw Error(VSIE_E_ARG, std::string("cannot read ") + path);
+    const uint64_t total = (uint64_t)fsize;
     char magic[8];
     uint32_t ver = 0, nrec = 0;
     uint64_t hash = 0;
@@ -2033,12 +2059,14 @@ int vsie_checkpoint_load(vsie_handle* hd, const char* path) {
     for (uint32_t i = 0; i < nrec; ++i) {
       uint32_t what = 0, index = 0;
       uint64_t nb = 0;
-      if (std::fread(&what, 4, 1, f) != 1 || std::fread(&index, 4, 1, f) != 1 || std::fread(&nb, 8, 1, f) != 1 ||
-          nb > ((uint64_t)1 << 36))
-        throw Error(VSIE_E_ARG, "corrupt checkpoint");
+      if (std::fread(&what, 4, 1, f) != 1 || std::fread(&index, 4, 1, f) != 1 || std::fread(&nb, 8, 1, f) != 1)
+        throw Error(VSIE_E_ARG, "truncated checkpoint");
+      const long pos = std::ftell(f);
+      if (pos < 0 || (uint64_t)pos > total || nb > total - (uint64_t)pos)
+        throw Error(VSIE_E_ARG, "truncated checkpoint");
       std::vector<unsigned char> b(nb);
       if (std::fread(b.data(), 1, nb, f) != nb) throw Error(VSIE_E_ARG, "truncated checkpoint");
-      if (what != VSIE_X_TT_CORES && what != VSIE_X_ACA) throw Error(VSIE_E_ARG, "corrupt checkpoint");
+      if (!checkpoint_record_ok(H, what, index, b)) throw Error(VSIE_E_ARG, "corrupt checkpoint");
       recs.push_back({{what, index}, std::move(b)});
     }
     for (const auto& r : recs) {
